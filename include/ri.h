@@ -1,0 +1,177 @@
+/*
+ * ri.h -- reduced-interface speculative data-parallel recognizer (RID) for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Borsotti, Breveglieri, Crespi Reghizzi, Morzenti, "Minimizing
+ * speculation overhead in a parallel recognizer for regular texts",
+ * arXiv 2412.14975.
+ *
+ * The problem (Sect. 2): given a regular language L, written as a regular
+ * expression, and a text x of n bytes, decide whether x is in L.  The text is
+ * cut into c non-empty chunks; every chunk is scanned independently by a
+ * deterministic chunk automaton from each of its possible start states (the
+ * reach phase), and the per-chunk start->end maps are joined to check
+ * consistency and acceptance (the join phase).
+ *
+ * RI_ALGO_RID runs the chunk automaton of Sect. 3: an RI-DFA whose start
+ * (interface) states are the singletons of an NFA for L, after the interface
+ * reduction of Sect. 3.4.  RI_ALGO_DFA is the classic baseline of Sect. 2
+ * (Fig. 2): the minimal DFA speculated from all of its states.
+ * RI_ALGO_SUBSET speculates from all states of the unminimized powerset DFA
+ * of the position NFA (a second baseline for languages whose minimal DFA is
+ * trivially small).
+ *
+ * Every call returns RI_OK (0) or a negative RI_ERR_* code; ri_last_error()
+ * then gives a message for the calling thread.  No C++ exception crosses
+ * this interface.  All functions are thread-safe; calls that share a stream
+ * are ordered by that stream.
+ *
+ * Streams are passed as `void *` and are hipStream_t values (NULL = the
+ * null stream).  Device pointers are plain HIP device addresses (for
+ * example `torch.Tensor.data_ptr()` of a CUDA/ROCm tensor).
+ */
+#ifndef RI_H
+#define RI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------ */
+#define RI_OK          0
+#define RI_ERR_PARSE  (-1)   /* malformed expression; the message gives the byte offset */
+#define RI_ERR_LIMIT  (-2)   /* an automaton exceeds max_states, or a size limit of the
+                                device path is exceeded (see ri_recognize_ex) */
+#define RI_ERR_NOMEM  (-3)   /* host or device allocation failed */
+#define RI_ERR_DEVICE (-4)   /* a HIP call failed (no device, launch error, ...) */
+#define RI_ERR_ARG    (-5)   /* invalid argument: NULL pointer, bad algo, misaligned text */
+
+/* ---- algorithms -------------------------------------------------------- */
+#define RI_ALGO_RID     0    /* RI-DFA chunk automaton, reduced interface (Sects. 3.1-3.4) */
+#define RI_ALGO_DFA     1    /* minimal DFA, all states speculated (Sect. 2, Fig. 2)      */
+#define RI_ALGO_SUBSET  2    /* powerset DFA of the position NFA, all states speculated  */
+#define RI_NUM_ALGOS    3
+
+typedef struct ri_handle ri_handle;   /* opaque; immutable after ri_build */
+
+typedef struct {
+    uint32_t max_states;   /* cap on the states of any automaton built; 0 = 1<<20 */
+    uint32_t flags;        /* reserved, must be 0 */
+} ri_build_opts;
+
+typedef struct {
+    int32_t  accept;       /* 1 iff x is in L (Th. 1)                                  */
+    int32_t  final_state;  /* state of the minimal, trimmed DFA after x, numbered
+                              breadth-first from the initial state with bytes scanned
+                              in ascending order; -1 when the run dies               */
+    uint64_t n;            /* text length                                              */
+    uint32_t chunks;       /* number of chunks c actually used                         */
+    uint32_t chunk_size;   /* bytes per chunk (the last one may be shorter)            */
+} ri_result;
+
+typedef struct {
+    uint32_t nfa_states;          /* |Q_N|: trimmed position NFA (Sect. 4.1)          */
+    uint32_t interface_states;    /* |I^{B_min}| = states of the quotient NFA N'      */
+    uint32_t ridfa_states;        /* |P'|: states of B' = RI-DFA(N')                  */
+    uint32_t ridfa_full_states;   /* |P|: states of B = RI-DFA(N) before reduction   */
+    uint32_t min_dfa_states;      /* |Q_min| of the trimmed minimal DFA               */
+    uint32_t subset_dfa_states;   /* states of the powerset DFA of N                  */
+    uint32_t classes;             /* K: byte classes                                  */
+    uint32_t accepts_empty;       /* 1 iff the empty text is in L                     */
+    uint32_t starts[RI_NUM_ALGOS];      /* speculative starts per chunk, per algo      */
+    uint32_t entry_bytes[RI_NUM_ALGOS]; /* bytes per transition-table entry, per algo  */
+    uint64_t table_bytes[RI_NUM_ALGOS]; /* device transition-table bytes, per algo     */
+} ri_info_t;
+
+/*
+ * ri_build -- construct every automaton for the expression `re` (re_len
+ * bytes; see the package documentation for the syntax) on the host:
+ * position NFA N, RI-DFA B = RI-DFA(N) (Sect. 3.1), Nerode classes of B and
+ * the interface reduction (Sect. 3.4), the quotient NFA N' whose states are
+ * the surviving interface states, B' = RI-DFA(N'), the minimal DFA and the
+ * powerset DFA.  No device call is made; tables are uploaded to the current
+ * device by the first recognition call on it.
+ * opts may be NULL.  On success *out owns everything until ri_free.
+ * Errors: RI_ERR_ARG (NULL re/out, flags != 0), RI_ERR_PARSE, RI_ERR_LIMIT,
+ * RI_ERR_NOMEM.
+ */
+int ri_build(const char *re, size_t re_len, const ri_build_opts *opts, ri_handle **out);
+
+/* ri_free -- release host and device memory of a handle; NULL is a no-op.
+ * No call on the handle may be in flight. */
+void ri_free(ri_handle *h);
+
+/* ri_info -- sizes of the constructed automata (host only). */
+int ri_info(const ri_handle *h, ri_info_t *out);
+
+/*
+ * ri_recognize -- recognize the device-resident text `text_dev` of n bytes
+ * with RI_ALGO_RID and an automatically chosen chunk count.  Equivalent to
+ * ri_recognize_ex(h, text_dev, n, stream, RI_ALGO_RID, 0, out).
+ */
+int ri_recognize(const ri_handle *h, const uint8_t *text_dev, size_t n, void *stream,
+                 ri_result *out);
+
+/*
+ * ri_recognize_ex -- chunked speculative recognition (Sects. 2 and 3.2).
+ *
+ * text_dev : device pointer to n bytes, 16-byte aligned (RI_ERR_ARG otherwise);
+ *            owned by the caller and read-only; must stay valid until return.
+ * n        : text length; n = 0 decides whether the empty text is in L without
+ *            touching the device.
+ * stream   : hipStream_t on which all work is enqueued; the call synchronizes
+ *            this stream (only) before it returns.
+ * algo     : RI_ALGO_RID, RI_ALGO_DFA or RI_ALGO_SUBSET.
+ * chunks   : requested chunk count c (0 = choose automatically).  Chunks are
+ *            ceil(n/c) bytes rounded up to a multiple of 16, so the count used
+ *            (reported in out->chunks) can be smaller; c is clamped to n.
+ * out      : result (host memory).
+ * Chunk i covers bytes [i*s, min((i+1)*s, n)) with s = out->chunk_size.
+ * Scratch memory is owned by the handle, cached per stream and reused.
+ * Errors: RI_ERR_ARG, RI_ERR_LIMIT (interface too large for the device join,
+ * table too large for the device path), RI_ERR_NOMEM, RI_ERR_DEVICE.
+ */
+int ri_recognize_ex(const ri_handle *h, const uint8_t *text_dev, size_t n, void *stream,
+                    int algo, uint32_t chunks, ri_result *out);
+
+/*
+ * ri_chunk_maps -- the reach phase only, for inspection: like ri_recognize_ex,
+ * and in addition copies the chunk maps lambda_i (Sects. 2 and 3.2) to the
+ * host array maps[c * starts + s] (int32, caller-owned, `cap` entries), where
+ * s indexes the algorithm's start list (ri_info starts[algo]) and the value
+ * is the chunk automaton's end state, or -1 when the run dies (or, for chunk
+ * 0, for every start but the initial one).  RI_ERR_ARG if cap is too small.
+ */
+int ri_chunk_maps(const ri_handle *h, const uint8_t *text_dev, size_t n, void *stream,
+                  int algo, uint32_t chunks, int32_t *maps, size_t cap, ri_result *out);
+
+/*
+ * ri_state_content -- for RI_ALGO_RID, the content of RI-DFA state `state`
+ * (the states of N' it stands for, Sect. 3.1), written in ascending order to
+ * members[0..*count) (at most cap entries); start s of RI_ALGO_RID is the
+ * singleton {s} of N'.  For RI_ALGO_DFA / RI_ALGO_SUBSET, the minimal-DFA
+ * state that the state stands for (one entry), or no entry for none.
+ */
+int ri_state_content(const ri_handle *h, int algo, uint32_t state, uint32_t *members,
+                     uint32_t cap, uint32_t *count);
+
+/*
+ * ri_set_profiling / ri_last_timings -- when enabled, each recognition call
+ * records HIP events on its stream around its kernels; ri_last_timings then
+ * returns, for the last completed call on this handle, in milliseconds:
+ * ms[0] reach kernel, ms[1] join kernels, ms[2] whole enqueue-to-result.
+ */
+int ri_set_profiling(ri_handle *h, int enable);
+int ri_last_timings(const ri_handle *h, float ms[3]);
+
+/* ri_last_error -- message of the last failing call on this thread. */
+const char *ri_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RI_H */

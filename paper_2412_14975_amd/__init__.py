@@ -1,0 +1,13 @@
+"""MI355X-native reduced-interface speculative data-parallel recognizer.
+
+Implements the chunked recognizer of Borsotti, Breveglieri, Crespi Reghizzi
+and Morzenti, "Minimizing speculation overhead in a parallel recognizer for
+regular texts" (arXiv 2412.14975): an RI-DFA chunk automaton (Sect. 3) whose
+reach and join phases run as HIP kernels on gfx950, behind the C ABI of
+include/ri.h (libri.so).  ``binding`` is the ctypes layer with the C names.
+"""
+
+from .binding import (  # noqa: F401
+    ALGOS, RIError, Recognizer, ri_build, ri_chunk_maps, ri_free, ri_info, ri_last_error,
+    ri_last_timings, ri_recognize, ri_recognize_ex, ri_set_profiling, ri_state_content,
+)

@@ -1,0 +1,235 @@
+"""ctypes binding of libri.so (include/ri.h), with the C names.
+
+Argument marshalling only: every step of recognition runs in the library's
+HIP kernels.  Texts are torch uint8 tensors on the GPU; streams are
+``torch.cuda.Stream`` objects (default: torch's current stream).  There is no
+CPU path: without the built library or without a GPU tensor these functions
+raise.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime that libri.so binds to)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libri.so")
+
+RI_OK, RI_ERR_PARSE, RI_ERR_LIMIT, RI_ERR_NOMEM, RI_ERR_DEVICE, RI_ERR_ARG = 0, -1, -2, -3, -4, -5
+RI_ALGO_RID, RI_ALGO_DFA, RI_ALGO_SUBSET = 0, 1, 2
+RI_NUM_ALGOS = 3
+ALGOS = {"rid": RI_ALGO_RID, "dfa": RI_ALGO_DFA, "subset": RI_ALGO_SUBSET}
+
+SYMBOLS = ("ri_build", "ri_free", "ri_info", "ri_recognize", "ri_recognize_ex",
+           "ri_chunk_maps", "ri_state_content", "ri_set_profiling", "ri_last_timings",
+           "ri_last_error")
+
+
+class RIError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class ri_build_opts(ctypes.Structure):
+    _fields_ = [("max_states", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class ri_result(ctypes.Structure):
+    _fields_ = [("accept", ctypes.c_int32), ("final_state", ctypes.c_int32),
+                ("n", ctypes.c_uint64), ("chunks", ctypes.c_uint32),
+                ("chunk_size", ctypes.c_uint32)]
+
+
+class ri_info_t(ctypes.Structure):
+    _fields_ = [("nfa_states", ctypes.c_uint32), ("interface_states", ctypes.c_uint32),
+                ("ridfa_states", ctypes.c_uint32), ("ridfa_full_states", ctypes.c_uint32),
+                ("min_dfa_states", ctypes.c_uint32), ("subset_dfa_states", ctypes.c_uint32),
+                ("classes", ctypes.c_uint32), ("accepts_empty", ctypes.c_uint32),
+                ("starts", ctypes.c_uint32 * RI_NUM_ALGOS),
+                ("entry_bytes", ctypes.c_uint32 * RI_NUM_ALGOS),
+                ("table_bytes", ctypes.c_uint64 * RI_NUM_ALGOS)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libri.so (built by ``__graft_entry__.build()``); raise if missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, u32, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_int
+    L.ri_build.argtypes = [ctypes.c_char_p, sz, ctypes.POINTER(ri_build_opts), ctypes.POINTER(vp)]
+    L.ri_free.argtypes = [vp]
+    L.ri_free.restype = None
+    L.ri_info.argtypes = [vp, ctypes.POINTER(ri_info_t)]
+    L.ri_recognize.argtypes = [vp, vp, sz, vp, ctypes.POINTER(ri_result)]
+    L.ri_recognize_ex.argtypes = [vp, vp, sz, vp, i32, u32, ctypes.POINTER(ri_result)]
+    L.ri_chunk_maps.argtypes = [vp, vp, sz, vp, i32, u32, vp, sz, ctypes.POINTER(ri_result)]
+    L.ri_state_content.argtypes = [vp, i32, u32, ctypes.POINTER(u32), u32, ctypes.POINTER(u32)]
+    L.ri_set_profiling.argtypes = [vp, i32]
+    L.ri_last_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
+    L.ri_last_error.argtypes = []
+    L.ri_last_error.restype = ctypes.c_char_p
+    for name in SYMBOLS:
+        if name not in ("ri_free", "ri_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != RI_OK:
+        raise RIError(rc, lib().ri_last_error().decode(errors="replace"))
+
+
+def _algo(a) -> int:
+    return ALGOS[a] if isinstance(a, str) else int(a)
+
+
+def _text_ptr(text: torch.Tensor) -> tuple:
+    if not isinstance(text, torch.Tensor) or text.dtype != torch.uint8 or text.dim() != 1:
+        raise TypeError("text must be a 1-D torch.uint8 tensor")
+    if not text.is_cuda:
+        raise TypeError("text must be on the GPU (no CPU path)")
+    if not text.is_contiguous():
+        raise TypeError("text must be contiguous")
+    return text.data_ptr(), text.numel()
+
+
+def _stream_ptr(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if isinstance(stream, torch.cuda.Stream) else int(stream)
+
+
+# ---------------------------------------------------------------------------
+# the C functions
+# ---------------------------------------------------------------------------
+
+def ri_build(regex, max_states: int = 0) -> int:
+    if isinstance(regex, str):
+        regex = regex.encode("latin-1")
+    regex = bytes(regex)
+    h = ctypes.c_void_p()
+    opts = ri_build_opts(max_states, 0)
+    _check(lib().ri_build(regex, len(regex), ctypes.byref(opts), ctypes.byref(h)))
+    return h.value
+
+
+def ri_free(h: int) -> None:
+    lib().ri_free(h)
+
+
+def ri_info(h: int) -> dict:
+    info = ri_info_t()
+    _check(lib().ri_info(h, ctypes.byref(info)))
+    out = {name: getattr(info, name) for name, _ in ri_info_t._fields_}
+    for k in ("starts", "entry_bytes", "table_bytes"):
+        out[k] = list(out[k])
+    return out
+
+
+def _result(r: ri_result) -> dict:
+    return dict(accept=bool(r.accept), final_state=int(r.final_state), n=int(r.n),
+                chunks=int(r.chunks), chunk_size=int(r.chunk_size))
+
+
+def ri_recognize(h: int, text: torch.Tensor, stream=None) -> dict:
+    ptr, n = _text_ptr(text)
+    r = ri_result()
+    _check(lib().ri_recognize(h, ptr, n, _stream_ptr(stream), ctypes.byref(r)))
+    return _result(r)
+
+
+def ri_recognize_ex(h: int, text: torch.Tensor, stream=None, algo="rid", chunks: int = 0) -> dict:
+    ptr, n = _text_ptr(text)
+    r = ri_result()
+    _check(lib().ri_recognize_ex(h, ptr, n, _stream_ptr(stream), _algo(algo), int(chunks),
+                                 ctypes.byref(r)))
+    return _result(r)
+
+
+def ri_chunk_maps(h: int, text: torch.Tensor, stream=None, algo="rid", chunks: int = 0):
+    """Returns (result dict, int32 numpy array [chunks, starts]) of the chunk
+    maps.  A first call sizes the output from the chunk count actually used."""
+    import numpy as np
+    ptr, n = _text_ptr(text)
+    L = ri_info(h)["starts"][_algo(algo)]
+    first = ri_recognize_ex(h, text, stream, algo, chunks)
+    cap = max(1, first["chunks"] * L)
+    maps = np.full(cap, -1, dtype=np.int32)
+    r = ri_result()
+    _check(lib().ri_chunk_maps(h, ptr, n, _stream_ptr(stream), _algo(algo), int(chunks),
+                               maps.ctypes.data, cap, ctypes.byref(r)))
+    res = _result(r)
+    c = res["chunks"]
+    return res, maps[: c * L].reshape(c, L)
+
+
+def ri_state_content(h: int, algo, state: int) -> list:
+    cap = 1 << 16
+    buf = (ctypes.c_uint32 * cap)()
+    cnt = ctypes.c_uint32(0)
+    _check(lib().ri_state_content(h, _algo(algo), int(state), buf, cap, ctypes.byref(cnt)))
+    return list(buf[: cnt.value])
+
+
+def ri_set_profiling(h: int, enable: bool) -> None:
+    _check(lib().ri_set_profiling(h, 1 if enable else 0))
+
+
+def ri_last_timings(h: int) -> list:
+    ms = (ctypes.c_float * 3)()
+    _check(lib().ri_last_timings(h, ms))
+    return [float(x) for x in ms]
+
+
+def ri_last_error() -> str:
+    return lib().ri_last_error().decode(errors="replace")
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper
+# ---------------------------------------------------------------------------
+
+class Recognizer:
+    """Owns one handle: ``Recognizer(regex).recognize(text_tensor)``."""
+
+    def __init__(self, regex, max_states: int = 0):
+        self.handle = ri_build(regex, max_states)
+
+    def info(self) -> dict:
+        return ri_info(self.handle)
+
+    def recognize(self, text, algo="rid", chunks: int = 0, stream=None) -> dict:
+        return ri_recognize_ex(self.handle, text, stream, algo, chunks)
+
+    def chunk_maps(self, text, algo="rid", chunks: int = 0, stream=None):
+        return ri_chunk_maps(self.handle, text, stream, algo, chunks)
+
+    def state_content(self, algo, state: int) -> list:
+        return ri_state_content(self.handle, algo, state)
+
+    def set_profiling(self, enable: bool = True) -> None:
+        ri_set_profiling(self.handle, enable)
+
+    def last_timings(self) -> list:
+        return ri_last_timings(self.handle)
+
+    def close(self) -> None:
+        if self.handle:
+            ri_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,305 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle.
+
+Every comparison is bit-exact: ``accept`` and ``final_state`` (canonical
+minimal-DFA id) against the oracle's serial recognizer, and the chunk maps
+lambda_i against the oracle's own runs over the same chunk boundaries:
+RI-DFA end states are compared by content (the set of N' states they stand
+for), since state ids depend on construction order; DFA end states are
+canonical ids and are compared directly.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import gen
+
+torch = pytest.importorskip("torch")
+ri = pytest.importorskip("paper_2412_14975_amd")
+
+pytestmark = pytest.mark.gpu
+
+ALGOS = ("rid", "dfa", "subset")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ri.binding.lib()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.uint8)).to("cuda")
+
+
+class Ref:
+    """Oracle automata for one expression, with dense tables for the C scan."""
+
+    def __init__(self, pattern):
+        self.b = oracle.build(pattern)
+        self.tdfa = oracle.dense_table(self.b.dfa.n, self.b.dfa.delta)
+        self._tbq = None
+
+    @property
+    def tbq(self):
+        if self._tbq is None:
+            self._tbq = oracle.dense_table(self.b.Bq.n, self.b.Bq.delta)
+        return self._tbq
+
+    def serial(self, x):
+        return oracle.serial(self.b.dfa, x, self.tdfa)
+
+
+def check_maps(rec, ref, x, algo, chunks, sample=None, rng=None):
+    """Compare the chunk maps of the HIP path with the oracle's runs."""
+    res, maps = rec.chunk_maps(dev(x), algo=algo, chunks=chunks)
+    n, cs, c = len(x), res["chunk_size"], res["chunks"]
+    assert c == -(-n // cs)
+    idx = range(c) if sample is None else sorted(set([0, c - 1] + list(rng.choice(c, size=sample))))
+    for i in idx:
+        lo, hi = i * cs, min(n, (i + 1) * cs)
+        if algo == "rid":
+            B = ref.b.Bq
+            for q in range(ref.b.nfa_q.n):
+                want = None
+                if i == 0 and q != 0:
+                    want = None
+                else:
+                    end, _ = oracle.run(ref.tbq, B.initial[q], x, lo, hi)
+                    want = B.content[end] if end >= 0 else None
+                got = maps[i, q]
+                got_c = frozenset(rec.state_content("rid", int(got))) if got >= 0 else None
+                assert got_c == want, (i, q)
+        elif algo == "dfa":
+            for s in range(ref.b.dfa.n):
+                want = -1 if (i == 0 and s != 0) else oracle.run(ref.tdfa, s, x, lo, hi)[0]
+                assert maps[i, s] == want, (i, s)
+    return res
+
+
+# ---------------------------------------------------------------------------
+# tiny workload: (a|b)*a(a|b)^3, 1 MiB
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def tiny():
+    rx = gen.c1_regex()
+    rec = ri.Recognizer(rx)
+    yield rec, Ref(rx)
+    rec.close()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("chunks", [64, 0, 1, 1000, 65536])
+def test_tiny_accept_and_final(tiny, seed, algo, chunks):
+    rec, ref = tiny
+    acc, rej = gen.c1_texts(seed)
+    for x, expect in ((acc, True), (rej, False)):
+        want = ref.serial(x)
+        assert want[0] is expect
+        got = rec.recognize(dev(x), algo=algo, chunks=chunks)
+        assert (got["accept"], got["final_state"]) == want
+        assert got["n"] == len(x)
+
+
+@pytest.mark.parametrize("algo", ["rid", "dfa"])
+def test_tiny_chunk_maps(tiny, algo):
+    rec, ref = tiny
+    acc, _ = gen.c1_texts(3, n=(1 << 14) + 5)      # ragged last chunk
+    check_maps(rec, ref, acc, algo, 64)
+    check_maps(rec, ref, acc, algo, 1000)
+
+
+# ---------------------------------------------------------------------------
+# random expressions, ragged sizes, every algorithm
+# ---------------------------------------------------------------------------
+
+def small_pattern(rng, alphabet, depth, maxpos=40):
+    while True:
+        p = gen.random_regex(rng, alphabet, depth)
+        if oracle.position_nfa(p).n <= maxpos:
+            return p
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_expressions(seed):
+    rng = gen.PCG(777 + seed)
+    alphabet = b"abcd"[: 2 + seed % 3]
+    pattern = small_pattern(rng, alphabet, int(rng.integers(1, 4)))
+    ref = Ref(pattern)
+    rec = ri.Recognizer(pattern)
+    try:
+        for n in (1, 5, 15, 16, 17, 63, 200, 4097, 70001):
+            x = gen.random_text(rng, alphabet + b"z", n) if seed % 4 == 0 else gen.random_text(rng, alphabet, n)
+            want = ref.serial(x)
+            for algo in ALGOS:
+                for chunks in (1, 3, n, 0):
+                    got = rec.recognize(dev(x), algo=algo, chunks=chunks)
+                    assert (got["accept"], got["final_state"]) == want, (pattern, n, algo, chunks)
+        x = gen.random_text(rng, alphabet, 3001)
+        check_maps(rec, ref, x, "rid", 37)
+        check_maps(rec, ref, x, "dfa", 37)
+    finally:
+        rec.close()
+
+
+def test_accepted_texts_of_random_expressions():
+    """Texts built as members (random walks to acceptance on the oracle DFA),
+    so that acceptance, not just rejection, is exercised on long inputs."""
+    rng = gen.PCG(4242)
+    for _ in range(8):
+        pattern = small_pattern(rng, b"abc", 3)
+        ref = Ref(pattern)
+        d = ref.b.dfa
+        if d.n == 0 or not d.final:
+            continue
+        # walk, then finish along a shortest path to a final state
+        s, out = 0, []
+        for _ in range(5000):
+            moves = sorted(d.delta[s].items())
+            if not moves:
+                break
+            b, s = moves[int(rng.integers(0, len(moves)))]
+            out.append(b)
+        dist = {f: [] for f in d.final}
+        frontier = list(d.final)
+        pred = [[] for _ in range(d.n)]
+        for q in range(d.n):
+            for b, t in d.delta[q].items():
+                pred[t].append((q, b))
+        while frontier:
+            nxt = []
+            for t in frontier:
+                for q, b in pred[t]:
+                    if q not in dist:
+                        dist[q] = [b] + dist[t]
+                        nxt.append(q)
+            frontier = nxt
+        if s not in dist:
+            continue
+        x = np.frombuffer(bytes(out + dist[s]), dtype=np.uint8)
+        want = ref.serial(x)
+        assert want[0] is True
+        rec = ri.Recognizer(pattern)
+        try:
+            for algo in ALGOS:
+                for chunks in (1, 7, 100, 0):
+                    got = rec.recognize(dev(x), algo=algo, chunks=chunks)
+                    assert (got["accept"], got["final_state"]) == want
+        finally:
+            rec.close()
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+
+def test_edge_cases():
+    rec = ri.Recognizer(b"ab*")
+    ref = Ref(b"ab*")
+    try:
+        # empty text: decided on the host, no device work
+        r = rec.recognize(torch.empty(0, dtype=torch.uint8, device="cuda"))
+        assert (r["accept"], r["final_state"]) == (False, 0)
+        # one byte, more chunks than bytes
+        for x in (b"a", b"b", b"abbb", b"ab\x00b"):
+            xx = np.frombuffer(x, dtype=np.uint8)
+            for algo in ALGOS:
+                for chunks in (1, 2, 100):
+                    got = rec.recognize(dev(xx), algo=algo, chunks=chunks)
+                    assert (got["accept"], got["final_state"]) == ref.serial(xx)
+                    assert got["chunks"] >= 1
+        # misaligned text is refused, not read
+        buf = torch.zeros(64, dtype=torch.uint8, device="cuda")
+        with pytest.raises(ri.RIError) as e:
+            rec.recognize(buf[1:])
+        assert e.value.code == ri.binding.RI_ERR_ARG
+        # no CPU path
+        with pytest.raises(TypeError):
+            rec.recognize(torch.zeros(16, dtype=torch.uint8))
+    finally:
+        rec.close()
+
+
+def test_empty_language_and_empty_string_language():
+    e = ri.Recognizer(b"a[^\\x00-\\xff]")
+    try:
+        x = dev(np.frombuffer(b"a" * 100, dtype=np.uint8))
+        for algo in ALGOS:
+            assert e.recognize(x, algo=algo) == dict(accept=False, final_state=-1, n=100, chunks=0,
+                                                     chunk_size=0)
+    finally:
+        e.close()
+    eps = ri.Recognizer(b"()")
+    try:
+        r = eps.recognize(torch.empty(0, dtype=torch.uint8, device="cuda"))
+        assert (r["accept"], r["final_state"]) == (True, 0)
+        r = eps.recognize(dev(np.frombuffer(b"x" * 33, dtype=np.uint8)), algo="dfa")
+        assert (r["accept"], r["final_state"]) == (False, -1)
+    finally:
+        eps.close()
+
+
+def test_side_stream_and_handle_reuse(tiny):
+    rec, ref = tiny
+    acc, rej = gen.c1_texts(9, n=1 << 18)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ta, tr = dev(acc), dev(rej)
+        for _ in range(3):
+            for x, t in ((acc, ta), (rej, tr)):
+                got = rec.recognize(t, algo="rid", chunks=0, stream=s)
+                assert (got["accept"], got["final_state"]) == ref.serial(x)
+
+
+# ---------------------------------------------------------------------------
+# motif union over {A,C,G,T}: 256 MiB
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_motif_union_full_size(seed):
+    rx, motifs = gen.c2_regex_and_motifs(seed)
+    ref = Ref(rx)
+    x, rej = gen.c2_texts(seed, motifs=motifs)
+    rec = ri.Recognizer(rx)
+    try:
+        for text in (x, rej):
+            want = ref.serial(text)
+            t = dev(text)
+            for algo in ("rid", "dfa") + (("subset",) if seed == 0 else ()):
+                for chunks in ((0, 1024, 262144) if algo != "subset" else (0,)):
+                    got = rec.recognize(t, algo=algo, chunks=chunks)
+                    assert (got["accept"], got["final_state"]) == want, (algo, chunks)
+            del t
+        res = check_maps(rec, ref, x, "rid", 0, sample=6, rng=gen.PCG(seed))
+        assert res["chunks"] > 1000
+    finally:
+        rec.close()
+    torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------
+# log lines: 1 GiB
+# ---------------------------------------------------------------------------
+
+def test_log_lines_full_size():
+    rx = gen.c3_regex()
+    ref = Ref(rx)
+    x, r1, r2 = gen.c3_texts(0)
+    assert len(x) > (1 << 30) - 4096
+    rec = ri.Recognizer(rx)
+    try:
+        for text in (x, r1, r2):
+            want = ref.serial(text)
+            t = dev(text)
+            for algo in ("rid", "dfa"):
+                got = rec.recognize(t, algo=algo)
+                assert (got["accept"], got["final_state"]) == want, algo
+            del t
+        check_maps(rec, ref, x, "rid", 0, sample=4, rng=gen.PCG(1))
+        check_maps(rec, ref, x, "dfa", 0, sample=4, rng=gen.PCG(2))
+    finally:
+        rec.close()
+    torch.cuda.empty_cache()

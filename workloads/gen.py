@@ -206,44 +206,56 @@ def _c3_batch(rng: np.random.Generator, nlines: int) -> np.ndarray:
         add(_K_ALNUM, vl[:, f])
     add(_K_LIT, 1, ord("\n"))
 
-    kind = np.stack(segs_kind, axis=1).ravel()
+    kind = np.stack(segs_kind, axis=1).ravel().astype(np.uint8)
     length = np.stack(segs_len, axis=1).ravel()
-    lit = np.stack(segs_lit, axis=1).ravel()
-    total = int(length.sum())
+    lit = np.stack(segs_lit, axis=1).ravel().astype(np.uint8)
     bkind = np.repeat(kind, length)
-    blit = np.repeat(lit, length)
-    out = np.empty(total, dtype=np.uint8)
-    m = bkind == _K_LIT
-    out[m] = blit[m].astype(np.uint8)
+    out = np.repeat(lit, length)          # literal bytes in place
     for k, alpha in ((_K_DIG, _DIG), (_K_LOW, _LOW), (_K_ALNUM, _ALNUM)):
-        m = bkind == k
-        cnt = int(m.sum())
-        out[m] = alpha[rng.integers(0, len(alpha), size=cnt)]
+        idx = np.flatnonzero(bkind == k)
+        out[idx] = alpha[rng.integers(0, len(alpha), size=len(idx), dtype=np.uint8)]
     return out
 
 
-def c3_texts(seed: int, n: int = 1 << 30, batch_lines: int = 1 << 18):
+def c3_texts(seed: int, n: int = 1 << 30, batch_lines: int = 1 << 17, workers: int = 0):
     """Return (text, rejected_random, rejected_guaranteed).
 
     ``text`` is whole lines only, at most ``n`` bytes.  ``rejected_random``
     has one byte replaced by a different random byte (it may still be in the
     language); ``rejected_guaranteed`` has the same byte replaced by 0x01.
+
+    Batch i of ``batch_lines`` lines draws from the i-th child of
+    ``SeedSequence(seed)``, so the bytes do not depend on ``workers`` (the
+    number of threads generating batches concurrently; 0 = all cores, at
+    most 16).
     """
-    rng = PCG(seed)
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
+    if workers <= 0:
+        workers = max(1, min(16, os.cpu_count() or 1))
+    children = np.random.SeedSequence(int(seed)).spawn(1 << 14)
     pieces = []
     have = 0
-    while have < n:
-        b = _c3_batch(rng, batch_lines)
-        nl = np.flatnonzero(b == ord("\n"))
-        room = n - have
-        if len(b) > room:
-            k = np.searchsorted(nl, room - 1, side="right")
-            b = b[: (int(nl[k - 1]) + 1) if k > 0 else 0]
-            pieces.append(b)
-            have += len(b)
-            break
-        pieces.append(b)
-        have += len(b)
+    nxt = 0
+    with ThreadPoolExecutor(max_workers=workers) as pool:
+        while have < n:
+            if nxt + workers > len(children):
+                raise ValueError("text too long for the batch schedule")
+            rngs = [np.random.Generator(np.random.PCG64(children[nxt + i])) for i in range(workers)]
+            nxt += workers
+            for b in pool.map(lambda r: _c3_batch(r, batch_lines), rngs):
+                if have >= n:
+                    break
+                room = n - have
+                if len(b) > room:
+                    nl = np.flatnonzero(b[:room] == ord("\n"))
+                    b = b[: int(nl[-1]) + 1] if len(nl) else b[:0]
+                    pieces.append(b)
+                    have = n
+                    break
+                pieces.append(b)
+                have += len(b)
     t = np.concatenate(pieces) if pieces else np.zeros(0, dtype=np.uint8)
     r1 = t.copy()
     r2 = t.copy()
