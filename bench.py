@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Benchmark: GB/s of text recognized by chunked RI-DFA speculation (RID)
+against all-states DFA speculation, bit-exact, with p50/p99 per call.
+
+One step = one ri_recognize_ex call over the whole text: reach kernel, join
+kernels, finalize kernel and the read-back of the result, with the text
+already resident in HBM.  Default workload: the motif union over {A,C,G,T}
+(256 MiB).  Prints ONE JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload motif|log|tiny]
+                  [--chunks C] [--seed S] [--no-cpu-baseline]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="motif", choices=["motif", "log", "tiny"])
+    ap.add_argument("--chunks", type=int, default=0)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    return ap.parse_args()
+
+
+def workload(name, seed):
+    from workloads import gen
+    if name == "motif":
+        rx, motifs = gen.c2_regex_and_motifs(seed)
+        x, _ = gen.c2_texts(seed, motifs=motifs)
+        return rx, x, "motif-union-ACGT-256MiB"
+    if name == "log":
+        rx = gen.c3_regex()
+        x, _, _ = gen.c3_texts(seed)
+        return rx, x, "log-lines-1GiB"
+    rx = gen.c1_regex()
+    x, _ = gen.c1_texts(seed)
+    return rx, x, "regexp-k3-1MiB"
+
+
+def time_algo(torch, rec, t, algo, chunks, steps, warmup, want):
+    """Returns dict with per-call times (s), whole-run time and kernel timings."""
+    for _ in range(warmup):
+        r = rec.recognize(t, algo=algo, chunks=chunks)
+    torch.cuda.synchronize()
+    rec.set_profiling(True)
+    per_call, reach_ms, join_ms, kern_ms, warm_ms, exact = [], [], [], [], [], True
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        c0 = time.perf_counter()
+        r = rec.recognize(t, algo=algo, chunks=chunks)
+        per_call.append(time.perf_counter() - c0)
+        ms = rec.last_timings()
+        reach_ms.append(ms[0])
+        join_ms.append(ms[1])
+        kern_ms.append(ms[3])
+        warm_ms.append(ms[4])
+        exact &= (r["accept"], r["final_state"]) == want
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    rec.set_profiling(False)
+    return dict(per_call=np.array(per_call), total=total, reach_ms=np.array(reach_ms),
+                join_ms=np.array(join_ms), kern_ms=np.array(kern_ms), warm_ms=np.array(warm_ms),
+                result=r, exact=exact)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this recognizer runs on one GPU only; --gpus must be 1 "
+              "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2412_14975_amd as ri
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU", file=sys.stderr)
+        sys.exit(2)
+
+    rx, x, wname = workload(args.workload, args.seed)
+    n = len(x)
+    print(f"# workload {wname}: n={n} bytes", file=sys.stderr, flush=True)
+
+    # expected result from the oracle (serial scan, host)
+    import oracle
+    ref = oracle.build(rx)
+    table = oracle.dense_table(ref.dfa.n, ref.dfa.delta)
+    want = oracle.serial(ref.dfa, x, table)
+    print(f"# oracle result {want}", file=sys.stderr, flush=True)
+
+    rec = ri.Recognizer(rx)
+    info = rec.info()
+    t = torch.from_numpy(x).to("cuda")
+    torch.cuda.synchronize()
+
+    rid = time_algo(torch, rec, t, "rid", args.chunks, args.steps, args.warmup, want)
+    print(f"# rid done", file=sys.stderr, flush=True)
+    dfa = time_algo(torch, rec, t, "dfa", args.chunks, args.steps, args.warmup, want)
+    print(f"# dfa done", file=sys.stderr, flush=True)
+
+    def summary(m):
+        p50 = float(np.percentile(m["per_call"], 50))
+        p99 = float(np.percentile(m["per_call"], 99))
+        return dict(gbps=n * args.steps / m["total"] / 1e9, ms_per_step=m["total"] / args.steps * 1e3,
+                    p50_ms=p50 * 1e3, p99_ms=p99 * 1e3, gbps_p50=n / p50 / 1e9, gbps_p99=n / p99 / 1e9,
+                    reach_ms=float(m["reach_ms"].mean()), join_ms=float(m["join_ms"].mean()),
+                    long_ms=float(m["kern_ms"].mean()), warm_ms=float(m["warm_ms"].mean()),
+                    chunks=m["result"]["chunks"], chunk_size=m["result"]["chunk_size"],
+                    bitexact=bool(m["exact"]))
+
+    s_rid, s_dfa = summary(rid), summary(dfa)
+
+    # roofline of the dominant kernel: the long-run kernel of the converging
+    # reach.  Algorithmic bytes per launch = the text bytes it must read, i.e.
+    # every chunk after its warm-up prefix (the merged runs of one chunk read
+    # the same bytes; the run records, 12 B per run, are < 2% and left out).
+    L = info["starts"][0]
+    cs, c = s_rid["chunk_size"], s_rid["chunks"]
+    warm = rec.get_option("warmup_bytes")
+    long_bytes = sum(max(0, min(cs, n - i * cs) - warm) for i in range(c)) if c < 5_000_000 else n
+    achieved = long_bytes / (s_rid["long_ms"] * 1e-3) / 1e9
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                kernel="long_kernel", algorithmic_bytes=int(long_bytes),
+                reach_phase_gbps=round(n / (s_rid["reach_ms"] * 1e-3) / 1e9, 1))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's serial recognizer (plain C scan), one host core, whole text
+        # repeated until about --cpu-seconds have passed
+        reps, c0 = 0, time.perf_counter()
+        while True:
+            oracle.serial(ref.dfa, x, table)
+            reps += 1
+            if time.perf_counter() - c0 >= args.cpu_seconds:
+                break
+        dt = time.perf_counter() - c0
+        cpu = dict(value=round(n * reps / dt / 1e9, 4), unit="GB/s", cores=1, kind="oracle",
+                   sample=f"{reps} serial scans of the whole {n}-byte text by the oracle's "
+                          f"minimal-DFA scan ({dt:.1f} s)")
+
+    out = {
+        "metric": "GB/s of text recognized, RI-DFA vs all-states DFA speculation (bit-exact); p50/p99",
+        "value": round(s_rid["gbps"], 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(s_rid["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": wname, "n_bytes": n, "seed": args.seed, "algo": "rid",
+                   "chunks": s_rid["chunks"], "chunk_size": s_rid["chunk_size"],
+                   "interface_starts": L, "min_dfa_states": info["min_dfa_states"],
+                   "ridfa_states": info["ridfa_states"]},
+        "p50_ms": round(s_rid["p50_ms"], 4),
+        "p99_ms": round(s_rid["p99_ms"], 4),
+        "gbps_p50": round(s_rid["gbps_p50"], 2),
+        "gbps_p99": round(s_rid["gbps_p99"], 2),
+        "bitexact": s_rid["bitexact"] and s_dfa["bitexact"],
+        "rid": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s_rid.items()},
+        "all_states_dfa": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s_dfa.items()},
+        "speedup_rid_vs_dfa": round(s_rid["gbps"] / s_dfa["gbps"], 4),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    rec.close()
+
+
+if __name__ == "__main__":
+    main()

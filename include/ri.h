@@ -162,10 +162,34 @@ int ri_state_content(const ri_handle *h, int algo, uint32_t state, uint32_t *mem
  * ri_set_profiling / ri_last_timings -- when enabled, each recognition call
  * records HIP events on its stream around its kernels; ri_last_timings then
  * returns, for the last completed call on this handle, in milliseconds:
- * ms[0] reach kernel, ms[1] join kernels, ms[2] whole enqueue-to-result.
+ * ms[0] reach phase (all reach kernels), ms[1] join and finalize kernels,
+ * ms[2] whole enqueue-to-result, ms[3] the dominant reach kernel alone
+ * (the plain reach kernel, or the long-run kernel of the converging reach),
+ * ms[4] the warm-up kernel of the converging reach (0 for the plain one).
  */
 int ri_set_profiling(ri_handle *h, int enable);
-int ri_last_timings(const ri_handle *h, float ms[3]);
+int ri_last_timings(const ri_handle *h, float ms[5]);
+
+/*
+ * ri_set_option / ri_get_option -- per-handle tuning of the reach phase;
+ * a new value applies to calls that start after it is set.
+ *   RI_OPT_CONVERGE       1 (default): every run is scanned for a warm-up of
+ *                         RI_OPT_WARMUP_BYTES, then the runs of a chunk that
+ *                         are in the same state are merged (state
+ *                         convergence; the chunk maps are unchanged).
+ *                         0: every run is scanned to the chunk end or to its
+ *                         death, as the reach phase is stated.
+ *   RI_OPT_WARMUP_BYTES   multiple of 16 in [16, 1<<20]; default 64.
+ *   RI_OPT_RUNS_PER_LANE  independent runs per GPU lane: 0 (automatic), 1, 2, 4.
+ *   RI_OPT_CHUNK_TARGET   chunk count aimed at when chunks = 0; default 131072.
+ * Errors: RI_ERR_ARG for an unknown option or a value out of range.
+ */
+#define RI_OPT_CONVERGE       1
+#define RI_OPT_WARMUP_BYTES   2
+#define RI_OPT_RUNS_PER_LANE  3
+#define RI_OPT_CHUNK_TARGET   4
+int ri_set_option(ri_handle *h, int option, int64_t value);
+int ri_get_option(const ri_handle *h, int option, int64_t *value);
 
 /* ri_last_error -- message of the last failing call on this thread. */
 const char *ri_last_error(void);

@@ -24,7 +24,10 @@ ALGOS = {"rid": RI_ALGO_RID, "dfa": RI_ALGO_DFA, "subset": RI_ALGO_SUBSET}
 
 SYMBOLS = ("ri_build", "ri_free", "ri_info", "ri_recognize", "ri_recognize_ex",
            "ri_chunk_maps", "ri_state_content", "ri_set_profiling", "ri_last_timings",
-           "ri_last_error")
+           "ri_set_option", "ri_get_option", "ri_last_error")
+RI_OPT_CONVERGE, RI_OPT_WARMUP_BYTES, RI_OPT_RUNS_PER_LANE, RI_OPT_CHUNK_TARGET = 1, 2, 3, 4
+OPTIONS = {"converge": RI_OPT_CONVERGE, "warmup_bytes": RI_OPT_WARMUP_BYTES,
+           "runs_per_lane": RI_OPT_RUNS_PER_LANE, "chunk_target": RI_OPT_CHUNK_TARGET}
 
 
 class RIError(RuntimeError):
@@ -75,6 +78,8 @@ def lib() -> ctypes.CDLL:
     L.ri_state_content.argtypes = [vp, i32, u32, ctypes.POINTER(u32), u32, ctypes.POINTER(u32)]
     L.ri_set_profiling.argtypes = [vp, i32]
     L.ri_last_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
+    L.ri_set_option.argtypes = [vp, i32, ctypes.c_int64]
+    L.ri_get_option.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64)]
     L.ri_last_error.argtypes = []
     L.ri_last_error.restype = ctypes.c_char_p
     for name in SYMBOLS:
@@ -185,8 +190,21 @@ def ri_set_profiling(h: int, enable: bool) -> None:
     _check(lib().ri_set_profiling(h, 1 if enable else 0))
 
 
+def ri_set_option(h: int, option, value: int) -> None:
+    opt = OPTIONS[option] if isinstance(option, str) else int(option)
+    _check(lib().ri_set_option(h, opt, int(value)))
+
+
+def ri_get_option(h: int, option) -> int:
+    opt = OPTIONS[option] if isinstance(option, str) else int(option)
+    v = ctypes.c_int64(0)
+    _check(lib().ri_get_option(h, opt, ctypes.byref(v)))
+    return int(v.value)
+
+
 def ri_last_timings(h: int) -> list:
-    ms = (ctypes.c_float * 3)()
+    """[reach phase, join + finalize, whole call, dominant reach kernel, warm-up kernel] in ms."""
+    ms = (ctypes.c_float * 5)()
     _check(lib().ri_last_timings(h, ms))
     return [float(x) for x in ms]
 
@@ -222,6 +240,12 @@ class Recognizer:
 
     def last_timings(self) -> list:
         return ri_last_timings(self.handle)
+
+    def set_option(self, option, value: int) -> None:
+        ri_set_option(self.handle, option, value)
+
+    def get_option(self, option) -> int:
+        return ri_get_option(self.handle, option)
 
     def close(self) -> None:
         if self.handle:

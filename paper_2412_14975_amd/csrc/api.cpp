@@ -24,7 +24,6 @@ int fail(int code, const std::string &msg) {
 }
 
 constexpr uint32_t kJoinGroup = 64;          // members per join group
-constexpr uint32_t kAutoChunks = 131072;     // chunk count aimed at by chunks = 0
 constexpr uint64_t kMinAutoChunk = 256;      // smallest automatic chunk size (bytes)
 constexpr uint64_t kMaxLamBytes = 1ull << 31;
 constexpr int kMaxDevices = 64;
@@ -72,14 +71,19 @@ struct Workspace {
     std::mutex mu;
     int device = -1;
     hipStream_t stream = nullptr;
-    uint32_t *counter = nullptr;
+    uint32_t *counters = nullptr;   // [4], zero between calls
     int32_t *dres = nullptr;
     int32_t *hres = nullptr;        // pinned
-    void *lam = nullptr;
-    size_t lam_cap = 0;
-    void *buf[2] = {nullptr, nullptr};
-    size_t buf_cap[2] = {0, 0};
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    struct Buf { void *p = nullptr; size_t cap = 0; };
+    Buf lam, alias, run_base, run_chunk, run_state, run_final, dbg, join[2];
+    hipEvent_t ev[6] = {};
+};
+
+struct Options {
+    int converge = 1;
+    uint32_t warm = 64;
+    uint32_t runs_per_lane = 0;
+    uint32_t chunk_target = 131072;
 };
 
 }  // namespace
@@ -91,8 +95,8 @@ struct ri_handle {
     DeviceCopy dev[kMaxDevices];
     std::vector<std::unique_ptr<Workspace>> ws;
     bool profiling = false;
-    float last_ms[3] = {0, 0, 0};
-    uint32_t runs_per_lane[RI_NUM_ALGOS] = {0, 0, 0};
+    float last_ms[5] = {0, 0, 0, 0, 0};
+    Options opt;
 };
 
 namespace {
@@ -226,8 +230,8 @@ int get_workspace(ri_handle *h, int device, hipStream_t stream, Workspace **out)
     auto w = std::make_unique<Workspace>();
     w->device = device;
     w->stream = stream;
-    HIP_TRY(hipMalloc(reinterpret_cast<void **>(&w->counter), 16));
-    HIP_TRY(hipMemset(w->counter, 0, 16));
+    HIP_TRY(hipMalloc(reinterpret_cast<void **>(&w->counters), 64));
+    HIP_TRY(hipMemset(w->counters, 0, 64));
     HIP_TRY(hipMalloc(reinterpret_cast<void **>(&w->dres), 16));
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&w->hres), 16, hipHostMallocDefault));
     for (auto &e : w->ev) HIP_TRY(hipEventCreate(&e));
@@ -236,14 +240,14 @@ int get_workspace(ri_handle *h, int device, hipStream_t stream, Workspace **out)
     return RI_OK;
 }
 
-int grow(void **p, size_t *cap, size_t need) {
-    if (need <= *cap) return RI_OK;
-    if (*p) HIP_TRY(hipFree(*p));
-    *p = nullptr;
-    *cap = 0;
+int grow(Workspace::Buf &b, size_t need) {
+    if (need <= b.cap) return RI_OK;
+    if (b.p) HIP_TRY(hipFree(b.p));
+    b.p = nullptr;
+    b.cap = 0;
     need = round_up(need, 1 << 20);
-    HIP_TRY(hipMalloc(p, need));
-    *cap = need;
+    HIP_TRY(hipMalloc(&b.p, need));
+    b.cap = need;
     return RI_OK;
 }
 
@@ -252,10 +256,10 @@ struct Plan {
     uint32_t nchunks = 0;
 };
 
-int plan_chunks(const AlgoHost &H, uint64_t n, uint32_t chunks, Plan *p) {
+int plan_chunks(const AlgoHost &H, uint64_t n, uint32_t chunks, uint32_t target, Plan *p) {
     uint64_t cs;
     if (chunks == 0) {
-        cs = std::max<uint64_t>(round_up((n + kAutoChunks - 1) / kAutoChunks, 16), kMinAutoChunk);
+        cs = std::max<uint64_t>(round_up((n + target - 1) / target, 16), kMinAutoChunk);
         while ((uint64_t)H.L * ((n + cs - 1) / cs) * H.lam_bytes > kMaxLamBytes) cs *= 2;
     } else {
         cs = round_up((n + chunks - 1) / chunks, 16);
@@ -295,7 +299,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     if (device < 0 || device >= kMaxDevices) return fail(RI_ERR_DEVICE, "device index out of range");
 
     Plan plan;
-    int rc = plan_chunks(H, n, chunks, &plan);
+    int rc = plan_chunks(H, n, chunks, h->opt.chunk_target, &plan);
     if (rc) return rc;
     if (maps && maps_cap < (size_t)plan.nchunks * H.L)
         return fail(RI_ERR_ARG, "maps buffer too small");
@@ -312,98 +316,175 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     DeviceCopy &dc = h->dev[device];
     const AlgoDevice &D = dc.algo[algo];
 
-    // buffers
-    const uint32_t ng0 = (plan.nchunks + kJoinGroup - 1) / kJoinGroup;
+    const Options opt = h->opt;
+    const bool conv = opt.converge != 0;
+    // level-0 join group: the widest power of two <= 64 whose LDS tile of
+    // chunk maps (L x G0 x 4 bytes) stays within 64 KiB; 0 = unstaged join
+    uint32_t g0 = 64;
+    while (g0 > 0 && (size_t)H.L * g0 * 4 > 65536) g0 /= 2;
+    const uint32_t ng0 = (plan.nchunks + (g0 ? g0 : kJoinGroup) - 1) / (g0 ? g0 : kJoinGroup);
     const size_t row_words = H.relational ? H.W : 1;
-    rc = grow(&ws->lam, &ws->lam_cap, (size_t)H.L * plan.nchunks * H.lam_bytes);
-    if (rc) return rc;
-    const size_t bufneed = (size_t)ng0 * H.L * row_words * 4;
-    for (int b = 0; b < 2; ++b) {
-        rc = grow(&ws->buf[b], &ws->buf_cap[b], bufneed);
-        if (rc) return rc;
+    const size_t pairs = (size_t)H.L * plan.nchunks;
+
+    ri::KernelShape shape;
+    shape.entry_bytes = (int)H.entry_bytes;
+    shape.tile_bytes = (int)H.lam_bytes;
+    shape.alias_bytes = H.L <= 254 ? 1 : 2;
+    uint32_t R = opt.runs_per_lane ? opt.runs_per_lane : 4;
+    shape.block_threads = 1024;
+    const size_t lds_tables = H.table.size() + 256;
+    shape.table_in_lds = lds_tables <= dc.max_lds;
+
+    // buffers
+    if (conv) {
+        if (H.L > 65534) return fail(RI_ERR_LIMIT, "too many starts for the converging reach");
+        rc = grow(ws->alias, pairs * shape.alias_bytes);
+        if (!rc) rc = grow(ws->run_base, (size_t)plan.nchunks * 4);
+        if (!rc) rc = grow(ws->run_chunk, pairs * 4);
+        if (!rc) rc = grow(ws->run_state, pairs * 4);
+        if (!rc) rc = grow(ws->run_final, pairs * 4);
+    } else {
+        rc = grow(ws->lam, pairs * H.lam_bytes);
     }
+    if (!rc) rc = grow(ws->join[0], (size_t)ng0 * H.L * row_words * 4);
+    if (!rc) rc = grow(ws->join[1], (size_t)ng0 * H.L * row_words * 4);
+    if (!rc && maps) rc = grow(ws->dbg, pairs * 4);
+    if (rc) return rc;
 
-    // reach configuration
-    ri::ReachConfig cfg;
-    cfg.entry_bytes = (int)H.entry_bytes;
-    cfg.lam_bytes = (int)H.lam_bytes;
-    uint32_t R = h->runs_per_lane[algo];
-    if (R == 0) R = 4;
-    while (R > 1 && R / 2 >= H.L) R /= 2;
-    cfg.runs_per_lane = (int)R;
-    cfg.block_threads = 1024;
-    const size_t lds_table = H.table.size() + 256;
-    cfg.table_in_lds = lds_table <= dc.max_lds;
-    const size_t lds = cfg.table_in_lds ? lds_table : 256;
-
-    ri::ReachArgs ra;
-    ra.text = text;
-    ra.n = n;
-    ra.cs = plan.cs;
-    ra.nchunks = plan.nchunks;
-    ra.table = D.table;
-    ra.table_bytes = (uint32_t)H.table.size();
-    ra.cls = dc.cls;
-    ra.starts = D.starts;
-    ra.L = H.L;
-    ra.K = H.K;
-    ra.dead = H.dead;
-    ra.lam = ws->lam;
-    ra.job_counter = ws->counter;
-    ra.chunk_groups = (plan.nchunks + 63) / 64;
-    const uint32_t groups = (H.L + R - 1) / R;
-    ra.njobs = groups * ra.chunk_groups;
-    const int per_cu = std::max(1, ri::reach_blocks_per_cu(cfg, lds));
-    const uint32_t waves_per_block = cfg.block_threads / 64;
-    int grid = (int)std::min<uint64_t>((uint64_t)dc.cus * per_cu,
-                                       (ra.njobs + waves_per_block - 1) / waves_per_block);
-    grid = std::max(grid, 1);
+    ri::ScanArgs sa;
+    sa.text = text;
+    sa.n = n;
+    sa.cs = plan.cs;
+    sa.nchunks = plan.nchunks;
+    sa.table = D.table;
+    sa.table_bytes = (uint32_t)H.table.size();
+    sa.cls = dc.cls;
+    sa.starts = D.starts;
+    sa.L = H.L;
+    sa.K = H.K;
+    sa.dead = H.dead;
+    const uint32_t chunk_groups = (plan.nchunks + 63) / 64;
 
     if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[0], stream));
-    HIP_TRY(ri::launch_reach(ra, cfg, grid, lds, stream));
+    if (!conv) {
+        while (R > 1 && R / 2 >= H.L) R /= 2;
+        shape.runs_per_lane = (int)R;
+        const size_t lds = shape.table_in_lds ? lds_tables : 256;
+        ri::PlainArgs pa;
+        pa.s = sa;
+        pa.lam = ws->lam.p;
+        pa.job_counter = ws->counters + 3;
+        pa.chunk_groups = chunk_groups;
+        pa.njobs = ((H.L + R - 1) / R) * chunk_groups;
+        const int per_cu = std::max(1, ri::blocks_per_cu(0, shape, lds));
+        const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)dc.cus * per_cu, (pa.njobs + 15) / 16));
+        HIP_TRY(ri::launch_plain(pa, shape, grid, lds, stream));
+        if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[4], stream));
+    } else {
+        // warm-up and merging
+        ri::KernelShape ws_shape = shape;
+        uint32_t Rw = R;
+        while (Rw > 1 && Rw / 2 >= H.L) Rw /= 2;
+        ws_shape.runs_per_lane = (int)Rw;
+        // widest tile (chunks per group) that fits, table in LDS if possible
+        uint32_t cw = 64;
+        size_t lds_w = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (cw = 64; cw >= 1; cw /= 2) {
+                lds_w = ri::warm_lds_bytes(ws_shape, H.L, (uint32_t)H.table.size(), cw);
+                if (lds_w <= dc.max_lds && (cw >= 16 || pass == 1)) break;
+            }
+            if (cw >= 1 && lds_w <= dc.max_lds) break;
+            ws_shape.table_in_lds = false;
+        }
+        if (cw < 1 || lds_w > dc.max_lds) return fail(RI_ERR_LIMIT, "too many starts for the warm-up tile");
+        ri::WarmArgs wa;
+        wa.s = sa;
+        wa.warm = opt.warm;
+        wa.cw = cw;
+        wa.chunk_groups = (plan.nchunks + cw - 1) / cw;
+        wa.alias = ws->alias.p;
+        wa.run_base = static_cast<uint32_t *>(ws->run_base.p);
+        wa.run_chunk = static_cast<uint32_t *>(ws->run_chunk.p);
+        wa.run_state = static_cast<uint32_t *>(ws->run_state.p);
+        wa.counters = ws->counters;
+        const int per_cu_w = std::max(1, ri::blocks_per_cu(1, ws_shape, lds_w));
+        const int grid_w = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)dc.cus * per_cu_w, wa.chunk_groups));
+        HIP_TRY(ri::launch_warm(wa, ws_shape, grid_w, lds_w, stream));
+        if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[5], stream));
+        // merged runs to the chunk ends
+        ri::KernelShape ls = shape;
+        ls.runs_per_lane = (int)(opt.runs_per_lane ? opt.runs_per_lane : 2);
+        const size_t lds_l = shape.table_in_lds ? lds_tables : 256;
+        ri::LongArgs la;
+        la.s = sa;
+        la.warm = opt.warm;
+        la.run_chunk = wa.run_chunk;
+        la.run_state = wa.run_state;
+        la.run_final = static_cast<uint32_t *>(ws->run_final.p);
+        la.counters = ws->counters;
+        const int per_cu_l = std::max(1, ri::blocks_per_cu(2, ls, lds_l));
+        const int grid_l = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)dc.cus * per_cu_l,
+                                                                          (pairs + 64ull * 16 - 1) / (64ull * 16)));
+        HIP_TRY(ri::launch_long(la, ls, grid_l, lds_l, stream));
+        if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[4], stream));
+    }
     if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[1], stream));
 
     // join tree
     ri::JoinArgs ja;
-    ja.lam = ws->lam;
-    ja.lam_bytes = (int)H.lam_bytes;
+    ja.converged = conv;
+    ja.lam = ws->lam.p;
+    ja.alias = ws->alias.p;
+    ja.run_base = static_cast<const uint32_t *>(ws->run_base.p);
+    ja.run_final = static_cast<const uint32_t *>(ws->run_final.p);
+    ja.tile_bytes = (int)H.lam_bytes;
+    ja.alias_bytes = shape.alias_bytes;
     ja.nchunks = plan.nchunks;
     ja.content = D.content;
     ja.L = H.L;
     ja.G = kJoinGroup;
     ja.in = nullptr;
     ja.nin = 0;
-    ja.out = ws->buf[0];
-    if (H.relational) HIP_TRY(ri::launch_join0_rel(ja, (int)H.W, stream));
-    else HIP_TRY(ri::launch_join0_fun(ja, stream));
+    ja.out = ws->join[0].p;
+    if (g0 > 0) {
+        ja.G = g0;
+        HIP_TRY(ri::launch_join0_tile(ja, H.relational ? (int)H.W : 0, stream));
+        ja.G = kJoinGroup;
+    } else if (H.relational) {
+        HIP_TRY(ri::launch_join0_rel(ja, (int)H.W, stream));
+    } else {
+        HIP_TRY(ri::launch_join0_fun(ja, stream));
+    }
     int cur = 0;
     uint32_t nin = ng0;
     while (nin > 1) {
-        ja.in = ws->buf[cur];
+        ja.in = ws->join[cur].p;
         ja.nin = nin;
-        ja.out = ws->buf[cur ^ 1];
+        ja.out = ws->join[cur ^ 1].p;
         if (H.relational) HIP_TRY(ri::launch_joinN_rel(ja, (int)H.W, stream));
         else HIP_TRY(ri::launch_joinN_fun(ja, stream));
         cur ^= 1;
         nin = (nin + kJoinGroup - 1) / kJoinGroup;
     }
+    if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(ws->dbg.p), stream));
     ri::FinalArgs fa;
-    fa.total = ws->buf[cur];
+    fa.total = ws->join[cur].p;
     fa.fmask = D.fmask;
     fa.hash = D.hash;
     fa.hash_cap = H.hash_cap;
     fa.final_of_state = D.final_of_state;
     fa.accept_of_state = D.accept_of_state;
     fa.result = ws->dres;
-    fa.job_counter = ws->counter;
+    fa.counters = ws->counters;
     if (H.relational) HIP_TRY(ri::launch_finalize_rel(fa, (int)H.W, stream));
     else HIP_TRY(ri::launch_finalize_fun(fa, stream));
     if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[2], stream));
     HIP_TRY(hipMemcpyAsync(ws->hres, ws->dres, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-    std::vector<uint8_t> lam_host;
+    std::vector<int32_t> lam_host;
     if (maps) {
-        lam_host.resize((size_t)H.L * plan.nchunks * H.lam_bytes);
-        HIP_TRY(hipMemcpyAsync(lam_host.data(), ws->lam, lam_host.size(), hipMemcpyDeviceToHost, stream));
+        lam_host.resize(pairs);
+        HIP_TRY(hipMemcpyAsync(lam_host.data(), ws->dbg.p, pairs * 4, hipMemcpyDeviceToHost, stream));
     }
     if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[3], stream));
     HIP_TRY(hipStreamSynchronize(stream));
@@ -414,27 +495,23 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     out->chunk_size = (uint32_t)plan.cs;
     if (out->final_state == -3) return fail(RI_ERR_DEVICE, "internal: final subset not found");
     if (h->profiling) {
-        float ms[3];
+        float ms[5] = {0, 0, 0, 0, 0};
         HIP_TRY(hipEventElapsedTime(&ms[0], ws->ev[0], ws->ev[1]));
         HIP_TRY(hipEventElapsedTime(&ms[1], ws->ev[1], ws->ev[2]));
         HIP_TRY(hipEventElapsedTime(&ms[2], ws->ev[0], ws->ev[3]));
+        if (conv) {
+            HIP_TRY(hipEventElapsedTime(&ms[4], ws->ev[0], ws->ev[5]));
+            HIP_TRY(hipEventElapsedTime(&ms[3], ws->ev[5], ws->ev[4]));
+        } else {
+            HIP_TRY(hipEventElapsedTime(&ms[3], ws->ev[0], ws->ev[4]));
+        }
         std::lock_guard<std::mutex> lk(h->mu);
         std::memcpy(h->last_ms, ms, sizeof(ms));
     }
     if (maps) {
-        for (uint32_t s = 0; s < H.L; ++s)
-            for (uint32_t c = 0; c < plan.nchunks; ++c) {
-                const size_t i = (size_t)s * plan.nchunks + c;
-                int32_t v;
-                if (H.lam_bytes == 2) {
-                    uint16_t x = reinterpret_cast<const uint16_t *>(lam_host.data())[i];
-                    v = x == 0xFFFF ? -1 : x;
-                } else {
-                    uint32_t x = reinterpret_cast<const uint32_t *>(lam_host.data())[i];
-                    v = x == 0xFFFFFFFFu ? -1 : (int32_t)x;
-                }
-                maps[(size_t)c * H.L + s] = v;
-            }
+        for (uint32_t s2 = 0; s2 < H.L; ++s2)
+            for (uint32_t c = 0; c < plan.nchunks; ++c)
+                maps[(size_t)c * H.L + s2] = lam_host[(size_t)s2 * plan.nchunks + c];
     }
     return RI_OK;
 }
@@ -487,12 +564,12 @@ void ri_free(ri_handle *h) {
         int prev = 0;
         (void)hipGetDevice(&prev);
         (void)hipSetDevice(w->device);
-        (void)hipFree(w->counter);
+        (void)hipFree(w->counters);
         (void)hipFree(w->dres);
         (void)hipHostFree(w->hres);
-        (void)hipFree(w->lam);
-        (void)hipFree(w->buf[0]);
-        (void)hipFree(w->buf[1]);
+        for (Workspace::Buf *b : {&w->lam, &w->alias, &w->run_base, &w->run_chunk, &w->run_state,
+                                  &w->run_final, &w->dbg, &w->join[0], &w->join[1]})
+            (void)hipFree(b->p);
         for (auto e : w->ev) (void)hipEventDestroy(e);
         (void)hipSetDevice(prev);
     }
@@ -563,11 +640,47 @@ int ri_set_profiling(ri_handle *h, int enable) {
     return RI_OK;
 }
 
-int ri_last_timings(const ri_handle *h, float ms[3]) {
+int ri_last_timings(const ri_handle *h, float ms[5]) {
     if (!h || !ms) return fail(RI_ERR_ARG, "NULL argument");
     std::lock_guard<std::mutex> lk(const_cast<ri_handle *>(h)->mu);
     std::memcpy(ms, h->last_ms, sizeof(h->last_ms));
     return RI_OK;
+}
+
+int ri_set_option(ri_handle *h, int option, int64_t value) {
+    if (!h) return fail(RI_ERR_ARG, "NULL handle");
+    std::lock_guard<std::mutex> lk(h->mu);
+    switch (option) {
+    case RI_OPT_CONVERGE:
+        if (value != 0 && value != 1) return fail(RI_ERR_ARG, "RI_OPT_CONVERGE must be 0 or 1");
+        h->opt.converge = (int)value;
+        return RI_OK;
+    case RI_OPT_WARMUP_BYTES:
+        if (value < 16 || value > (1 << 20) || value % 16) return fail(RI_ERR_ARG, "bad warm-up length");
+        h->opt.warm = (uint32_t)value;
+        return RI_OK;
+    case RI_OPT_RUNS_PER_LANE:
+        if (value != 0 && value != 1 && value != 2 && value != 4) return fail(RI_ERR_ARG, "runs per lane: 0, 1, 2 or 4");
+        h->opt.runs_per_lane = (uint32_t)value;
+        return RI_OK;
+    case RI_OPT_CHUNK_TARGET:
+        if (value < 1 || value > (1ll << 30)) return fail(RI_ERR_ARG, "bad chunk target");
+        h->opt.chunk_target = (uint32_t)value;
+        return RI_OK;
+    }
+    return fail(RI_ERR_ARG, "unknown option");
+}
+
+int ri_get_option(const ri_handle *h, int option, int64_t *value) {
+    if (!h || !value) return fail(RI_ERR_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(const_cast<ri_handle *>(h)->mu);
+    switch (option) {
+    case RI_OPT_CONVERGE: *value = h->opt.converge; return RI_OK;
+    case RI_OPT_WARMUP_BYTES: *value = h->opt.warm; return RI_OK;
+    case RI_OPT_RUNS_PER_LANE: *value = h->opt.runs_per_lane; return RI_OK;
+    case RI_OPT_CHUNK_TARGET: *value = h->opt.chunk_target; return RI_OK;
+    }
+    return fail(RI_ERR_ARG, "unknown option");
 }
 
 const char *ri_last_error(void) { return g_error.c_str(); }

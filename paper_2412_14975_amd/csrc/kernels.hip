@@ -1,129 +1,493 @@
 // HIP kernels of the recognizer for gfx950 (CDNA4, wave64).
 //
-// reach     -- the reach phase (Sect. 2): for every chunk and every start
-//              state of the chunk automaton, one deterministic run over the
-//              chunk; the end state (or "no run") is the chunk map lambda_i.
-//              Integer table lookups only: no MFMA work exists on this path.
-// join*     -- the join phase as an associative composition of chunk maps
-//              over a tree of groups of G consecutive members.
-//              Relations (RI-DFA, Sect. 3.2): row s of a chunk is the content
-//              of lambda_i({s}), a set of interface states; composing two
-//              chunks unions the rows of the second over the set bits of the
-//              first, which is PLAS_i = lambda_i(if(PLAS_{i-1}) & PIS_i) taken
-//              for every possible PLAS_{i-1} at once.
-//              Functions (DFA, Sect. 2): lambda_i is a partial map Q -> Q and
-//              composition is a gather.
-// finalize  -- row 0 (the initial state) of the composition of all chunks:
-//              acceptance test and the minimal-DFA state of the result.
+// Reach phase (Sect. 2): for every chunk and every start state of the chunk
+// automaton, one deterministic run over the chunk; its end state (or "no
+// run") is the chunk map lambda_i.  Integer table lookups only; no MFMA work
+// exists on this path.
+//
+//   plain_kernel  every (chunk, start) run to the chunk end or its death, as
+//                 the paper's reach phase is stated.
+//   warm_kernel + long_kernel
+//                 the same chunk maps with state convergence, an optimization
+//                 the paper names as compatible with the RI-DFA (Sect. 5):
+//                 every run is scanned for a short warm-up; the runs of one
+//                 chunk that are then in the same state have the same future
+//                 (the chunk automaton is deterministic), so they are merged
+//                 into one run that alone is scanned to the chunk end.
+//
+// Join phase: an associative composition of chunk maps over a tree of
+// groups of G consecutive members.
+//   Relations (RI-DFA, Sect. 3.2): row s of a chunk is the content of
+//   lambda_i({s}), a set of interface states.  Composing two chunks unions
+//   the rows of the second over the set bits of the first, which is
+//   PLAS_i = lambda_i(if(PLAS_{i-1}) & PIS_i) taken for every PLAS_{i-1}.
+//   Functions (DFA, Sect. 2): lambda_i is a partial map Q -> Q; composition
+//   is a gather.
+// finalize: row 0 (the initial state) of the composition of all chunks,
+// the acceptance test and the minimal-DFA state of the result.
 #include "kernels.hpp"
+
+#include <type_traits>
 
 namespace ri {
 namespace {
 
 constexpr int kWave = 64;
 
-template <typename TL> __device__ __forceinline__ TL no_run() { return (TL)~(TL)0; }
+template <typename T> __device__ __forceinline__ constexpr T all_ones() { return (T)~(T)0; }
+
+// Copy the transition table (optionally) and the byte-class map into LDS.
+// Layout: [table_bytes if LDS][256 class bytes][caller's area].
+template <typename TE, bool LDS>
+__device__ __forceinline__ void stage_tables(const ScanArgs &s, uint8_t *smem, const TE *&tab,
+                                             const uint8_t *&cls) {
+    uint32_t off = 0;
+    if constexpr (LDS) {
+        uint4 *dst = reinterpret_cast<uint4 *>(smem);
+        const uint4 *src = reinterpret_cast<const uint4 *>(s.table);
+        for (uint32_t i = threadIdx.x; i < s.table_bytes / 16; i += blockDim.x) dst[i] = src[i];
+        tab = reinterpret_cast<const TE *>(smem);
+        off = s.table_bytes;
+    } else {
+        tab = reinterpret_cast<const TE *>(s.table);
+    }
+    uint8_t *c = smem + off;
+    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) c[i] = s.cls[i];
+    cls = c;
+}
+
+template <typename TE, bool LDS>
+__host__ __device__ constexpr uint32_t tables_lds(uint32_t table_bytes) {
+    return (LDS ? table_bytes : 0u) + 256u;
+}
+
+// 16 steps of R runs over the same 16 bytes (runs of one chunk).
+template <typename TE, int R>
+__device__ __forceinline__ void step16_shared(uint32_t (&st)[R], const uint4 v, const TE *tab,
+                                              const uint8_t *cls) {
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const uint32_t c = cls[(w[i >> 2] >> ((i & 3) * 8)) & 0xffu];
+#pragma unroll
+        for (int r = 0; r < R; ++r) st[r] = tab[st[r] + c];
+    }
+}
+
+// 16 steps of R runs over R different 16-byte blocks (runs of R chunks).
+template <typename TE, int R>
+__device__ __forceinline__ void step16_each(uint32_t (&st)[R], const uint4 (&v)[R], const TE *tab,
+                                            const uint8_t *cls) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t w = i < 4 ? v[r].x : i < 8 ? v[r].y : i < 12 ? v[r].z : v[r].w;
+            const uint32_t c = cls[(w >> ((i & 3) * 8)) & 0xffu];
+            st[r] = tab[st[r] + c];
+        }
+    }
+}
+
+__device__ __forceinline__ void load64(uint4 (&b)[4], const uint8_t *p) {
+    const uint4 *q = reinterpret_cast<const uint4 *>(p);
+    b[0] = q[0]; b[1] = q[1]; b[2] = q[2]; b[3] = q[3];
+}
+
+template <int R>
+__device__ __forceinline__ bool any_alive(const uint32_t (&st)[R], uint32_t dead) {
+    bool a = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) a |= st[r] != dead;
+    return a;
+}
+
+// Scan text[p, end) with R runs of one chunk.  64-byte blocks are scanned
+// while the next one is already being loaded (one block of read-ahead hides
+// the HBM latency behind 64 dependent lookups); then 16-byte blocks and the
+// ragged tail.  The wave leaves the block loop when no lane has a live run
+// with work left.
+template <typename TE, int R>
+__device__ __forceinline__ void scan_shared(uint32_t (&st)[R], const uint8_t *text, uint64_t p,
+                                            uint64_t end, const TE *tab, const uint8_t *cls,
+                                            uint32_t dead) {
+    const uint64_t vend = p + ((end - p) & ~(uint64_t)15);
+    const uint64_t bend = p + ((end - p) & ~(uint64_t)63);
+    uint4 cur[4];
+    if (p < bend) load64(cur, text + p);
+    for (;;) {
+        const bool work = p < bend && any_alive<R>(st, dead);
+        if (__ballot(work) == 0) break;
+        if (work) {
+            uint4 nxt[4];
+            load64(nxt, text + (p + 64 < bend ? p + 64 : p));
+#pragma unroll
+            for (int q = 0; q < 4; ++q) step16_shared<TE, R>(st, cur[q], tab, cls);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cur[q] = nxt[q];
+            p += 64;
+        }
+    }
+    for (; p < vend && any_alive<R>(st, dead); p += 16)
+        step16_shared<TE, R>(st, *reinterpret_cast<const uint4 *>(text + p), tab, cls);
+    for (p = p < vend ? vend : p; p < end && any_alive<R>(st, dead); ++p) {
+        const uint32_t c = cls[text[p]];
+#pragma unroll
+        for (int r = 0; r < R; ++r) st[r] = tab[st[r] + c];
+    }
+}
+
+// One run over text[p, end) without wave votes (p .. vend in 16-byte blocks).
+template <typename TE>
+__device__ __forceinline__ uint32_t scan_lane(uint32_t st, const uint8_t *text, uint64_t p,
+                                              uint64_t vend, uint64_t end, const TE *tab,
+                                              const uint8_t *cls, uint32_t dead) {
+    uint32_t s1[1] = {st};
+    for (; p < vend && s1[0] != dead; p += 16)
+        step16_shared<TE, 1>(s1, *reinterpret_cast<const uint4 *>(text + p), tab, cls);
+    for (p = p < vend ? vend : p; p < end && s1[0] != dead; ++p) s1[0] = tab[s1[0] + cls[text[p]]];
+    return s1[0];
+}
+
+__device__ __forceinline__ uint32_t wave_ticket(uint32_t *counter) {
+    uint32_t t = 0;
+    if (threadIdx.x % kWave == 0) t = atomicAdd(counter, 1u);
+    return __shfl(t, 0);
+}
 
 // ---------------------------------------------------------------------------
-// reach
+// plain reach
 // ---------------------------------------------------------------------------
 //
-// Work decomposition.  A job is 64 consecutive chunks x R consecutive starts;
-// lane l of the wave scans chunk (64*cg + l) from the R starts (g*R .. g*R+R-1)
-// at once, so the R runs share each byte and each class lookup and give the
-// lane R independent lookup chains.  Jobs are numbered start-group-major and
-// handed out by a global counter to persistent blocks, so that the groups
-// whose runs survive whole chunks are spread over every CU first.  A wave
-// leaves its job as soon as every run of every lane has died (wave vote).
-//
-// Table layout.  Row-major [state][class] entries holding the row offset of
-// the next state (next * K), so a step is one add and one load; the dead row
-// points to itself, so a dead run needs no branch.  The table and the byte
-// class map sit in LDS when they fit.
-template <typename TE, typename TL, int R, bool LDS_TABLE>
-__global__ void __launch_bounds__(1024) reach_kernel(ReachArgs a) {
+// A job is 64 consecutive chunks x R consecutive starts: lane l scans chunk
+// (64*cg + l) from the R starts at once, so the R runs share each byte and
+// class lookup and give the lane R independent lookup chains.  Jobs are
+// numbered start-group-major and handed out by a global counter to
+// persistent blocks.
+template <typename TE, typename TL, int R, bool LDS>
+__global__ void __launch_bounds__(1024) plain_kernel(PlainArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     const TE *tab;
     const uint8_t *cls;
-    if constexpr (LDS_TABLE) {
-        uint4 *dst = reinterpret_cast<uint4 *>(smem);
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.table);
-        for (uint32_t i = threadIdx.x; i < a.table_bytes / 16; i += blockDim.x) dst[i] = src[i];
-        uint8_t *c = smem + a.table_bytes;
-        for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) c[i] = a.cls[i];
-        __syncthreads();
-        tab = reinterpret_cast<const TE *>(smem);
-        cls = smem + a.table_bytes;
-    } else {
-        uint8_t *c = smem;
-        for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) c[i] = a.cls[i];
-        __syncthreads();
-        tab = reinterpret_cast<const TE *>(a.table);
-        cls = smem;
-    }
-
+    stage_tables<TE, LDS>(a.s, smem, tab, cls);
+    __syncthreads();
     const uint32_t lane = threadIdx.x % kWave;
     TL *lam = reinterpret_cast<TL *>(a.lam);
-
     for (;;) {
-        uint32_t job = 0;
-        if (lane == 0) job = atomicAdd(a.job_counter, 1u);
-        job = __shfl(job, 0);
+        const uint32_t job = wave_ticket(a.job_counter);
         if (job >= a.njobs) break;
         const uint32_t g = job / a.chunk_groups;
-        const uint32_t cg = job - g * a.chunk_groups;
-        const uint32_t chunk = cg * kWave + lane;
-        const bool chunk_ok = chunk < a.nchunks;
+        const uint32_t chunk = (job - g * a.chunk_groups) * kWave + lane;
+        const bool ok = chunk < a.s.nchunks;
         uint64_t begin = 0, end = 0;
-        if (chunk_ok) {
-            begin = (uint64_t)chunk * a.cs;
-            end = begin + a.cs < a.n ? begin + a.cs : a.n;
+        if (ok) {
+            begin = (uint64_t)chunk * a.s.cs;
+            end = begin + a.s.cs < a.s.n ? begin + a.s.cs : a.s.n;
         }
         uint32_t st[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t s = g * R + r;
             // chunk 0 is scanned from the initial state only (I_1 = {q0})
-            const bool on = chunk_ok && s < a.L && (chunk != 0 || s == 0);
-            st[r] = on ? a.starts[s] : a.dead;
+            st[r] = (ok && s < a.s.L && (chunk != 0 || s == 0)) ? a.s.starts[s] : a.s.dead;
         }
-
-        uint64_t p = begin;
-        const uint64_t vend = begin + ((end - begin) & ~(uint64_t)15);
-        for (;;) {
-            bool alive = false;
-#pragma unroll
-            for (int r = 0; r < R; ++r) alive |= st[r] != a.dead;
-            const bool work = alive && p < vend;
-            if (__ballot(work) == 0) break;
-            if (work) {
-                const uint4 v = *reinterpret_cast<const uint4 *>(a.text + p);
-                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const uint32_t c = cls[(w[i >> 2] >> ((i & 3) * 8)) & 0xffu];
-#pragma unroll
-                    for (int r = 0; r < R; ++r) st[r] = tab[st[r] + c];
-                }
-                p += 16;
-            }
-        }
-        // ragged tail of the last chunk
-        for (; p < end; ++p) {
-            const uint32_t c = cls[a.text[p]];
-#pragma unroll
-            for (int r = 0; r < R; ++r) st[r] = tab[st[r] + c];
-        }
-        if (chunk_ok) {
+        scan_shared<TE, R>(st, a.s.text, begin, end, tab, cls, a.s.dead);
+        if (ok) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const uint32_t s = g * R + r;
-                if (s < a.L)
-                    lam[(uint64_t)s * a.nchunks + chunk] =
-                        st[r] == a.dead ? no_run<TL>() : (TL)(st[r] / a.K);
+                if (s < a.s.L)
+                    lam[(uint64_t)s * a.s.nchunks + chunk] =
+                        st[r] == a.s.dead ? all_ones<TL>() : (TL)(st[r] / a.s.K);
             }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// converging reach, step 1: warm-up and merging
+// ---------------------------------------------------------------------------
+//
+// A block takes groups of CW consecutive chunks (CW a power of two <= 64,
+// chosen so that the LDS tile fits).  Its waves share out the start groups:
+// lane l scans chunk (l % CW) from R starts of sub-group (l / CW), so a wave
+// covers CW chunks x (64/CW) x R starts, for the first `warm` bytes of each
+// chunk; the state ids go to an LDS tile [L][CW].  Lanes 0..CW-1 of wave 0
+// then merge, per chunk, the runs that are in the same state: the first
+// kDedupCap distinct states are searched; a chunk with more distinct states
+// keeps every live run as its own run.  Runs are allocated with one atomic
+// per group (wave prefix sum), so the runs of one chunk are consecutive.
+template <typename TE, typename TL, typename TA, int R, bool LDS>
+__global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ uint32_t s_cg, s_job;
+    const TE *tab;
+    const uint8_t *cls;
+    stage_tables<TE, LDS>(a.s, smem, tab, cls);
+    const uint32_t L = a.s.L;
+    const uint32_t CW = a.cw;
+    const uint32_t spl = kWave / CW;                   // start sub-groups per wave
+    uint8_t *area = smem + tables_lds<TE, LDS>(a.s.table_bytes);
+    TL *tile = reinterpret_cast<TL *>(area);           // [L][CW]
+    uint32_t *list = reinterpret_cast<uint32_t *>(
+        area + (((size_t)L * CW * sizeof(TL) + 15) & ~(size_t)15));   // [kDedupCap][64]
+    const uint32_t lane = threadIdx.x % kWave;
+    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t col = lane % CW, sub = lane / CW;
+    const uint32_t groups = (L + spl * R - 1) / (spl * R);
+    TA *alias = reinterpret_cast<TA *>(a.alias);
+
+    for (;;) {
+        __syncthreads();   // tables staged / previous group finished with the tile
+        if (threadIdx.x == 0) {
+            s_cg = atomicAdd(&a.counters[0], 1u);
+            s_job = 0;
+        }
+        __syncthreads();
+        const uint32_t cg = s_cg;
+        if (cg >= a.chunk_groups) break;
+        const uint32_t chunk = cg * CW + col;
+        const bool ok = chunk < a.s.nchunks;
+        uint64_t begin = 0, end = 0;
+        if (ok) {
+            begin = (uint64_t)chunk * a.s.cs;
+            end = begin + a.s.cs < a.s.n ? begin + a.s.cs : a.s.n;
+        }
+        const uint64_t wend = begin + a.warm < end ? begin + a.warm : end;
+
+        // warm-up of every start
+        for (;;) {
+            uint32_t g = 0;
+            if (lane == 0) g = atomicAdd(&s_job, 1u);
+            g = __shfl(g, 0);
+            if (g >= groups) break;
+            const uint32_t s0 = (g * spl + sub) * R;
+            uint32_t st[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t s = s0 + r;
+                st[r] = (ok && s < L && (chunk != 0 || s == 0)) ? a.s.starts[s] : a.s.dead;
+            }
+            scan_shared<TE, R>(st, a.s.text, begin, wend, tab, cls, a.s.dead);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t s = s0 + r;
+                if (s < L) tile[s * CW + col] = st[r] == a.s.dead ? all_ones<TL>() : (TL)(st[r] / a.s.K);
+            }
+        }
+        __syncthreads();
+
+        if (wave == 0) {
+            const bool mine = lane < CW;
+            // pass 1: distinct live states of this lane's chunk
+            uint32_t D = 0;
+            bool spill = false;
+            if (mine) {
+                for (uint32_t s = 0; s < L; ++s) {
+                    const TL v = tile[s * CW + lane];
+                    if (v == all_ones<TL>()) continue;
+                    bool found = false;
+                    for (uint32_t i = 0; i < D && !found; ++i) found = list[i * kWave + lane] == (uint32_t)v;
+                    if (found) continue;
+                    if (D == kDedupCap) { spill = true; break; }
+                    list[D * kWave + lane] = v;
+                    ++D;
+                }
+                if (spill) {
+                    D = 0;
+                    for (uint32_t s = 0; s < L; ++s) D += tile[s * CW + lane] != all_ones<TL>();
+                }
+            }
+            // run allocation: inclusive prefix sum of D over the wave
+            uint32_t incl = D;
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t o = __shfl_up(incl, d);
+                if ((int)lane >= d) incl += o;
+            }
+            uint32_t base = 0;
+            if (lane == kWave - 1) base = atomicAdd(&a.counters[1], incl);
+            base = __shfl(base, kWave - 1);
+            const uint32_t first = base + incl - D;
+            const uint32_t chunk_d = cg * CW + lane;
+            const bool ok_d = mine && chunk_d < a.s.nchunks;
+            if (ok_d) a.run_base[chunk_d] = first;
+            // pass 2: aliases and run records
+            if (ok_d) {
+                uint32_t k = 0;
+                for (uint32_t s = 0; s < L; ++s) {
+                    const TL v = tile[s * CW + lane];
+                    TA al = all_ones<TA>();
+                    if (v != all_ones<TL>()) {
+                        if (spill) {
+                            al = (TA)k;
+                            a.run_chunk[first + k] = chunk_d;
+                            a.run_state[first + k] = v;
+                            ++k;
+                        } else {
+                            uint32_t i = 0;
+                            while (list[i * kWave + lane] != (uint32_t)v) ++i;
+                            al = (TA)i;
+                        }
+                    }
+                    alias[(uint64_t)s * a.s.nchunks + chunk_d] = al;
+                }
+                if (!spill) {
+                    for (uint32_t i = 0; i < D; ++i) {
+                        a.run_chunk[first + i] = chunk_d;
+                        a.run_state[first + i] = list[i * kWave + lane];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// converging reach, step 2: merged runs to the chunk end
+// ---------------------------------------------------------------------------
+//
+// A job is 64 x R runs; lane l takes runs (job*64R + r*64 + l).  The R runs
+// of a lane belong to different chunks: each loads its own 16-byte blocks,
+// and the 16 x R lookups of one block step are interleaved so the lane has
+// R independent chains in flight.  Runs of equal length (all but the last
+// chunk's) advance in lockstep; a lane whose runs differ finishes them one
+// by one.
+template <typename TE, int R, bool LDS>
+__global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const TE *tab;
+    const uint8_t *cls;
+    stage_tables<TE, LDS>(a.s, smem, tab, cls);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x % kWave;
+    const uint32_t nruns = *reinterpret_cast<volatile uint32_t *>(&a.counters[1]);
+    const uint32_t per_job = kWave * R;
+    const uint32_t njobs = (nruns + per_job - 1) / per_job;
+    const uint32_t dead = a.s.dead;
+    for (;;) {
+        const uint32_t job = wave_ticket(&a.counters[2]);
+        if (job >= njobs) break;
+        uint64_t p[R], vend[R], end[R];
+        uint32_t st[R];
+        bool ok[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t i = job * per_job + r * kWave + lane;
+            ok[r] = i < nruns;
+            p[r] = vend[r] = end[r] = 0;
+            st[r] = dead;
+            if (ok[r]) {
+                const uint64_t b = (uint64_t)a.run_chunk[i] * a.s.cs;
+                const uint64_t e = b + a.s.cs < a.s.n ? b + a.s.cs : a.s.n;
+                p[r] = b + a.warm < e ? b + a.warm : e;
+                vend[r] = p[r] + ((e - p[r]) & ~(uint64_t)15);
+                end[r] = e;
+                st[r] = a.run_state[i] * a.s.K;
+            }
+        }
+        // lockstep 64-byte block loop with one block of read-ahead per run.
+        // A run that has no whole block left is parked on the dead row (so
+        // that stepping it changes nothing) until the lane's other runs are
+        // done; its state is restored for the ragged remainder.
+        uint64_t bend[R];
+        uint32_t parked[R];
+        bool pk[R];
+        uint4 cur[R][4];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            bend[r] = p[r] + ((end[r] - p[r]) & ~(uint64_t)63);
+            pk[r] = false;
+            parked[r] = dead;
+            if (ok[r] && p[r] < bend[r]) load64(cur[r], a.s.text + p[r]);
+            else cur[r][0] = cur[r][1] = cur[r][2] = cur[r][3] = make_uint4(0, 0, 0, 0);
+        }
+        for (;;) {
+            bool work = false;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (ok[r] && !pk[r] && p[r] >= bend[r]) {
+                    parked[r] = st[r];
+                    st[r] = dead;
+                    pk[r] = true;
+                }
+                work |= ok[r] && !pk[r] && st[r] != dead;
+            }
+            if (__ballot(work) == 0) break;
+            if (work) {
+                uint4 nxt[R][4];
+                bool act[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    act[r] = ok[r] && !pk[r] && st[r] != dead;
+                    const uint64_t q = act[r] && p[r] + 64 < bend[r] ? p[r] + 64 : p[r];
+                    if (act[r]) load64(nxt[r], a.s.text + q);
+                    else nxt[r][0] = nxt[r][1] = nxt[r][2] = nxt[r][3] = make_uint4(0, 0, 0, 0);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    uint4 v[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) v[r] = cur[r][q];
+                    step16_each<TE, R>(st, v, tab, cls);
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) cur[r][q] = nxt[r][q];
+                    p[r] += act[r] ? 64 : 0;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (pk[r]) st[r] = parked[r];
+        // remaining blocks and ragged tails, run by run
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (ok[r]) {
+                const uint32_t f = scan_lane<TE>(st[r], a.s.text, p[r], vend[r], end[r], tab, cls, dead);
+                a.run_final[job * per_job + r * kWave + lane] = f == dead ? kNoState : f / a.s.K;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// views of the chunk maps for the join
+// ---------------------------------------------------------------------------
+
+template <typename TL>
+struct PlainView {
+    const TL *lam;
+    uint32_t nchunks;
+    __device__ __forceinline__ uint32_t get(uint32_t s, uint32_t c) const {
+        const TL v = lam[(uint64_t)s * nchunks + c];
+        return v == all_ones<TL>() ? kNoState : (uint32_t)v;
+    }
+};
+
+template <typename TA>
+struct ConvView {
+    const TA *alias;
+    const uint32_t *base;
+    const uint32_t *fin;
+    uint32_t nchunks;
+    __device__ __forceinline__ uint32_t get(uint32_t s, uint32_t c) const {
+        const TA v = alias[(uint64_t)s * nchunks + c];
+        return v == all_ones<TA>() ? kNoState : fin[base[c] + v];
+    }
+};
+
+template <class F>
+hipError_t with_view(const JoinArgs &a, F &&f) {
+    if (!a.converged) {
+        if (a.tile_bytes == 2) return f(PlainView<uint16_t>{(const uint16_t *)a.lam, a.nchunks});
+        return f(PlainView<uint32_t>{(const uint32_t *)a.lam, a.nchunks});
+    }
+    if (a.alias_bytes == 1)
+        return f(ConvView<uint8_t>{(const uint8_t *)a.alias, a.run_base, a.run_final, a.nchunks});
+    return f(ConvView<uint16_t>{(const uint16_t *)a.alias, a.run_base, a.run_final, a.nchunks});
 }
 
 // ---------------------------------------------------------------------------
@@ -155,21 +519,20 @@ __device__ __forceinline__ bool empty_row(const uint32_t (&x)[W]) {
 // Level 0: thread per (group of G chunks, start s).  X starts as the content
 // of lambda_first(s); each later chunk of the group replaces X by the union
 // of content(lambda_c(t)) over t in X.
-template <int W, typename TL>
-__global__ void __launch_bounds__(256) join0_rel_kernel(JoinArgs a) {
+template <int W, class View>
+__global__ void __launch_bounds__(256) join0_rel_kernel(JoinArgs a, View view) {
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t ngroups = (a.nchunks + a.G - 1) / a.G;
     if (tid >= (uint64_t)ngroups * a.L) return;
     const uint32_t grp = (uint32_t)(tid / a.L), s = (uint32_t)(tid % a.L);
-    const TL *lam = reinterpret_cast<const TL *>(a.lam);
     const uint32_t c0 = grp * a.G;
     const uint32_t c1 = c0 + a.G < a.nchunks ? c0 + a.G : a.nchunks;
     uint32_t x[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) x[w] = 0;
     {
-        const TL v = lam[(uint64_t)s * a.nchunks + c0];
-        if (v != no_run<TL>()) or_row<W>(x, a.content + (uint64_t)v * W);
+        const uint32_t v = view.get(s, c0);
+        if (v != kNoState) or_row<W>(x, a.content + (uint64_t)v * W);
     }
     for (uint32_t c = c0 + 1; c < c1 && !empty_row<W>(x); ++c) {
         uint32_t y[W];
@@ -178,9 +541,8 @@ __global__ void __launch_bounds__(256) join0_rel_kernel(JoinArgs a) {
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             for (uint32_t bits = x[w]; bits; bits &= bits - 1) {
-                const uint32_t t = w * 32 + __builtin_ctz(bits);
-                const TL v = lam[(uint64_t)t * a.nchunks + c];
-                if (v != no_run<TL>()) or_row<W>(y, a.content + (uint64_t)v * W);
+                const uint32_t v = view.get(w * 32 + __builtin_ctz(bits), c);
+                if (v != kNoState) or_row<W>(y, a.content + (uint64_t)v * W);
             }
         }
 #pragma unroll
@@ -189,6 +551,60 @@ __global__ void __launch_bounds__(256) join0_rel_kernel(JoinArgs a) {
     uint32_t *out = reinterpret_cast<uint32_t *>(a.out) + tid * W;
 #pragma unroll
     for (int w = 0; w < W; ++w) out[w] = x[w];
+}
+
+// Level 0, staged: one block per group of G consecutive chunks.  The group's
+// chunk maps are first gathered into LDS as state ids ([L][G], one coalesced
+// sweep), so the chains of dependent lookups below run at LDS latency.
+// W = 0: partial functions (DFA); W > 0: relations (RI-DFA).
+template <int W, class View>
+__global__ void __launch_bounds__(256) join0_tile_kernel(JoinArgs a, View view) {
+    extern __shared__ __align__(16) uint32_t lt[];
+    const uint32_t G = a.G;
+    const uint32_t grp = blockIdx.x;
+    const uint32_t c0 = grp * G;
+    const uint32_t gn = c0 + G < a.nchunks ? G : a.nchunks - c0;
+    for (uint32_t i = threadIdx.x; i < a.L * G; i += blockDim.x) {
+        const uint32_t s = i / G, c = i - s * G;
+        lt[i] = c < gn ? view.get(s, c0 + c) : kNoState;
+    }
+    __syncthreads();
+    for (uint32_t s = threadIdx.x; s < a.L; s += blockDim.x) {
+        if constexpr (W == 0) {
+            uint32_t v = lt[s * G];
+            for (uint32_t c = 1; c < gn && v != kNoState; ++c) v = lt[v * G + c];
+            reinterpret_cast<int32_t *>(a.out)[(uint64_t)grp * a.L + s] = v == kNoState ? -1 : (int32_t)v;
+        } else {
+            uint32_t x[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) x[w] = 0;
+            {
+                const uint32_t v = lt[s * G];
+                if (v != kNoState) or_row<W>(x, a.content + (uint64_t)v * W);
+            }
+            for (uint32_t c = 1; c < gn && !empty_row<W>(x); ++c) {
+                uint32_t y[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) y[w] = 0;
+                uint32_t last = kNoState;   // runs of one chunk are often shared: skip repeats
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    for (uint32_t bits = x[w]; bits; bits &= bits - 1) {
+                        const uint32_t v = lt[(w * 32 + __builtin_ctz(bits)) * G + c];
+                        if (v != kNoState && v != last) {
+                            or_row<W>(y, a.content + (uint64_t)v * W);
+                            last = v;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int w = 0; w < W; ++w) x[w] = y[w];
+            }
+            uint32_t *out = reinterpret_cast<uint32_t *>(a.out) + ((uint64_t)grp * a.L + s) * W;
+#pragma unroll
+            for (int w = 0; w < W; ++w) out[w] = x[w];
+        }
+    }
 }
 
 // Level >= 1: thread per (group of G relations, row s).
@@ -228,18 +644,17 @@ __global__ void __launch_bounds__(256) joinN_rel_kernel(JoinArgs a) {
 // join: partial functions over DFA states
 // ---------------------------------------------------------------------------
 
-template <typename TL>
-__global__ void __launch_bounds__(256) join0_fun_kernel(JoinArgs a) {
+template <class View>
+__global__ void __launch_bounds__(256) join0_fun_kernel(JoinArgs a, View view) {
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t ngroups = (a.nchunks + a.G - 1) / a.G;
     if (tid >= (uint64_t)ngroups * a.L) return;
     const uint32_t grp = (uint32_t)(tid / a.L), s = (uint32_t)(tid % a.L);
-    const TL *lam = reinterpret_cast<const TL *>(a.lam);
     const uint32_t c0 = grp * a.G;
     const uint32_t c1 = c0 + a.G < a.nchunks ? c0 + a.G : a.nchunks;
-    TL v = lam[(uint64_t)s * a.nchunks + c0];
-    for (uint32_t c = c0 + 1; c < c1 && v != no_run<TL>(); ++c) v = lam[(uint64_t)v * a.nchunks + c];
-    reinterpret_cast<int32_t *>(a.out)[tid] = v == no_run<TL>() ? -1 : (int32_t)v;
+    uint32_t v = view.get(s, c0);
+    for (uint32_t c = c0 + 1; c < c1 && v != kNoState; ++c) v = view.get(v, c);
+    reinterpret_cast<int32_t *>(a.out)[tid] = v == kNoState ? -1 : (int32_t)v;
 }
 
 __global__ void __launch_bounds__(256) joinN_fun_kernel(JoinArgs a) {
@@ -255,6 +670,15 @@ __global__ void __launch_bounds__(256) joinN_fun_kernel(JoinArgs a) {
     reinterpret_cast<int32_t *>(a.out)[tid] = v;
 }
 
+template <class View>
+__global__ void __launch_bounds__(256) materialize_kernel(JoinArgs a, View view, int32_t *out) {
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= (uint64_t)a.L * a.nchunks) return;
+    const uint32_t s = (uint32_t)(tid / a.nchunks), c = (uint32_t)(tid % a.nchunks);
+    const uint32_t v = view.get(s, c);
+    out[tid] = v == kNoState ? -1 : (int32_t)v;
+}
+
 // ---------------------------------------------------------------------------
 // finalize
 // ---------------------------------------------------------------------------
@@ -267,6 +691,10 @@ __device__ __forceinline__ uint32_t hash_words(const uint32_t (&x)[W]) {
 #pragma unroll
     for (int w = 0; w < W; ++w) { h ^= x[w]; h *= 16777619u; }
     return h;
+}
+
+__device__ __forceinline__ void reset_counters(uint32_t *c) {
+    c[0] = 0; c[1] = 0; c[2] = 0; c[3] = 0;
 }
 
 template <int W>
@@ -298,7 +726,7 @@ __global__ void finalize_rel_kernel(FinalArgs a) {
     }
     a.result[0] = acc != 0;
     a.result[1] = fin;
-    *a.job_counter = 0;
+    reset_counters(a.counters);
 }
 
 __global__ void finalize_fun_kernel(FinalArgs a) {
@@ -306,87 +734,119 @@ __global__ void finalize_fun_kernel(FinalArgs a) {
     const int32_t t = reinterpret_cast<const int32_t *>(a.total)[0];
     a.result[0] = t >= 0 ? (int32_t)a.accept_of_state[t] : 0;
     a.result[1] = t >= 0 ? a.final_of_state[t] : -1;
-    *a.job_counter = 0;
-}
-
-template <typename TE, typename TL, int R>
-hipError_t launch_reach_t(const ReachArgs &a, bool lds, int grid, size_t lds_bytes, int block,
-                          hipStream_t s) {
-    if (lds)
-        hipLaunchKernelGGL((reach_kernel<TE, TL, R, true>), dim3(grid), dim3(block), lds_bytes, s, a);
-    else
-        hipLaunchKernelGGL((reach_kernel<TE, TL, R, false>), dim3(grid), dim3(block), lds_bytes, s, a);
-    return hipGetLastError();
-}
-
-template <typename TE, typename TL>
-hipError_t launch_reach_r(const ReachArgs &a, const ReachConfig &c, int grid, size_t lds, hipStream_t s) {
-    switch (c.runs_per_lane) {
-    case 1: return launch_reach_t<TE, TL, 1>(a, c.table_in_lds, grid, lds, c.block_threads, s);
-    case 2: return launch_reach_t<TE, TL, 2>(a, c.table_in_lds, grid, lds, c.block_threads, s);
-    case 4: return launch_reach_t<TE, TL, 4>(a, c.table_in_lds, grid, lds, c.block_threads, s);
-    case 8: return launch_reach_t<TE, TL, 8>(a, c.table_in_lds, grid, lds, c.block_threads, s);
-    }
-    return hipErrorInvalidValue;
-}
-
-template <typename TE>
-hipError_t launch_reach_l(const ReachArgs &a, const ReachConfig &c, int grid, size_t lds, hipStream_t s) {
-    if (c.lam_bytes == 2) return launch_reach_r<TE, uint16_t>(a, c, grid, lds, s);
-    if (c.lam_bytes == 4) return launch_reach_r<TE, uint32_t>(a, c, grid, lds, s);
-    return hipErrorInvalidValue;
-}
-
-template <typename TE, typename TL, int R>
-const void *reach_fn(bool lds) {
-    return lds ? reinterpret_cast<const void *>(&reach_kernel<TE, TL, R, true>)
-               : reinterpret_cast<const void *>(&reach_kernel<TE, TL, R, false>);
-}
-
-template <typename TE, typename TL>
-const void *reach_fn_r(const ReachConfig &c) {
-    switch (c.runs_per_lane) {
-    case 1: return reach_fn<TE, TL, 1>(c.table_in_lds);
-    case 2: return reach_fn<TE, TL, 2>(c.table_in_lds);
-    case 4: return reach_fn<TE, TL, 4>(c.table_in_lds);
-    case 8: return reach_fn<TE, TL, 8>(c.table_in_lds);
-    }
-    return nullptr;
-}
-
-template <typename TE>
-const void *reach_fn_l(const ReachConfig &c) {
-    return c.lam_bytes == 2 ? reach_fn_r<TE, uint16_t>(c) : reach_fn_r<TE, uint32_t>(c);
-}
-
-const void *reach_function(const ReachConfig &c) {
-    switch (c.entry_bytes) {
-    case 1: return reach_fn_l<uint8_t>(c);
-    case 2: return reach_fn_l<uint16_t>(c);
-    case 4: return reach_fn_l<uint32_t>(c);
-    }
-    return nullptr;
+    reset_counters(a.counters);
 }
 
 uint32_t blocks_for(uint64_t threads, uint32_t per) { return (uint32_t)((threads + per - 1) / per); }
 
-}  // namespace
+// ---- template dispatch ----------------------------------------------------
 
-hipError_t launch_reach(const ReachArgs &a, const ReachConfig &c, int grid, size_t lds, hipStream_t s) {
-    switch (c.entry_bytes) {
-    case 1: return launch_reach_l<uint8_t>(a, c, grid, lds, s);
-    case 2: return launch_reach_l<uint16_t>(a, c, grid, lds, s);
-    case 4: return launch_reach_l<uint32_t>(a, c, grid, lds, s);
+template <class F>
+hipError_t dispatch_te(int eb, F &&f) {
+    switch (eb) {
+    case 1: return f((uint8_t)0);
+    case 2: return f((uint16_t)0);
+    case 4: return f((uint32_t)0);
     }
     return hipErrorInvalidValue;
 }
 
-int reach_blocks_per_cu(const ReachConfig &c, size_t lds_bytes) {
-    const void *fn = reach_function(c);
-    if (!fn) return 0;
+template <int N> struct IntC { static constexpr int value = N; };
+
+template <class F>
+hipError_t dispatch_r(int r, F &&f) {
+    switch (r) {
+    case 1: return f(IntC<1>{});
+    case 2: return f(IntC<2>{});
+    case 4: return f(IntC<4>{});
+    }
+    return hipErrorInvalidValue;
+}
+
+template <class F>
+hipError_t dispatch_b(bool b, F &&f) {
+    return b ? f(std::true_type{}) : f(std::false_type{});
+}
+
+template <class F>
+hipError_t dispatch_tl(int tb, F &&f) {
+    if (tb == 2) return f((uint16_t)0);
+    if (tb == 4) return f((uint32_t)0);
+    return hipErrorInvalidValue;
+}
+
+template <class F>
+hipError_t dispatch_ta(int ab, F &&f) {
+    if (ab == 1) return f((uint8_t)0);
+    if (ab == 2) return f((uint16_t)0);
+    return hipErrorInvalidValue;
+}
+
+const void *g_fn = nullptr;   // set by the dispatch below when only the function is wanted
+
+}  // namespace
+
+hipError_t launch_plain(const PlainArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st) {
+    return dispatch_te(k.entry_bytes, [&](auto te) {
+        return dispatch_tl(k.tile_bytes, [&](auto tl) {
+            return dispatch_r(k.runs_per_lane, [&](auto r) {
+                return dispatch_b(k.table_in_lds, [&](auto lds_t) {
+                    auto fn = plain_kernel<decltype(te), decltype(tl), decltype(r)::value, decltype(lds_t)::value>;
+                    if (grid == 0) { g_fn = reinterpret_cast<const void *>(fn); return hipSuccess; }
+                    hipLaunchKernelGGL(fn, dim3(grid), dim3(k.block_threads), lds, st, a);
+                    return hipGetLastError();
+                });
+            });
+        });
+    });
+}
+
+hipError_t launch_warm(const WarmArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st) {
+    return dispatch_te(k.entry_bytes, [&](auto te) {
+        return dispatch_tl(k.tile_bytes, [&](auto tl) {
+            return dispatch_ta(k.alias_bytes, [&](auto ta) {
+                return dispatch_r(k.runs_per_lane, [&](auto r) {
+                    return dispatch_b(k.table_in_lds, [&](auto lds_t) {
+                        auto fn = warm_kernel<decltype(te), decltype(tl), decltype(ta), decltype(r)::value,
+                                              decltype(lds_t)::value>;
+                        if (grid == 0) { g_fn = reinterpret_cast<const void *>(fn); return hipSuccess; }
+                        hipLaunchKernelGGL(fn, dim3(grid), dim3(k.block_threads), lds, st, a);
+                        return hipGetLastError();
+                    });
+                });
+            });
+        });
+    });
+}
+
+size_t warm_lds_bytes(const KernelShape &k, uint32_t L, uint32_t table_bytes, uint32_t cw) {
+    const size_t tables = (k.table_in_lds ? table_bytes : 0) + 256;
+    const size_t tile = ((size_t)L * cw * k.tile_bytes + 15) & ~(size_t)15;
+    return tables + tile + (size_t)kDedupCap * kWave * 4;
+}
+
+hipError_t launch_long(const LongArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st) {
+    return dispatch_te(k.entry_bytes, [&](auto te) {
+        return dispatch_r(k.runs_per_lane, [&](auto r) {
+            return dispatch_b(k.table_in_lds, [&](auto lds_t) {
+                auto fn = long_kernel<decltype(te), decltype(r)::value, decltype(lds_t)::value>;
+                if (grid == 0) { g_fn = reinterpret_cast<const void *>(fn); return hipSuccess; }
+                hipLaunchKernelGGL(fn, dim3(grid), dim3(k.block_threads), lds, st, a);
+                return hipGetLastError();
+            });
+        });
+    });
+}
+
+int blocks_per_cu(int which, const KernelShape &k, size_t lds) {
+    g_fn = nullptr;
+    hipError_t e = hipSuccess;
+    if (which == 0) e = launch_plain(PlainArgs{}, k, 0, lds, nullptr);
+    else if (which == 1) e = launch_warm(WarmArgs{}, k, 0, lds, nullptr);
+    else e = launch_long(LongArgs{}, k, 0, lds, nullptr);
+    if (e != hipSuccess || !g_fn) return 0;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, c.block_threads, lds_bytes) != hipSuccess)
-        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, g_fn, k.block_threads, lds) != hipSuccess) return 0;
     return nb;
 }
 
@@ -405,14 +865,27 @@ int reach_blocks_per_cu(const ReachConfig &c, size_t lds_bytes) {
 hipError_t launch_join0_rel(const JoinArgs &a, int W, hipStream_t s) {
     const uint32_t ngroups = (a.nchunks + a.G - 1) / a.G;
     const uint32_t nb = blocks_for((uint64_t)ngroups * a.L, 256);
-#define CALL0(w)                                                                                   \
-    if (a.lam_bytes == 2)                                                                          \
-        hipLaunchKernelGGL((join0_rel_kernel<w, uint16_t>), dim3(nb), dim3(256), 0, s, a);        \
-    else                                                                                           \
-        hipLaunchKernelGGL((join0_rel_kernel<w, uint32_t>), dim3(nb), dim3(256), 0, s, a);
-    RI_DISPATCH_W(W, CALL0)
+    return with_view(a, [&](auto view) {
+#define CALL0(w) hipLaunchKernelGGL((join0_rel_kernel<w, decltype(view)>), dim3(nb), dim3(256), 0, s, a, view);
+        RI_DISPATCH_W(W, CALL0)
 #undef CALL0
-    return hipGetLastError();
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_join0_tile(const JoinArgs &a, int W, hipStream_t s) {
+    const uint32_t ngroups = (a.nchunks + a.G - 1) / a.G;
+    const size_t lds = (size_t)a.L * a.G * 4;
+    return with_view(a, [&](auto view) {
+        if (W == 0) {
+            hipLaunchKernelGGL((join0_tile_kernel<0, decltype(view)>), dim3(ngroups), dim3(256), lds, s, a, view);
+            return hipGetLastError();
+        }
+#define CALLT(w) hipLaunchKernelGGL((join0_tile_kernel<w, decltype(view)>), dim3(ngroups), dim3(256), lds, s, a, view);
+        RI_DISPATCH_W(W, CALLT)
+#undef CALLT
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_joinN_rel(const JoinArgs &a, int W, hipStream_t s) {
@@ -427,11 +900,10 @@ hipError_t launch_joinN_rel(const JoinArgs &a, int W, hipStream_t s) {
 hipError_t launch_join0_fun(const JoinArgs &a, hipStream_t s) {
     const uint32_t ngroups = (a.nchunks + a.G - 1) / a.G;
     const uint32_t nb = blocks_for((uint64_t)ngroups * a.L, 256);
-    if (a.lam_bytes == 2)
-        hipLaunchKernelGGL((join0_fun_kernel<uint16_t>), dim3(nb), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((join0_fun_kernel<uint32_t>), dim3(nb), dim3(256), 0, s, a);
-    return hipGetLastError();
+    return with_view(a, [&](auto view) {
+        hipLaunchKernelGGL((join0_fun_kernel<decltype(view)>), dim3(nb), dim3(256), 0, s, a, view);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_joinN_fun(const JoinArgs &a, hipStream_t s) {
@@ -439,6 +911,14 @@ hipError_t launch_joinN_fun(const JoinArgs &a, hipStream_t s) {
     const uint32_t nb = blocks_for((uint64_t)ngroups * a.L, 256);
     hipLaunchKernelGGL(joinN_fun_kernel, dim3(nb), dim3(256), 0, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_materialize(const JoinArgs &a, int32_t *out, hipStream_t s) {
+    const uint32_t nb = blocks_for((uint64_t)a.L * a.nchunks, 256);
+    return with_view(a, [&](auto view) {
+        hipLaunchKernelGGL((materialize_kernel<decltype(view)>), dim3(nb), dim3(256), 0, s, a, view, out);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_finalize_rel(const FinalArgs &a, int W, hipStream_t s) {

@@ -7,8 +7,10 @@
 
 namespace ri {
 
-// Reach phase: every (chunk, start) run of the chunk automaton.
-struct ReachArgs {
+constexpr uint32_t kNoState = 0xFFFFFFFFu;   // "no run" in run_final / materialized maps
+
+// Text, chunking and chunk-automaton tables shared by every reach kernel.
+struct ScanArgs {
     const uint8_t *text;       // n bytes, 16-byte aligned
     uint64_t n;
     uint64_t cs;               // chunk size, multiple of 16
@@ -20,29 +22,68 @@ struct ReachArgs {
     uint32_t L;
     uint32_t K;
     uint32_t dead;             // entry offset of the dead row
-    void *lam;                 // [L][nchunks] end state ids, all-ones = no run
-    uint32_t *job_counter;     // zero on entry, zeroed again by finalize
-    uint32_t njobs;
-    uint32_t chunk_groups;     // ceil(nchunks / 64)
 };
 
-struct ReachConfig {
-    int entry_bytes;           // 1, 2, 4
-    int lam_bytes;             // 2, 4
-    int runs_per_lane;         // 1, 2, 4, 8
+struct KernelShape {
+    int entry_bytes;           // table entry: 1, 2, 4
+    int tile_bytes;            // state ids in chunk maps / tiles: 2, 4
+    int alias_bytes;           // local run index: 1, 2
+    int runs_per_lane;         // 1, 2, 4
     bool table_in_lds;
     int block_threads;         // 1024
 };
 
-hipError_t launch_reach(const ReachArgs &a, const ReachConfig &cfg, int grid_blocks,
-                        size_t lds_bytes, hipStream_t s);
-// blocks of the reach kernel that fit on one CU for this config
-int reach_blocks_per_cu(const ReachConfig &cfg, size_t lds_bytes);
+// ---- plain reach: every (chunk, start) run to the chunk end or its death ----
+struct PlainArgs {
+    ScanArgs s;
+    void *lam;                 // [L][nchunks] state ids, all-ones = no run
+    uint32_t *job_counter;     // zero on entry
+    uint32_t njobs;
+    uint32_t chunk_groups;     // ceil(nchunks / 64)
+};
+hipError_t launch_plain(const PlainArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st);
 
-// Join phase.
+// ---- converging reach, step 1: warm-up of every run, then merging of runs
+// of one chunk that are in the same state (state convergence) ----
+constexpr uint32_t kDedupCap = 32;   // distinct states searched per chunk
+struct WarmArgs {
+    ScanArgs s;
+    uint32_t warm;             // bytes scanned by every run before merging (multiple of 16)
+    uint32_t cw;               // chunks per group: power of two <= 64
+    uint32_t chunk_groups;     // ceil(nchunks / cw)
+    void *alias;               // [L][nchunks] local run index, all-ones = no run
+    uint32_t *run_base;        // [nchunks] first run of the chunk
+    uint32_t *run_chunk;       // [cap]
+    uint32_t *run_state;       // [cap] state id after the warm-up, kNoState if none
+    uint32_t *counters;        // [0] chunk-group ticket, [1] runs allocated
+};
+hipError_t launch_warm(const WarmArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st);
+size_t warm_lds_bytes(const KernelShape &k, uint32_t L, uint32_t table_bytes, uint32_t cw);
+
+// ---- converging reach, step 2: the merged runs to the chunk end ----
+struct LongArgs {
+    ScanArgs s;
+    uint32_t warm;
+    const uint32_t *run_chunk;
+    const uint32_t *run_state;
+    uint32_t *run_final;       // state id at the chunk end, kNoState if the run died
+    uint32_t *counters;        // [1] runs allocated (read), [2] job ticket
+};
+hipError_t launch_long(const LongArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st);
+
+// blocks of a kernel that fit on one CU: which = 0 plain, 1 warm, 2 long
+int blocks_per_cu(int which, const KernelShape &k, size_t lds);
+
+// ---- join ----
 struct JoinArgs {
-    const void *lam;           // level 0: chunk maps [L][nchunks]
-    int lam_bytes;
+    // level 0 input: either plain chunk maps or the converged form
+    bool converged;
+    const void *lam;           // plain: [L][nchunks]
+    const void *alias;         // converged: [L][nchunks]
+    const uint32_t *run_base;  // converged
+    const uint32_t *run_final; // converged
+    int tile_bytes;
+    int alias_bytes;
     uint32_t nchunks;
     const uint32_t *content;   // relations: content bitsets [nstates][W]
     const void *in;            // level >= 1: [nin][L] functions or [nin][L][W] relations
@@ -51,11 +92,14 @@ struct JoinArgs {
     uint32_t L;
     uint32_t G;                // members per group
 };
-
 hipError_t launch_join0_rel(const JoinArgs &a, int W, hipStream_t s);
+// level 0 with the group's chunk maps staged in LDS (L * G * 4 bytes); W = 0 for functions
+hipError_t launch_join0_tile(const JoinArgs &a, int W, hipStream_t s);
 hipError_t launch_joinN_rel(const JoinArgs &a, int W, hipStream_t s);
 hipError_t launch_join0_fun(const JoinArgs &a, hipStream_t s);
 hipError_t launch_joinN_fun(const JoinArgs &a, hipStream_t s);
+// chunk maps as [L][nchunks] int32 (-1 = no run), for inspection
+hipError_t launch_materialize(const JoinArgs &a, int32_t *out, hipStream_t s);
 
 struct FinalArgs {
     const void *total;         // one relation [L][W] or one function [L]
@@ -65,9 +109,8 @@ struct FinalArgs {
     const int32_t *final_of_state;   // functions
     const uint8_t *accept_of_state;  // functions
     int32_t *result;           // [0] accept, [1] final state
-    uint32_t *job_counter;     // reset to zero
+    uint32_t *counters;        // [0..3] reset to zero for the next call
 };
-
 hipError_t launch_finalize_rel(const FinalArgs &a, int W, hipStream_t s);
 hipError_t launch_finalize_fun(const FinalArgs &a, hipStream_t s);
 

@@ -21,6 +21,18 @@ pytestmark = pytest.mark.gpu
 
 ALGOS = ("rid", "dfa", "subset")
 
+# reach pipelines: converging (warm-up + merge) with two warm-up lengths, and plain
+MODES = {"conv64": dict(converge=1, warmup_bytes=64), "conv16": dict(converge=1, warmup_bytes=16),
+         "plain": dict(converge=0)}
+
+
+def make(pattern, mode="conv64", runs_per_lane=0):
+    rec = ri.Recognizer(pattern)
+    for k, v in MODES[mode].items():
+        rec.set_option(k, v)
+    rec.set_option("runs_per_lane", runs_per_lane)
+    return rec
+
 
 @pytest.fixture(scope="module", autouse=True)
 def gpu():
@@ -82,10 +94,10 @@ def check_maps(rec, ref, x, algo, chunks, sample=None, rng=None):
 # tiny workload: (a|b)*a(a|b)^3, 1 MiB
 # ---------------------------------------------------------------------------
 
-@pytest.fixture(scope="module")
-def tiny():
+@pytest.fixture(scope="module", params=sorted(MODES))
+def tiny(request):
     rx = gen.c1_regex()
-    rec = ri.Recognizer(rx)
+    rec = make(rx, request.param)
     yield rec, Ref(rx)
     rec.close()
 
@@ -124,12 +136,13 @@ def small_pattern(rng, alphabet, depth, maxpos=40):
 
 
 @pytest.mark.parametrize("seed", range(24))
-def test_random_expressions(seed):
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_random_expressions(seed, mode):
     rng = gen.PCG(777 + seed)
     alphabet = b"abcd"[: 2 + seed % 3]
     pattern = small_pattern(rng, alphabet, int(rng.integers(1, 4)))
     ref = Ref(pattern)
-    rec = ri.Recognizer(pattern)
+    rec = make(pattern, mode, runs_per_lane=(0, 1, 2, 4)[seed % 4])
     try:
         for n in (1, 5, 15, 16, 17, 63, 200, 4097, 70001):
             x = gen.random_text(rng, alphabet + b"z", n) if seed % 4 == 0 else gen.random_text(rng, alphabet, n)
@@ -182,7 +195,7 @@ def test_accepted_texts_of_random_expressions():
         x = np.frombuffer(bytes(out + dist[s]), dtype=np.uint8)
         want = ref.serial(x)
         assert want[0] is True
-        rec = ri.Recognizer(pattern)
+        rec = make(pattern, ("conv64", "conv16", "plain")[_ % 3])
         try:
             for algo in ALGOS:
                 for chunks in (1, 7, 100, 0):
@@ -192,12 +205,38 @@ def test_accepted_texts_of_random_expressions():
             rec.close()
 
 
+@pytest.mark.parametrize("mode", ["conv64", "conv16"])
+def test_runs_that_never_converge(mode):
+    """Counting a's modulo 37: the minimal DFA permutes its 37 states, so
+    runs never die and never merge; each chunk keeps more distinct states
+    than the merge step searches and falls back to one run per start."""
+    rx = b"((b*a){37})*b*"
+    ref = Ref(rx)
+    rec = make(rx, mode)
+    try:
+        assert rec.info()["starts"][1] == 37
+        rng = gen.PCG(37)
+        for n in (37 * 5, 100003):
+            x = gen.random_text(rng, b"ab", n)
+            want = ref.serial(x)
+            for algo in ALGOS:
+                for chunks in (3, 64, 0):
+                    got = rec.recognize(dev(x), algo=algo, chunks=chunks)
+                    assert (got["accept"], got["final_state"]) == want, (algo, chunks)
+        x = gen.random_text(rng, b"ab", 20000)
+        check_maps(rec, ref, x, "dfa", 50)
+        check_maps(rec, ref, x, "rid", 50)
+    finally:
+        rec.close()
+
+
 # ---------------------------------------------------------------------------
 # edge cases
 # ---------------------------------------------------------------------------
 
-def test_edge_cases():
-    rec = ri.Recognizer(b"ab*")
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_edge_cases(mode):
+    rec = make(b"ab*", mode)
     ref = Ref(b"ab*")
     try:
         # empty text: decided on the host, no device work
@@ -263,7 +302,8 @@ def test_motif_union_full_size(seed):
     rx, motifs = gen.c2_regex_and_motifs(seed)
     ref = Ref(rx)
     x, rej = gen.c2_texts(seed, motifs=motifs)
-    rec = ri.Recognizer(rx)
+    rec = make(rx, "conv64")
+    plain = make(rx, "plain")
     try:
         for text in (x, rej):
             want = ref.serial(text)
@@ -272,11 +312,17 @@ def test_motif_union_full_size(seed):
                 for chunks in ((0, 1024, 262144) if algo != "subset" else (0,)):
                     got = rec.recognize(t, algo=algo, chunks=chunks)
                     assert (got["accept"], got["final_state"]) == want, (algo, chunks)
+            if seed == 0:
+                for algo in ("rid", "dfa"):
+                    got = plain.recognize(t, algo=algo, chunks=16384)
+                    assert (got["accept"], got["final_state"]) == want, ("plain", algo)
             del t
         res = check_maps(rec, ref, x, "rid", 0, sample=6, rng=gen.PCG(seed))
         assert res["chunks"] > 1000
+        check_maps(plain, ref, x, "rid", 4096, sample=4, rng=gen.PCG(seed + 9))
     finally:
         rec.close()
+        plain.close()
     torch.cuda.empty_cache()
 
 
@@ -289,7 +335,7 @@ def test_log_lines_full_size():
     ref = Ref(rx)
     x, r1, r2 = gen.c3_texts(0)
     assert len(x) > (1 << 30) - 4096
-    rec = ri.Recognizer(rx)
+    rec = make(rx, "conv64")
     try:
         for text in (x, r1, r2):
             want = ref.serial(text)
