@@ -75,7 +75,7 @@ struct Workspace {
     int32_t *dres = nullptr;
     int32_t *hres = nullptr;        // pinned
     struct Buf { void *p = nullptr; size_t cap = 0; };
-    Buf lam, alias, run_base, run_chunk, run_state, run_final, dbg, join[2];
+    Buf lam, alias, run_base, run_chunk, run_state, run_final, dbg, join[2], ncls[2];
     hipEvent_t ev[6] = {};
 };
 
@@ -346,8 +346,12 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     } else {
         rc = grow(ws->lam, pairs * H.lam_bytes);
     }
-    if (!rc) rc = grow(ws->join[0], (size_t)ng0 * H.L * row_words * 4);
-    if (!rc) rc = grow(ws->join[1], (size_t)ng0 * H.L * row_words * 4);
+    // join buffers: at most ceil(nchunks / 2) relations of L rows (or classes)
+    const size_t nrel_max = std::max<size_t>(ng0, (plan.nchunks + 1) / 2);
+    if (!rc) rc = grow(ws->join[0], nrel_max * H.L * row_words * 4);
+    if (!rc) rc = grow(ws->join[1], nrel_max * H.L * row_words * 4);
+    if (!rc) rc = grow(ws->ncls[0], nrel_max * 4);
+    if (!rc) rc = grow(ws->ncls[1], nrel_max * 4);
     if (!rc && maps) rc = grow(ws->dbg, pairs * 4);
     if (rc) return rc;
 
@@ -386,18 +390,22 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         uint32_t Rw = R;
         while (Rw > 1 && Rw / 2 >= H.L) Rw /= 2;
         ws_shape.runs_per_lane = (int)Rw;
-        // widest tile (chunks per group) that fits, table in LDS if possible
-        uint32_t cw = 64;
+        // tile width (chunks per group): prefer >= 16 chunks within half the
+        // LDS (two blocks per CU), then anything that fits, then the table in
+        // global memory
+        uint32_t cw = 0;
         size_t lds_w = 0;
-        for (int pass = 0; pass < 2; ++pass) {
-            for (cw = 64; cw >= 1; cw /= 2) {
-                lds_w = ri::warm_lds_bytes(ws_shape, H.L, (uint32_t)H.table.size(), cw);
-                if (lds_w <= dc.max_lds && (cw >= 16 || pass == 1)) break;
+        auto pick = [&](size_t budget, uint32_t min_cw) -> bool {
+            for (uint32_t c = 64; c >= min_cw && c >= 1; c /= 2) {
+                const size_t l = ri::warm_lds_bytes(ws_shape, H.L, (uint32_t)H.table.size(), c);
+                if (l <= budget) { cw = c; lds_w = l; return true; }
             }
-            if (cw >= 1 && lds_w <= dc.max_lds) break;
+            return false;
+        };
+        if (!(ws_shape.table_in_lds && (pick(dc.max_lds / 2, 16) || pick(dc.max_lds, 1)))) {
             ws_shape.table_in_lds = false;
+            if (!pick(dc.max_lds, 1)) return fail(RI_ERR_LIMIT, "too many starts for the warm-up tile");
         }
-        if (cw < 1 || lds_w > dc.max_lds) return fail(RI_ERR_LIMIT, "too many starts for the warm-up tile");
         ri::WarmArgs wa;
         wa.s = sa;
         wa.warm = opt.warm;
@@ -447,29 +455,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     ja.in = nullptr;
     ja.nin = 0;
     ja.out = ws->join[0].p;
-    if (g0 > 0) {
-        ja.G = g0;
-        HIP_TRY(ri::launch_join0_tile(ja, H.relational ? (int)H.W : 0, stream));
-        ja.G = kJoinGroup;
-    } else if (H.relational) {
-        HIP_TRY(ri::launch_join0_rel(ja, (int)H.W, stream));
-    } else {
-        HIP_TRY(ri::launch_join0_fun(ja, stream));
-    }
-    int cur = 0;
-    uint32_t nin = ng0;
-    while (nin > 1) {
-        ja.in = ws->join[cur].p;
-        ja.nin = nin;
-        ja.out = ws->join[cur ^ 1].p;
-        if (H.relational) HIP_TRY(ri::launch_joinN_rel(ja, (int)H.W, stream));
-        else HIP_TRY(ri::launch_joinN_fun(ja, stream));
-        cur ^= 1;
-        nin = (nin + kJoinGroup - 1) / kJoinGroup;
-    }
-    if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(ws->dbg.p), stream));
     ri::FinalArgs fa;
-    fa.total = ws->join[cur].p;
     fa.fmask = D.fmask;
     fa.hash = D.hash;
     fa.hash_cap = H.hash_cap;
@@ -477,8 +463,75 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     fa.accept_of_state = D.accept_of_state;
     fa.result = ws->dres;
     fa.counters = ws->counters;
-    if (H.relational) HIP_TRY(ri::launch_finalize_rel(fa, (int)H.W, stream));
-    else HIP_TRY(ri::launch_finalize_fun(fa, stream));
+
+    // class-partitioned join for merged runs of a relational chunk automaton:
+    // the group size is the widest power of two <= 64 whose LDS stays in 64 KiB
+    ri::ClsJoinArgs ca{};
+    ca.alias = ws->alias.p;
+    ca.nchunks = plan.nchunks;
+    ca.L = H.L;
+    ca.run_base = ja.run_base;
+    ca.run_final = ja.run_final;
+    ca.content = D.content;
+    uint32_t gc = 0;
+    if (conv && H.relational) {
+        for (gc = 64; gc >= 2; gc /= 2) {
+            ca.G = gc;
+            if (ri::cls_join_lds(ca, (int)H.W, shape.alias_bytes) <= 65536) break;
+        }
+        if (gc < 2) gc = 0;
+    }
+    if (gc) {
+        ca.G = gc;
+        ca.nmembers = plan.nchunks;
+        ca.span = 1;
+        ca.ncls_out = static_cast<uint32_t *>(ws->ncls[0].p);
+        ca.cont_out = static_cast<uint32_t *>(ws->join[0].p);
+        HIP_TRY(ri::launch_join_cls(ca, (int)H.W, shape.alias_bytes, true, stream));
+        int cur = 0;
+        uint32_t nm = (plan.nchunks + gc - 1) / gc;
+        uint64_t span = gc;
+        while (nm > 1) {
+            ca.nmembers = nm;
+            ca.span = span;
+            ca.ncls_in = static_cast<const uint32_t *>(ws->ncls[cur].p);
+            ca.cont_in = static_cast<const uint32_t *>(ws->join[cur].p);
+            ca.ncls_out = static_cast<uint32_t *>(ws->ncls[cur ^ 1].p);
+            ca.cont_out = static_cast<uint32_t *>(ws->join[cur ^ 1].p);
+            HIP_TRY(ri::launch_join_cls(ca, (int)H.W, shape.alias_bytes, false, stream));
+            cur ^= 1;
+            span *= gc;
+            nm = (nm + gc - 1) / gc;
+        }
+        if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(ws->dbg.p), stream));
+        ca.cont_in = static_cast<const uint32_t *>(ws->join[cur].p);
+        HIP_TRY(ri::launch_finalize_cls(fa, ca, (int)H.W, shape.alias_bytes, stream));
+    } else {
+        if (g0 > 0) {
+            ja.G = g0;
+            HIP_TRY(ri::launch_join0_tile(ja, H.relational ? (int)H.W : 0, stream));
+            ja.G = kJoinGroup;
+        } else if (H.relational) {
+            HIP_TRY(ri::launch_join0_rel(ja, (int)H.W, stream));
+        } else {
+            HIP_TRY(ri::launch_join0_fun(ja, stream));
+        }
+        int cur = 0;
+        uint32_t nin = ng0;
+        while (nin > 1) {
+            ja.in = ws->join[cur].p;
+            ja.nin = nin;
+            ja.out = ws->join[cur ^ 1].p;
+            if (H.relational) HIP_TRY(ri::launch_joinN_rel(ja, (int)H.W, stream));
+            else HIP_TRY(ri::launch_joinN_fun(ja, stream));
+            cur ^= 1;
+            nin = (nin + kJoinGroup - 1) / kJoinGroup;
+        }
+        if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(ws->dbg.p), stream));
+        fa.total = ws->join[cur].p;
+        if (H.relational) HIP_TRY(ri::launch_finalize_rel(fa, (int)H.W, stream));
+        else HIP_TRY(ri::launch_finalize_fun(fa, stream));
+    }
     if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[2], stream));
     HIP_TRY(hipMemcpyAsync(ws->hres, ws->dres, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     std::vector<int32_t> lam_host;
@@ -568,7 +621,8 @@ void ri_free(ri_handle *h) {
         (void)hipFree(w->dres);
         (void)hipHostFree(w->hres);
         for (Workspace::Buf *b : {&w->lam, &w->alias, &w->run_base, &w->run_chunk, &w->run_state,
-                                  &w->run_final, &w->dbg, &w->join[0], &w->join[1]})
+                                  &w->run_final, &w->dbg, &w->join[0], &w->join[1], &w->ncls[0],
+                                  &w->ncls[1]})
             (void)hipFree(b->p);
         for (auto e : w->ev) (void)hipEventDestroy(e);
         (void)hipSetDevice(prev);

@@ -209,18 +209,19 @@ __global__ void __launch_bounds__(1024) plain_kernel(PlainArgs a) {
 // ---------------------------------------------------------------------------
 //
 // A block takes groups of CW consecutive chunks (CW a power of two <= 64,
-// chosen so that the LDS tile fits).  Its waves share out the start groups:
-// lane l scans chunk (l % CW) from R starts of sub-group (l / CW), so a wave
-// covers CW chunks x (64/CW) x R starts, for the first `warm` bytes of each
-// chunk; the state ids go to an LDS tile [L][CW].  Lanes 0..CW-1 of wave 0
-// then merge, per chunk, the runs that are in the same state: the first
-// kDedupCap distinct states are searched; a chunk with more distinct states
-// keeps every live run as its own run.  Runs are allocated with one atomic
-// per group (wave prefix sum), so the runs of one chunk are consecutive.
+// chosen so that the LDS tiles fit).  Its waves share out the start groups:
+// lane l scans chunk (l % CW) from R starts of sub-group (l / CW), for the
+// first `warm` bytes of the chunk; state ids go to an LDS tile [L][CW].
+// Merging then takes one chunk per wave, lanes over the starts: a leader
+// loop (one ballot per distinct state) gives every live start the index of
+// its state's class, in order of first appearance.  A chunk with more than
+// 64 distinct states keeps every live start as its own run.  Run slots are
+// allocated with one atomic per group, so the runs of a chunk are
+// consecutive; the alias tile is written out coalesced over chunks.
 template <typename TE, typename TL, typename TA, int R, bool LDS>
 __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
-    __shared__ uint32_t s_cg, s_job;
+    __shared__ uint32_t s_cg, s_job, s_base;
     const TE *tab;
     const uint8_t *cls;
     stage_tables<TE, LDS>(a.s, smem, tab, cls);
@@ -228,17 +229,22 @@ __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
     const uint32_t CW = a.cw;
     const uint32_t spl = kWave / CW;                   // start sub-groups per wave
     uint8_t *area = smem + tables_lds<TE, LDS>(a.s.table_bytes);
-    TL *tile = reinterpret_cast<TL *>(area);           // [L][CW]
-    uint32_t *list = reinterpret_cast<uint32_t *>(
-        area + (((size_t)L * CW * sizeof(TL) + 15) & ~(size_t)15));   // [kDedupCap][64]
+    uint32_t *cstate = reinterpret_cast<uint32_t *>(area);                // [CW][64] class states
+    uint32_t *dcount = cstate + (size_t)CW * kWave;                       // [CW] runs per chunk (+ spill flag)
+    uint32_t *dfirst = dcount + CW;                                       // [CW] first run (group-relative)
+    TL *tile = reinterpret_cast<TL *>(dfirst + CW);                       // [L][CW] state ids
+    TA *atile = reinterpret_cast<TA *>(
+        reinterpret_cast<uint8_t *>(tile) + (((size_t)L * CW * sizeof(TL) + 15) & ~(size_t)15));  // [L][CW]
     const uint32_t lane = threadIdx.x % kWave;
     const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t nwaves = blockDim.x / kWave;
     const uint32_t col = lane % CW, sub = lane / CW;
     const uint32_t groups = (L + spl * R - 1) / (spl * R);
-    TA *alias = reinterpret_cast<TA *>(a.alias);
+    constexpr uint32_t kSpill = 0x80000000u;
+    const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
 
     for (;;) {
-        __syncthreads();   // tables staged / previous group finished with the tile
+        __syncthreads();   // tables staged / previous group done with the tiles
         if (threadIdx.x == 0) {
             s_cg = atomicAdd(&a.counters[0], 1u);
             s_job = 0;
@@ -246,99 +252,125 @@ __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
         __syncthreads();
         const uint32_t cg = s_cg;
         if (cg >= a.chunk_groups) break;
-        const uint32_t chunk = cg * CW + col;
-        const bool ok = chunk < a.s.nchunks;
-        uint64_t begin = 0, end = 0;
-        if (ok) {
-            begin = (uint64_t)chunk * a.s.cs;
-            end = begin + a.s.cs < a.s.n ? begin + a.s.cs : a.s.n;
-        }
-        const uint64_t wend = begin + a.warm < end ? begin + a.warm : end;
 
         // warm-up of every start
-        for (;;) {
-            uint32_t g = 0;
-            if (lane == 0) g = atomicAdd(&s_job, 1u);
-            g = __shfl(g, 0);
-            if (g >= groups) break;
-            const uint32_t s0 = (g * spl + sub) * R;
-            uint32_t st[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const uint32_t s = s0 + r;
-                st[r] = (ok && s < L && (chunk != 0 || s == 0)) ? a.s.starts[s] : a.s.dead;
+        {
+            const uint32_t chunk = cg * CW + col;
+            const bool ok = chunk < a.s.nchunks;
+            uint64_t begin = 0, end = 0;
+            if (ok) {
+                begin = (uint64_t)chunk * a.s.cs;
+                end = begin + a.s.cs < a.s.n ? begin + a.s.cs : a.s.n;
             }
-            scan_shared<TE, R>(st, a.s.text, begin, wend, tab, cls, a.s.dead);
+            const uint64_t wend = begin + a.warm < end ? begin + a.warm : end;
+            for (;;) {
+                uint32_t g = 0;
+                if (lane == 0) g = atomicAdd(&s_job, 1u);
+                g = __shfl(g, 0);
+                if (g >= groups) break;
+                const uint32_t s0 = (g * spl + sub) * R;
+                uint32_t st[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const uint32_t s = s0 + r;
-                if (s < L) tile[s * CW + col] = st[r] == a.s.dead ? all_ones<TL>() : (TL)(st[r] / a.s.K);
+                for (int r = 0; r < R; ++r) {
+                    const uint32_t s = s0 + r;
+                    st[r] = (ok && s < L && (chunk != 0 || s == 0)) ? a.s.starts[s] : a.s.dead;
+                }
+                scan_shared<TE, R>(st, a.s.text, begin, wend, tab, cls, a.s.dead);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const uint32_t s = s0 + r;
+                    if (s < L) tile[s * CW + col] = st[r] == a.s.dead ? all_ones<TL>() : (TL)(st[r] / a.s.K);
+                }
             }
         }
         __syncthreads();
 
-        if (wave == 0) {
-            const bool mine = lane < CW;
-            // pass 1: distinct live states of this lane's chunk
-            uint32_t D = 0;
+        // merge: one chunk per wave, lanes over starts
+        for (uint32_t c = wave; c < CW; c += nwaves) {
+            uint32_t D = 0;           // classes so far (wave-uniform)
             bool spill = false;
-            if (mine) {
-                for (uint32_t s = 0; s < L; ++s) {
-                    const TL v = tile[s * CW + lane];
-                    if (v == all_ones<TL>()) continue;
-                    bool found = false;
-                    for (uint32_t i = 0; i < D && !found; ++i) found = list[i * kWave + lane] == (uint32_t)v;
-                    if (found) continue;
-                    if (D == kDedupCap) { spill = true; break; }
-                    list[D * kWave + lane] = v;
+            for (uint32_t s0 = 0; s0 < L && !spill; s0 += kWave) {
+                const uint32_t s = s0 + lane;
+                const uint32_t v = s < L ? (uint32_t)tile[s * CW + c] : (uint32_t)all_ones<TL>();
+                const bool live = v != (uint32_t)all_ones<TL>();
+                uint32_t al = (uint32_t)all_ones<TA>();
+                // existing classes
+                for (uint32_t i = 0; i < D; ++i)
+                    if (live && v == cstate[c * kWave + i]) al = i;
+                uint64_t open = __ballot(live && al == (uint32_t)all_ones<TA>());
+                while (open) {
+                    const int leader = __builtin_ctzll(open);
+                    const uint32_t lv = (uint32_t)__shfl((int)v, leader);
+                    if (D == kWave) { spill = true; break; }
+                    const uint64_t same = __ballot(live && v == lv);
+                    if (live && v == lv) al = D;
+                    if (lane == 0) cstate[c * kWave + D] = lv;
                     ++D;
+                    open &= ~same;
                 }
-                if (spill) {
-                    D = 0;
-                    for (uint32_t s = 0; s < L; ++s) D += tile[s * CW + lane] != all_ones<TL>();
+                if (!spill && s < L) atile[s * CW + c] = (TA)al;
+            }
+            if (spill) {
+                // every live start is its own run, numbered in start order
+                D = 0;
+                for (uint32_t s0 = 0; s0 < L; s0 += kWave) {
+                    const uint32_t s = s0 + lane;
+                    const bool live = s < L && tile[s * CW + c] != all_ones<TL>();
+                    const uint64_t m = __ballot(live);
+                    if (s < L) atile[s * CW + c] = live ? (TA)(D + __builtin_popcountll(m & lane_lt)) : all_ones<TA>();
+                    D += __builtin_popcountll(m);
                 }
             }
-            // run allocation: inclusive prefix sum of D over the wave
-            uint32_t incl = D;
+            if (lane == 0) dcount[c] = D | (spill ? kSpill : 0u);
+        }
+        __syncthreads();
+
+        // run slots: prefix over the group's chunks, one global atomic
+        if (wave == 0) {
+            const uint32_t d = lane < CW ? (dcount[lane] & ~kSpill) : 0u;
+            uint32_t incl = d;
 #pragma unroll
-            for (int d = 1; d < kWave; d <<= 1) {
-                const uint32_t o = __shfl_up(incl, d);
-                if ((int)lane >= d) incl += o;
+            for (int k = 1; k < kWave; k <<= 1) {
+                const uint32_t o = __shfl_up(incl, k);
+                if ((int)lane >= k) incl += o;
             }
-            uint32_t base = 0;
-            if (lane == kWave - 1) base = atomicAdd(&a.counters[1], incl);
-            base = __shfl(base, kWave - 1);
-            const uint32_t first = base + incl - D;
-            const uint32_t chunk_d = cg * CW + lane;
-            const bool ok_d = mine && chunk_d < a.s.nchunks;
-            if (ok_d) a.run_base[chunk_d] = first;
-            // pass 2: aliases and run records
-            if (ok_d) {
-                uint32_t k = 0;
-                for (uint32_t s = 0; s < L; ++s) {
-                    const TL v = tile[s * CW + lane];
-                    TA al = all_ones<TA>();
-                    if (v != all_ones<TL>()) {
-                        if (spill) {
-                            al = (TA)k;
-                            a.run_chunk[first + k] = chunk_d;
-                            a.run_state[first + k] = v;
-                            ++k;
-                        } else {
-                            uint32_t i = 0;
-                            while (list[i * kWave + lane] != (uint32_t)v) ++i;
-                            al = (TA)i;
+            if (lane < CW) dfirst[lane] = incl - d;
+            if (lane == kWave - 1) s_base = atomicAdd(&a.counters[1], incl);
+        }
+        __syncthreads();
+        const uint32_t base = s_base;
+
+        // run records: one chunk per wave
+        for (uint32_t c = wave; c < CW; c += nwaves) {
+            const uint32_t chunk = cg * CW + c;
+            if (chunk >= a.s.nchunks) continue;
+            const uint32_t first = base + dfirst[c];
+            if (lane == 0) a.run_base[chunk] = first;
+            const uint32_t dc = dcount[c];
+            if (!(dc & kSpill)) {
+                if (lane < dc) {
+                    a.run_chunk[first + lane] = chunk;
+                    a.run_state[first + lane] = cstate[c * kWave + lane];
+                }
+            } else {
+                for (uint32_t s0 = 0; s0 < L; s0 += kWave) {
+                    const uint32_t s = s0 + lane;
+                    if (s < L) {
+                        const TA al = atile[s * CW + c];
+                        if (al != all_ones<TA>()) {
+                            a.run_chunk[first + al] = chunk;
+                            a.run_state[first + al] = tile[s * CW + c];
                         }
                     }
-                    alias[(uint64_t)s * a.s.nchunks + chunk_d] = al;
-                }
-                if (!spill) {
-                    for (uint32_t i = 0; i < D; ++i) {
-                        a.run_chunk[first + i] = chunk_d;
-                        a.run_state[first + i] = list[i * kWave + lane];
-                    }
                 }
             }
+        }
+        // alias tile out, coalesced over chunks
+        TA *alias = reinterpret_cast<TA *>(a.alias);
+        for (uint32_t i = threadIdx.x; i < L * CW; i += blockDim.x) {
+            const uint32_t s = i / CW, c = i - s * CW;
+            const uint32_t chunk = cg * CW + c;
+            if (chunk < a.s.nchunks) alias[(uint64_t)s * a.s.nchunks + chunk] = atile[i];
         }
     }
 }
@@ -607,6 +639,154 @@ __global__ void __launch_bounds__(256) join0_tile_kernel(JoinArgs a, View view) 
     }
 }
 
+// ---------------------------------------------------------------------------
+// join over merged runs: class-partitioned relations (RI-DFA)
+// ---------------------------------------------------------------------------
+//
+// After merging, the starts of a chunk fall into a few classes (one per
+// run); starts of one class have the same row.  A relation over a span of
+// chunks is kept as the classes of its FIRST chunk (the alias column of that
+// chunk) plus one propagated content bitset per class.  Composing relations
+// propagates each class content X through the next member: the member's
+// classes hit by X are {alias[t][first chunk] : t in X}, and the new X is the
+// union of their contents.  Only the first member's classes are propagated,
+// so a group costs (#classes) chains instead of L.
+//
+// One block per group of G members.  LDS holds the members' first-chunk
+// alias columns [L][G] and the contents of each member's first kClsStage
+// classes; larger classes are read from global memory.
+constexpr uint32_t kClsStage = 8;
+
+template <int W, typename TA, bool LEVEL0>
+__global__ void __launch_bounds__(256) join_cls_kernel(ClsJoinArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint32_t *scont = reinterpret_cast<uint32_t *>(smem);                    // [G][kClsStage][W]
+    uint32_t *sncls = scont + (size_t)a.G * kClsStage * W;                    // [G]
+    TA *salias = reinterpret_cast<TA *>(sncls + a.G);                         // [L][G]
+    const uint32_t G = a.G, L = a.L;
+    const uint32_t grp = blockIdx.x;
+    const uint32_t m0 = grp * G;
+    const uint32_t gn = m0 + G < a.nmembers ? G : a.nmembers - m0;
+    const TA *alias = reinterpret_cast<const TA *>(a.alias);
+
+    // member k of the group: first chunk (m0 + k) * span
+    for (uint32_t i = threadIdx.x; i < G; i += blockDim.x) sncls[i] = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < L * G; i += blockDim.x) {
+        const uint32_t t = i / G, k = i - t * G;
+        TA v = all_ones<TA>();
+        if (k < gn) {
+            v = alias[(uint64_t)t * a.nchunks + (uint64_t)(m0 + k) * a.span];
+            if (LEVEL0 && v != all_ones<TA>()) atomicMax(&sncls[k], (uint32_t)v + 1);
+        }
+        salias[i] = v;
+    }
+    if (!LEVEL0)
+        for (uint32_t k = threadIdx.x; k < gn; k += blockDim.x) sncls[k] = a.ncls_in[m0 + k];
+    __syncthreads();
+
+    // contents of member k's class b (global)
+    auto content_ptr = [&](uint32_t k, uint32_t b) -> const uint32_t * {
+        if (LEVEL0) {
+            const uint32_t c = m0 + k;
+            const uint32_t f = a.run_final[a.run_base[c] + b];
+            return f == kNoState ? nullptr : a.content + (uint64_t)f * W;
+        }
+        return a.cont_in + ((uint64_t)(m0 + k) * L + b) * W;
+    };
+    for (uint32_t i = threadIdx.x; i < gn * kClsStage; i += blockDim.x) {
+        const uint32_t k = i / kClsStage, b = i - k * kClsStage;
+        uint32_t *dst = scont + (size_t)i * W;
+        const uint32_t *src = b < sncls[k] ? content_ptr(k, b) : nullptr;
+#pragma unroll
+        for (int w = 0; w < W; ++w) dst[w] = src ? src[w] : 0u;
+    }
+    __syncthreads();
+
+    // one wave per class of member 0; lane w < W holds word w of the content
+    const uint32_t lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const uint32_t nw = blockDim.x / kWave;
+    const uint32_t ncls0 = sncls[0];
+    for (uint32_t cls = wave; cls < ncls0; cls += nw) {
+        uint32_t xw = 0;
+        if (lane < (uint32_t)W) {
+            const uint32_t *src = cls < kClsStage ? scont + (size_t)cls * W : content_ptr(0, cls);
+            xw = src ? src[lane] : 0u;
+        }
+        for (uint32_t k = 1; k < gn; ++k) {
+            if (__ballot(xw != 0) == 0) break;
+            uint32_t hit = 0;          // staged classes (< kClsStage) hit, this lane's share
+            uint32_t yw = 0;
+            for (uint32_t t0 = 0; t0 < L; t0 += kWave) {
+                const uint32_t t = t0 + lane;
+                const uint32_t word = __shfl(xw, (int)((t0 + lane) / 32 < (uint32_t)W ? (t0 + lane) / 32 : 0));
+                const bool in = t < L && ((word >> (t & 31)) & 1u);
+                const TA b = in ? salias[t * G + k] : all_ones<TA>();
+                if (b != all_ones<TA>() && (uint32_t)b < kClsStage) hit |= 1u << b;
+                // classes beyond the staged ones: OR their contents lane by lane
+                uint64_t big = __ballot(b != all_ones<TA>() && (uint32_t)b >= kClsStage);
+                while (big) {
+                    const int src_lane = __builtin_ctzll(big);
+                    big &= big - 1;
+                    const uint32_t bb = (uint32_t)__shfl((int)b, src_lane);
+                    const uint32_t *src = content_ptr(k, bb);
+                    if (src && lane < (uint32_t)W) yw |= src[lane];
+                }
+            }
+            // OR of the hit masks over the wave
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) hit |= (uint32_t)__shfl_xor((int)hit, d);
+            if (lane < (uint32_t)W)
+                for (; hit; hit &= hit - 1) yw |= scont[((size_t)k * kClsStage + __builtin_ctz(hit)) * W + lane];
+            xw = yw;
+        }
+        if (lane < (uint32_t)W) a.cont_out[((uint64_t)grp * L + cls) * W + lane] = xw;
+    }
+    if (threadIdx.x == 0) a.ncls_out[grp] = ncls0;
+}
+
+// Row of start 0 of the single remaining relation: class alias[0][chunk 0].
+template <int W, typename TA>
+__global__ void finalize_cls_kernel(FinalArgs f, ClsJoinArgs a) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const TA c0 = reinterpret_cast<const TA *>(a.alias)[0];
+    uint32_t x[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = 0;
+    if (c0 != all_ones<TA>()) {
+        const uint32_t *row = a.cont_in + (uint64_t)c0 * W;
+#pragma unroll
+        for (int w = 0; w < W; ++w) x[w] = row[w];
+    }
+    uint32_t acc = 0, any = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        acc |= x[w] & f.fmask[w];
+        any |= x[w];
+    }
+    int32_t fin = -1;
+    if (any) {
+        fin = -3;
+        uint32_t h = 2166136261u;
+#pragma unroll
+        for (int w = 0; w < W; ++w) { h ^= x[w]; h *= 16777619u; }
+        uint32_t slot = h & (f.hash_cap - 1);
+        for (uint32_t probe = 0; probe < f.hash_cap; ++probe) {
+            const uint32_t *e = f.hash + (uint64_t)slot * (W + 1);
+            const int32_t val = (int32_t)e[W];
+            if (val == -2) break;
+            bool eq = true;
+#pragma unroll
+            for (int w = 0; w < W; ++w) eq &= e[w] == x[w];
+            if (eq) { fin = val; break; }
+            slot = (slot + 1) & (f.hash_cap - 1);
+        }
+    }
+    f.result[0] = acc != 0;
+    f.result[1] = fin;
+    f.counters[0] = 0; f.counters[1] = 0; f.counters[2] = 0; f.counters[3] = 0;
+}
+
 // Level >= 1: thread per (group of G relations, row s).
 template <int W>
 __global__ void __launch_bounds__(256) joinN_rel_kernel(JoinArgs a) {
@@ -821,8 +1001,10 @@ hipError_t launch_warm(const WarmArgs &a, const KernelShape &k, int grid, size_t
 
 size_t warm_lds_bytes(const KernelShape &k, uint32_t L, uint32_t table_bytes, uint32_t cw) {
     const size_t tables = (k.table_in_lds ? table_bytes : 0) + 256;
+    const size_t head = (size_t)cw * kWave * 4 + (size_t)cw * 8;
     const size_t tile = ((size_t)L * cw * k.tile_bytes + 15) & ~(size_t)15;
-    return tables + tile + (size_t)kDedupCap * kWave * 4;
+    const size_t atile = (size_t)L * cw * k.alias_bytes;
+    return tables + head + tile + atile;
 }
 
 hipError_t launch_long(const LongArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st) {
@@ -917,6 +1099,32 @@ hipError_t launch_materialize(const JoinArgs &a, int32_t *out, hipStream_t s) {
     const uint32_t nb = blocks_for((uint64_t)a.L * a.nchunks, 256);
     return with_view(a, [&](auto view) {
         hipLaunchKernelGGL((materialize_kernel<decltype(view)>), dim3(nb), dim3(256), 0, s, a, view, out);
+        return hipGetLastError();
+    });
+}
+
+size_t cls_join_lds(const ClsJoinArgs &a, int W, int alias_bytes) {
+    return (size_t)a.G * kClsStage * W * 4 + (size_t)a.G * 4 + (((size_t)a.L * a.G * alias_bytes + 15) & ~(size_t)15);
+}
+
+hipError_t launch_join_cls(const ClsJoinArgs &a, int W, int alias_bytes, bool level0, hipStream_t s) {
+    const uint32_t ngroups = (a.nmembers + a.G - 1) / a.G;
+    const size_t lds = cls_join_lds(a, W, alias_bytes);
+    return dispatch_ta(alias_bytes, [&](auto ta) {
+        return dispatch_b(level0, [&](auto l0) {
+#define CALLC(w) hipLaunchKernelGGL((join_cls_kernel<w, decltype(ta), decltype(l0)::value>), dim3(ngroups), dim3(256), lds, s, a);
+            RI_DISPATCH_W(W, CALLC)
+#undef CALLC
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t launch_finalize_cls(const FinalArgs &f, const ClsJoinArgs &a, int W, int alias_bytes, hipStream_t s) {
+    return dispatch_ta(alias_bytes, [&](auto ta) {
+#define CALLFC(w) hipLaunchKernelGGL((finalize_cls_kernel<w, decltype(ta)>), dim3(1), dim3(64), 0, s, f, a);
+        RI_DISPATCH_W(W, CALLFC)
+#undef CALLFC
         return hipGetLastError();
     });
 }

@@ -101,6 +101,28 @@ hipError_t launch_joinN_fun(const JoinArgs &a, hipStream_t s);
 // chunk maps as [L][nchunks] int32 (-1 = no run), for inspection
 hipError_t launch_materialize(const JoinArgs &a, int32_t *out, hipStream_t s);
 
+// Join over merged runs with class-partitioned relations (converging reach,
+// relational chunk automata).  Level 0 members are chunks (span 1, classes =
+// runs of the chunk); level >= 1 members are relations of the level below
+// (span = chunks per member; classes of a member = runs of its first chunk).
+struct ClsJoinArgs {
+    const void *alias;         // [L][nchunks] local run index, all-ones = no run
+    uint32_t nchunks;
+    uint32_t L;
+    uint32_t G;                // members per group
+    uint32_t nmembers;
+    uint64_t span;             // chunks per member
+    const uint32_t *run_base;  // level 0
+    const uint32_t *run_final; // level 0
+    const uint32_t *content;   // level 0: content bitsets [nstates][W]
+    const uint32_t *ncls_in;   // level >= 1: [nmembers]
+    const uint32_t *cont_in;   // level >= 1: [nmembers][L][W]; finalize: the last relation
+    uint32_t *ncls_out;        // [ngroups]
+    uint32_t *cont_out;        // [ngroups][L][W]
+};
+size_t cls_join_lds(const ClsJoinArgs &a, int W, int alias_bytes);
+hipError_t launch_join_cls(const ClsJoinArgs &a, int W, int alias_bytes, bool level0, hipStream_t s);
+
 struct FinalArgs {
     const void *total;         // one relation [L][W] or one function [L]
     const uint32_t *fmask;     // relations: final N' states (W words)
@@ -113,5 +135,6 @@ struct FinalArgs {
 };
 hipError_t launch_finalize_rel(const FinalArgs &a, int W, hipStream_t s);
 hipError_t launch_finalize_fun(const FinalArgs &a, hipStream_t s);
+hipError_t launch_finalize_cls(const FinalArgs &f, const ClsJoinArgs &a, int W, int alias_bytes, hipStream_t s);
 
 }  // namespace ri
