@@ -41,7 +41,8 @@ struct AlgoHost {
     bool relational = false;
     uint32_t nstates = 0, K = 0, L = 0, W = 0;
     uint32_t entry_bytes = 0, lam_bytes = 2;
-    uint32_t dead = 0;                         // entry offset of the dead row
+    uint32_t dead = 0;                         // byte offset of the dead row
+    uint16_t code[256] = {};                   // byte -> class * entry_bytes
     std::vector<uint8_t> table;                // padded to 16 bytes
     std::vector<uint32_t> starts;              // entry offsets of the start states
     std::vector<uint32_t> content;             // relations: [nstates][W]
@@ -55,6 +56,7 @@ struct AlgoHost {
 struct AlgoDevice {
     void *table = nullptr;
     uint32_t *starts = nullptr, *content = nullptr, *fmask = nullptr, *hash = nullptr;
+    uint16_t *code = nullptr;
     int32_t *final_of_state = nullptr;
     uint8_t *accept_of_state = nullptr;
 };
@@ -101,24 +103,30 @@ struct ri_handle {
 
 namespace {
 
-void pack_table(AlgoHost &h, uint32_t n, uint32_t K, const std::vector<int32_t> &delta) {
+// Entries and byte codes are byte offsets: entry = next_state * K * eb, code[b]
+// = class(b) * eb, so a step is one add and one load.  eb (1, 2 or 4 bytes)
+// is the narrowest width that holds the dead row's offset n * K * eb.
+void pack_table(AlgoHost &h, uint32_t n, uint32_t K, const std::vector<int32_t> &delta,
+                const uint8_t cls[256]) {
     h.nstates = n;
     h.K = K;
-    const uint64_t maxv = (uint64_t)n * K;     // offset of the dead row
-    h.entry_bytes = maxv <= 0xFF ? 1 : maxv <= 0xFFFF ? 2 : 4;
-    h.dead = (uint32_t)maxv;
+    const uint64_t rows = (uint64_t)n * K;
+    h.entry_bytes = rows <= 0xFF ? 1 : rows * 2 <= 0xFFFF ? 2 : 4;
+    const uint32_t eb = h.entry_bytes;
+    h.dead = (uint32_t)(rows * eb);
     const uint64_t entries = (uint64_t)(n + 1) * K;
-    h.table.assign(round_up(entries * h.entry_bytes, 16), 0);
+    h.table.assign(round_up(entries * eb, 16), 0);
     auto put = [&](uint64_t i, uint32_t v) {
-        if (h.entry_bytes == 1) h.table[i] = (uint8_t)v;
-        else if (h.entry_bytes == 2) reinterpret_cast<uint16_t *>(h.table.data())[i] = (uint16_t)v;
+        if (eb == 1) h.table[i] = (uint8_t)v;
+        else if (eb == 2) reinterpret_cast<uint16_t *>(h.table.data())[i] = (uint16_t)v;
         else reinterpret_cast<uint32_t *>(h.table.data())[i] = v;
     };
     for (uint32_t s = 0; s <= n; ++s)
         for (uint32_t k = 0; k < K; ++k) {
             int32_t t = s < n ? delta[(size_t)s * K + k] : -1;
-            put((uint64_t)s * K + k, t < 0 ? h.dead : (uint32_t)t * K);
+            put((uint64_t)s * K + k, t < 0 ? h.dead : (uint32_t)t * K * eb);
         }
+    for (int b = 0; b < 256; ++b) h.code[b] = (uint16_t)(cls[b] * eb);
     h.lam_bytes = n < 0xFFFF ? 2 : 4;
 }
 
@@ -129,14 +137,14 @@ void pack_all(ri_handle *h) {
 
     // RI_ALGO_RID: B' with the singletons of N' as starts; relational join
     AlgoHost &r = h->algo[RI_ALGO_RID];
-    pack_table(r, A.Bq.n, K, A.Bq.delta);
+    pack_table(r, A.Bq.n, K, A.Bq.delta, A.cls);
     r.relational = true;
     r.L = A.nq.n;
     uint32_t W = 1;
     while (W * 32 < r.L) W *= 2;
     r.W = W;
     r.starts.resize(r.L);
-    for (uint32_t q = 0; q < r.L; ++q) r.starts[q] = A.Bq.initial[q] * K;
+    for (uint32_t q = 0; q < r.L; ++q) r.starts[q] = A.Bq.initial[q] * K * r.entry_bytes;
     r.content.assign((size_t)A.Bq.n * W, 0);
     for (uint32_t p = 0; p < A.Bq.n; ++p)
         for (uint32_t q : A.Bq.content[p]) r.content[(size_t)p * W + q / 32] |= 1u << (q % 32);
@@ -161,10 +169,10 @@ void pack_all(ri_handle *h) {
 
     // RI_ALGO_DFA: minimal DFA, all states as starts; functional join
     AlgoHost &d = h->algo[RI_ALGO_DFA];
-    pack_table(d, A.dmin_n, K, A.dmin_delta);
+    pack_table(d, A.dmin_n, K, A.dmin_delta, A.cls);
     d.L = A.dmin_n;
     d.starts.resize(d.L);
-    for (uint32_t s = 0; s < d.L; ++s) d.starts[s] = s * K;
+    for (uint32_t s = 0; s < d.L; ++s) d.starts[s] = s * K * d.entry_bytes;
     d.final_of_state.resize(d.L);
     d.accept_of_state.resize(d.L);
     for (uint32_t s = 0; s < d.L; ++s) {
@@ -174,10 +182,10 @@ void pack_all(ri_handle *h) {
 
     // RI_ALGO_SUBSET: powerset DFA of N, all states as starts
     AlgoHost &u = h->algo[RI_ALGO_SUBSET];
-    pack_table(u, A.dsub_n, K, A.dsub_delta);
+    pack_table(u, A.dsub_n, K, A.dsub_delta, A.cls);
     u.L = A.dsub_n;
     u.starts.resize(u.L);
-    for (uint32_t s = 0; s < u.L; ++s) u.starts[s] = s * K;
+    for (uint32_t s = 0; s < u.L; ++s) u.starts[s] = s * K * u.entry_bytes;
     u.final_of_state = A.dsub_final_id;
     u.accept_of_state = A.dsub_accept;
 }
@@ -210,6 +218,7 @@ int ensure_device(ri_handle *h, int device) {
         const AlgoHost &H = h->algo[a];
         AlgoDevice &D = dc.algo[a];
         HIP_TRY(upload(&D.table, H.table.data(), H.table.size()));
+        HIP_TRY(upload(&D.code, H.code, sizeof(H.code)));
         HIP_TRY(upload(&D.starts, H.starts.data(), H.starts.size() * 4));
         if (H.relational) {
             HIP_TRY(upload(&D.content, H.content.data(), H.content.size() * 4));
@@ -332,7 +341,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     shape.alias_bytes = H.L <= 254 ? 1 : 2;
     uint32_t R = opt.runs_per_lane ? opt.runs_per_lane : 4;
     shape.block_threads = 1024;
-    const size_t lds_tables = H.table.size() + 256;
+    const size_t lds_tables = H.table.size() + 512;
     shape.table_in_lds = lds_tables <= dc.max_lds;
 
     // buffers
@@ -362,10 +371,10 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     sa.nchunks = plan.nchunks;
     sa.table = D.table;
     sa.table_bytes = (uint32_t)H.table.size();
-    sa.cls = dc.cls;
+    sa.code = D.code;
     sa.starts = D.starts;
     sa.L = H.L;
-    sa.K = H.K;
+    sa.row_bytes = H.K * H.entry_bytes;
     sa.dead = H.dead;
     const uint32_t chunk_groups = (plan.nchunks + 63) / 64;
 
@@ -373,7 +382,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     if (!conv) {
         while (R > 1 && R / 2 >= H.L) R /= 2;
         shape.runs_per_lane = (int)R;
-        const size_t lds = shape.table_in_lds ? lds_tables : 256;
+        const size_t lds = shape.table_in_lds ? lds_tables : 512;
         ri::PlainArgs pa;
         pa.s = sa;
         pa.lam = ws->lam.p;
@@ -423,7 +432,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         // merged runs to the chunk ends
         ri::KernelShape ls = shape;
         ls.runs_per_lane = (int)(opt.runs_per_lane ? opt.runs_per_lane : 2);
-        const size_t lds_l = shape.table_in_lds ? lds_tables : 256;
+        const size_t lds_l = shape.table_in_lds ? lds_tables : 512;
         ri::LongArgs la;
         la.s = sa;
         la.warm = opt.warm;
@@ -432,8 +441,9 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         la.run_final = static_cast<uint32_t *>(ws->run_final.p);
         la.counters = ws->counters;
         const int per_cu_l = std::max(1, ri::blocks_per_cu(2, ls, lds_l));
+        const uint64_t max_jobs = (pairs + 64ull * ls.runs_per_lane - 1) / (64ull * ls.runs_per_lane);
         const int grid_l = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)dc.cus * per_cu_l,
-                                                                          (pairs + 64ull * 16 - 1) / (64ull * 16)));
+                                                                          (max_jobs + 15) / 16));
         HIP_TRY(ri::launch_long(la, ls, grid_l, lds_l, stream));
         if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[4], stream));
     }
@@ -604,6 +614,7 @@ void ri_free(ri_handle *h) {
         (void)hipFree(dc.cls);
         for (auto &D : dc.algo) {
             (void)hipFree(D.table);
+            (void)hipFree(D.code);
             (void)hipFree(D.starts);
             (void)hipFree(D.content);
             (void)hipFree(D.fmask);

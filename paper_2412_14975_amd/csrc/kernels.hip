@@ -36,11 +36,12 @@ constexpr int kWave = 64;
 
 template <typename T> __device__ __forceinline__ constexpr T all_ones() { return (T)~(T)0; }
 
-// Copy the transition table (optionally) and the byte-class map into LDS.
-// Layout: [table_bytes if LDS][256 class bytes][caller's area].
+// Copy the transition table (optionally) and the byte-code map into LDS.
+// Layout: [table_bytes if LDS][256 x u16 byte codes][caller's area].
+// Table and codes hold byte offsets, so one step is next = *(TE *)(tab + st + code).
 template <typename TE, bool LDS>
 __device__ __forceinline__ void stage_tables(const ScanArgs &s, uint8_t *smem, const TE *&tab,
-                                             const uint8_t *&cls) {
+                                             const uint16_t *&cls) {
     uint32_t off = 0;
     if constexpr (LDS) {
         uint4 *dst = reinterpret_cast<uint4 *>(smem);
@@ -51,40 +52,46 @@ __device__ __forceinline__ void stage_tables(const ScanArgs &s, uint8_t *smem, c
     } else {
         tab = reinterpret_cast<const TE *>(s.table);
     }
-    uint8_t *c = smem + off;
-    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) c[i] = s.cls[i];
+    uint16_t *c = reinterpret_cast<uint16_t *>(smem + off);
+    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) c[i] = s.code[i];
     cls = c;
 }
 
 template <typename TE, bool LDS>
 __host__ __device__ constexpr uint32_t tables_lds(uint32_t table_bytes) {
-    return (LDS ? table_bytes : 0u) + 256u;
+    return (LDS ? table_bytes : 0u) + 512u;
+}
+
+// One transition: st and c are byte offsets into the table.
+template <typename TE>
+__device__ __forceinline__ uint32_t next_state(const TE *tab, uint32_t st, uint32_t c) {
+    return *reinterpret_cast<const TE *>(reinterpret_cast<const uint8_t *>(tab) + st + c);
 }
 
 // 16 steps of R runs over the same 16 bytes (runs of one chunk).
 template <typename TE, int R>
 __device__ __forceinline__ void step16_shared(uint32_t (&st)[R], const uint4 v, const TE *tab,
-                                              const uint8_t *cls) {
+                                              const uint16_t *cls) {
     const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const uint32_t c = cls[(w[i >> 2] >> ((i & 3) * 8)) & 0xffu];
 #pragma unroll
-        for (int r = 0; r < R; ++r) st[r] = tab[st[r] + c];
+        for (int r = 0; r < R; ++r) st[r] = next_state<TE>(tab, st[r], c);
     }
 }
 
 // 16 steps of R runs over R different 16-byte blocks (runs of R chunks).
 template <typename TE, int R>
 __device__ __forceinline__ void step16_each(uint32_t (&st)[R], const uint4 (&v)[R], const TE *tab,
-                                            const uint8_t *cls) {
+                                            const uint16_t *cls) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t w = i < 4 ? v[r].x : i < 8 ? v[r].y : i < 12 ? v[r].z : v[r].w;
             const uint32_t c = cls[(w >> ((i & 3) * 8)) & 0xffu];
-            st[r] = tab[st[r] + c];
+            st[r] = next_state<TE>(tab, st[r], c);
         }
     }
 }
@@ -109,7 +116,7 @@ __device__ __forceinline__ bool any_alive(const uint32_t (&st)[R], uint32_t dead
 // with work left.
 template <typename TE, int R>
 __device__ __forceinline__ void scan_shared(uint32_t (&st)[R], const uint8_t *text, uint64_t p,
-                                            uint64_t end, const TE *tab, const uint8_t *cls,
+                                            uint64_t end, const TE *tab, const uint16_t *cls,
                                             uint32_t dead) {
     const uint64_t vend = p + ((end - p) & ~(uint64_t)15);
     const uint64_t bend = p + ((end - p) & ~(uint64_t)63);
@@ -133,7 +140,7 @@ __device__ __forceinline__ void scan_shared(uint32_t (&st)[R], const uint8_t *te
     for (p = p < vend ? vend : p; p < end && any_alive<R>(st, dead); ++p) {
         const uint32_t c = cls[text[p]];
 #pragma unroll
-        for (int r = 0; r < R; ++r) st[r] = tab[st[r] + c];
+        for (int r = 0; r < R; ++r) st[r] = next_state<TE>(tab, st[r], c);
     }
 }
 
@@ -141,11 +148,11 @@ __device__ __forceinline__ void scan_shared(uint32_t (&st)[R], const uint8_t *te
 template <typename TE>
 __device__ __forceinline__ uint32_t scan_lane(uint32_t st, const uint8_t *text, uint64_t p,
                                               uint64_t vend, uint64_t end, const TE *tab,
-                                              const uint8_t *cls, uint32_t dead) {
+                                              const uint16_t *cls, uint32_t dead) {
     uint32_t s1[1] = {st};
     for (; p < vend && s1[0] != dead; p += 16)
         step16_shared<TE, 1>(s1, *reinterpret_cast<const uint4 *>(text + p), tab, cls);
-    for (p = p < vend ? vend : p; p < end && s1[0] != dead; ++p) s1[0] = tab[s1[0] + cls[text[p]]];
+    for (p = p < vend ? vend : p; p < end && s1[0] != dead; ++p) s1[0] = next_state<TE>(tab, s1[0], cls[text[p]]);
     return s1[0];
 }
 
@@ -168,7 +175,7 @@ template <typename TE, typename TL, int R, bool LDS>
 __global__ void __launch_bounds__(1024) plain_kernel(PlainArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     const TE *tab;
-    const uint8_t *cls;
+    const uint16_t *cls;
     stage_tables<TE, LDS>(a.s, smem, tab, cls);
     __syncthreads();
     const uint32_t lane = threadIdx.x % kWave;
@@ -198,7 +205,7 @@ __global__ void __launch_bounds__(1024) plain_kernel(PlainArgs a) {
                 const uint32_t s = g * R + r;
                 if (s < a.s.L)
                     lam[(uint64_t)s * a.s.nchunks + chunk] =
-                        st[r] == a.s.dead ? all_ones<TL>() : (TL)(st[r] / a.s.K);
+                        st[r] == a.s.dead ? all_ones<TL>() : (TL)(st[r] / a.s.row_bytes);
             }
         }
     }
@@ -221,9 +228,9 @@ __global__ void __launch_bounds__(1024) plain_kernel(PlainArgs a) {
 template <typename TE, typename TL, typename TA, int R, bool LDS>
 __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
-    __shared__ uint32_t s_cg, s_job, s_base;
+    __shared__ uint32_t s_job, s_base;
     const TE *tab;
-    const uint8_t *cls;
+    const uint16_t *cls;
     stage_tables<TE, LDS>(a.s, smem, tab, cls);
     const uint32_t L = a.s.L;
     const uint32_t CW = a.cw;
@@ -243,15 +250,11 @@ __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
     constexpr uint32_t kSpill = 0x80000000u;
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
 
-    for (;;) {
+    // chunk groups cost about the same: static grid-stride schedule
+    for (uint32_t cg = blockIdx.x; cg < a.chunk_groups; cg += gridDim.x) {
         __syncthreads();   // tables staged / previous group done with the tiles
-        if (threadIdx.x == 0) {
-            s_cg = atomicAdd(&a.counters[0], 1u);
-            s_job = 0;
-        }
+        if (threadIdx.x == 0) s_job = 0;
         __syncthreads();
-        const uint32_t cg = s_cg;
-        if (cg >= a.chunk_groups) break;
 
         // warm-up of every start
         {
@@ -279,7 +282,7 @@ __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const uint32_t s = s0 + r;
-                    if (s < L) tile[s * CW + col] = st[r] == a.s.dead ? all_ones<TL>() : (TL)(st[r] / a.s.K);
+                    if (s < L) tile[s * CW + col] = st[r] == a.s.dead ? all_ones<TL>() : (TL)(st[r] / a.s.row_bytes);
                 }
             }
         }
@@ -389,7 +392,7 @@ template <typename TE, int R, bool LDS>
 __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     const TE *tab;
-    const uint8_t *cls;
+    const uint16_t *cls;
     stage_tables<TE, LDS>(a.s, smem, tab, cls);
     __syncthreads();
     const uint32_t lane = threadIdx.x % kWave;
@@ -397,9 +400,10 @@ __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
     const uint32_t per_job = kWave * R;
     const uint32_t njobs = (nruns + per_job - 1) / per_job;
     const uint32_t dead = a.s.dead;
-    for (;;) {
-        const uint32_t job = wave_ticket(&a.counters[2]);
-        if (job >= njobs) break;
+    // jobs cost about the same (runs of one chunk length): static schedule
+    const uint32_t nwaves_grid = gridDim.x * (blockDim.x / kWave);
+    for (uint32_t job = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; job < njobs;
+         job += nwaves_grid) {
         uint64_t p[R], vend[R], end[R];
         uint32_t st[R];
         bool ok[R];
@@ -415,7 +419,7 @@ __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
                 p[r] = b + a.warm < e ? b + a.warm : e;
                 vend[r] = p[r] + ((e - p[r]) & ~(uint64_t)15);
                 end[r] = e;
-                st[r] = a.run_state[i] * a.s.K;
+                st[r] = a.run_state[i] * a.s.row_bytes;
             }
         }
         // lockstep 64-byte block loop with one block of read-ahead per run.
@@ -479,7 +483,7 @@ __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
         for (int r = 0; r < R; ++r) {
             if (ok[r]) {
                 const uint32_t f = scan_lane<TE>(st[r], a.s.text, p[r], vend[r], end[r], tab, cls, dead);
-                a.run_final[job * per_job + r * kWave + lane] = f == dead ? kNoState : f / a.s.K;
+                a.run_final[job * per_job + r * kWave + lane] = f == dead ? kNoState : f / a.s.row_bytes;
             }
         }
     }
@@ -1000,7 +1004,7 @@ hipError_t launch_warm(const WarmArgs &a, const KernelShape &k, int grid, size_t
 }
 
 size_t warm_lds_bytes(const KernelShape &k, uint32_t L, uint32_t table_bytes, uint32_t cw) {
-    const size_t tables = (k.table_in_lds ? table_bytes : 0) + 256;
+    const size_t tables = (k.table_in_lds ? table_bytes : 0) + 512;
     const size_t head = (size_t)cw * kWave * 4 + (size_t)cw * 8;
     const size_t tile = ((size_t)L * cw * k.tile_bytes + 15) & ~(size_t)15;
     const size_t atile = (size_t)L * cw * k.alias_bytes;

@@ -15,13 +15,14 @@ struct ScanArgs {
     uint64_t n;
     uint64_t cs;               // chunk size, multiple of 16
     uint32_t nchunks;
-    const void *table;         // (nstates + 1) * K entries, row nstates = dead row
+    const void *table;         // (nstates + 1) rows of K entries, row nstates = dead row;
+                               // an entry is the BYTE offset of the next state's row
     uint32_t table_bytes;      // padded to 16
-    const uint8_t *cls;        // byte -> class
-    const uint32_t *starts;    // L start rows (entry offsets = state * K)
+    const uint16_t *code;      // byte -> class * entry_bytes (byte offset within a row)
+    const uint32_t *starts;    // L start rows (byte offsets = state * row_bytes)
     uint32_t L;
-    uint32_t K;
-    uint32_t dead;             // entry offset of the dead row
+    uint32_t row_bytes;        // K * entry_bytes
+    uint32_t dead;             // byte offset of the dead row
 };
 
 struct KernelShape {
@@ -55,7 +56,7 @@ struct WarmArgs {
     uint32_t *run_base;        // [nchunks] first run of the chunk
     uint32_t *run_chunk;       // [cap]
     uint32_t *run_state;       // [cap] state id after the warm-up, kNoState if none
-    uint32_t *counters;        // [0] chunk-group ticket, [1] runs allocated
+    uint32_t *counters;        // [1] runs allocated
 };
 hipError_t launch_warm(const WarmArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st);
 size_t warm_lds_bytes(const KernelShape &k, uint32_t L, uint32_t table_bytes, uint32_t cw);
@@ -67,7 +68,7 @@ struct LongArgs {
     const uint32_t *run_chunk;
     const uint32_t *run_state;
     uint32_t *run_final;       // state id at the chunk end, kNoState if the run died
-    uint32_t *counters;        // [1] runs allocated (read), [2] job ticket
+    uint32_t *counters;        // [1] runs allocated (read)
 };
 hipError_t launch_long(const LongArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st);
 
