@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip ri_autotune (the chunk count is then the library default)")
     return ap.parse_args()
 
 
@@ -110,6 +112,14 @@ def main():
     t = torch.from_numpy(x).to("cuda")
     torch.cuda.synchronize()
 
+    tuning = {}
+    if not args.no_tune and args.chunks == 0:
+        # setup, outside the timed region: pick chunk target / warm-up / runs
+        # per lane for each algorithm on this text (same grid for both)
+        for algo in ("rid", "dfa"):
+            tuning[algo] = rec.autotune(t, algo=algo)
+            print(f"# tuned {algo}: {tuning[algo]}", file=sys.stderr, flush=True)
+
     rid = time_algo(torch, rec, t, "rid", args.chunks, args.steps, args.warmup, want)
     print(f"# rid done", file=sys.stderr, flush=True)
     dfa = time_algo(torch, rec, t, "dfa", args.chunks, args.steps, args.warmup, want)
@@ -133,7 +143,7 @@ def main():
     # the same bytes; the run records, 12 B per run, are < 2% and left out).
     L = info["starts"][0]
     cs, c = s_rid["chunk_size"], s_rid["chunks"]
-    warm = rec.get_option("warmup_bytes")
+    warm = tuning["rid"]["warmup_bytes"] if "rid" in tuning else rec.get_option("warmup_bytes")
     long_bytes = sum(max(0, min(cs, n - i * cs) - warm) for i in range(c)) if c < 5_000_000 else n
     achieved = long_bytes / (s_rid["long_ms"] * 1e-3) / 1e9
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -181,6 +191,8 @@ def main():
         "rid": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s_rid.items()},
         "all_states_dfa": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s_dfa.items()},
         "speedup_rid_vs_dfa": round(s_rid["gbps"] / s_dfa["gbps"], 4),
+        "tuning": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                   for k, v in tuning.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

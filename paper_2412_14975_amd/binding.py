@@ -24,7 +24,7 @@ ALGOS = {"rid": RI_ALGO_RID, "dfa": RI_ALGO_DFA, "subset": RI_ALGO_SUBSET}
 
 SYMBOLS = ("ri_build", "ri_free", "ri_info", "ri_recognize", "ri_recognize_ex",
            "ri_chunk_maps", "ri_state_content", "ri_set_profiling", "ri_last_timings",
-           "ri_set_option", "ri_get_option", "ri_last_error")
+           "ri_set_option", "ri_get_option", "ri_autotune", "ri_last_error")
 RI_OPT_CONVERGE, RI_OPT_WARMUP_BYTES, RI_OPT_RUNS_PER_LANE, RI_OPT_CHUNK_TARGET = 1, 2, 3, 4
 OPTIONS = {"converge": RI_OPT_CONVERGE, "warmup_bytes": RI_OPT_WARMUP_BYTES,
            "runs_per_lane": RI_OPT_RUNS_PER_LANE, "chunk_target": RI_OPT_CHUNK_TARGET}
@@ -44,6 +44,12 @@ class ri_result(ctypes.Structure):
     _fields_ = [("accept", ctypes.c_int32), ("final_state", ctypes.c_int32),
                 ("n", ctypes.c_uint64), ("chunks", ctypes.c_uint32),
                 ("chunk_size", ctypes.c_uint32)]
+
+
+class ri_tuning(ctypes.Structure):
+    _fields_ = [("chunk_target", ctypes.c_uint32), ("warmup_bytes", ctypes.c_uint32),
+                ("runs_per_lane", ctypes.c_uint32), ("trials", ctypes.c_uint32),
+                ("best_ms", ctypes.c_float)]
 
 
 class ri_info_t(ctypes.Structure):
@@ -80,6 +86,7 @@ def lib() -> ctypes.CDLL:
     L.ri_last_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
     L.ri_set_option.argtypes = [vp, i32, ctypes.c_int64]
     L.ri_get_option.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64)]
+    L.ri_autotune.argtypes = [vp, vp, sz, vp, i32, ctypes.POINTER(ri_tuning)]
     L.ri_last_error.argtypes = []
     L.ri_last_error.restype = ctypes.c_char_p
     for name in SYMBOLS:
@@ -202,6 +209,13 @@ def ri_get_option(h: int, option) -> int:
     return int(v.value)
 
 
+def ri_autotune(h: int, text: torch.Tensor, stream=None, algo="rid") -> dict:
+    ptr, n = _text_ptr(text)
+    t = ri_tuning()
+    _check(lib().ri_autotune(h, ptr, n, _stream_ptr(stream), _algo(algo), ctypes.byref(t)))
+    return {name: getattr(t, name) for name, _ in ri_tuning._fields_}
+
+
 def ri_last_timings(h: int) -> list:
     """[reach phase, join + finalize, whole call, dominant reach kernel, warm-up kernel] in ms."""
     ms = (ctypes.c_float * 5)()
@@ -246,6 +260,9 @@ class Recognizer:
 
     def get_option(self, option) -> int:
         return ri_get_option(self.handle, option)
+
+    def autotune(self, text, algo="rid", stream=None) -> dict:
+        return ri_autotune(self.handle, text, stream, algo)
 
     def close(self) -> None:
         if self.handle:

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -99,6 +100,8 @@ struct ri_handle {
     bool profiling = false;
     float last_ms[5] = {0, 0, 0, 0, 0};
     Options opt;
+    bool tuned_valid[RI_NUM_ALGOS] = {false, false, false};
+    Options tuned[RI_NUM_ALGOS];
 };
 
 namespace {
@@ -308,7 +311,12 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     if (device < 0 || device >= kMaxDevices) return fail(RI_ERR_DEVICE, "device index out of range");
 
     Plan plan;
-    int rc = plan_chunks(H, n, chunks, h->opt.chunk_target, &plan);
+    uint32_t target = h->opt.chunk_target;
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        if (chunks == 0 && h->opt.converge && h->tuned_valid[algo]) target = h->tuned[algo].chunk_target;
+    }
+    int rc = plan_chunks(H, n, chunks, target, &plan);
     if (rc) return rc;
     if (maps && maps_cap < (size_t)plan.nchunks * H.L)
         return fail(RI_ERR_ARG, "maps buffer too small");
@@ -325,7 +333,11 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     DeviceCopy &dc = h->dev[device];
     const AlgoDevice &D = dc.algo[algo];
 
-    const Options opt = h->opt;
+    Options opt;
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        opt = (chunks == 0 && h->opt.converge && h->tuned_valid[algo]) ? h->tuned[algo] : h->opt;
+    }
     const bool conv = opt.converge != 0;
     // level-0 join group: the widest power of two <= 64 whose LDS tile of
     // chunk maps (L x G0 x 4 bytes) stays within 64 KiB; 0 = unstaged join
@@ -339,7 +351,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     shape.entry_bytes = (int)H.entry_bytes;
     shape.tile_bytes = (int)H.lam_bytes;
     shape.alias_bytes = H.L <= 254 ? 1 : 2;
-    uint32_t R = opt.runs_per_lane ? opt.runs_per_lane : 4;
+    uint32_t R = opt.runs_per_lane ? opt.runs_per_lane : 4;     // warm-up (runs of one chunk)
     shape.block_threads = 1024;
     const size_t lds_tables = H.table.size() + 512;
     shape.table_in_lds = lds_tables <= dc.max_lds;
@@ -431,7 +443,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[5], stream));
         // merged runs to the chunk ends
         ri::KernelShape ls = shape;
-        ls.runs_per_lane = (int)(opt.runs_per_lane ? opt.runs_per_lane : 2);
+        ls.runs_per_lane = (int)(opt.runs_per_lane ? opt.runs_per_lane : 1);
         const size_t lds_l = shape.table_in_lds ? lds_tables : 512;
         ri::LongArgs la;
         la.s = sa;
@@ -715,6 +727,7 @@ int ri_last_timings(const ri_handle *h, float ms[5]) {
 int ri_set_option(ri_handle *h, int option, int64_t value) {
     if (!h) return fail(RI_ERR_ARG, "NULL handle");
     std::lock_guard<std::mutex> lk(h->mu);
+    for (bool &v : h->tuned_valid) v = false;
     switch (option) {
     case RI_OPT_CONVERGE:
         if (value != 0 && value != 1) return fail(RI_ERR_ARG, "RI_OPT_CONVERGE must be 0 or 1");
@@ -746,6 +759,79 @@ int ri_get_option(const ri_handle *h, int option, int64_t *value) {
     case RI_OPT_CHUNK_TARGET: *value = h->opt.chunk_target; return RI_OK;
     }
     return fail(RI_ERR_ARG, "unknown option");
+}
+
+int ri_autotune(ri_handle *h, const uint8_t *text, size_t n, void *stream, int algo, ri_tuning *out) {
+    if (!h) return fail(RI_ERR_ARG, "NULL handle");
+    if (algo < 0 || algo >= RI_NUM_ALGOS) return fail(RI_ERR_ARG, "unknown algorithm");
+    Options saved;
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        saved = h->opt;
+        h->tuned_valid[algo] = false;
+    }
+    static const uint32_t kTargets[] = {32768, 65536, 131072, 262144};
+    static const uint32_t kWarm[] = {16, 32, 64};
+    static const uint32_t kRuns[] = {1, 2};
+    ri_result first{}, r{};
+    int rc = recognize(h, text, n, stream, algo, 0, &first, nullptr, 0);
+    if (rc) return rc;
+    Options best = saved;
+    double best_ms = 1e30;
+    uint32_t trials = 0;
+    uint32_t prev_chunks = 0;
+    for (uint32_t tgt : kTargets) {
+        for (uint32_t w : kWarm) {
+            for (uint32_t R : kRuns) {
+                {
+                    std::lock_guard<std::mutex> lk(h->mu);
+                    h->opt = saved;
+                    h->opt.converge = 1;
+                    h->opt.chunk_target = tgt;
+                    h->opt.warm = w;
+                    h->opt.runs_per_lane = R;
+                }
+                rc = recognize(h, text, n, stream, algo, 0, &r, nullptr, 0);   // warm
+                if (rc) break;
+                double t[3];
+                for (double &ti : t) {
+                    auto t0 = std::chrono::steady_clock::now();
+                    rc = recognize(h, text, n, stream, algo, 0, &r, nullptr, 0);
+                    ti = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                    if (rc) break;
+                }
+                if (rc) break;
+                if (r.accept != first.accept || r.final_state != first.final_state) {
+                    std::lock_guard<std::mutex> lk(h->mu);
+                    h->opt = saved;
+                    return fail(RI_ERR_DEVICE, "internal: results differ between tuning trials");
+                }
+                std::sort(t, t + 3);
+                ++trials;
+                if (t[1] < best_ms) {
+                    best_ms = t[1];
+                    best = h->opt;
+                }
+            }
+            if (rc) break;
+        }
+        if (rc) break;
+        if (r.chunks == prev_chunks) break;   // text too short for more chunks
+        prev_chunks = r.chunks;
+    }
+    std::lock_guard<std::mutex> lk(h->mu);
+    h->opt = saved;
+    if (rc) return rc;
+    h->tuned[algo] = best;
+    h->tuned_valid[algo] = true;
+    if (out) {
+        out->chunk_target = best.chunk_target;
+        out->warmup_bytes = best.warm;
+        out->runs_per_lane = best.runs_per_lane;
+        out->trials = trials;
+        out->best_ms = (float)best_ms;
+    }
+    return RI_OK;
 }
 
 const char *ri_last_error(void) { return g_error.c_str(); }

@@ -281,6 +281,26 @@ def test_empty_language_and_empty_string_language():
         eps.close()
 
 
+def test_autotune_keeps_results_exact():
+    rx, motifs = gen.c2_regex_and_motifs(1)
+    ref = Ref(rx)
+    x, rej = gen.c2_texts(1, n=1 << 24, motifs=motifs)
+    rec = ri.Recognizer(rx)
+    try:
+        t = dev(x)
+        for algo in ("rid", "dfa"):
+            tun = rec.autotune(t, algo=algo)
+            assert tun["trials"] >= 6 and tun["best_ms"] > 0
+            for text in (x, rej):
+                got = rec.recognize(dev(text), algo=algo)
+                assert (got["accept"], got["final_state"]) == ref.serial(text)
+        rec.set_option("warmup_bytes", 32)     # explicit options drop the tuned setting
+        got = rec.recognize(t, algo="rid")
+        assert (got["accept"], got["final_state"]) == ref.serial(x)
+    finally:
+        rec.close()
+
+
 def test_side_stream_and_handle_reuse(tiny):
     rec, ref = tiny
     acc, rej = gen.c1_texts(9, n=1 << 18)
