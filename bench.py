@@ -37,7 +37,73 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-tune", action="store_true",
                     help="skip ri_autotune (the chunk count is then the library default)")
+    ap.add_argument("--tune-rid", metavar="TARGET:WARM:RUNS",
+                    help="use these reach settings for RID instead of ri_autotune")
+    ap.add_argument("--tune-dfa", metavar="TARGET:WARM:RUNS",
+                    help="use these reach settings for the DFA instead of ri_autotune")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the paper-literal (non-merging) reach comparison")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="one 256 MiB device-to-device copy before timing (known-size kernel "
+                         "for scaling FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU: turn two rocprofv3 --pmc counter CSVs into the traffic record "
+                         "under profiles/ and exit")
     return ap.parse_args()
+
+
+KERNEL_SRC = os.path.join(ROOT, "paper_2412_14975_amd", "csrc", "kernels.hip")
+CALIB_BYTES = 256 << 20
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_record_path(workload_name):
+    return os.path.join(ROOT, "profiles", f"traffic_long_kernel_{workload_name}.json")
+
+
+def summarize_traffic(fetch_csv, write_csv, workload_name):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the RID long-run kernel,
+    scaled by the same counters read on the known-size calibration copy."""
+    import csv
+
+    def per_kernel(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        by_dispatch = {}
+        for r in rows:
+            by_dispatch.setdefault((r["Dispatch_Id"], r["Kernel_Name"]), 0.0)
+            by_dispatch[(r["Dispatch_Id"], r["Kernel_Name"])] += float(r["Counter_Value"])
+        return by_dispatch
+
+    out = {"kernel_source_sha256": kernel_source_hash(), "workload": workload_name}
+    for counter, path, key in (("FETCH_SIZE", fetch_csv, "fetch"), ("WRITE_SIZE", write_csv, "write")):
+        d = per_kernel(path, counter)
+        copies = [v for (i, k), v in d.items() if "copyBuffer" in k]
+        longs = [v for (i, k), v in d.items() if "long_kernel<unsigned short" in k]
+        calib = max(copies)                      # the 256 MiB copy is the largest copy
+        factor = CALIB_BYTES / (calib * 1024.0)
+        med = float(np.median(longs))
+        out[key] = {"kib_per_dispatch_raw": med, "calib_copy_kib_raw": calib,
+                    "scale": factor, "bytes_per_dispatch": med * 1024.0 * factor,
+                    "dispatches": len(longs)}
+    out["traffic_bytes_per_launch"] = out["fetch"]["bytes_per_dispatch"] + out["write"]["bytes_per_dispatch"]
+    with open(traffic_record_path(workload_name), "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+def load_traffic(workload_name):
+    p = traffic_record_path(workload_name)
+    if not os.path.exists(p):
+        return None
+    rec = json.load(open(p))
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None    # kernels changed since the counters were taken
+    return rec
 
 
 def workload(name, seed):
@@ -55,8 +121,17 @@ def workload(name, seed):
     return rx, x, "regexp-k3-1MiB"
 
 
-def time_algo(torch, rec, t, algo, chunks, steps, warmup, want):
+def apply_setting(rec, setting):
+    """setting: dict with chunk_target / warmup_bytes / runs_per_lane, or None
+    (keep what ri_autotune stored in the handle)."""
+    if setting:
+        for k in ("chunk_target", "warmup_bytes", "runs_per_lane"):
+            rec.set_option(k, setting[k])
+
+
+def time_algo(torch, rec, t, algo, chunks, steps, warmup, want, setting=None):
     """Returns dict with per-call times (s), whole-run time and kernel timings."""
+    apply_setting(rec, setting)
     for _ in range(warmup):
         r = rec.recognize(t, algo=algo, chunks=chunks)
     torch.cuda.synchronize()
@@ -84,6 +159,10 @@ def time_algo(torch, rec, t, algo, chunks, steps, warmup, want):
 
 def main():
     args = parse()
+    if args.traffic_from:
+        names = {"motif": "motif-union-ACGT-256MiB", "log": "log-lines-1GiB", "tiny": "regexp-k3-1MiB"}
+        summarize_traffic(args.traffic_from[0], args.traffic_from[1], names[args.workload])
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this recognizer runs on one GPU only; --gpus must be 1 "
               "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
@@ -111,19 +190,52 @@ def main():
     info = rec.info()
     t = torch.from_numpy(x).to("cuda")
     torch.cuda.synchronize()
+    if args.calib_copy:
+        src = torch.empty(CALIB_BYTES, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
-    tuning = {}
+    tuning, fixed = {}, {}
+    for algo, spec in (("rid", args.tune_rid), ("dfa", args.tune_dfa)):
+        if spec:
+            tgt, w, r = (int(v) for v in spec.split(":"))
+            fixed[algo] = dict(chunk_target=tgt, warmup_bytes=w, runs_per_lane=r)
+            tuning[algo] = dict(fixed[algo], trials=0, source="given")
     if not args.no_tune and args.chunks == 0:
         # setup, outside the timed region: pick chunk target / warm-up / runs
         # per lane for each algorithm on this text (same grid for both)
         for algo in ("rid", "dfa"):
+            if algo in fixed:
+                continue
             tuning[algo] = rec.autotune(t, algo=algo)
+            tuning[algo]["source"] = "ri_autotune"
             print(f"# tuned {algo}: {tuning[algo]}", file=sys.stderr, flush=True)
+            fixed[algo] = {k: tuning[algo][k] for k in ("chunk_target", "warmup_bytes", "runs_per_lane")}
 
-    rid = time_algo(torch, rec, t, "rid", args.chunks, args.steps, args.warmup, want)
+    rid = time_algo(torch, rec, t, "rid", args.chunks, args.steps, args.warmup, want, fixed.get("rid"))
     print(f"# rid done", file=sys.stderr, flush=True)
-    dfa = time_algo(torch, rec, t, "dfa", args.chunks, args.steps, args.warmup, want)
+    dfa = time_algo(torch, rec, t, "dfa", args.chunks, args.steps, args.warmup, want, fixed.get("dfa"))
     print(f"# dfa done", file=sys.stderr, flush=True)
+
+    plain = None
+    if not args.no_plain:
+        # the paper-literal reach (every run to the chunk end or its death, no
+        # merging), RID vs all-states DFA at the RID chunk count
+        c_rid = rid["result"]["chunks"]
+        apply_setting(rec, fixed.get("rid"))
+        rec.set_option("converge", 0)
+        plain = {}
+        for algo in ("rid", "dfa"):
+            m = time_algo(torch, rec, t, algo, c_rid, 5, 1, want)
+            plain[algo] = dict(gbps=round(n * 5 / m["total"] / 1e9, 2),
+                               ms_per_step=round(m["total"] / 5 * 1e3, 4),
+                               reach_ms=round(float(m["reach_ms"].mean()), 4),
+                               chunks=m["result"]["chunks"], bitexact=bool(m["exact"]))
+        plain["speedup_rid_vs_dfa"] = round(plain["rid"]["gbps"] / plain["dfa"]["gbps"], 4)
+        rec.set_option("converge", 1)
+        print(f"# plain done", file=sys.stderr, flush=True)
 
     def summary(m):
         p50 = float(np.percentile(m["per_call"], 50))
@@ -143,11 +255,13 @@ def main():
     # the same bytes; the run records, 12 B per run, are < 2% and left out).
     L = info["starts"][0]
     cs, c = s_rid["chunk_size"], s_rid["chunks"]
-    warm = tuning["rid"]["warmup_bytes"] if "rid" in tuning else rec.get_option("warmup_bytes")
+    warm = fixed["rid"]["warmup_bytes"] if "rid" in fixed else rec.get_option("warmup_bytes")
     long_bytes = sum(max(0, min(cs, n - i * cs) - warm) for i in range(c)) if c < 5_000_000 else n
     achieved = long_bytes / (s_rid["long_ms"] * 1e-3) / 1e9
+    trec = load_traffic(wname)
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=(round(trec["traffic_bytes_per_launch"]) if trec else None),
                 kernel="long_kernel", algorithmic_bytes=int(long_bytes),
                 reach_phase_gbps=round(n / (s_rid["reach_ms"] * 1e-3) / 1e9, 1))
 
@@ -187,12 +301,15 @@ def main():
         "p99_ms": round(s_rid["p99_ms"], 4),
         "gbps_p50": round(s_rid["gbps_p50"], 2),
         "gbps_p99": round(s_rid["gbps_p99"], 2),
-        "bitexact": s_rid["bitexact"] and s_dfa["bitexact"],
+        "bitexact": s_rid["bitexact"] and s_dfa["bitexact"] and (
+            plain is None or (plain["rid"]["bitexact"] and plain["dfa"]["bitexact"])),
         "rid": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s_rid.items()},
         "all_states_dfa": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s_dfa.items()},
         "speedup_rid_vs_dfa": round(s_rid["gbps"] / s_dfa["gbps"], 4),
         "tuning": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                    for k, v in tuning.items()},
+        "command": " ".join(["python", "bench.py"] + sys.argv[1:]),
+        "plain_reach": plain,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
