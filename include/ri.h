@@ -179,7 +179,7 @@ int ri_last_timings(const ri_handle *h, float ms[5]);
  *                         convergence; the chunk maps are unchanged).
  *                         0: every run is scanned to the chunk end or to its
  *                         death, as the reach phase is stated.
- *   RI_OPT_WARMUP_BYTES   multiple of 16 in [16, 1<<20]; default 64.
+ *   RI_OPT_WARMUP_BYTES   multiple of 16 in [16, 256]; default 64.
  *   RI_OPT_RUNS_PER_LANE  independent runs per GPU lane: 0 (automatic), 1, 2, 4.
  *   RI_OPT_CHUNK_TARGET   chunk count aimed at when chunks = 0; default 131072.
  * Errors: RI_ERR_ARG for an unknown option or a value out of range.
@@ -210,6 +210,106 @@ typedef struct {
 } ri_tuning;
 int ri_autotune(ri_handle *h, const uint8_t *text_dev, size_t n, void *stream, int algo,
                 ri_tuning *out);
+
+/* ---- batches ------------------------------------------------------------
+ *
+ * Many texts, each with its own automaton and algorithm, recognized by one
+ * sequence of launches.  Requests are grouped by (handle, algo); within a
+ * group every text is cut into chunks of the group's chunk size, and all
+ * chunks of all texts of the group go through one converging reach
+ * (RI_OPT_CONVERGE = 1 whatever the handle's setting) and one join tree
+ * whose groups never span two texts, so each text's result is exactly the
+ * one ri_recognize_ex gives for it (Th. 1 applies to every text alone).
+ */
+typedef struct ri_batch ri_batch;   /* opaque */
+
+typedef struct {
+    const ri_handle *h;        /* automaton; must stay alive while the batch exists  */
+    const uint8_t *text_dev;   /* device pointer, 16-byte aligned; NULL allowed if n = 0 */
+    uint64_t n;                /* text length (0 allowed)                             */
+    int32_t algo;              /* RI_ALGO_RID, RI_ALGO_DFA or RI_ALGO_SUBSET          */
+    uint32_t reserved;         /* must be 0                                           */
+} ri_request;
+
+typedef struct {
+    uint32_t texts;            /* requests                                            */
+    uint32_t groups;           /* (handle, algo) groups                               */
+    uint64_t slots;            /* chunks over all groups                              */
+    uint64_t bytes;            /* text bytes over all requests                        */
+    uint64_t device_bytes;     /* device memory held by the batch (not the tables)    */
+    uint32_t kernels;          /* kernel launches per run                             */
+    uint32_t captured;         /* 1 after a successful ri_batch_capture               */
+} ri_batch_info;
+
+typedef struct {
+    const ri_handle *h;
+    int32_t algo;
+    uint32_t texts;
+    uint32_t slots;            /* chunks of the group                                 */
+    uint64_t bytes;
+    uint32_t chunk_bytes;      /* chunk size used for every text of the group         */
+    uint32_t warmup_bytes;
+    uint32_t runs_per_lane;
+    uint32_t join_levels;
+    float tuned_ms;            /* best time found by ri_batch_autotune, else 0        */
+} ri_batch_group;
+
+typedef struct {
+    uint32_t trials;           /* settings timed                                      */
+    float best_ms;             /* sum over groups of the best group times             */
+} ri_batch_tuning;
+
+/*
+ * ri_batch_create -- plan a batch of `count` requests on the current device:
+ * build the chunk descriptors and join levels, upload the automata that are
+ * not yet on the device and allocate every buffer the batch needs.  The
+ * requests array is copied; the texts are read only by later runs, so they
+ * must stay valid (and unchanged in place and size) until the last run.
+ * chunk_bytes: multiple of 16, the chunk size of every group; 0 = chosen per
+ * group from its total size (about 131072 chunks per group, 256 B to 1 MiB).
+ * Synchronous.  Errors: RI_ERR_ARG (NULL pointers, misaligned text, bad
+ * algo, chunk_bytes not a multiple of 16), RI_ERR_LIMIT (interface too large
+ * for the device join, more than 2^31 chunk maps in a group), RI_ERR_NOMEM,
+ * RI_ERR_DEVICE.
+ */
+int ri_batch_create(const ri_request *reqs, uint32_t count, uint32_t chunk_bytes, ri_batch **out);
+
+/* ri_batch_free -- release the batch (not the handles); NULL is a no-op.
+ * No run or graph launch of the batch may be in flight. */
+void ri_batch_free(ri_batch *b);
+
+/*
+ * ri_batch_run -- enqueue the whole batch on `stream` and return without
+ * waiting.  results_dev: device array of 2 * count int32, written as
+ * results_dev[2*i] = accept, results_dev[2*i+1] = final state of request i
+ * (the values of ri_result).  Allocates nothing and makes no synchronous
+ * call, so it may be captured into a HIP graph by the caller.  Runs of one
+ * batch must not overlap (they share its buffers): order them on one stream.
+ */
+int ri_batch_run(ri_batch *b, void *stream, int32_t *results_dev);
+
+/*
+ * ri_batch_capture / ri_batch_launch -- capture one run of the batch into a
+ * HIP graph kept by the batch (groups become independent branches that may
+ * execute concurrently), writing to results_dev; ri_batch_launch then
+ * launches that graph on `stream` (one call, no host work per text).  A
+ * new capture replaces the previous graph; ri_batch_autotune drops it.
+ */
+int ri_batch_capture(ri_batch *b, int32_t *results_dev);
+int ri_batch_launch(ri_batch *b, void *stream);
+
+/* ri_batch_get_info / ri_batch_get_group -- sizes of the plan. */
+int ri_batch_get_info(const ri_batch *b, ri_batch_info *out);
+int ri_batch_get_group(const ri_batch *b, uint32_t index, ri_batch_group *out);
+
+/*
+ * ri_batch_autotune -- for every group independently, time the batch under
+ * a fixed grid of chunk sizes (unless chunk_bytes was given at creation) and
+ * warm-up lengths, keep for each group its fastest setting and re-plan with
+ * it.  Every trial's results must equal the first trial's (RI_ERR_DEVICE
+ * otherwise).  Synchronizes `stream`; allocates.  out may be NULL.
+ */
+int ri_batch_autotune(ri_batch *b, void *stream, ri_batch_tuning *out);
 
 /* ri_last_error -- message of the last failing call on this thread. */
 const char *ri_last_error(void);

@@ -24,7 +24,9 @@ ALGOS = {"rid": RI_ALGO_RID, "dfa": RI_ALGO_DFA, "subset": RI_ALGO_SUBSET}
 
 SYMBOLS = ("ri_build", "ri_free", "ri_info", "ri_recognize", "ri_recognize_ex",
            "ri_chunk_maps", "ri_state_content", "ri_set_profiling", "ri_last_timings",
-           "ri_set_option", "ri_get_option", "ri_autotune", "ri_last_error")
+           "ri_set_option", "ri_get_option", "ri_autotune", "ri_last_error",
+           "ri_batch_create", "ri_batch_free", "ri_batch_run", "ri_batch_capture",
+           "ri_batch_launch", "ri_batch_get_info", "ri_batch_get_group", "ri_batch_autotune")
 RI_OPT_CONVERGE, RI_OPT_WARMUP_BYTES, RI_OPT_RUNS_PER_LANE, RI_OPT_CHUNK_TARGET = 1, 2, 3, 4
 OPTIONS = {"converge": RI_OPT_CONVERGE, "warmup_bytes": RI_OPT_WARMUP_BYTES,
            "runs_per_lane": RI_OPT_RUNS_PER_LANE, "chunk_target": RI_OPT_CHUNK_TARGET}
@@ -62,6 +64,29 @@ class ri_info_t(ctypes.Structure):
                 ("table_bytes", ctypes.c_uint64 * RI_NUM_ALGOS)]
 
 
+class ri_request(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_void_p), ("text_dev", ctypes.c_void_p), ("n", ctypes.c_uint64),
+                ("algo", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
+
+
+class ri_batch_info(ctypes.Structure):
+    _fields_ = [("texts", ctypes.c_uint32), ("groups", ctypes.c_uint32), ("slots", ctypes.c_uint64),
+                ("bytes", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
+                ("kernels", ctypes.c_uint32), ("captured", ctypes.c_uint32)]
+
+
+class ri_batch_group(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_void_p), ("algo", ctypes.c_int32), ("texts", ctypes.c_uint32),
+                ("slots", ctypes.c_uint32), ("bytes", ctypes.c_uint64),
+                ("chunk_bytes", ctypes.c_uint32), ("warmup_bytes", ctypes.c_uint32),
+                ("runs_per_lane", ctypes.c_uint32), ("join_levels", ctypes.c_uint32),
+                ("tuned_ms", ctypes.c_float)]
+
+
+class ri_batch_tuning(ctypes.Structure):
+    _fields_ = [("trials", ctypes.c_uint32), ("best_ms", ctypes.c_float)]
+
+
 _lib = None
 
 
@@ -87,10 +112,19 @@ def lib() -> ctypes.CDLL:
     L.ri_set_option.argtypes = [vp, i32, ctypes.c_int64]
     L.ri_get_option.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64)]
     L.ri_autotune.argtypes = [vp, vp, sz, vp, i32, ctypes.POINTER(ri_tuning)]
+    L.ri_batch_create.argtypes = [ctypes.POINTER(ri_request), u32, u32, ctypes.POINTER(vp)]
+    L.ri_batch_free.argtypes = [vp]
+    L.ri_batch_free.restype = None
+    L.ri_batch_run.argtypes = [vp, vp, vp]
+    L.ri_batch_capture.argtypes = [vp, vp]
+    L.ri_batch_launch.argtypes = [vp, vp]
+    L.ri_batch_get_info.argtypes = [vp, ctypes.POINTER(ri_batch_info)]
+    L.ri_batch_get_group.argtypes = [vp, u32, ctypes.POINTER(ri_batch_group)]
+    L.ri_batch_autotune.argtypes = [vp, vp, ctypes.POINTER(ri_batch_tuning)]
     L.ri_last_error.argtypes = []
     L.ri_last_error.restype = ctypes.c_char_p
     for name in SYMBOLS:
-        if name not in ("ri_free", "ri_last_error"):
+        if name not in ("ri_free", "ri_last_error", "ri_batch_free"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -227,9 +261,108 @@ def ri_last_error() -> str:
     return lib().ri_last_error().decode(errors="replace")
 
 
+def _results_ptr(results: torch.Tensor, count: int) -> int:
+    if (not isinstance(results, torch.Tensor) or results.dtype != torch.int32 or not results.is_cuda
+            or not results.is_contiguous() or results.numel() < 2 * count):
+        raise TypeError("results must be a contiguous int32 GPU tensor of at least 2 * count entries")
+    return results.data_ptr()
+
+
+def ri_batch_create(requests, chunk_bytes: int = 0) -> int:
+    """requests: sequence of (handle, text tensor, algo).  The texts must stay
+    alive and unchanged while the batch is used."""
+    arr = (ri_request * max(1, len(requests)))()
+    for i, (h, text, algo) in enumerate(requests):
+        ptr, n = _text_ptr(text)
+        arr[i] = ri_request(h, ptr if n else None, n, _algo(algo), 0)
+    b = ctypes.c_void_p()
+    _check(lib().ri_batch_create(arr, len(requests), int(chunk_bytes), ctypes.byref(b)))
+    return b.value
+
+
+def ri_batch_free(b: int) -> None:
+    lib().ri_batch_free(b)
+
+
+def ri_batch_run(b: int, results: torch.Tensor, stream=None) -> None:
+    info = ri_batch_get_info(b)
+    _check(lib().ri_batch_run(b, _stream_ptr(stream), _results_ptr(results, info["texts"])))
+
+
+def ri_batch_capture(b: int, results: torch.Tensor) -> None:
+    info = ri_batch_get_info(b)
+    _check(lib().ri_batch_capture(b, _results_ptr(results, info["texts"])))
+
+
+def ri_batch_launch(b: int, stream=None) -> None:
+    _check(lib().ri_batch_launch(b, _stream_ptr(stream)))
+
+
+def ri_batch_get_info(b: int) -> dict:
+    i = ri_batch_info()
+    _check(lib().ri_batch_get_info(b, ctypes.byref(i)))
+    return {name: getattr(i, name) for name, _ in ri_batch_info._fields_}
+
+
+def ri_batch_get_group(b: int, index: int) -> dict:
+    g = ri_batch_group()
+    _check(lib().ri_batch_get_group(b, int(index), ctypes.byref(g)))
+    return {name: getattr(g, name) for name, _ in ri_batch_group._fields_}
+
+
+def ri_batch_autotune(b: int, stream=None) -> dict:
+    t = ri_batch_tuning()
+    _check(lib().ri_batch_autotune(b, _stream_ptr(stream), ctypes.byref(t)))
+    return {name: getattr(t, name) for name, _ in ri_batch_tuning._fields_}
+
+
 # ---------------------------------------------------------------------------
-# convenience wrapper
+# convenience wrappers
 # ---------------------------------------------------------------------------
+
+class Batch:
+    """Owns one batch: ``Batch([(recognizer, text, "rid"), ...]).run()`` returns
+    an int32 GPU tensor [count, 2] of (accept, final state)."""
+
+    def __init__(self, requests, chunk_bytes: int = 0):
+        reqs = [(r.handle if isinstance(r, Recognizer) else r, t, a) for r, t, a in requests]
+        self._texts = [t for _, t, _ in reqs]     # keep the texts alive
+        self.count = len(reqs)
+        self.handle = ri_batch_create(reqs, chunk_bytes)
+        dev = self._texts[0].device if self._texts else torch.device("cuda")
+        self.results = torch.zeros(max(1, self.count) * 2, dtype=torch.int32, device=dev)
+
+    def run(self, stream=None) -> torch.Tensor:
+        ri_batch_run(self.handle, self.results, stream)
+        return self.results[: 2 * self.count].view(self.count, 2)
+
+    def capture(self) -> None:
+        ri_batch_capture(self.handle, self.results)
+
+    def launch(self, stream=None) -> torch.Tensor:
+        ri_batch_launch(self.handle, stream)
+        return self.results[: 2 * self.count].view(self.count, 2)
+
+    def info(self) -> dict:
+        return ri_batch_get_info(self.handle)
+
+    def group(self, index: int) -> dict:
+        return ri_batch_get_group(self.handle, index)
+
+    def autotune(self, stream=None) -> dict:
+        return ri_batch_autotune(self.handle, stream)
+
+    def close(self) -> None:
+        if self.handle:
+            ri_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
 
 class Recognizer:
     """Owns one handle: ``Recognizer(regex).recognize(text_tensor)``."""

@@ -286,6 +286,119 @@ int plan_chunks(const AlgoHost &H, uint64_t n, uint32_t chunks, uint32_t target,
     return RI_OK;
 }
 
+ri::KernelShape base_shape(const AlgoHost &H, const DeviceCopy &dc) {
+    ri::KernelShape shape;
+    shape.entry_bytes = (int)H.entry_bytes;
+    shape.tile_bytes = (int)H.lam_bytes;
+    shape.alias_bytes = H.L <= 254 ? 1 : 2;
+    shape.runs_per_lane = 1;
+    shape.block_threads = 1024;
+    shape.table_in_lds = H.table.size() + 512 <= dc.max_lds;
+    return shape;
+}
+
+// Launch configuration of the converging reach over `nchunks` chunks of at
+// most cs bytes.
+struct ConvCfg {
+    ri::KernelShape warm_shape, long_shape;
+    uint32_t cw = 0;
+    size_t lds_w = 0, lds_l = 0;
+    int grid_w = 1, grid_l = 1;
+    uint32_t chunk_groups = 0;
+};
+
+int conv_config(const AlgoHost &H, const DeviceCopy &dc, const Options &opt, uint64_t cs, uint32_t nchunks,
+                ConvCfg *c) {
+    if (H.L > 65534) return fail(RI_ERR_LIMIT, "too many starts for the converging reach");
+    const ri::KernelShape shape = base_shape(H, dc);
+    const size_t lds_tables = H.table.size() + 512;
+    // warm-up: runs of one chunk share a lane
+    c->warm_shape = shape;
+    uint32_t Rw = opt.runs_per_lane ? opt.runs_per_lane : 4;
+    while (Rw > 1 && Rw / 2 >= H.L) Rw /= 2;
+    c->warm_shape.runs_per_lane = (int)Rw;
+    // tile width (chunks per group): prefer >= 16 chunks within half the LDS
+    // (two blocks per CU), then anything that fits, then the table in global
+    // memory
+    const uint32_t ws = (uint32_t)std::min<uint64_t>(opt.warm, cs);
+    auto pick = [&](size_t budget, uint32_t min_cw) -> bool {
+        for (uint32_t w = 64; w >= min_cw && w >= 1; w /= 2) {
+            const size_t l = ri::warm_lds_bytes(c->warm_shape, H.L, (uint32_t)H.table.size(), w, ws);
+            if (l <= budget) { c->cw = w; c->lds_w = l; return true; }
+        }
+        return false;
+    };
+    if (!(c->warm_shape.table_in_lds && (pick(dc.max_lds / 2, 16) || pick(dc.max_lds, 1)))) {
+        c->warm_shape.table_in_lds = false;
+        if (!pick(dc.max_lds, 1)) return fail(RI_ERR_LIMIT, "too many starts for the warm-up tile");
+    }
+    c->chunk_groups = (nchunks + c->cw - 1) / c->cw;
+    const int per_cu_w = std::max(1, ri::blocks_per_cu(1, c->warm_shape, c->lds_w));
+    c->grid_w = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)dc.cus * per_cu_w, c->chunk_groups));
+    // long runs: one run per lane unless set
+    c->long_shape = shape;
+    c->long_shape.runs_per_lane = (int)(opt.runs_per_lane ? opt.runs_per_lane : 1);
+    c->lds_l = shape.table_in_lds ? lds_tables : 512;
+    const uint64_t pairs = (uint64_t)H.L * nchunks;
+    const int per_cu_l = std::max(1, ri::blocks_per_cu(2, c->long_shape, c->lds_l));
+    const uint64_t max_jobs = (pairs + 64ull * c->long_shape.runs_per_lane - 1) / (64ull * c->long_shape.runs_per_lane);
+    c->grid_l = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)dc.cus * per_cu_l, (max_jobs + 15) / 16));
+    return RI_OK;
+}
+
+struct ReachBufs {
+    void *alias;
+    uint32_t *run_base, *run_chunk, *run_state, *run_final, *counters;
+};
+
+// Warm-up and merging, then the merged runs to the chunk ends; `mid`
+// (optional) is recorded between the two kernels.
+int launch_conv(const ConvCfg &c, const ri::ScanArgs &sa, const Options &opt, const ReachBufs &rb,
+                hipStream_t stream, hipEvent_t mid) {
+    ri::WarmArgs wa{};
+    wa.s = sa;
+    wa.warm = opt.warm;
+    wa.cw = c.cw;
+    wa.chunk_groups = c.chunk_groups;
+    wa.alias = rb.alias;
+    wa.run_base = rb.run_base;
+    wa.run_chunk = rb.run_chunk;
+    wa.run_state = rb.run_state;
+    wa.counters = rb.counters;
+    HIP_TRY(ri::launch_warm(wa, c.warm_shape, c.grid_w, c.lds_w, stream));
+    if (mid) HIP_TRY(hipEventRecord(mid, stream));
+    ri::LongArgs la{};
+    la.s = sa;
+    la.warm = opt.warm;
+    la.run_chunk = rb.run_chunk;
+    la.run_state = rb.run_state;
+    la.run_final = rb.run_final;
+    la.counters = rb.counters;
+    HIP_TRY(ri::launch_long(la, c.long_shape, c.grid_l, c.lds_l, stream));
+    return RI_OK;
+}
+
+// Members per group of the class-partitioned join: the widest power of two
+// <= 64 whose LDS stays within 64 KiB; 0 if none does.
+uint32_t cls_group(const AlgoHost &H, int alias_bytes) {
+    ri::ClsJoinArgs ca{};
+    ca.L = H.L;
+    for (uint32_t gc = 64; gc >= 2; gc /= 2) {
+        ca.G = gc;
+        if (ri::cls_join_lds(ca, (int)H.W, alias_bytes) <= 65536) return gc;
+    }
+    return 0;
+}
+
+// Members per group of the staged level-0 join (functions or relations): the
+// widest power of two <= 64 whose tile of chunk maps (L x G x 4 bytes) stays
+// within 64 KiB; 0 = unstaged join.
+uint32_t tile_group(const AlgoHost &H) {
+    uint32_t g0 = 64;
+    while (g0 > 0 && (size_t)H.L * g0 * 4 > 65536) g0 /= 2;
+    return g0;
+}
+
 int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v, int algo,
               uint32_t chunks, ri_result *out, int32_t *maps, size_t maps_cap) {
     ri_handle *h = const_cast<ri_handle *>(hc);
@@ -339,26 +452,22 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         opt = (chunks == 0 && h->opt.converge && h->tuned_valid[algo]) ? h->tuned[algo] : h->opt;
     }
     const bool conv = opt.converge != 0;
-    // level-0 join group: the widest power of two <= 64 whose LDS tile of
-    // chunk maps (L x G0 x 4 bytes) stays within 64 KiB; 0 = unstaged join
-    uint32_t g0 = 64;
-    while (g0 > 0 && (size_t)H.L * g0 * 4 > 65536) g0 /= 2;
+    const uint32_t g0 = tile_group(H);
     const uint32_t ng0 = (plan.nchunks + (g0 ? g0 : kJoinGroup) - 1) / (g0 ? g0 : kJoinGroup);
     const size_t row_words = H.relational ? H.W : 1;
     const size_t pairs = (size_t)H.L * plan.nchunks;
 
-    ri::KernelShape shape;
-    shape.entry_bytes = (int)H.entry_bytes;
-    shape.tile_bytes = (int)H.lam_bytes;
-    shape.alias_bytes = H.L <= 254 ? 1 : 2;
-    uint32_t R = opt.runs_per_lane ? opt.runs_per_lane : 4;     // warm-up (runs of one chunk)
-    shape.block_threads = 1024;
+    ri::KernelShape shape = base_shape(H, dc);
+    uint32_t R = opt.runs_per_lane ? opt.runs_per_lane : 4;
     const size_t lds_tables = H.table.size() + 512;
-    shape.table_in_lds = lds_tables <= dc.max_lds;
+    ConvCfg cc;
+    if (conv) {
+        rc = conv_config(H, dc, opt, plan.cs, plan.nchunks, &cc);
+        if (rc) return rc;
+    }
 
     // buffers
     if (conv) {
-        if (H.L > 65534) return fail(RI_ERR_LIMIT, "too many starts for the converging reach");
         rc = grow(ws->alias, pairs * shape.alias_bytes);
         if (!rc) rc = grow(ws->run_base, (size_t)plan.nchunks * 4);
         if (!rc) rc = grow(ws->run_chunk, pairs * 4);
@@ -376,7 +485,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     if (!rc && maps) rc = grow(ws->dbg, pairs * 4);
     if (rc) return rc;
 
-    ri::ScanArgs sa;
+    ri::ScanArgs sa{};
     sa.text = text;
     sa.n = n;
     sa.cs = plan.cs;
@@ -395,7 +504,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         while (R > 1 && R / 2 >= H.L) R /= 2;
         shape.runs_per_lane = (int)R;
         const size_t lds = shape.table_in_lds ? lds_tables : 512;
-        ri::PlainArgs pa;
+        ri::PlainArgs pa{};
         pa.s = sa;
         pa.lam = ws->lam.p;
         pa.job_counter = ws->counters + 3;
@@ -406,63 +515,17 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         HIP_TRY(ri::launch_plain(pa, shape, grid, lds, stream));
         if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[4], stream));
     } else {
-        // warm-up and merging
-        ri::KernelShape ws_shape = shape;
-        uint32_t Rw = R;
-        while (Rw > 1 && Rw / 2 >= H.L) Rw /= 2;
-        ws_shape.runs_per_lane = (int)Rw;
-        // tile width (chunks per group): prefer >= 16 chunks within half the
-        // LDS (two blocks per CU), then anything that fits, then the table in
-        // global memory
-        uint32_t cw = 0;
-        size_t lds_w = 0;
-        auto pick = [&](size_t budget, uint32_t min_cw) -> bool {
-            for (uint32_t c = 64; c >= min_cw && c >= 1; c /= 2) {
-                const size_t l = ri::warm_lds_bytes(ws_shape, H.L, (uint32_t)H.table.size(), c);
-                if (l <= budget) { cw = c; lds_w = l; return true; }
-            }
-            return false;
-        };
-        if (!(ws_shape.table_in_lds && (pick(dc.max_lds / 2, 16) || pick(dc.max_lds, 1)))) {
-            ws_shape.table_in_lds = false;
-            if (!pick(dc.max_lds, 1)) return fail(RI_ERR_LIMIT, "too many starts for the warm-up tile");
-        }
-        ri::WarmArgs wa;
-        wa.s = sa;
-        wa.warm = opt.warm;
-        wa.cw = cw;
-        wa.chunk_groups = (plan.nchunks + cw - 1) / cw;
-        wa.alias = ws->alias.p;
-        wa.run_base = static_cast<uint32_t *>(ws->run_base.p);
-        wa.run_chunk = static_cast<uint32_t *>(ws->run_chunk.p);
-        wa.run_state = static_cast<uint32_t *>(ws->run_state.p);
-        wa.counters = ws->counters;
-        const int per_cu_w = std::max(1, ri::blocks_per_cu(1, ws_shape, lds_w));
-        const int grid_w = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)dc.cus * per_cu_w, wa.chunk_groups));
-        HIP_TRY(ri::launch_warm(wa, ws_shape, grid_w, lds_w, stream));
-        if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[5], stream));
-        // merged runs to the chunk ends
-        ri::KernelShape ls = shape;
-        ls.runs_per_lane = (int)(opt.runs_per_lane ? opt.runs_per_lane : 1);
-        const size_t lds_l = shape.table_in_lds ? lds_tables : 512;
-        ri::LongArgs la;
-        la.s = sa;
-        la.warm = opt.warm;
-        la.run_chunk = wa.run_chunk;
-        la.run_state = wa.run_state;
-        la.run_final = static_cast<uint32_t *>(ws->run_final.p);
-        la.counters = ws->counters;
-        const int per_cu_l = std::max(1, ri::blocks_per_cu(2, ls, lds_l));
-        const uint64_t max_jobs = (pairs + 64ull * ls.runs_per_lane - 1) / (64ull * ls.runs_per_lane);
-        const int grid_l = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)dc.cus * per_cu_l,
-                                                                          (max_jobs + 15) / 16));
-        HIP_TRY(ri::launch_long(la, ls, grid_l, lds_l, stream));
+        ReachBufs rb{ws->alias.p, static_cast<uint32_t *>(ws->run_base.p), static_cast<uint32_t *>(ws->run_chunk.p),
+                     static_cast<uint32_t *>(ws->run_state.p), static_cast<uint32_t *>(ws->run_final.p),
+                     ws->counters};
+        rc = launch_conv(cc, sa, opt, rb, stream, h->profiling ? ws->ev[5] : nullptr);
+        if (rc) return rc;
         if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[4], stream));
     }
     if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[1], stream));
 
     // join tree
-    ri::JoinArgs ja;
+    ri::JoinArgs ja{};
     ja.converged = conv;
     ja.lam = ws->lam.p;
     ja.alias = ws->alias.p;
@@ -477,7 +540,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     ja.in = nullptr;
     ja.nin = 0;
     ja.out = ws->join[0].p;
-    ri::FinalArgs fa;
+    ri::FinalArgs fa{};
     fa.fmask = D.fmask;
     fa.hash = D.hash;
     fa.hash_cap = H.hash_cap;
@@ -495,14 +558,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     ca.run_base = ja.run_base;
     ca.run_final = ja.run_final;
     ca.content = D.content;
-    uint32_t gc = 0;
-    if (conv && H.relational) {
-        for (gc = 64; gc >= 2; gc /= 2) {
-            ca.G = gc;
-            if (ri::cls_join_lds(ca, (int)H.W, shape.alias_bytes) <= 65536) break;
-        }
-        if (gc < 2) gc = 0;
-    }
+    const uint32_t gc = conv && H.relational ? cls_group(H, shape.alias_bytes) : 0;
     if (gc) {
         ca.G = gc;
         ca.nmembers = plan.nchunks;
@@ -587,6 +643,346 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         for (uint32_t s2 = 0; s2 < H.L; ++s2)
             for (uint32_t c = 0; c < plan.nchunks; ++c)
                 maps[(size_t)c * H.L + s2] = lam_host[(size_t)s2 * plan.nchunks + c];
+    }
+    return RI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches: texts grouped by (automaton, algorithm); every group is one
+// converging reach over all of its texts' chunks (chunk descriptors), a join
+// tree whose groups never mix two texts, and one result per text
+// ---------------------------------------------------------------------------
+
+constexpr uint64_t kBatchAutoChunkTarget = 131072;   // chunks aimed at per group when unset
+constexpr uint64_t kBatchMinChunk = 256;
+constexpr uint64_t kBatchMaxChunk = 1ull << 20;
+constexpr int kBatchSide = 4;                         // concurrent branches of a captured batch
+
+struct BatchLevel {
+    uint32_t ngroups = 0;
+    size_t first = 0, count = 0, gchunk = 0;   // byte offsets in the descriptor block
+};
+
+struct BatchGroup {
+    ri_handle *h = nullptr;
+    int algo = 0;
+    std::vector<uint32_t> req;                // request indices
+    uint64_t cs = 0;                          // chunk bytes
+    Options opt;
+    bool empty = false;                       // the automaton accepts nothing
+    uint32_t slots = 0;
+    uint64_t bytes = 0;
+    uint32_t gjoin = 0;                       // level-0 group size
+    uint32_t gupper = 0;                      // group size above level 0
+    ConvCfg cc;
+    std::vector<BatchLevel> levels;
+    size_t off_addr = 0, off_len = 0, off_slot = 0, off_out = 0;
+    Workspace::Buf desc, alias, run_base, run_chunk, run_state, run_final, join[2], ncls[2];
+    uint32_t *counters = nullptr;
+    float tuned_ms = 0;
+};
+
+}  // namespace
+
+struct ri_batch {
+    int device = 0;
+    std::vector<ri_request> reqs;
+    std::vector<BatchGroup> groups;
+    uint64_t bytes = 0;
+    uint32_t fixed_chunk = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int32_t *graph_results = nullptr;
+    hipStream_t side[kBatchSide] = {};
+    hipEvent_t fork = nullptr, joins[kBatchSide] = {};
+};
+
+namespace {
+
+template <typename T>
+size_t put_array(std::vector<uint8_t> &blob, const std::vector<T> &v) {
+    const size_t off = round_up(blob.size(), 16);
+    blob.resize(off + v.size() * sizeof(T));
+    if (!v.empty()) std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+}
+
+void release(Workspace::Buf &b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+// Chunk descriptors, join levels and buffers of one group for its chunk size.
+int plan_group(ri_batch *b, BatchGroup &g) {
+    ri_handle *h = g.h;
+    const AlgoHost &H = h->algo[g.algo];
+    DeviceCopy &dc = h->dev[b->device];
+    std::vector<uint8_t> blob;
+    std::vector<uint32_t> text_slot, text_out;
+    for (uint32_t r : g.req) text_out.push_back(r);
+    g.levels.clear();
+    g.slots = 0;
+    g.bytes = 0;
+    if (g.empty) {
+        text_slot.assign(g.req.size(), 0);
+        g.off_slot = put_array(blob, text_slot);
+        g.off_out = put_array(blob, text_out);
+    } else {
+        if (H.relational && H.W > 64)
+            return fail(RI_ERR_LIMIT, "interface larger than 2048 states is not supported by the device join");
+        const uint64_t cs = g.cs;
+        std::vector<uint64_t> addr;
+        std::vector<uint32_t> len;
+        std::vector<uint32_t> mfirst, mcount;   // member range of each text at the current level
+        for (uint32_t r : g.req) {
+            const ri_request &q = b->reqs[r];
+            const uint64_t nc = q.n == 0 ? 1 : (q.n + cs - 1) / cs;
+            if (addr.size() + nc > 0x7fffffffull) return fail(RI_ERR_LIMIT, "too many chunks in one batch group");
+            text_slot.push_back((uint32_t)addr.size());
+            mfirst.push_back((uint32_t)addr.size());
+            mcount.push_back((uint32_t)nc);
+            for (uint64_t j = 0; j < nc; ++j) {
+                const uint64_t o = j * cs;
+                addr.push_back(reinterpret_cast<uint64_t>(q.text_dev) + (q.n ? o : 0));
+                const uint64_t l = q.n ? std::min<uint64_t>(cs, q.n - o) : 0;
+                len.push_back((uint32_t)l | (j == 0 ? 0x80000000u : 0u));
+            }
+            g.bytes += q.n;
+        }
+        g.slots = (uint32_t)addr.size();
+        if ((uint64_t)H.L * g.slots > 0x7fffffffull) return fail(RI_ERR_LIMIT, "chunk maps of one batch group exceed the device budget");
+        g.off_addr = put_array(blob, addr);
+        g.off_len = put_array(blob, len);
+        g.off_slot = put_array(blob, text_slot);
+        g.off_out = put_array(blob, text_out);
+        // join levels: groups of consecutive members of one text, until every
+        // text has a single group (group i of the last level is text i)
+        const int alias_bytes = H.L <= 254 ? 1 : 2;
+        if (H.relational) {
+            g.gjoin = g.gupper = cls_group(H, alias_bytes);
+            if (!g.gjoin) return fail(RI_ERR_LIMIT, "interface too large for the batched join");
+        } else {
+            g.gjoin = tile_group(H);
+            if (!g.gjoin) g.gjoin = kJoinGroup;
+            g.gupper = kJoinGroup;
+        }
+        std::vector<uint32_t> mchunk;   // first chunk of each member (level >= 1)
+        uint32_t G = g.gjoin;
+        size_t max_groups = 0;
+        for (int level = 0;; ++level) {
+            std::vector<uint32_t> first, count, gchunk;
+            bool done = true;
+            for (size_t t = 0; t < mfirst.size(); ++t) {
+                const uint32_t f0 = (uint32_t)first.size();
+                uint32_t k = 0;
+                for (uint32_t j = 0; j < mcount[t]; j += G, ++k) {
+                    const uint32_t m = mfirst[t] + j;
+                    first.push_back(m);
+                    count.push_back(std::min(G, mcount[t] - j));
+                    gchunk.push_back(level == 0 ? m : mchunk[m]);
+                }
+                mfirst[t] = f0;
+                mcount[t] = k;
+                done &= k == 1;
+            }
+            BatchLevel lv;
+            lv.ngroups = (uint32_t)first.size();
+            lv.first = put_array(blob, first);
+            lv.count = put_array(blob, count);
+            lv.gchunk = put_array(blob, gchunk);
+            g.levels.push_back(lv);
+            max_groups = std::max<size_t>(max_groups, first.size());
+            mchunk.swap(gchunk);
+            G = g.gupper;
+            if (done) break;
+        }
+        const size_t pairs = (size_t)H.L * g.slots;
+        const size_t row_words = H.relational ? H.W : 1;
+        int rc = conv_config(H, dc, g.opt, cs, g.slots, &g.cc);
+        if (!rc) rc = grow(g.alias, pairs * alias_bytes);
+        if (!rc) rc = grow(g.run_base, (size_t)g.slots * 4);
+        if (!rc) rc = grow(g.run_chunk, pairs * 4);
+        if (!rc) rc = grow(g.run_state, pairs * 4);
+        if (!rc) rc = grow(g.run_final, pairs * 4);
+        for (int i = 0; i < 2 && !rc; ++i) {
+            rc = grow(g.join[i], max_groups * H.L * row_words * 4);
+            if (!rc) rc = grow(g.ncls[i], max_groups * 4);
+        }
+        if (rc) return rc;
+        if (!g.counters) {
+            HIP_TRY(hipMalloc(reinterpret_cast<void **>(&g.counters), 64));
+            HIP_TRY(hipMemset(g.counters, 0, 64));
+        }
+    }
+    int rc = grow(g.desc, blob.size());
+    if (rc) return rc;
+    HIP_TRY(hipMemcpy(g.desc.p, blob.data(), blob.size(), hipMemcpyHostToDevice));
+    return RI_OK;
+}
+
+template <typename T>
+const T *at_off(const BatchGroup &g, size_t off) {
+    return reinterpret_cast<const T *>(static_cast<const uint8_t *>(g.desc.p) + off);
+}
+
+// Enqueue one group's kernels; results[2 * request] = (accept, final state).
+int run_group(ri_batch *b, const BatchGroup &g, hipStream_t stream, int32_t *results) {
+    ri::BatchFinalArgs bf{};
+    bf.ntexts = (uint32_t)g.req.size();
+    bf.text_slot = at_off<uint32_t>(g, g.off_slot);
+    bf.text_out = at_off<uint32_t>(g, g.off_out);
+    bf.results = results;
+    if (g.empty) {
+        HIP_TRY(ri::launch_batch_fill(bf, stream));
+        return RI_OK;
+    }
+    const AlgoHost &H = g.h->algo[g.algo];
+    const AlgoDevice &D = g.h->dev[b->device].algo[g.algo];
+    ri::ScanArgs sa{};
+    sa.text = nullptr;
+    sa.n = 0;
+    sa.cs = g.cs;
+    sa.nchunks = g.slots;
+    sa.chunk_addr = at_off<uint64_t>(g, g.off_addr);
+    sa.chunk_len = at_off<uint32_t>(g, g.off_len);
+    sa.table = D.table;
+    sa.table_bytes = (uint32_t)H.table.size();
+    sa.code = D.code;
+    sa.starts = D.starts;
+    sa.L = H.L;
+    sa.row_bytes = H.K * H.entry_bytes;
+    sa.dead = H.dead;
+    ReachBufs rb{g.alias.p, static_cast<uint32_t *>(g.run_base.p), static_cast<uint32_t *>(g.run_chunk.p),
+                 static_cast<uint32_t *>(g.run_state.p), static_cast<uint32_t *>(g.run_final.p), g.counters};
+    int rc = launch_conv(g.cc, sa, g.opt, rb, stream, nullptr);
+    if (rc) return rc;
+
+    const int alias_bytes = g.cc.long_shape.alias_bytes;
+    ri::FinalArgs fa{};
+    fa.fmask = D.fmask;
+    fa.hash = D.hash;
+    fa.hash_cap = H.hash_cap;
+    fa.final_of_state = D.final_of_state;
+    fa.accept_of_state = D.accept_of_state;
+    fa.counters = g.counters;
+    int cur = 0;
+    if (H.relational) {
+        ri::ClsJoinArgs ca{};
+        ca.alias = g.alias.p;
+        ca.nchunks = g.slots;
+        ca.L = H.L;
+        ca.run_base = rb.run_base;
+        ca.run_final = rb.run_final;
+        ca.content = D.content;
+        ca.span = 1;
+        for (size_t l = 0; l < g.levels.size(); ++l) {
+            const BatchLevel &lv = g.levels[l];
+            ca.G = l == 0 ? g.gjoin : g.gupper;
+            ca.grp_first = at_off<uint32_t>(g, lv.first);
+            ca.grp_count = at_off<uint32_t>(g, lv.count);
+            ca.ngroups = lv.ngroups;
+            ca.member_chunk = l == 0 ? nullptr : at_off<uint32_t>(g, g.levels[l - 1].gchunk);
+            ca.nmembers = l == 0 ? g.slots : g.levels[l - 1].ngroups;
+            ca.ncls_in = l == 0 ? nullptr : static_cast<const uint32_t *>(g.ncls[cur].p);
+            ca.cont_in = l == 0 ? nullptr : static_cast<const uint32_t *>(g.join[cur].p);
+            const int o = l == 0 ? 0 : cur ^ 1;
+            ca.ncls_out = static_cast<uint32_t *>(g.ncls[o].p);
+            ca.cont_out = static_cast<uint32_t *>(g.join[o].p);
+            HIP_TRY(ri::launch_join_cls(ca, (int)H.W, alias_bytes, l == 0, stream));
+            cur = o;
+        }
+        ca.cont_in = static_cast<const uint32_t *>(g.join[cur].p);
+        HIP_TRY(ri::launch_batch_final_cls(bf, fa, ca, (int)H.W, alias_bytes, stream));
+    } else {
+        ri::JoinArgs ja{};
+        ja.converged = true;
+        ja.alias = g.alias.p;
+        ja.run_base = rb.run_base;
+        ja.run_final = rb.run_final;
+        ja.tile_bytes = (int)H.lam_bytes;
+        ja.alias_bytes = alias_bytes;
+        ja.nchunks = g.slots;
+        ja.L = H.L;
+        for (size_t l = 0; l < g.levels.size(); ++l) {
+            const BatchLevel &lv = g.levels[l];
+            ja.G = l == 0 ? g.gjoin : g.gupper;
+            ja.grp_first = at_off<uint32_t>(g, lv.first);
+            ja.grp_count = at_off<uint32_t>(g, lv.count);
+            ja.ngroups = lv.ngroups;
+            const int o = l == 0 ? 0 : cur ^ 1;
+            ja.out = g.join[o].p;
+            if (l == 0) {
+                if (tile_group(H)) HIP_TRY(ri::launch_join0_tile(ja, 0, stream));
+                else HIP_TRY(ri::launch_join0_fun(ja, stream));
+            } else {
+                ja.in = g.join[cur].p;
+                ja.nin = g.levels[l - 1].ngroups;
+                HIP_TRY(ri::launch_joinN_fun(ja, stream));
+            }
+            cur = o;
+        }
+        fa.total = g.join[cur].p;
+        HIP_TRY(ri::launch_batch_final_fun(bf, fa, H.L, stream));
+    }
+    return RI_OK;
+}
+
+void drop_graph(ri_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_results = nullptr;
+}
+
+int check_device(const ri_batch *b) {
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    if (device != b->device) return fail(RI_ERR_ARG, "the batch was created on another device");
+    return RI_OK;
+}
+
+int batch_setup(ri_batch *b, const ri_request *reqs, uint32_t count, uint32_t chunk_bytes) {
+    HIP_TRY(hipGetDevice(&b->device));
+    if (b->device < 0 || b->device >= kMaxDevices) return fail(RI_ERR_DEVICE, "device index out of range");
+    b->reqs.assign(reqs, reqs + count);
+    b->fixed_chunk = chunk_bytes;
+    for (uint32_t i = 0; i < count; ++i) {
+        ri_handle *h = const_cast<ri_handle *>(reqs[i].h);
+        BatchGroup *g = nullptr;
+        for (auto &x : b->groups)
+            if (x.h == h && x.algo == reqs[i].algo) g = &x;
+        if (!g) {
+            b->groups.emplace_back();
+            g = &b->groups.back();
+            g->h = h;
+            g->algo = reqs[i].algo;
+            g->empty = h->A.empty_language;
+        }
+        g->req.push_back(i);
+        b->bytes += reqs[i].n;
+    }
+    for (auto &s : b->side) HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    for (auto &e : b->joins) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto &g : b->groups) {
+        {
+            std::lock_guard<std::mutex> lk(g.h->mu);
+            g.opt = g.h->tuned_valid[g.algo] ? g.h->tuned[g.algo] : g.h->opt;
+            if (!g.empty) {
+                const int rc = ensure_device(g.h, b->device);
+                if (rc) return rc;
+            }
+        }
+        uint64_t bytes = 0;
+        for (uint32_t r : g.req) bytes += b->reqs[r].n;
+        g.cs = chunk_bytes ? chunk_bytes
+                           : std::min(kBatchMaxChunk,
+                                      std::max(kBatchMinChunk, round_up((bytes + kBatchAutoChunkTarget - 1) /
+                                                                            kBatchAutoChunkTarget, 16)));
+        const int rc = plan_group(b, g);
+        if (rc) return rc;
     }
     return RI_OK;
 }
@@ -734,7 +1130,7 @@ int ri_set_option(ri_handle *h, int option, int64_t value) {
         h->opt.converge = (int)value;
         return RI_OK;
     case RI_OPT_WARMUP_BYTES:
-        if (value < 16 || value > (1 << 20) || value % 16) return fail(RI_ERR_ARG, "bad warm-up length");
+        if (value < 16 || value > 256 || value % 16) return fail(RI_ERR_ARG, "bad warm-up length");
         h->opt.warm = (uint32_t)value;
         return RI_OK;
     case RI_OPT_RUNS_PER_LANE:
@@ -830,6 +1226,230 @@ int ri_autotune(ri_handle *h, const uint8_t *text, size_t n, void *stream, int a
         out->runs_per_lane = best.runs_per_lane;
         out->trials = trials;
         out->best_ms = (float)best_ms;
+    }
+    return RI_OK;
+}
+
+int ri_batch_create(const ri_request *reqs, uint32_t count, uint32_t chunk_bytes, ri_batch **out) {
+    if (!out || (count > 0 && !reqs)) return fail(RI_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    if (chunk_bytes % 16) return fail(RI_ERR_ARG, "chunk_bytes must be a multiple of 16");
+    if (chunk_bytes > (1u << 30)) return fail(RI_ERR_ARG, "chunk_bytes too large");
+    for (uint32_t i = 0; i < count; ++i) {
+        const ri_request &q = reqs[i];
+        if (!q.h) return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": NULL handle");
+        if (q.algo < 0 || q.algo >= RI_NUM_ALGOS) return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": unknown algorithm");
+        if (q.reserved != 0) return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": reserved must be 0");
+        if (q.n > 0 && !q.text_dev) return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": NULL text pointer");
+        if (q.n > 0 && (reinterpret_cast<uintptr_t>(q.text_dev) & 15))
+            return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": text must be 16-byte aligned");
+    }
+    ri_batch *b = new ri_batch();
+    const int rc = batch_setup(b, reqs, count, chunk_bytes);
+    if (rc) {
+        ri_batch_free(b);
+        return rc;
+    }
+    *out = b;
+    return RI_OK;
+}
+
+void ri_batch_free(ri_batch *b) {
+    if (!b) return;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(b->device);
+    drop_graph(b);
+    for (auto &g : b->groups) {
+        for (Workspace::Buf *x : {&g.desc, &g.alias, &g.run_base, &g.run_chunk, &g.run_state, &g.run_final,
+                                  &g.join[0], &g.join[1], &g.ncls[0], &g.ncls[1]})
+            release(*x);
+        if (g.counters) (void)hipFree(g.counters);
+    }
+    for (auto s : b->side)
+        if (s) (void)hipStreamDestroy(s);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    for (auto e : b->joins)
+        if (e) (void)hipEventDestroy(e);
+    (void)hipSetDevice(prev);
+    delete b;
+}
+
+int ri_batch_run(ri_batch *b, void *stream_v, int32_t *results_dev) {
+    if (!b || (!results_dev && !b->reqs.empty())) return fail(RI_ERR_ARG, "NULL argument");
+    int rc = check_device(b);
+    if (rc) return rc;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
+    for (const auto &g : b->groups) {
+        rc = run_group(b, g, stream, results_dev);
+        if (rc) return rc;
+    }
+    return RI_OK;
+}
+
+int ri_batch_capture(ri_batch *b, int32_t *results_dev) {
+    if (!b || (!results_dev && !b->reqs.empty())) return fail(RI_ERR_ARG, "NULL argument");
+    int rc = check_device(b);
+    if (rc) return rc;
+    drop_graph(b);
+    hipStream_t cap = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        return fail(RI_ERR_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    }
+    // groups are independent: spread them over concurrent branches
+    e = hipEventRecord(b->fork, cap);
+    for (int k = 0; k < kBatchSide && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->side[k], b->fork, 0);
+    for (size_t i = 0; i < b->groups.size() && e == hipSuccess && rc == RI_OK; ++i)
+        rc = run_group(b, b->groups[i], b->side[i % kBatchSide], results_dev);
+    for (int k = 0; k < kBatchSide && e == hipSuccess; ++k) {
+        e = hipEventRecord(b->joins[k], b->side[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cap, b->joins[k], 0);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cap, &graph);
+    (void)hipStreamDestroy(cap);
+    if (rc || e != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        if (rc) return rc;
+        return fail(RI_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b->graph = graph;
+    e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        drop_graph(b);
+        return fail(RI_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    b->graph_results = results_dev;
+    return RI_OK;
+}
+
+int ri_batch_launch(ri_batch *b, void *stream) {
+    if (!b) return fail(RI_ERR_ARG, "NULL batch");
+    if (!b->exec) return fail(RI_ERR_ARG, "the batch has no captured graph (ri_batch_capture)");
+    int rc = check_device(b);
+    if (rc) return rc;
+    HIP_TRY(hipGraphLaunch(b->exec, reinterpret_cast<hipStream_t>(stream)));
+    return RI_OK;
+}
+
+int ri_batch_get_info(const ri_batch *b, ri_batch_info *out) {
+    if (!b || !out) return fail(RI_ERR_ARG, "NULL argument");
+    std::memset(out, 0, sizeof(*out));
+    out->texts = (uint32_t)b->reqs.size();
+    out->groups = (uint32_t)b->groups.size();
+    out->bytes = b->bytes;
+    for (const auto &g : b->groups) {
+        out->slots += g.slots;
+        out->kernels += g.empty ? 1 : 2 + (uint32_t)g.levels.size() + 1;
+        for (const Workspace::Buf *x : {&g.desc, &g.alias, &g.run_base, &g.run_chunk, &g.run_state, &g.run_final,
+                                        &g.join[0], &g.join[1], &g.ncls[0], &g.ncls[1]})
+            out->device_bytes += x->cap;
+    }
+    out->captured = b->exec != nullptr;
+    return RI_OK;
+}
+
+int ri_batch_get_group(const ri_batch *b, uint32_t index, ri_batch_group *out) {
+    if (!b || !out) return fail(RI_ERR_ARG, "NULL argument");
+    if (index >= b->groups.size()) return fail(RI_ERR_ARG, "group index out of range");
+    const BatchGroup &g = b->groups[index];
+    std::memset(out, 0, sizeof(*out));
+    out->h = g.h;
+    out->algo = g.algo;
+    out->texts = (uint32_t)g.req.size();
+    out->slots = g.slots;
+    out->bytes = g.bytes;
+    out->chunk_bytes = (uint32_t)g.cs;
+    out->warmup_bytes = g.opt.warm;
+    out->runs_per_lane = g.opt.runs_per_lane;
+    out->join_levels = (uint32_t)g.levels.size();
+    out->tuned_ms = g.tuned_ms;
+    return RI_OK;
+}
+
+int ri_batch_autotune(ri_batch *b, void *stream_v, ri_batch_tuning *out) {
+    if (!b) return fail(RI_ERR_ARG, "NULL batch");
+    int rc = check_device(b);
+    if (rc) return rc;
+    drop_graph(b);
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
+    static const uint32_t kChunk[] = {1024, 2048, 4096, 8192, 16384, 65536};
+    static const uint32_t kWarm[] = {32, 64, 128};
+    const size_t ng = b->groups.size();
+    const size_t nr = b->reqs.size();
+    int32_t *dres = nullptr;
+    HIP_TRY(hipMalloc(reinterpret_cast<void **>(&dres), std::max<size_t>(nr, 1) * 8));
+    std::vector<int32_t> ref(nr * 2), got(nr * 2);
+    std::vector<hipEvent_t> ev(ng + 1);
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    std::vector<float> best(ng, 1e30f);
+    std::vector<uint64_t> best_cs(ng);
+    std::vector<uint32_t> best_warm(ng);
+    uint32_t trials = 0;
+    bool have_ref = false;
+    auto cleanup = [&]() {
+        (void)hipFree(dres);
+        for (auto e : ev) (void)hipEventDestroy(e);
+    };
+    for (uint32_t cs : kChunk) {
+        if (b->fixed_chunk && cs != kChunk[0]) break;
+        for (uint32_t w : kWarm) {
+            for (auto &g : b->groups) {
+                g.cs = b->fixed_chunk ? b->fixed_chunk : cs;
+                g.opt.warm = w;
+                rc = g.empty ? RI_OK : plan_group(b, g);
+                if (rc) { cleanup(); return rc; }
+            }
+            std::vector<float> ms(ng, 0.f);
+            for (int it = 0; it < 3 && !rc; ++it) {   // first pass is a warm-up
+                for (size_t i = 0; i < ng && !rc; ++i) {
+                    if (hipEventRecord(ev[i], stream) != hipSuccess) rc = fail(RI_ERR_DEVICE, "hipEventRecord");
+                    if (!rc) rc = run_group(b, b->groups[i], stream, dres);
+                }
+                if (!rc && hipEventRecord(ev[ng], stream) != hipSuccess) rc = fail(RI_ERR_DEVICE, "hipEventRecord");
+                if (!rc && hipStreamSynchronize(stream) != hipSuccess) rc = fail(RI_ERR_DEVICE, "hipStreamSynchronize");
+                for (size_t i = 0; i < ng && !rc && it > 0; ++i) {
+                    float t = 0;
+                    if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) rc = fail(RI_ERR_DEVICE, "hipEventElapsedTime");
+                    ms[i] += t / 2;
+                }
+            }
+            if (!rc && nr && hipMemcpy(got.data(), dres, nr * 8, hipMemcpyDeviceToHost) != hipSuccess)
+                rc = fail(RI_ERR_DEVICE, "hipMemcpy");
+            if (rc) { cleanup(); return rc; }
+            if (!have_ref) {
+                ref = got;
+                have_ref = true;
+            } else if (got != ref) {
+                cleanup();
+                return fail(RI_ERR_DEVICE, "internal: results differ between tuning trials");
+            }
+            ++trials;
+            for (size_t i = 0; i < ng; ++i)
+                if (ms[i] < best[i]) {
+                    best[i] = ms[i];
+                    best_cs[i] = b->groups[i].cs;
+                    best_warm[i] = w;
+                }
+        }
+    }
+    float total = 0;
+    for (size_t i = 0; i < ng; ++i) {
+        BatchGroup &g = b->groups[i];
+        g.cs = best_cs[i];
+        g.opt.warm = best_warm[i];
+        g.tuned_ms = best[i];
+        total += best[i];
+        rc = g.empty ? RI_OK : plan_group(b, g);
+        if (rc) { cleanup(); return rc; }
+    }
+    cleanup();
+    if (out) {
+        out->trials = trials;
+        out->best_ms = total;
     }
     return RI_OK;
 }

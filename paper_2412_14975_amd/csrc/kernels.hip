@@ -101,6 +101,26 @@ __device__ __forceinline__ void load64(uint4 (&b)[4], const uint8_t *p) {
     b[0] = q[0]; b[1] = q[1]; b[2] = q[2]; b[3] = q[3];
 }
 
+// Chunk `chunk` as absolute addresses [b, e), and whether it begins its text
+// (such a chunk is scanned from the initial state only).
+__device__ __forceinline__ void chunk_bounds(const ScanArgs &s, uint32_t chunk, uint64_t &b, uint64_t &e,
+                                             bool &first) {
+    if (s.chunk_addr) {
+        const uint32_t l = s.chunk_len[chunk];
+        b = s.chunk_addr[chunk];
+        e = b + (l & 0x7fffffffu);
+        first = (l >> 31) != 0;
+    } else {
+        const uint64_t o = (uint64_t)chunk * s.cs;
+        const uint64_t t = reinterpret_cast<uint64_t>(s.text);
+        b = t + o;
+        e = t + (o + s.cs < s.n ? o + s.cs : s.n);
+        first = chunk == 0;
+    }
+}
+
+__device__ __forceinline__ const uint8_t *at(uint64_t p) { return reinterpret_cast<const uint8_t *>(p); }
+
 template <int R>
 __device__ __forceinline__ bool any_alive(const uint32_t (&st)[R], uint32_t dead) {
     bool a = false;
@@ -115,19 +135,18 @@ __device__ __forceinline__ bool any_alive(const uint32_t (&st)[R], uint32_t dead
 // ragged tail.  The wave leaves the block loop when no lane has a live run
 // with work left.
 template <typename TE, int R>
-__device__ __forceinline__ void scan_shared(uint32_t (&st)[R], const uint8_t *text, uint64_t p,
-                                            uint64_t end, const TE *tab, const uint16_t *cls,
-                                            uint32_t dead) {
+__device__ __forceinline__ void scan_shared(uint32_t (&st)[R], uint64_t p, uint64_t end, const TE *tab,
+                                            const uint16_t *cls, uint32_t dead) {
     const uint64_t vend = p + ((end - p) & ~(uint64_t)15);
     const uint64_t bend = p + ((end - p) & ~(uint64_t)63);
     uint4 cur[4];
-    if (p < bend) load64(cur, text + p);
+    if (p < bend) load64(cur, at(p));
     for (;;) {
         const bool work = p < bend && any_alive<R>(st, dead);
         if (__ballot(work) == 0) break;
         if (work) {
             uint4 nxt[4];
-            load64(nxt, text + (p + 64 < bend ? p + 64 : p));
+            load64(nxt, at(p + 64 < bend ? p + 64 : p));
 #pragma unroll
             for (int q = 0; q < 4; ++q) step16_shared<TE, R>(st, cur[q], tab, cls);
 #pragma unroll
@@ -136,9 +155,9 @@ __device__ __forceinline__ void scan_shared(uint32_t (&st)[R], const uint8_t *te
         }
     }
     for (; p < vend && any_alive<R>(st, dead); p += 16)
-        step16_shared<TE, R>(st, *reinterpret_cast<const uint4 *>(text + p), tab, cls);
+        step16_shared<TE, R>(st, *reinterpret_cast<const uint4 *>(at(p)), tab, cls);
     for (p = p < vend ? vend : p; p < end && any_alive<R>(st, dead); ++p) {
-        const uint32_t c = cls[text[p]];
+        const uint32_t c = cls[*at(p)];
 #pragma unroll
         for (int r = 0; r < R; ++r) st[r] = next_state<TE>(tab, st[r], c);
     }
@@ -146,13 +165,12 @@ __device__ __forceinline__ void scan_shared(uint32_t (&st)[R], const uint8_t *te
 
 // One run over text[p, end) without wave votes (p .. vend in 16-byte blocks).
 template <typename TE>
-__device__ __forceinline__ uint32_t scan_lane(uint32_t st, const uint8_t *text, uint64_t p,
-                                              uint64_t vend, uint64_t end, const TE *tab,
-                                              const uint16_t *cls, uint32_t dead) {
+__device__ __forceinline__ uint32_t scan_lane(uint32_t st, uint64_t p, uint64_t vend, uint64_t end,
+                                              const TE *tab, const uint16_t *cls, uint32_t dead) {
     uint32_t s1[1] = {st};
     for (; p < vend && s1[0] != dead; p += 16)
-        step16_shared<TE, 1>(s1, *reinterpret_cast<const uint4 *>(text + p), tab, cls);
-    for (p = p < vend ? vend : p; p < end && s1[0] != dead; ++p) s1[0] = next_state<TE>(tab, s1[0], cls[text[p]]);
+        step16_shared<TE, 1>(s1, *reinterpret_cast<const uint4 *>(at(p)), tab, cls);
+    for (p = p < vend ? vend : p; p < end && s1[0] != dead; ++p) s1[0] = next_state<TE>(tab, s1[0], cls[*at(p)]);
     return s1[0];
 }
 
@@ -187,18 +205,16 @@ __global__ void __launch_bounds__(1024) plain_kernel(PlainArgs a) {
         const uint32_t chunk = (job - g * a.chunk_groups) * kWave + lane;
         const bool ok = chunk < a.s.nchunks;
         uint64_t begin = 0, end = 0;
-        if (ok) {
-            begin = (uint64_t)chunk * a.s.cs;
-            end = begin + a.s.cs < a.s.n ? begin + a.s.cs : a.s.n;
-        }
+        bool first = false;
+        if (ok) chunk_bounds(a.s, chunk, begin, end, first);
         uint32_t st[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t s = g * R + r;
-            // chunk 0 is scanned from the initial state only (I_1 = {q0})
-            st[r] = (ok && s < a.s.L && (chunk != 0 || s == 0)) ? a.s.starts[s] : a.s.dead;
+            // the first chunk of a text is scanned from the initial state only (I_1 = {q0})
+            st[r] = (ok && s < a.s.L && (!first || s == 0)) ? a.s.starts[s] : a.s.dead;
         }
-        scan_shared<TE, R>(st, a.s.text, begin, end, tab, cls, a.s.dead);
+        scan_shared<TE, R>(st, begin, end, tab, cls, a.s.dead);
         if (ok) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -225,6 +241,12 @@ __global__ void __launch_bounds__(1024) plain_kernel(PlainArgs a) {
 // 64 distinct states keeps every live start as its own run.  Run slots are
 // allocated with one atomic per group, so the runs of a chunk are
 // consecutive; the alias tile is written out coalesced over chunks.
+// Row strides of the LDS tiles, padded so that a wave reading one column
+// (lanes over starts) hits distinct banks: the stride in 4-byte words is odd.
+template <typename T> __host__ __device__ constexpr uint32_t tile_stride(uint32_t cols) {
+    return cols + (sizeof(T) == 1 ? 4u : sizeof(T) == 2 ? 2u : 1u);
+}
+
 template <typename TE, typename TL, typename TA, int R, bool LDS>
 __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -234,14 +256,18 @@ __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
     stage_tables<TE, LDS>(a.s, smem, tab, cls);
     const uint32_t L = a.s.L;
     const uint32_t CW = a.cw;
+    const uint32_t WS = a.warm < a.s.cs ? a.warm : (uint32_t)a.s.cs;   // staged bytes per chunk
+    const uint32_t TS = tile_stride<TL>(CW), AS = tile_stride<TA>(CW);
     const uint32_t spl = kWave / CW;                   // start sub-groups per wave
     uint8_t *area = smem + tables_lds<TE, LDS>(a.s.table_bytes);
     uint32_t *cstate = reinterpret_cast<uint32_t *>(area);                // [CW][64] class states
     uint32_t *dcount = cstate + (size_t)CW * kWave;                       // [CW] runs per chunk (+ spill flag)
     uint32_t *dfirst = dcount + CW;                                       // [CW] first run (group-relative)
-    TL *tile = reinterpret_cast<TL *>(dfirst + CW);                       // [L][CW] state ids
+    uint16_t *scode = reinterpret_cast<uint16_t *>(dfirst + CW);          // [WS][CW] byte codes
+    TL *tile = reinterpret_cast<TL *>(
+        reinterpret_cast<uint8_t *>(scode) + (((size_t)WS * CW * 2 + 15) & ~(size_t)15));   // [L][TS]
     TA *atile = reinterpret_cast<TA *>(
-        reinterpret_cast<uint8_t *>(tile) + (((size_t)L * CW * sizeof(TL) + 15) & ~(size_t)15));  // [L][CW]
+        reinterpret_cast<uint8_t *>(tile) + (((size_t)L * TS * sizeof(TL) + 15) & ~(size_t)15));  // [L][AS]
     const uint32_t lane = threadIdx.x % kWave;
     const uint32_t wave = threadIdx.x / kWave;
     const uint32_t nwaves = blockDim.x / kWave;
@@ -254,18 +280,40 @@ __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
     for (uint32_t cg = blockIdx.x; cg < a.chunk_groups; cg += gridDim.x) {
         __syncthreads();   // tables staged / previous group done with the tiles
         if (threadIdx.x == 0) s_job = 0;
+        // stage the warm-up bytes of the group's chunks as byte codes,
+        // step-major so that lanes (chunks) read consecutive entries
+        for (uint32_t i = threadIdx.x; i < CW * (WS / 16); i += blockDim.x) {
+            const uint32_t c = i % CW, q = i / CW;
+            const uint32_t chunk = cg * CW + c;
+            uint32_t w4[4] = {0, 0, 0, 0};
+            if (chunk < a.s.nchunks) {
+                uint64_t b, e;
+                bool first;
+                chunk_bounds(a.s, chunk, b, e, first);
+                const uint64_t b0 = b + q * 16;
+                if (b0 + 16 <= e) {
+                    const uint4 v = *reinterpret_cast<const uint4 *>(at(b0));
+                    w4[0] = v.x; w4[1] = v.y; w4[2] = v.z; w4[3] = v.w;
+                } else {
+                    for (uint32_t k = 0; b0 + k < e; ++k) w4[k / 4] |= (uint32_t)*at(b0 + k) << (8 * (k % 4));
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) scode[(q * 16 + k) * CW + c] = cls[(w4[k / 4] >> (8 * (k % 4))) & 0xffu];
+        }
         __syncthreads();
 
-        // warm-up of every start
+        // warm-up of every start from the staged codes
         {
             const uint32_t chunk = cg * CW + col;
             const bool ok = chunk < a.s.nchunks;
-            uint64_t begin = 0, end = 0;
+            uint32_t wlen = 0;
+            bool first = false;
             if (ok) {
-                begin = (uint64_t)chunk * a.s.cs;
-                end = begin + a.s.cs < a.s.n ? begin + a.s.cs : a.s.n;
+                uint64_t b, e;
+                chunk_bounds(a.s, chunk, b, e, first);
+                wlen = e - b < WS ? (uint32_t)(e - b) : WS;
             }
-            const uint64_t wend = begin + a.warm < end ? begin + a.warm : end;
             for (;;) {
                 uint32_t g = 0;
                 if (lane == 0) g = atomicAdd(&s_job, 1u);
@@ -276,13 +324,29 @@ __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const uint32_t s = s0 + r;
-                    st[r] = (ok && s < L && (chunk != 0 || s == 0)) ? a.s.starts[s] : a.s.dead;
+                    st[r] = (ok && s < L && (!first || s == 0)) ? a.s.starts[s] : a.s.dead;
                 }
-                scan_shared<TE, R>(st, a.s.text, begin, wend, tab, cls, a.s.dead);
+                for (uint32_t j0 = 0; j0 < WS; j0 += 16) {
+                    if (__ballot(any_alive<R>(st, a.s.dead) && j0 < wlen) == 0) break;
+                    if (j0 + 16 <= wlen) {
+#pragma unroll
+                        for (int k = 0; k < 16; ++k) {
+                            const uint32_t c = scode[(j0 + k) * CW + col];
+#pragma unroll
+                            for (int r = 0; r < R; ++r) st[r] = next_state<TE>(tab, st[r], c);
+                        }
+                    } else {
+                        for (uint32_t j = j0; j < wlen; ++j) {
+                            const uint32_t c = scode[j * CW + col];
+#pragma unroll
+                            for (int r = 0; r < R; ++r) st[r] = next_state<TE>(tab, st[r], c);
+                        }
+                    }
+                }
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const uint32_t s = s0 + r;
-                    if (s < L) tile[s * CW + col] = st[r] == a.s.dead ? all_ones<TL>() : (TL)(st[r] / a.s.row_bytes);
+                    if (s < L) tile[s * TS + col] = st[r] == a.s.dead ? all_ones<TL>() : (TL)(st[r] / a.s.row_bytes);
                 }
             }
         }
@@ -294,10 +358,9 @@ __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
             bool spill = false;
             for (uint32_t s0 = 0; s0 < L && !spill; s0 += kWave) {
                 const uint32_t s = s0 + lane;
-                const uint32_t v = s < L ? (uint32_t)tile[s * CW + c] : (uint32_t)all_ones<TL>();
+                const uint32_t v = s < L ? (uint32_t)tile[s * TS + c] : (uint32_t)all_ones<TL>();
                 const bool live = v != (uint32_t)all_ones<TL>();
                 uint32_t al = (uint32_t)all_ones<TA>();
-                // existing classes
                 for (uint32_t i = 0; i < D; ++i)
                     if (live && v == cstate[c * kWave + i]) al = i;
                 uint64_t open = __ballot(live && al == (uint32_t)all_ones<TA>());
@@ -311,16 +374,16 @@ __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
                     ++D;
                     open &= ~same;
                 }
-                if (!spill && s < L) atile[s * CW + c] = (TA)al;
+                if (!spill && s < L) atile[s * AS + c] = (TA)al;
             }
             if (spill) {
                 // every live start is its own run, numbered in start order
                 D = 0;
                 for (uint32_t s0 = 0; s0 < L; s0 += kWave) {
                     const uint32_t s = s0 + lane;
-                    const bool live = s < L && tile[s * CW + c] != all_ones<TL>();
+                    const bool live = s < L && tile[s * TS + c] != all_ones<TL>();
                     const uint64_t m = __ballot(live);
-                    if (s < L) atile[s * CW + c] = live ? (TA)(D + __builtin_popcountll(m & lane_lt)) : all_ones<TA>();
+                    if (s < L) atile[s * AS + c] = live ? (TA)(D + __builtin_popcountll(m & lane_lt)) : all_ones<TA>();
                     D += __builtin_popcountll(m);
                 }
             }
@@ -359,10 +422,10 @@ __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
                 for (uint32_t s0 = 0; s0 < L; s0 += kWave) {
                     const uint32_t s = s0 + lane;
                     if (s < L) {
-                        const TA al = atile[s * CW + c];
+                        const TA al = atile[s * AS + c];
                         if (al != all_ones<TA>()) {
                             a.run_chunk[first + al] = chunk;
-                            a.run_state[first + al] = tile[s * CW + c];
+                            a.run_state[first + al] = tile[s * TS + c];
                         }
                     }
                 }
@@ -373,7 +436,7 @@ __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
         for (uint32_t i = threadIdx.x; i < L * CW; i += blockDim.x) {
             const uint32_t s = i / CW, c = i - s * CW;
             const uint32_t chunk = cg * CW + c;
-            if (chunk < a.s.nchunks) alias[(uint64_t)s * a.s.nchunks + chunk] = atile[i];
+            if (chunk < a.s.nchunks) alias[(uint64_t)s * a.s.nchunks + chunk] = atile[s * AS + c];
         }
     }
 }
@@ -414,8 +477,9 @@ __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
             p[r] = vend[r] = end[r] = 0;
             st[r] = dead;
             if (ok[r]) {
-                const uint64_t b = (uint64_t)a.run_chunk[i] * a.s.cs;
-                const uint64_t e = b + a.s.cs < a.s.n ? b + a.s.cs : a.s.n;
+                uint64_t b, e;
+                bool first;
+                chunk_bounds(a.s, a.run_chunk[i], b, e, first);
                 p[r] = b + a.warm < e ? b + a.warm : e;
                 vend[r] = p[r] + ((e - p[r]) & ~(uint64_t)15);
                 end[r] = e;
@@ -435,7 +499,7 @@ __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
             bend[r] = p[r] + ((end[r] - p[r]) & ~(uint64_t)63);
             pk[r] = false;
             parked[r] = dead;
-            if (ok[r] && p[r] < bend[r]) load64(cur[r], a.s.text + p[r]);
+            if (ok[r] && p[r] < bend[r]) load64(cur[r], at(p[r]));
             else cur[r][0] = cur[r][1] = cur[r][2] = cur[r][3] = make_uint4(0, 0, 0, 0);
         }
         for (;;) {
@@ -457,7 +521,7 @@ __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
                 for (int r = 0; r < R; ++r) {
                     act[r] = ok[r] && !pk[r] && st[r] != dead;
                     const uint64_t q = act[r] && p[r] + 64 < bend[r] ? p[r] + 64 : p[r];
-                    if (act[r]) load64(nxt[r], a.s.text + q);
+                    if (act[r]) load64(nxt[r], at(q));
                     else nxt[r][0] = nxt[r][1] = nxt[r][2] = nxt[r][3] = make_uint4(0, 0, 0, 0);
                 }
 #pragma unroll
@@ -482,7 +546,7 @@ __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (ok[r]) {
-                const uint32_t f = scan_lane<TE>(st[r], a.s.text, p[r], vend[r], end[r], tab, cls, dead);
+                const uint32_t f = scan_lane<TE>(st[r], p[r], vend[r], end[r], tab, cls, dead);
                 a.run_final[job * per_job + r * kWave + lane] = f == dead ? kNoState : f / a.s.row_bytes;
             }
         }
@@ -598,8 +662,8 @@ __global__ void __launch_bounds__(256) join0_tile_kernel(JoinArgs a, View view) 
     extern __shared__ __align__(16) uint32_t lt[];
     const uint32_t G = a.G;
     const uint32_t grp = blockIdx.x;
-    const uint32_t c0 = grp * G;
-    const uint32_t gn = c0 + G < a.nchunks ? G : a.nchunks - c0;
+    const uint32_t c0 = a.grp_first ? a.grp_first[grp] : grp * G;
+    const uint32_t gn = a.grp_first ? a.grp_count[grp] : c0 + G < a.nchunks ? G : a.nchunks - c0;
     for (uint32_t i = threadIdx.x; i < a.L * G; i += blockDim.x) {
         const uint32_t s = i / G, c = i - s * G;
         lt[i] = c < gn ? view.get(s, c0 + c) : kNoState;
@@ -666,24 +730,26 @@ __global__ void __launch_bounds__(256) join_cls_kernel(ClsJoinArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     uint32_t *scont = reinterpret_cast<uint32_t *>(smem);                    // [G][kClsStage][W]
     uint32_t *sncls = scont + (size_t)a.G * kClsStage * W;                    // [G]
-    TA *salias = reinterpret_cast<TA *>(sncls + a.G);                         // [L][G]
+    TA *salias = reinterpret_cast<TA *>(sncls + a.G);                         // [L][GS]
     const uint32_t G = a.G, L = a.L;
+    const uint32_t GS = tile_stride<TA>(G);
     const uint32_t grp = blockIdx.x;
-    const uint32_t m0 = grp * G;
-    const uint32_t gn = m0 + G < a.nmembers ? G : a.nmembers - m0;
+    const uint32_t m0 = a.grp_first ? a.grp_first[grp] : grp * G;
+    const uint32_t gn = a.grp_first ? a.grp_count[grp] : m0 + G < a.nmembers ? G : a.nmembers - m0;
     const TA *alias = reinterpret_cast<const TA *>(a.alias);
 
-    // member k of the group: first chunk (m0 + k) * span
+    // member k of the group: first chunk (m0 + k) * span, or as listed
     for (uint32_t i = threadIdx.x; i < G; i += blockDim.x) sncls[i] = 0;
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < L * G; i += blockDim.x) {
         const uint32_t t = i / G, k = i - t * G;
         TA v = all_ones<TA>();
         if (k < gn) {
-            v = alias[(uint64_t)t * a.nchunks + (uint64_t)(m0 + k) * a.span];
+            const uint64_t c = a.member_chunk ? a.member_chunk[m0 + k] : (uint64_t)(m0 + k) * a.span;
+            v = alias[(uint64_t)t * a.nchunks + c];
             if (LEVEL0 && v != all_ones<TA>()) atomicMax(&sncls[k], (uint32_t)v + 1);
         }
-        salias[i] = v;
+        salias[t * GS + k] = v;
     }
     if (!LEVEL0)
         for (uint32_t k = threadIdx.x; k < gn; k += blockDim.x) sncls[k] = a.ncls_in[m0 + k];
@@ -725,7 +791,7 @@ __global__ void __launch_bounds__(256) join_cls_kernel(ClsJoinArgs a) {
                 const uint32_t t = t0 + lane;
                 const uint32_t word = __shfl(xw, (int)((t0 + lane) / 32 < (uint32_t)W ? (t0 + lane) / 32 : 0));
                 const bool in = t < L && ((word >> (t & 31)) & 1u);
-                const TA b = in ? salias[t * G + k] : all_ones<TA>();
+                const TA b = in ? salias[t * GS + k] : all_ones<TA>();
                 if (b != all_ones<TA>() && (uint32_t)b < kClsStage) hit |= 1u << b;
                 // classes beyond the staged ones: OR their contents lane by lane
                 uint64_t big = __ballot(b != all_ones<TA>() && (uint32_t)b >= kClsStage);
@@ -747,48 +813,6 @@ __global__ void __launch_bounds__(256) join_cls_kernel(ClsJoinArgs a) {
         if (lane < (uint32_t)W) a.cont_out[((uint64_t)grp * L + cls) * W + lane] = xw;
     }
     if (threadIdx.x == 0) a.ncls_out[grp] = ncls0;
-}
-
-// Row of start 0 of the single remaining relation: class alias[0][chunk 0].
-template <int W, typename TA>
-__global__ void finalize_cls_kernel(FinalArgs f, ClsJoinArgs a) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const TA c0 = reinterpret_cast<const TA *>(a.alias)[0];
-    uint32_t x[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) x[w] = 0;
-    if (c0 != all_ones<TA>()) {
-        const uint32_t *row = a.cont_in + (uint64_t)c0 * W;
-#pragma unroll
-        for (int w = 0; w < W; ++w) x[w] = row[w];
-    }
-    uint32_t acc = 0, any = 0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-        acc |= x[w] & f.fmask[w];
-        any |= x[w];
-    }
-    int32_t fin = -1;
-    if (any) {
-        fin = -3;
-        uint32_t h = 2166136261u;
-#pragma unroll
-        for (int w = 0; w < W; ++w) { h ^= x[w]; h *= 16777619u; }
-        uint32_t slot = h & (f.hash_cap - 1);
-        for (uint32_t probe = 0; probe < f.hash_cap; ++probe) {
-            const uint32_t *e = f.hash + (uint64_t)slot * (W + 1);
-            const int32_t val = (int32_t)e[W];
-            if (val == -2) break;
-            bool eq = true;
-#pragma unroll
-            for (int w = 0; w < W; ++w) eq &= e[w] == x[w];
-            if (eq) { fin = val; break; }
-            slot = (slot + 1) & (f.hash_cap - 1);
-        }
-    }
-    f.result[0] = acc != 0;
-    f.result[1] = fin;
-    f.counters[0] = 0; f.counters[1] = 0; f.counters[2] = 0; f.counters[3] = 0;
 }
 
 // Level >= 1: thread per (group of G relations, row s).
@@ -831,11 +855,11 @@ __global__ void __launch_bounds__(256) joinN_rel_kernel(JoinArgs a) {
 template <class View>
 __global__ void __launch_bounds__(256) join0_fun_kernel(JoinArgs a, View view) {
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t ngroups = (a.nchunks + a.G - 1) / a.G;
+    const uint32_t ngroups = a.grp_first ? a.ngroups : (a.nchunks + a.G - 1) / a.G;
     if (tid >= (uint64_t)ngroups * a.L) return;
     const uint32_t grp = (uint32_t)(tid / a.L), s = (uint32_t)(tid % a.L);
-    const uint32_t c0 = grp * a.G;
-    const uint32_t c1 = c0 + a.G < a.nchunks ? c0 + a.G : a.nchunks;
+    const uint32_t c0 = a.grp_first ? a.grp_first[grp] : grp * a.G;
+    const uint32_t c1 = a.grp_first ? c0 + a.grp_count[grp] : c0 + a.G < a.nchunks ? c0 + a.G : a.nchunks;
     uint32_t v = view.get(s, c0);
     for (uint32_t c = c0 + 1; c < c1 && v != kNoState; ++c) v = view.get(v, c);
     reinterpret_cast<int32_t *>(a.out)[tid] = v == kNoState ? -1 : (int32_t)v;
@@ -843,12 +867,12 @@ __global__ void __launch_bounds__(256) join0_fun_kernel(JoinArgs a, View view) {
 
 __global__ void __launch_bounds__(256) joinN_fun_kernel(JoinArgs a) {
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t ngroups = (a.nin + a.G - 1) / a.G;
+    const uint32_t ngroups = a.grp_first ? a.ngroups : (a.nin + a.G - 1) / a.G;
     if (tid >= (uint64_t)ngroups * a.L) return;
     const uint32_t grp = (uint32_t)(tid / a.L), s = (uint32_t)(tid % a.L);
     const int32_t *in = reinterpret_cast<const int32_t *>(a.in);
-    const uint32_t k0 = grp * a.G;
-    const uint32_t k1 = k0 + a.G < a.nin ? k0 + a.G : a.nin;
+    const uint32_t k0 = a.grp_first ? a.grp_first[grp] : grp * a.G;
+    const uint32_t k1 = a.grp_first ? k0 + a.grp_count[grp] : k0 + a.G < a.nin ? k0 + a.G : a.nin;
     int32_t v = in[(uint64_t)k0 * a.L + s];
     for (uint32_t k = k0 + 1; k < k1 && v >= 0; ++k) v = in[(uint64_t)k * a.L + v];
     reinterpret_cast<int32_t *>(a.out)[tid] = v;
@@ -881,36 +905,91 @@ __device__ __forceinline__ void reset_counters(uint32_t *c) {
     c[0] = 0; c[1] = 0; c[2] = 0; c[3] = 0;
 }
 
+// Acceptance and final state of the union content x of the relation row of
+// the initial state: accept iff x meets the final states of N', final state =
+// canonical minimal-DFA id stored under x in the hash table (-1: x empty).
 template <int W>
-__global__ void finalize_rel_kernel(FinalArgs a) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const uint32_t *row = reinterpret_cast<const uint32_t *>(a.total);   // row 0
-    uint32_t x[W];
+__device__ __forceinline__ void decide(const uint32_t (&x)[W], const FinalArgs &f, int32_t *res) {
     uint32_t acc = 0, any = 0;
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-        x[w] = row[w];
-        acc |= x[w] & a.fmask[w];
+        acc |= x[w] & f.fmask[w];
         any |= x[w];
     }
     int32_t fin = -1;
     if (any) {
         fin = -3;   // not found: cannot happen for a reachable subset
-        uint32_t slot = hash_words<W>(x) & (a.hash_cap - 1);
-        for (uint32_t probe = 0; probe < a.hash_cap; ++probe) {
-            const uint32_t *e = a.hash + (uint64_t)slot * (W + 1);
+        uint32_t slot = hash_words<W>(x) & (f.hash_cap - 1);
+        for (uint32_t probe = 0; probe < f.hash_cap; ++probe) {
+            const uint32_t *e = f.hash + (uint64_t)slot * (W + 1);
             const int32_t val = (int32_t)e[W];
             if (val == -2) break;   // empty slot
             bool eq = true;
 #pragma unroll
             for (int w = 0; w < W; ++w) eq &= e[w] == x[w];
             if (eq) { fin = val; break; }
-            slot = (slot + 1) & (a.hash_cap - 1);
+            slot = (slot + 1) & (f.hash_cap - 1);
         }
     }
-    a.result[0] = acc != 0;
-    a.result[1] = fin;
+    res[0] = acc != 0;
+    res[1] = fin;
+}
+
+template <int W>
+__device__ __forceinline__ void load_row(uint32_t (&x)[W], const uint32_t *row) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = row ? row[w] : 0u;
+}
+
+template <int W>
+__global__ void finalize_rel_kernel(FinalArgs a) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint32_t x[W];
+    load_row<W>(x, reinterpret_cast<const uint32_t *>(a.total));   // row 0
+    decide<W>(x, a, a.result);
     reset_counters(a.counters);
+}
+
+// Row of start 0 of the single remaining class-partitioned relation: the
+// class alias[0][chunk 0].
+template <int W, typename TA>
+__global__ void finalize_cls_kernel(FinalArgs f, ClsJoinArgs a) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const TA c0 = reinterpret_cast<const TA *>(a.alias)[0];
+    uint32_t x[W];
+    load_row<W>(x, c0 != all_ones<TA>() ? a.cont_in + (uint64_t)c0 * W : nullptr);
+    decide<W>(x, f, f.result);
+    reset_counters(f.counters);
+}
+
+// Batch: thread per text; group t of the last level holds text t's relation.
+template <int W, typename TA>
+__global__ void batch_final_cls_kernel(BatchFinalArgs b, FinalArgs f, ClsJoinArgs a) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) reset_counters(f.counters);
+    if (t >= b.ntexts) return;
+    const TA c0 = reinterpret_cast<const TA *>(a.alias)[b.text_slot[t]];   // start 0's class
+    uint32_t x[W];
+    load_row<W>(x, c0 != all_ones<TA>() ? a.cont_in + ((uint64_t)t * a.L + c0) * W : nullptr);
+    decide<W>(x, f, b.results + (uint64_t)b.text_out[t] * 2);
+}
+
+__global__ void batch_final_fun_kernel(BatchFinalArgs b, FinalArgs f, uint32_t L) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) reset_counters(f.counters);
+    if (t >= b.ntexts) return;
+    const int32_t v = reinterpret_cast<const int32_t *>(f.total)[(uint64_t)t * L];
+    int32_t *res = b.results + (uint64_t)b.text_out[t] * 2;
+    res[0] = v >= 0 ? (int32_t)f.accept_of_state[v] : 0;
+    res[1] = v >= 0 ? f.final_of_state[v] : -1;
+}
+
+__global__ void batch_fill_kernel(BatchFinalArgs b) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= b.ntexts) return;
+    int32_t *res = b.results + (uint64_t)b.text_out[t] * 2;
+    res[0] = 0;
+    res[1] = -1;
 }
 
 __global__ void finalize_fun_kernel(FinalArgs a) {
@@ -1003,12 +1082,15 @@ hipError_t launch_warm(const WarmArgs &a, const KernelShape &k, int grid, size_t
     });
 }
 
-size_t warm_lds_bytes(const KernelShape &k, uint32_t L, uint32_t table_bytes, uint32_t cw) {
+size_t warm_lds_bytes(const KernelShape &k, uint32_t L, uint32_t table_bytes, uint32_t cw, uint32_t ws) {
     const size_t tables = (k.table_in_lds ? table_bytes : 0) + 512;
     const size_t head = (size_t)cw * kWave * 4 + (size_t)cw * 8;
-    const size_t tile = ((size_t)L * cw * k.tile_bytes + 15) & ~(size_t)15;
-    const size_t atile = (size_t)L * cw * k.alias_bytes;
-    return tables + head + tile + atile;
+    const size_t codes = ((size_t)ws * cw * 2 + 15) & ~(size_t)15;
+    const uint32_t ts = k.tile_bytes == 2 ? tile_stride<uint16_t>(cw) : tile_stride<uint32_t>(cw);
+    const uint32_t as = k.alias_bytes == 1 ? tile_stride<uint8_t>(cw) : tile_stride<uint16_t>(cw);
+    const size_t tile = ((size_t)L * ts * k.tile_bytes + 15) & ~(size_t)15;
+    const size_t atile = (size_t)L * as * k.alias_bytes;
+    return tables + head + codes + tile + atile;
 }
 
 hipError_t launch_long(const LongArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st) {
@@ -1060,7 +1142,7 @@ hipError_t launch_join0_rel(const JoinArgs &a, int W, hipStream_t s) {
 }
 
 hipError_t launch_join0_tile(const JoinArgs &a, int W, hipStream_t s) {
-    const uint32_t ngroups = (a.nchunks + a.G - 1) / a.G;
+    const uint32_t ngroups = a.grp_first ? a.ngroups : (a.nchunks + a.G - 1) / a.G;
     const size_t lds = (size_t)a.L * a.G * 4;
     return with_view(a, [&](auto view) {
         if (W == 0) {
@@ -1084,7 +1166,7 @@ hipError_t launch_joinN_rel(const JoinArgs &a, int W, hipStream_t s) {
 }
 
 hipError_t launch_join0_fun(const JoinArgs &a, hipStream_t s) {
-    const uint32_t ngroups = (a.nchunks + a.G - 1) / a.G;
+    const uint32_t ngroups = a.grp_first ? a.ngroups : (a.nchunks + a.G - 1) / a.G;
     const uint32_t nb = blocks_for((uint64_t)ngroups * a.L, 256);
     return with_view(a, [&](auto view) {
         hipLaunchKernelGGL((join0_fun_kernel<decltype(view)>), dim3(nb), dim3(256), 0, s, a, view);
@@ -1093,7 +1175,7 @@ hipError_t launch_join0_fun(const JoinArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_joinN_fun(const JoinArgs &a, hipStream_t s) {
-    const uint32_t ngroups = (a.nin + a.G - 1) / a.G;
+    const uint32_t ngroups = a.grp_first ? a.ngroups : (a.nin + a.G - 1) / a.G;
     const uint32_t nb = blocks_for((uint64_t)ngroups * a.L, 256);
     hipLaunchKernelGGL(joinN_fun_kernel, dim3(nb), dim3(256), 0, s, a);
     return hipGetLastError();
@@ -1108,11 +1190,12 @@ hipError_t launch_materialize(const JoinArgs &a, int32_t *out, hipStream_t s) {
 }
 
 size_t cls_join_lds(const ClsJoinArgs &a, int W, int alias_bytes) {
-    return (size_t)a.G * kClsStage * W * 4 + (size_t)a.G * 4 + (((size_t)a.L * a.G * alias_bytes + 15) & ~(size_t)15);
+    const uint32_t gs = alias_bytes == 1 ? tile_stride<uint8_t>(a.G) : tile_stride<uint16_t>(a.G);
+    return (size_t)a.G * kClsStage * W * 4 + (size_t)a.G * 4 + (((size_t)a.L * gs * alias_bytes + 15) & ~(size_t)15);
 }
 
 hipError_t launch_join_cls(const ClsJoinArgs &a, int W, int alias_bytes, bool level0, hipStream_t s) {
-    const uint32_t ngroups = (a.nmembers + a.G - 1) / a.G;
+    const uint32_t ngroups = a.grp_first ? a.ngroups : (a.nmembers + a.G - 1) / a.G;
     const size_t lds = cls_join_lds(a, W, alias_bytes);
     return dispatch_ta(alias_bytes, [&](auto ta) {
         return dispatch_b(level0, [&](auto l0) {
@@ -1142,6 +1225,28 @@ hipError_t launch_finalize_rel(const FinalArgs &a, int W, hipStream_t s) {
 
 hipError_t launch_finalize_fun(const FinalArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(finalize_fun_kernel, dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_final_cls(const BatchFinalArgs &b, const FinalArgs &f, const ClsJoinArgs &a, int W,
+                                  int alias_bytes, hipStream_t s) {
+    const uint32_t blocks = blocks_for(b.ntexts ? b.ntexts : 1, 256);
+    return dispatch_ta(alias_bytes, [&](auto ta) {
+#define CALLBC(w) hipLaunchKernelGGL((batch_final_cls_kernel<w, decltype(ta)>), dim3(blocks), dim3(256), 0, s, b, f, a);
+        RI_DISPATCH_W(W, CALLBC)
+#undef CALLBC
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_batch_final_fun(const BatchFinalArgs &b, const FinalArgs &f, uint32_t L, hipStream_t s) {
+    hipLaunchKernelGGL(batch_final_fun_kernel, dim3(blocks_for(b.ntexts ? b.ntexts : 1, 256)), dim3(256), 0, s,
+                       b, f, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_fill(const BatchFinalArgs &b, hipStream_t s) {
+    hipLaunchKernelGGL(batch_fill_kernel, dim3(blocks_for(b.ntexts ? b.ntexts : 1, 256)), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 

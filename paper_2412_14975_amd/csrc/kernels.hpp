@@ -10,11 +10,16 @@ namespace ri {
 constexpr uint32_t kNoState = 0xFFFFFFFFu;   // "no run" in run_final / materialized maps
 
 // Text, chunking and chunk-automaton tables shared by every reach kernel.
+// One text: chunk i = text[i*cs, min((i+1)*cs, n)).  A batch of texts:
+// chunk_addr/chunk_len describe every chunk slot (absolute address, length
+// in the low 31 bits, bit 31 = first chunk of its text; length 0 = unused).
 struct ScanArgs {
-    const uint8_t *text;       // n bytes, 16-byte aligned
+    const uint8_t *text;       // n bytes, 16-byte aligned (one text)
     uint64_t n;
-    uint64_t cs;               // chunk size, multiple of 16
-    uint32_t nchunks;
+    uint64_t cs;               // chunk size, multiple of 16 (batch: the largest chunk)
+    uint32_t nchunks;          // chunks (batch: slots)
+    const uint64_t *chunk_addr;   // batch only, else nullptr
+    const uint32_t *chunk_len;    // batch only
     const void *table;         // (nstates + 1) rows of K entries, row nstates = dead row;
                                // an entry is the BYTE offset of the next state's row
     uint32_t table_bytes;      // padded to 16
@@ -49,7 +54,7 @@ hipError_t launch_plain(const PlainArgs &a, const KernelShape &k, int grid, size
 constexpr uint32_t kDedupCap = 32;   // distinct states searched per chunk
 struct WarmArgs {
     ScanArgs s;
-    uint32_t warm;             // bytes scanned by every run before merging (multiple of 16)
+    uint32_t warm;             // bytes scanned by every run before merging (multiple of 16, <= 256)
     uint32_t cw;               // chunks per group: power of two <= 64
     uint32_t chunk_groups;     // ceil(nchunks / cw)
     void *alias;               // [L][nchunks] local run index, all-ones = no run
@@ -59,7 +64,7 @@ struct WarmArgs {
     uint32_t *counters;        // [1] runs allocated
 };
 hipError_t launch_warm(const WarmArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st);
-size_t warm_lds_bytes(const KernelShape &k, uint32_t L, uint32_t table_bytes, uint32_t cw);
+size_t warm_lds_bytes(const KernelShape &k, uint32_t L, uint32_t table_bytes, uint32_t cw, uint32_t ws);
 
 // ---- converging reach, step 2: the merged runs to the chunk end ----
 struct LongArgs {
@@ -92,6 +97,9 @@ struct JoinArgs {
     void *out;                 // [nout][L] (int32) or [nout][L][W] (uint32)
     uint32_t L;
     uint32_t G;                // members per group
+    const uint32_t *grp_first;  // batch: explicit level-0 groups (see ClsJoinArgs), else nullptr
+    const uint32_t *grp_count;
+    uint32_t ngroups;
 };
 hipError_t launch_join0_rel(const JoinArgs &a, int W, hipStream_t s);
 // level 0 with the group's chunk maps staged in LDS (L * G * 4 bytes); W = 0 for functions
@@ -120,6 +128,13 @@ struct ClsJoinArgs {
     const uint32_t *cont_in;   // level >= 1: [nmembers][L][W]; finalize: the last relation
     uint32_t *ncls_out;        // [ngroups]
     uint32_t *cont_out;        // [ngroups][L][W]
+    // batch: explicit groups (members [grp_first[g], grp_first[g] + grp_count[g]),
+    // count <= G) and the first chunk of each member; nullptr = fixed groups of
+    // G consecutive members, member m starting at chunk m * span
+    const uint32_t *grp_first;
+    const uint32_t *grp_count;
+    const uint32_t *member_chunk;
+    uint32_t ngroups;          // with explicit groups
 };
 size_t cls_join_lds(const ClsJoinArgs &a, int W, int alias_bytes);
 hipError_t launch_join_cls(const ClsJoinArgs &a, int W, int alias_bytes, bool level0, hipStream_t s);
@@ -137,5 +152,20 @@ struct FinalArgs {
 hipError_t launch_finalize_rel(const FinalArgs &a, int W, hipStream_t s);
 hipError_t launch_finalize_fun(const FinalArgs &a, hipStream_t s);
 hipError_t launch_finalize_cls(const FinalArgs &f, const ClsJoinArgs &a, int W, int alias_bytes, hipStream_t s);
+
+// Batch results, one per text, from the last join level (one group per
+// text, in text order): a class-partitioned relation or a function.
+struct BatchFinalArgs {
+    uint32_t ntexts;
+    const uint32_t *text_slot;   // first chunk slot of each text
+    const uint32_t *text_out;    // result row of each text
+    int32_t *results;            // [rows][2]: accept, final state
+};
+hipError_t launch_batch_final_cls(const BatchFinalArgs &b, const FinalArgs &f, const ClsJoinArgs &a, int W,
+                                  int alias_bytes, hipStream_t s);
+// f.total: [ntexts][L] functions
+hipError_t launch_batch_final_fun(const BatchFinalArgs &b, const FinalArgs &f, uint32_t L, hipStream_t s);
+// results of texts whose automaton accepts nothing: (0, -1)
+hipError_t launch_batch_fill(const BatchFinalArgs &b, hipStream_t s);
 
 }  // namespace ri

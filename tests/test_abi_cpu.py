@@ -72,6 +72,33 @@ def test_null_and_bad_arguments():
     ri.ri_free(None)
 
 
+def test_batch_argument_checks_before_any_device_call():
+    """ri_batch_create validates every request on the host and returns
+    RI_ERR_ARG before touching a device."""
+    lib = ri.binding.lib()
+    Req = ri.binding.ri_request
+    out = ctypes.c_void_p()
+    hh = ri.ri_build(b"ab*")
+    try:
+        def create(reqs, chunk_bytes=0):
+            arr = (Req * max(1, len(reqs)))(*reqs)
+            return lib.ri_batch_create(arr, len(reqs), chunk_bytes, ctypes.byref(out))
+        assert create([Req(None, 0x1000, 16, 0, 0)]) == ri.binding.RI_ERR_ARG       # NULL handle
+        assert create([Req(hh, 0x1000, 16, 9, 0)]) == ri.binding.RI_ERR_ARG         # bad algo
+        assert create([Req(hh, 0x1000, 16, 0, 1)]) == ri.binding.RI_ERR_ARG         # reserved
+        assert create([Req(hh, None, 16, 0, 0)]) == ri.binding.RI_ERR_ARG           # NULL text, n > 0
+        assert create([Req(hh, 0x1001, 16, 0, 0)]) == ri.binding.RI_ERR_ARG         # misaligned
+        assert create([Req(hh, 0x1000, 16, 0, 0)], chunk_bytes=24) == ri.binding.RI_ERR_ARG
+        assert "16-byte" in ri.ri_last_error() or "multiple of 16" in ri.ri_last_error()
+        assert lib.ri_batch_create(None, 1, 0, ctypes.byref(out)) == ri.binding.RI_ERR_ARG
+        assert lib.ri_batch_run(None, None, None) == ri.binding.RI_ERR_ARG
+        assert lib.ri_batch_launch(None, None) == ri.binding.RI_ERR_ARG
+        assert lib.ri_batch_get_info(None, None) == ri.binding.RI_ERR_ARG
+        lib.ri_batch_free(None)
+    finally:
+        ri.ri_free(hh)
+
+
 def _compare_with_oracle(pattern):
     ref = oracle.build(pattern)
     h = ri.ri_build(pattern)

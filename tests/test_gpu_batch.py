@@ -1,0 +1,262 @@
+"""GPU parity of batches (include/ri.h, ri_batch_*): every text of a batch
+gets exactly the oracle's serial result (accept, canonical final state) and
+the result of recognizing it alone, whatever the mix of automata, algorithms,
+lengths (0, ragged, multi-level join trees) and chunk sizes; graph replays
+and autotuned plans give the same results.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import gen
+
+torch = pytest.importorskip("torch")
+ri = pytest.importorskip("paper_2412_14975_amd")
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ALGOS = ("rid", "dfa", "subset")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ri.binding.lib()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.uint8)).to("cuda")
+
+
+class MinRef:
+    """The oracle's minimal DFA of an expression and its serial recognizer."""
+
+    def __init__(self, pattern):
+        self.dfa = oracle.min_dfa_of(oracle.trim(oracle.position_nfa(pattern)))
+        self.table = oracle.dense_table(self.dfa.n, self.dfa.delta)
+
+    def serial(self, x):
+        return oracle.serial(self.dfa, x, self.table)
+
+
+def small_pattern(rng, alphabet, depth, maxpos=40):
+    while True:
+        p = gen.random_regex(rng, alphabet, depth)
+        if oracle.position_nfa(p).n <= maxpos:
+            return p
+
+
+def mixed_requests(seed):
+    """(pattern, text, algo) triples over several automata and lengths."""
+    rng = gen.PCG(4242 + seed)
+    pats = [gen.c1_regex(), b"ab*", b"a[^\\x00-\\xff]", b"()"]
+    pats += [small_pattern(rng, b"abc"[: 2 + k % 2], 3) for k in range(3)]
+    lengths = (0, 1, 15, 16, 17, 100, 1000, 4097, 65541, 300007)
+    out = []
+    for pi, p in enumerate(pats):
+        for li, n in enumerate(lengths):
+            if (pi + li) % 2:
+                continue
+            alpha = b"ab" if p in (gen.c1_regex(), b"ab*") else b"abcz"
+            x = gen.random_text(rng, alpha, n)
+            if p == gen.c1_regex() and n >= 4:
+                x[-4:] = np.frombuffer(b"abab", np.uint8)
+            out.append((p, x, ALGOS[(pi + li // 2) % 3]))
+    return out
+
+
+def check_batch(reqs, chunk_bytes, refs, recs, launch="run"):
+    texts = [dev(x) for _, x, _ in reqs]
+    b = ri.Batch([(recs[p], t, a) for (p, _, a), t in zip(reqs, texts)], chunk_bytes=chunk_bytes)
+    try:
+        if launch == "run":
+            got = b.run().cpu().numpy()
+        else:
+            b.capture()
+            got = b.launch().cpu().numpy()
+        torch.cuda.synchronize()
+        for i, (p, x, a) in enumerate(reqs):
+            want = refs[p].serial(x)
+            assert (bool(got[i, 0]), int(got[i, 1])) == want, (p, len(x), a, chunk_bytes)
+            if len(x) and i % 3 == 0:
+                alone = recs[p].recognize(texts[i], algo=a)
+                assert (alone["accept"], alone["final_state"]) == want
+        return b.info()
+    finally:
+        b.close()
+
+
+@pytest.fixture(scope="module")
+def mixed():
+    reqs = mixed_requests(0)
+    refs, recs = {}, {}
+    for p, _, _ in reqs:
+        if p not in refs:
+            refs[p] = MinRef(p)
+            recs[p] = ri.Recognizer(p)
+    yield reqs, refs, recs
+    for r in recs.values():
+        r.close()
+
+
+@pytest.mark.parametrize("chunk_bytes", [0, 16, 48, 256, 4096])
+def test_mixed_batch(mixed, chunk_bytes):
+    reqs, refs, recs = mixed
+    info = check_batch(reqs, chunk_bytes, refs, recs)
+    assert info["texts"] == len(reqs)
+    assert info["bytes"] == sum(len(x) for _, x, _ in reqs)
+
+
+def test_mixed_batch_graph(mixed):
+    reqs, refs, recs = mixed
+    info = check_batch(reqs, 64, refs, recs, launch="graph")
+    assert info["captured"] == 1
+
+
+def test_deep_join_trees():
+    """16-byte chunks: a 300 KB text has ~19k chunks, so the per-text join
+    tree has three or more levels; texts of one chunk sit beside it."""
+    p = gen.c1_regex()
+    ref, rec = MinRef(p), ri.Recognizer(p)
+    rng = gen.PCG(5)
+    xs = [gen.random_text(rng, b"ab", n) for n in (300000, 1, 16, 17, 1024, 65536, 70000)]
+    for x in xs[::2]:
+        if len(x) >= 4:
+            x[-4:] = np.frombuffer(b"abab", np.uint8)
+    try:
+        for algo in ALGOS:
+            reqs = [(p, x, algo) for x in xs]
+            b = ri.Batch([(rec, dev(x), algo) for x in xs], chunk_bytes=16)
+            try:
+                assert b.group(0)["join_levels"] >= 3
+                got = b.run().cpu().numpy()
+                for i, x in enumerate(xs):
+                    assert (bool(got[i, 0]), int(got[i, 1])) == ref.serial(x), (algo, len(x))
+            finally:
+                b.close()
+            del reqs
+    finally:
+        rec.close()
+
+
+def test_graph_replays_with_eager_work_between():
+    """Replay the captured graph several times; between replays the results
+    are overwritten by eager torch work, and every replay must restore them."""
+    p = gen.c1_regex()
+    ref, rec = MinRef(p), ri.Recognizer(p)
+    rng = gen.PCG(9)
+    xs = [gen.random_text(rng, b"ab", n) for n in (5000, 70001, 12345, 1 << 18)]
+    xs[0][-4:] = np.frombuffer(b"abab", np.uint8)
+    want = [ref.serial(x) for x in xs]
+    texts = [dev(x) for x in xs]
+    b = ri.Batch([(rec, t, a) for t, a in zip(texts, ("rid", "dfa", "rid", "subset"))], chunk_bytes=256)
+    try:
+        b.capture()
+        for rep in range(4):
+            b.results.fill_(-7)
+            torch.cuda.synchronize()
+            got = b.launch().cpu().numpy()
+            assert [(bool(a), int(f)) for a, f in got] == want, rep
+            scratch = torch.randn(1 << 20, device="cuda").sum()   # eager work between replays
+            float(scratch)
+    finally:
+        b.close()
+        rec.close()
+
+
+def test_batch_autotune_keeps_results():
+    rx, motifs = gen.c2_regex_and_motifs(2)
+    ref = MinRef(rx)
+    rng = gen.PCG(3)
+    xs = []
+    for k in range(12):
+        x, rej = gen.c2_texts(100 + k, n=int(rng.integers(1 << 10, 1 << 20)) // 16 * 16 + k, motifs=motifs)
+        xs.append(x if k % 2 == 0 else rej)
+    rec = ri.Recognizer(rx)
+    texts = [dev(x) for x in xs]
+    b = ri.Batch([(rec, t, ("rid", "dfa")[i % 2]) for i, t in enumerate(texts)])
+    try:
+        tun = b.autotune()
+        assert tun["trials"] >= 6 and tun["best_ms"] > 0
+        for g in range(b.info()["groups"]):
+            assert b.group(g)["tuned_ms"] > 0
+        got = b.run().cpu().numpy()
+        for i, x in enumerate(xs):
+            assert (bool(got[i, 0]), int(got[i, 1])) == ref.serial(x)
+    finally:
+        b.close()
+        rec.close()
+
+
+def test_batched_workload_sample():
+    """Four expressions of the batched workload, 48 texts of 1 KiB - 512 KiB,
+    half derived from the expression and half changed at one byte."""
+    spec = json.load(open(os.path.join(HERE, "golden", "c4_regexes.json")))
+    seed = spec["seed"]
+    chosen = spec["expressions"][::4]
+    lengths = gen.c4_lengths(11, count=48, lo=1 << 10, hi=1 << 19)
+    refs, recs, reqs = [], [], []
+    for e in chosen:
+        rx, tree, alphabet = gen.c4_candidate(seed, e["index"])
+        assert rx.decode("latin-1") == e["regex"]
+        refs.append(MinRef(rx))
+        recs.append(ri.Recognizer(rx))
+        reqs.append((tree, alphabet))
+    items = []
+    for i, n in enumerate(lengths):
+        k = i % len(chosen)
+        x, changed = gen.c4_text(11, i, reqs[k][0], reqs[k][1], int(n))
+        items.append((k, x, changed))
+    texts = [dev(x) for _, x, _ in items]
+    try:
+        for algo in ("rid", "dfa"):
+            b = ri.Batch([(recs[k], t, algo) for (k, _, _), t in zip(items, texts)])
+            try:
+                got = b.run().cpu().numpy()
+            finally:
+                b.close()
+            accepted = 0
+            for i, (k, x, changed) in enumerate(items):
+                want = refs[k].serial(x)
+                assert (bool(got[i, 0]), int(got[i, 1])) == want, (algo, i, len(x))
+                if not changed:
+                    assert want[0], "a derived text is in the language"
+                accepted += want[0]
+            assert 0 < accepted < len(items)
+    finally:
+        for r in recs:
+            r.close()
+
+
+def test_batch_argument_errors():
+    rec = ri.Recognizer(b"ab*")
+    try:
+        buf = torch.zeros(64, dtype=torch.uint8, device="cuda")
+        with pytest.raises(ri.RIError) as e:
+            ri.Batch([(rec, buf[1:], "rid")])
+        assert e.value.code == ri.binding.RI_ERR_ARG
+        with pytest.raises(ri.RIError):
+            ri.Batch([(rec, buf, "rid")], chunk_bytes=24)
+        b = ri.Batch([(rec, buf, "rid")])
+        try:
+            with pytest.raises(TypeError):
+                ri.ri_batch_run(b.handle, torch.zeros(1, dtype=torch.int32, device="cuda"))
+            with pytest.raises(ri.RIError):
+                ri.ri_batch_launch(b.handle)     # nothing captured yet
+        finally:
+            b.close()
+        # an empty batch runs and launches nothing
+        b = ri.Batch([])
+        try:
+            b.run()
+            assert b.info()["texts"] == 0
+        finally:
+            b.close()
+    finally:
+        rec.close()

@@ -323,3 +323,191 @@ def random_regex(rng: np.random.Generator, alphabet: bytes, depth: int) -> bytes
 def random_text(rng: np.random.Generator, alphabet: bytes, n: int) -> np.ndarray:
     a = np.frombuffer(alphabet, dtype=np.uint8)
     return np.ascontiguousarray(a[rng.integers(0, len(a), size=n)])
+
+
+# ---------------------------------------------------------------------------
+# batched workload: random expressions of a small grammar, texts sampled
+# from their syntax trees
+# ---------------------------------------------------------------------------
+#
+# Trees: ('lit', b) | ('cls', bytes, neg) | ('cat', [t...]) | ('alt', [t...])
+# | ('rep', t, m, hi) with hi None for an unbounded repeat.  Every subtree
+# denotes a non-empty language (the grammar has no empty set), so a text can
+# always be derived.  Derivations pick uniformly among alternatives and
+# class members; repeats draw their counts; one unbounded repeat takes the
+# length budget by concatenating independently derived copies of its body.
+
+def _lit_bytes(b: int) -> bytes:
+    c = bytes([b])
+    return c if c.isalnum() else b"\\x%02x" % b
+
+
+def c4_tree(rng: np.random.Generator, alphabet: bytes, depth: int):
+    def atom(d):
+        u = rng.random()
+        if d <= 0 or u < 0.4:
+            if rng.random() < 0.7:
+                return ("lit", alphabet[int(rng.integers(0, len(alphabet)))])
+            k = int(rng.integers(2, max(3, min(len(alphabet), 8) + 1)))
+            idx = np.sort(rng.choice(len(alphabet), size=min(k, len(alphabet)), replace=False))
+            return ("cls", bytes(alphabet[i] for i in idx), bool(rng.random() < 0.1))
+        if u < 0.7:
+            return ("cat", [post(d - 1) for _ in range(int(rng.integers(2, 4)))])
+        return ("alt", [post(d - 1) for _ in range(int(rng.integers(2, 4)))])
+
+    def post(d):
+        a = atom(d)
+        u = rng.random()
+        if u < 0.2:
+            return ("rep", a, 0, None)
+        if u < 0.28:
+            return ("rep", a, 1, None)
+        if u < 0.36:
+            return ("rep", a, 0, 1)
+        if u < 0.46:
+            m = int(rng.integers(1, 4))
+            return ("rep", a, m, m + int(rng.integers(0, 4)))
+        return a
+
+    return ("cat", [post(depth) for _ in range(int(rng.integers(2, 4)))])
+
+
+def render(t) -> bytes:
+    kind = t[0]
+    if kind == "lit":
+        return _lit_bytes(t[1])
+    if kind == "cls":
+        return b"[" + (b"^" if t[2] else b"") + b"".join(_lit_bytes(b) for b in t[1]) + b"]"
+    if kind == "cat":
+        return b"(" + b"".join(render(c) for c in t[1]) + b")"
+    if kind == "alt":
+        return b"(" + b"|".join(render(c) for c in t[1]) + b")"
+    body = render(t[1])
+    m, hi = t[2], t[3]
+    if hi is None:
+        return body + (b"*" if m == 0 else b"+" if m == 1 else b"{%d,}" % m)
+    if (m, hi) == (0, 1):
+        return body + b"?"
+    return body + (b"{%d}" % m if m == hi else b"{%d,%d}" % (m, hi))
+
+
+def _nonempty(t) -> bool:
+    """Whether t derives some non-empty text."""
+    kind = t[0]
+    if kind in ("lit", "cls"):
+        return True
+    if kind in ("cat", "alt"):
+        return any(_nonempty(c) for c in t[1])
+    return (t[3] is None or t[3] > 0) and _nonempty(t[1])
+
+
+def unbounded(t) -> bool:
+    """Whether t derives texts of every length beyond some bound, i.e. has an
+    unbounded repeat of a body that derives a non-empty text."""
+    kind = t[0]
+    if kind in ("lit", "cls"):
+        return False
+    if kind in ("cat", "alt"):
+        return any(unbounded(c) for c in t[1])
+    return (t[3] is None and _nonempty(t[1])) or ((t[3] is None or t[3] > 0) and unbounded(t[1]))
+
+
+def _class_pick(rng, members: bytes, neg: bool, alphabet: bytes) -> int:
+    if not neg:
+        return members[int(rng.integers(0, len(members)))]
+    pool = [b for b in alphabet if b not in members] or [b for b in range(256) if b not in members]
+    return pool[int(rng.integers(0, len(pool)))]
+
+
+def derive(rng: np.random.Generator, t, alphabet: bytes, budget: int = 0) -> np.ndarray:
+    """A text of L(t).  With budget > 0 the first unbounded repeat met takes
+    the budget: copies of its body are derived (a pool of 64) and
+    concatenated in random order until the budget is used."""
+    out = []
+    state = {"budget": int(budget)}
+
+    def go(t):
+        kind = t[0]
+        if kind == "lit":
+            out.append(np.array([t[1]], np.uint8))
+        elif kind == "cls":
+            out.append(np.array([_class_pick(rng, t[1], t[2], alphabet)], np.uint8))
+        elif kind == "cat":
+            for c in t[1]:
+                go(c)
+        elif kind == "alt":
+            kids = t[1]
+            if state["budget"] > 0:
+                long = [c for c in kids if unbounded(c)]
+                if long:
+                    go(long[int(rng.integers(0, len(long)))])
+                    return
+            go(kids[int(rng.integers(0, len(kids)))])
+        else:
+            body, m, hi = t[1], t[2], t[3]
+            if hi is None and state["budget"] > 0 and _nonempty(body):
+                b = state["budget"]
+                state["budget"] = 0
+                pool = []
+                for _ in range(64):
+                    sub = derive(rng, body, alphabet)
+                    if len(sub):
+                        pool.append(sub)
+                lens = np.array([len(p) for p in pool], np.int64)
+                flat = np.concatenate(pool)
+                starts = np.concatenate([[0], np.cumsum(lens)[:-1]])
+                cnt = max(m, int(b // max(1.0, lens.mean())) + 1)
+                pick = rng.integers(0, len(pool), size=cnt)
+                plen = lens[pick]
+                total = int(plen.sum())
+                first = np.repeat(starts[pick] - np.concatenate([[0], np.cumsum(plen)[:-1]]), plen)
+                out.append(flat[first + np.arange(total)])
+                return
+            if state["budget"] > 0 and unbounded(body):
+                reps = max(m, 1)
+            else:
+                top = hi if hi is not None else m + int(rng.geometric(0.5))
+                reps = int(rng.integers(m, top + 1))
+            for _ in range(reps):
+                go(body)
+
+    go(t)
+    return np.concatenate(out) if out else np.zeros(0, np.uint8)
+
+
+def c4_alphabet(k: int) -> bytes:
+    """The first k printable bytes."""
+    return bytes(range(0x20, 0x20 + int(k)))
+
+
+def c4_candidate(seed: int, index: int):
+    """Candidate expression `index` of the batched workload: (regex, tree,
+    alphabet).  Candidates are filtered by automaton size elsewhere."""
+    rng = PCG((int(seed) << 20) + int(index))
+    alphabet = c4_alphabet(int(rng.integers(4, 65)))
+    t = c4_tree(rng, alphabet, int(rng.integers(4, 8)))
+    return render(t), t, alphabet
+
+
+def c4_lengths(seed: int, count: int = 4096, lo: int = 1 << 10, hi: int = 1 << 22) -> np.ndarray:
+    """Text lengths, log-uniform in [lo, hi]."""
+    rng = PCG(seed)
+    return np.floor(np.exp(rng.uniform(np.log(lo), np.log(hi), size=count))).astype(np.int64)
+
+
+def c4_text(seed: int, i: int, tree, alphabet: bytes, n: int):
+    """Text i: derived from the tree to about n bytes (even i), or derived
+    and then changed at one uniform position to a different byte of the
+    alphabet (odd i).  Returns (text, changed)."""
+    rng = PCG((int(seed) << 24) + 7919 * int(i) + 1)
+    x = derive(rng, tree, alphabet, budget=n)
+    if len(x) > n:
+        # keep the derivation whole: a cut could leave L; only the budget is approximate
+        pass
+    changed = bool(i % 2 == 1 and len(x) > 0)
+    if changed:
+        x = x.copy()
+        p = int(rng.integers(0, len(x)))
+        others = [b for b in alphabet if b != x[p]]
+        x[p] = others[int(rng.integers(0, len(others)))]
+    return np.ascontiguousarray(x, dtype=np.uint8), changed
