@@ -7,8 +7,13 @@ kernels, finalize kernel and the read-back of the result, with the text
 already resident in HBM.  Default workload: the motif union over {A,C,G,T}
 (256 MiB).  Prints ONE JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--workload motif|log|tiny]
+  python bench.py [--steps K] [--warmup W] [--workload motif|log|tiny|batch]
                   [--chunks C] [--seed S] [--no-cpu-baseline]
+
+--workload batch: 4096 texts (1 KiB - 4 MiB, log-uniform, about 2 GB) over
+16 random expressions, recognized by one captured graph launch of a batch
+(ri_batch_*), RID and all-states DFA, against one ri_recognize_ex call per
+text.
 """
 
 import argparse
@@ -30,7 +35,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="motif", choices=["motif", "log", "tiny"])
+    ap.add_argument("--workload", default="motif", choices=["motif", "log", "tiny", "batch"])
+    ap.add_argument("--texts", type=int, default=4096, help="batch workload: number of texts")
+    ap.add_argument("--procs", type=int, default=8, help="batch workload: text generator processes")
     ap.add_argument("--chunks", type=int, default=0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -157,8 +164,201 @@ def time_algo(torch, rec, t, algo, chunks, steps, warmup, want, setting=None):
                 result=r, exact=exact)
 
 
+
+# ---------------------------------------------------------------------------
+# batched workload
+# ---------------------------------------------------------------------------
+
+BATCH_SEED = 21
+
+
+def _batch_texts(job):
+    """Worker: texts [i0, i1) of the batched workload."""
+    from workloads import gen
+    spec, lengths, i0, i1 = job
+    seed = spec["seed"]
+    trees = {}
+    out = []
+    for i in range(i0, i1):
+        k = i % len(spec["expressions"])
+        if k not in trees:
+            _, tree, alphabet = gen.c4_candidate(seed, spec["expressions"][k]["index"])
+            trees[k] = (tree, alphabet)
+        x, changed = gen.c4_text(BATCH_SEED, i, trees[k][0], trees[k][1], int(lengths[i]))
+        out.append((k, x, changed))
+    return out
+
+
+def batch_workload(count, procs):
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    from workloads import gen
+    spec = json.load(open(os.path.join(ROOT, "tests", "golden", "c4_regexes.json")))
+    lengths = gen.c4_lengths(BATCH_SEED, count=count)
+    step = 32
+    jobs = [(spec, lengths, i, min(count, i + step)) for i in range(0, count, step)]
+    items = []
+    # generated before the GPU is touched (fork of a process without a device context)
+    with ProcessPoolExecutor(max_workers=max(1, procs), mp_context=mp.get_context("fork")) as ex:
+        for part in ex.map(_batch_texts, jobs):
+            items.extend(part)
+    regexes = [gen.c4_candidate(spec["seed"], e["index"])[0] for e in spec["expressions"]]
+    return spec, regexes, items
+
+
+def main_batch(args):
+    t_gen = time.perf_counter()
+    spec, regexes, items = batch_workload(args.texts, args.procs)
+    total = sum(len(x) for _, x, _ in items)
+    print(f"# batch workload: {len(items)} texts, {total} bytes, {len(regexes)} expressions "
+          f"({time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
+
+    import torch
+    import paper_2412_14975_amd as ri
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU", file=sys.stderr)
+        sys.exit(2)
+
+    # expected results: the oracle's minimal DFAs and serial scans (threads:
+    # the C scan runs without the interpreter lock)
+    refs = []
+    for rx in regexes:
+        d = oracle.min_dfa_of(oracle.trim(oracle.position_nfa(rx)))
+        refs.append((d, oracle.dense_table(d.n, d.delta)))
+    with ThreadPoolExecutor(max_workers=max(1, args.procs)) as ex:
+        want = list(ex.map(lambda it: oracle.serial(refs[it[0]][0], it[1], refs[it[0]][1]), items))
+    print(f"# oracle results: {sum(w[0] for w in want)} of {len(want)} accepted", file=sys.stderr, flush=True)
+
+    # texts packed at 16-byte aligned offsets in one device buffer
+    offs, pos = [], 0
+    for _, x, _ in items:
+        offs.append(pos)
+        pos += (len(x) + 15) // 16 * 16
+    host = torch.empty(max(pos, 16), dtype=torch.uint8, pin_memory=True)
+    hv = host.numpy()
+    for (_, x, _), o in zip(items, offs):
+        hv[o:o + len(x)] = x
+    buf = host.to("cuda")
+    views = [buf[o:o + len(x)] for (_, x, _), o in zip(items, offs)]
+    recs = [ri.Recognizer(rx) for rx in regexes]
+    torch.cuda.synchronize()
+
+    res = {}
+    for algo in ("rid", "dfa"):
+        t0 = time.perf_counter()
+        b = ri.Batch([(recs[k], v, algo) for (k, _, _), v in zip(items, views)])
+        tun = b.autotune()
+        b.capture()
+        setup_s = time.perf_counter() - t0
+        for _ in range(args.warmup):
+            b.launch()
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for e0, e1 in evs:
+            e0.record(st)
+            b.launch(st)
+            e1.record(st)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        ms = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+        got = b.results[: 2 * len(items)].view(-1, 2).cpu().numpy()
+        exact = all((bool(g[0]), int(g[1])) == w for g, w in zip(got, want))
+        info = b.info()
+        groups = [b.group(g) for g in range(info["groups"])]
+        b.close()
+        res[algo] = dict(gbps=total * args.steps / wall / 1e9, ms_per_step=wall / args.steps * 1e3,
+                         p50_ms=float(np.percentile(ms, 50)), p99_ms=float(np.percentile(ms, 99)),
+                         gbps_p50=total / (np.percentile(ms, 50) * 1e-3) / 1e9,
+                         gbps_p99=total / (np.percentile(ms, 99) * 1e-3) / 1e9,
+                         bitexact=bool(exact), setup_s=setup_s, chunks=int(info["slots"]),
+                         kernels=int(info["kernels"]), device_bytes=int(info["device_bytes"]),
+                         tuning=dict(trials=tun["trials"], best_ms=tun["best_ms"],
+                                     chunk_bytes=sorted({g["chunk_bytes"] for g in groups}),
+                                     warmup_bytes=sorted({g["warmup_bytes"] for g in groups})))
+        print(f"# batch {algo}: {res[algo]['gbps']:.1f} GB/s exact={exact}", file=sys.stderr, flush=True)
+
+    # one ri_recognize_ex call per text (each call enqueues its kernels and
+    # waits for its result), same texts, same automata
+    per_text = {}
+    for algo in ("rid", "dfa"):
+        for k, v in zip(range(64), views):    # warm the per-stream workspaces
+            recs[items[k][0]].recognize(v, algo=algo)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        exact = True
+        for (k, _, _), v, w in zip(items, views, want):
+            r = recs[k].recognize(v, algo=algo)
+            exact &= (r["accept"], r["final_state"]) == w
+        wall = time.perf_counter() - w0
+        per_text[algo] = dict(gbps=total / wall / 1e9, ms=wall * 1e3, bitexact=bool(exact))
+        print(f"# per-text {algo}: {per_text[algo]['gbps']:.1f} GB/s", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        # oracle serial scans, one host core, texts in order until about --cpu-seconds
+        c0, nbytes, ntexts = time.perf_counter(), 0, 0
+        while time.perf_counter() - c0 < args.cpu_seconds:
+            k, x, _ = items[ntexts % len(items)]
+            oracle.serial(refs[k][0], x, refs[k][1])
+            nbytes += len(x)
+            ntexts += 1
+        dt = time.perf_counter() - c0
+        cpu = dict(value=round(nbytes / dt / 1e9, 4), unit="GB/s", cores=1, kind="oracle",
+                   sample=f"oracle serial minimal-DFA scans of the first {ntexts} texts "
+                          f"({nbytes} bytes, {dt:.1f} s)")
+
+    r = res["rid"]
+    achieved = total / (r["p50_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": "GB/s of text recognized, RI-DFA vs all-states DFA speculation (bit-exact); p50/p99",
+        "value": round(r["gbps"], 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"batched-{len(items)}-texts-16-expressions", "n_bytes": total,
+                   "texts": len(items), "expressions": len(regexes), "text_seed": BATCH_SEED,
+                   "expression_seed": spec["seed"], "launch": "one captured hipGraph per step"},
+        "p50_ms": round(r["p50_ms"], 4),
+        "p99_ms": round(r["p99_ms"], 4),
+        "bitexact": all(v["bitexact"] for v in res.values()) and all(v["bitexact"] for v in per_text.values()),
+        "batch": {a: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in m.items()} for a, m in res.items()},
+        "per_text_calls": {a: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in m.items()}
+                           for a, m in per_text.items()},
+        "speedup_rid_vs_dfa": round(res["rid"]["gbps"] / res["dfa"]["gbps"], 4),
+        "speedup_batch_vs_per_text": round(res["rid"]["gbps"] / per_text["rid"]["gbps"], 4),
+        "command": " ".join(["python", "bench.py"] + sys.argv[1:]),
+        "roofline": dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                         frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                         kernel="whole batch graph (text bytes / p50 graph time)",
+                         algorithmic_bytes=int(total)),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    for rc in recs:
+        rc.close()
+
+
 def main():
     args = parse()
+    if args.workload == "batch" and not args.traffic_from:
+        if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+            print("bench.py: this recognizer runs on one GPU only; --gpus must be 1", file=sys.stderr)
+            sys.exit(2)
+        main_batch(args)
+        return
     if args.traffic_from:
         names = {"motif": "motif-union-ACGT-256MiB", "log": "log-lines-1GiB", "tiny": "regexp-k3-1MiB"}
         summarize_traffic(args.traffic_from[0], args.traffic_from[1], names[args.workload])

@@ -182,12 +182,21 @@ int ri_last_timings(const ri_handle *h, float ms[5]);
  *   RI_OPT_WARMUP_BYTES   multiple of 16 in [16, 256]; default 64.
  *   RI_OPT_RUNS_PER_LANE  independent runs per GPU lane: 0 (automatic), 1, 2, 4.
  *   RI_OPT_CHUNK_TARGET   chunk count aimed at when chunks = 0; default 131072.
+ *   RI_OPT_JOIN           join of the converging reach for RI_ALGO_RID:
+ *                         0 (default): products of per-chunk hit matrices
+ *                         (rows = merged runs of a chunk, columns = merged
+ *                         runs of the next chunk), reduced as a tree; when a
+ *                         chunk keeps more than 8 runs the call falls back
+ *                         to 1.  1: class-partitioned relations composed
+ *                         member by member within groups.  Results are
+ *                         identical; only the speed differs.
  * Errors: RI_ERR_ARG for an unknown option or a value out of range.
  */
 #define RI_OPT_CONVERGE       1
 #define RI_OPT_WARMUP_BYTES   2
 #define RI_OPT_RUNS_PER_LANE  3
 #define RI_OPT_CHUNK_TARGET   4
+#define RI_OPT_JOIN           5
 int ri_set_option(ri_handle *h, int option, int64_t value);
 int ri_get_option(const ri_handle *h, int option, int64_t *value);
 

@@ -27,9 +27,10 @@ SYMBOLS = ("ri_build", "ri_free", "ri_info", "ri_recognize", "ri_recognize_ex",
            "ri_set_option", "ri_get_option", "ri_autotune", "ri_last_error",
            "ri_batch_create", "ri_batch_free", "ri_batch_run", "ri_batch_capture",
            "ri_batch_launch", "ri_batch_get_info", "ri_batch_get_group", "ri_batch_autotune")
-RI_OPT_CONVERGE, RI_OPT_WARMUP_BYTES, RI_OPT_RUNS_PER_LANE, RI_OPT_CHUNK_TARGET = 1, 2, 3, 4
+RI_OPT_CONVERGE, RI_OPT_WARMUP_BYTES, RI_OPT_RUNS_PER_LANE, RI_OPT_CHUNK_TARGET, RI_OPT_JOIN = 1, 2, 3, 4, 5
 OPTIONS = {"converge": RI_OPT_CONVERGE, "warmup_bytes": RI_OPT_WARMUP_BYTES,
-           "runs_per_lane": RI_OPT_RUNS_PER_LANE, "chunk_target": RI_OPT_CHUNK_TARGET}
+           "runs_per_lane": RI_OPT_RUNS_PER_LANE, "chunk_target": RI_OPT_CHUNK_TARGET,
+           "join": RI_OPT_JOIN}
 
 
 class RIError(RuntimeError):

@@ -78,12 +78,14 @@ struct Workspace {
     int32_t *dres = nullptr;
     int32_t *hres = nullptr;        // pinned
     struct Buf { void *p = nullptr; size_t cap = 0; };
-    Buf lam, alias, run_base, run_chunk, run_state, run_final, dbg, join[2], ncls[2];
+    Buf lam, alias, run_base, run_count, run_chunk, run_state, run_final, dbg, join[2], ncls[2], hprod[2],
+        hrows[2];
     hipEvent_t ev[6] = {};
 };
 
 struct Options {
     int converge = 1;
+    int join = 0;              // 0: hit-matrix products (class join when a chunk has too many runs); 1: class join
     uint32_t warm = 64;
     uint32_t runs_per_lane = 0;
     uint32_t chunk_target = 131072;
@@ -349,6 +351,7 @@ int conv_config(const AlgoHost &H, const DeviceCopy &dc, const Options &opt, uin
 struct ReachBufs {
     void *alias;
     uint32_t *run_base, *run_chunk, *run_state, *run_final, *counters;
+    uint32_t *run_count;
 };
 
 // Warm-up and merging, then the merged runs to the chunk ends; `mid`
@@ -362,6 +365,7 @@ int launch_conv(const ConvCfg &c, const ri::ScanArgs &sa, const Options &opt, co
     wa.chunk_groups = c.chunk_groups;
     wa.alias = rb.alias;
     wa.run_base = rb.run_base;
+    wa.run_count = rb.run_count;
     wa.run_chunk = rb.run_chunk;
     wa.run_state = rb.run_state;
     wa.counters = rb.counters;
@@ -473,6 +477,12 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         if (!rc) rc = grow(ws->run_chunk, pairs * 4);
         if (!rc) rc = grow(ws->run_state, pairs * 4);
         if (!rc) rc = grow(ws->run_final, pairs * 4);
+        if (!rc) rc = grow(ws->run_count, (size_t)plan.nchunks * 4);
+        const size_t nh = std::max<size_t>(1, (plan.nchunks + 62) / 64);   // level-0 hit products
+        for (int i = 0; i < 2 && !rc; ++i) {
+            rc = grow(ws->hprod[i], nh * ri::kRowCap * 8);
+            if (!rc) rc = grow(ws->hrows[i], nh * 4);
+        }
     } else {
         rc = grow(ws->lam, pairs * H.lam_bytes);
     }
@@ -517,7 +527,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     } else {
         ReachBufs rb{ws->alias.p, static_cast<uint32_t *>(ws->run_base.p), static_cast<uint32_t *>(ws->run_chunk.p),
                      static_cast<uint32_t *>(ws->run_state.p), static_cast<uint32_t *>(ws->run_final.p),
-                     ws->counters};
+                     ws->counters, static_cast<uint32_t *>(ws->run_count.p)};
         rc = launch_conv(cc, sa, opt, rb, stream, h->profiling ? ws->ev[5] : nullptr);
         if (rc) return rc;
         if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[4], stream));
@@ -559,10 +569,13 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     ca.run_final = ja.run_final;
     ca.content = D.content;
     const uint32_t gc = conv && H.relational ? cls_group(H, shape.alias_bytes) : 0;
-    if (gc) {
+    const bool hit = gc && opt.join == 0;
+    auto cls_join = [&]() -> int {
         ca.G = gc;
         ca.nmembers = plan.nchunks;
         ca.span = 1;
+        ca.ncls_in = nullptr;
+        ca.cont_in = nullptr;
         ca.ncls_out = static_cast<uint32_t *>(ws->ncls[0].p);
         ca.cont_out = static_cast<uint32_t *>(ws->join[0].p);
         HIP_TRY(ri::launch_join_cls(ca, (int)H.W, shape.alias_bytes, true, stream));
@@ -581,9 +594,46 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
             span *= gc;
             nm = (nm + gc - 1) / gc;
         }
-        if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(ws->dbg.p), stream));
         ca.cont_in = static_cast<const uint32_t *>(ws->join[cur].p);
         HIP_TRY(ri::launch_finalize_cls(fa, ca, (int)H.W, shape.alias_bytes, stream));
+        return RI_OK;
+    };
+    if (hit) {
+        // products of hit matrices: level 0 over the K - 1 matrices, then
+        // groups of 64 products until one is left
+        ri::HitArgs ha{};
+        ha.alias = ws->alias.p;
+        ha.nchunks = plan.nchunks;
+        ha.run_base = ja.run_base;
+        ha.run_count = static_cast<const uint32_t *>(ws->run_count.p);
+        ha.run_final = ja.run_final;
+        ha.content = D.content;
+        ha.prod_in = nullptr;
+        if (plan.nchunks > 1) {
+            int cur = 0;
+            ha.nmembers = plan.nchunks - 1;
+            ha.prod_out = static_cast<uint64_t *>(ws->hprod[0].p);
+            ha.rows_out = static_cast<uint32_t *>(ws->hrows[0].p);
+            HIP_TRY(ri::launch_hit_prod(ha, (int)H.W, shape.alias_bytes, true, stream));
+            uint32_t nm = (ha.nmembers + 63) / 64;
+            while (nm > 1) {
+                ha.nmembers = nm;
+                ha.prod_in = static_cast<const uint64_t *>(ws->hprod[cur].p);
+                ha.rows_in = static_cast<const uint32_t *>(ws->hrows[cur].p);
+                ha.prod_out = static_cast<uint64_t *>(ws->hprod[cur ^ 1].p);
+                ha.rows_out = static_cast<uint32_t *>(ws->hrows[cur ^ 1].p);
+                HIP_TRY(ri::launch_hit_prod(ha, (int)H.W, shape.alias_bytes, false, stream));
+                cur ^= 1;
+                nm = (nm + 63) / 64;
+            }
+            ha.prod_in = static_cast<const uint64_t *>(ws->hprod[cur].p);
+        }
+        if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(ws->dbg.p), stream));
+        HIP_TRY(ri::launch_finalize_hit(fa, ha, (int)H.W, shape.alias_bytes, stream));
+    } else if (gc) {
+        if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(ws->dbg.p), stream));
+        rc = cls_join();
+        if (rc) return rc;
     } else {
         if (g0 > 0) {
             ja.G = g0;
@@ -611,7 +661,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         else HIP_TRY(ri::launch_finalize_fun(fa, stream));
     }
     if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[2], stream));
-    HIP_TRY(hipMemcpyAsync(ws->hres, ws->dres, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(ws->hres, ws->dres, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     std::vector<int32_t> lam_host;
     if (maps) {
         lam_host.resize(pairs);
@@ -619,6 +669,14 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     }
     if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[3], stream));
     HIP_TRY(hipStreamSynchronize(stream));
+    if (hit && ws->hres[2] != 0) {
+        // some chunk kept more runs than a hit-matrix row can index: join
+        // again with the class join (the reach results are still in place)
+        rc = cls_join();
+        if (rc) return rc;
+        HIP_TRY(hipMemcpyAsync(ws->hres, ws->dres, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+    }
 
     out->accept = ws->hres[0];
     out->final_state = ws->hres[1];
@@ -1039,7 +1097,8 @@ void ri_free(ri_handle *h) {
         (void)hipFree(w->counters);
         (void)hipFree(w->dres);
         (void)hipHostFree(w->hres);
-        for (Workspace::Buf *b : {&w->lam, &w->alias, &w->run_base, &w->run_chunk, &w->run_state,
+        for (Workspace::Buf *b : {&w->lam, &w->alias, &w->run_base, &w->run_count, &w->hprod[0], &w->hprod[1],
+                                  &w->hrows[0], &w->hrows[1], &w->run_chunk, &w->run_state,
                                   &w->run_final, &w->dbg, &w->join[0], &w->join[1], &w->ncls[0],
                                   &w->ncls[1]})
             (void)hipFree(b->p);
@@ -1137,6 +1196,10 @@ int ri_set_option(ri_handle *h, int option, int64_t value) {
         if (value != 0 && value != 1 && value != 2 && value != 4) return fail(RI_ERR_ARG, "runs per lane: 0, 1, 2 or 4");
         h->opt.runs_per_lane = (uint32_t)value;
         return RI_OK;
+    case RI_OPT_JOIN:
+        if (value != 0 && value != 1) return fail(RI_ERR_ARG, "RI_OPT_JOIN must be 0 or 1");
+        h->opt.join = (int)value;
+        return RI_OK;
     case RI_OPT_CHUNK_TARGET:
         if (value < 1 || value > (1ll << 30)) return fail(RI_ERR_ARG, "bad chunk target");
         h->opt.chunk_target = (uint32_t)value;
@@ -1153,6 +1216,7 @@ int ri_get_option(const ri_handle *h, int option, int64_t *value) {
     case RI_OPT_WARMUP_BYTES: *value = h->opt.warm; return RI_OK;
     case RI_OPT_RUNS_PER_LANE: *value = h->opt.runs_per_lane; return RI_OK;
     case RI_OPT_CHUNK_TARGET: *value = h->opt.chunk_target; return RI_OK;
+    case RI_OPT_JOIN: *value = h->opt.join; return RI_OK;
     }
     return fail(RI_ERR_ARG, "unknown option");
 }

@@ -411,8 +411,12 @@ __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
             const uint32_t chunk = cg * CW + c;
             if (chunk >= a.s.nchunks) continue;
             const uint32_t first = base + dfirst[c];
-            if (lane == 0) a.run_base[chunk] = first;
             const uint32_t dc = dcount[c];
+            if (lane == 0) {
+                a.run_base[chunk] = first;
+                if (a.run_count) a.run_count[chunk] = dc & ~kSpill;
+                if ((dc & ~kSpill) > kRowCap) atomicOr(&a.counters[2], 1u);
+            }
             if (!(dc & kSpill)) {
                 if (lane < dc) {
                     a.run_chunk[first + lane] = chunk;
@@ -815,6 +819,100 @@ __global__ void __launch_bounds__(256) join_cls_kernel(ClsJoinArgs a) {
     if (threadIdx.x == 0) a.ncls_out[grp] = ncls0;
 }
 
+// ---------------------------------------------------------------------------
+// join over merged runs: products of hit matrices (RI-DFA)
+// ---------------------------------------------------------------------------
+
+// Row product: rows a[r] (bitmasks over the partner's rows) times b.
+__device__ __forceinline__ void rows_times(uint64_t (&a)[kRowCap], const uint64_t (&b)[kRowCap]) {
+#pragma unroll
+    for (uint32_t r = 0; r < kRowCap; ++r) {
+        uint64_t x = a[r], y = 0;
+        while (x) {
+            const uint32_t j = __builtin_ctzll(x);
+            x &= x - 1;
+            if (j < kRowCap) y |= b[j];
+        }
+        a[r] = y;
+    }
+}
+
+// Tree product of the wave's gn members (lane l holds member l): after it
+// lane 0 holds the product of all of them.
+__device__ __forceinline__ void wave_tree_product(uint64_t (&rows)[kRowCap], uint32_t lane, uint32_t gn) {
+#pragma unroll
+    for (uint32_t d = 1; d < kWave; d <<= 1) {
+        uint64_t b[kRowCap];
+#pragma unroll
+        for (uint32_t j = 0; j < kRowCap; ++j) b[j] = __shfl(rows[j], (int)((lane + d) % kWave));
+        if ((lane & (2 * d - 1)) == 0 && lane + d < gn) rows_times(rows, b);
+    }
+}
+
+// Level 0, fused with the hit rows: wave per group of 64 matrices; lane l
+// builds M_k (k = 64 g + l) from the end states of chunk k's runs and the
+// alias column of chunk k + 1.
+template <int W, typename TA>
+__global__ void __launch_bounds__(256) hit_prod0_kernel(HitArgs a) {
+    const uint32_t lane = threadIdx.x % kWave;
+    const uint32_t g = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const uint32_t ngroups = (a.nmembers + kWave - 1) / kWave;
+    if (g >= ngroups) return;
+    const uint32_t gn = g * kWave + kWave <= a.nmembers ? kWave : a.nmembers - g * kWave;
+    const uint32_t k = g * kWave + lane;
+    const TA *alias = reinterpret_cast<const TA *>(a.alias);
+    uint64_t rows[kRowCap];
+    uint32_t R = 0;
+    if (lane < gn) {
+        R = a.run_count[k];
+        R = R < kRowCap ? R : kRowCap;
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < kRowCap; ++r) {
+        uint64_t m = 0;
+        if (r < R) {
+            const uint32_t f = a.run_final[a.run_base[k] + r];
+            if (f != kNoState) {
+                const uint32_t *cw = a.content + (uint64_t)f * W;
+                for (uint32_t w = 0; w < (uint32_t)W; ++w) {
+                    for (uint32_t bits = cw[w]; bits; bits &= bits - 1) {
+                        const uint32_t t = w * 32 + __builtin_ctz(bits);
+                        const TA j = alias[(uint64_t)t * a.nchunks + k + 1];
+                        if (j != all_ones<TA>() && (uint32_t)j < 64) m |= 1ull << j;
+                    }
+                }
+            }
+        }
+        rows[r] = m;
+    }
+    wave_tree_product(rows, lane, gn);
+    if (lane == 0) {
+#pragma unroll
+        for (uint32_t r = 0; r < kRowCap; ++r) a.prod_out[(uint64_t)g * kRowCap + r] = rows[r];
+        a.rows_out[g] = R;
+    }
+}
+
+// Level >= 1: wave per group of 64 products of the level below.
+__global__ void __launch_bounds__(256) hit_prodN_kernel(HitArgs a) {
+    const uint32_t lane = threadIdx.x % kWave;
+    const uint32_t g = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const uint32_t ngroups = (a.nmembers + kWave - 1) / kWave;
+    if (g >= ngroups) return;
+    const uint32_t gn = g * kWave + kWave <= a.nmembers ? kWave : a.nmembers - g * kWave;
+    const uint32_t m = g * kWave + lane;
+    uint64_t rows[kRowCap];
+#pragma unroll
+    for (uint32_t r = 0; r < kRowCap; ++r) rows[r] = lane < gn ? a.prod_in[(uint64_t)m * kRowCap + r] : 0ull;
+    const uint32_t R = lane < gn ? a.rows_in[m] : 0u;
+    wave_tree_product(rows, lane, gn);
+    if (lane == 0) {
+#pragma unroll
+        for (uint32_t r = 0; r < kRowCap; ++r) a.prod_out[(uint64_t)g * kRowCap + r] = rows[r];
+        a.rows_out[g] = R;
+    }
+}
+
 // Level >= 1: thread per (group of G relations, row s).
 template <int W>
 __global__ void __launch_bounds__(256) joinN_rel_kernel(JoinArgs a) {
@@ -959,6 +1057,33 @@ __global__ void finalize_cls_kernel(FinalArgs f, ClsJoinArgs a) {
     uint32_t x[W];
     load_row<W>(x, c0 != all_ones<TA>() ? a.cont_in + (uint64_t)c0 * W : nullptr);
     decide<W>(x, f, f.result);
+    reset_counters(f.counters);
+}
+
+// Classes of the last chunk reached from start 0 (row a0 of the product, a0
+// = class of start 0 in chunk 0), union of their end-state contents, then
+// acceptance and final state.
+template <int W, typename TA>
+__global__ void finalize_hit_kernel(FinalArgs f, HitArgs a) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const TA a0 = reinterpret_cast<const TA *>(a.alias)[0];
+    uint64_t v = 0;
+    if (a0 != all_ones<TA>() && (uint32_t)a0 < kRowCap) v = a.prod_in ? a.prod_in[a0] : 1ull << a0;
+    const uint32_t last = a.nchunks - 1;
+    const uint32_t R = a.run_count[last];
+    uint32_t x[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = 0;
+    for (; v; v &= v - 1) {
+        const uint32_t c = __builtin_ctzll(v);
+        if (c >= R) continue;
+        const uint32_t fs = a.run_final[a.run_base[last] + c];
+        if (fs == kNoState) continue;
+#pragma unroll
+        for (int w = 0; w < W; ++w) x[w] |= a.content[(uint64_t)fs * W + w];
+    }
+    decide<W>(x, f, f.result);
+    f.result[2] = (int32_t)f.counters[2];
     reset_counters(f.counters);
 }
 
@@ -1226,6 +1351,30 @@ hipError_t launch_finalize_rel(const FinalArgs &a, int W, hipStream_t s) {
 hipError_t launch_finalize_fun(const FinalArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(finalize_fun_kernel, dim3(1), dim3(64), 0, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_hit_prod(const HitArgs &a, int W, int alias_bytes, bool level0, hipStream_t s) {
+    const uint32_t ngroups = (a.nmembers + kWave - 1) / kWave;
+    const uint32_t blocks = (ngroups + 3) / 4;
+    if (!level0) {
+        hipLaunchKernelGGL(hit_prodN_kernel, dim3(blocks), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+    return dispatch_ta(alias_bytes, [&](auto ta) {
+#define CALLH(w) hipLaunchKernelGGL((hit_prod0_kernel<w, decltype(ta)>), dim3(blocks), dim3(256), 0, s, a);
+        RI_DISPATCH_W(W, CALLH)
+#undef CALLH
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_finalize_hit(const FinalArgs &f, const HitArgs &a, int W, int alias_bytes, hipStream_t s) {
+    return dispatch_ta(alias_bytes, [&](auto ta) {
+#define CALLFH(w) hipLaunchKernelGGL((finalize_hit_kernel<w, decltype(ta)>), dim3(1), dim3(64), 0, s, f, a);
+        RI_DISPATCH_W(W, CALLFH)
+#undef CALLFH
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_batch_final_cls(const BatchFinalArgs &b, const FinalArgs &f, const ClsJoinArgs &a, int W,

@@ -59,9 +59,11 @@ struct WarmArgs {
     uint32_t chunk_groups;     // ceil(nchunks / cw)
     void *alias;               // [L][nchunks] local run index, all-ones = no run
     uint32_t *run_base;        // [nchunks] first run of the chunk
+    uint32_t *run_count;       // [nchunks] runs of the chunk (nullptr: not needed)
     uint32_t *run_chunk;       // [cap]
     uint32_t *run_state;       // [cap] state id after the warm-up, kNoState if none
-    uint32_t *counters;        // [1] runs allocated
+    uint32_t *counters;        // [1] runs allocated; [2] set to 1 when a chunk has more
+                               // than kRowCap runs
 };
 hipError_t launch_warm(const WarmArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st);
 size_t warm_lds_bytes(const KernelShape &k, uint32_t L, uint32_t table_bytes, uint32_t cw, uint32_t ws);
@@ -139,6 +141,30 @@ struct ClsJoinArgs {
 size_t cls_join_lds(const ClsJoinArgs &a, int W, int alias_bytes);
 hipError_t launch_join_cls(const ClsJoinArgs &a, int W, int alias_bytes, bool level0, hipStream_t s);
 
+// Join over merged runs by products of hit matrices (converging reach,
+// relational chunk automata).  M_k (chunk k -> k+1) has one row per run
+// (class) of chunk k: the bitmask of classes of chunk k+1 hit by the content
+// of the run's end state.  The text's relation restricted to the initial
+// state is row a0 of M_0 M_1 ... M_{K-2}; products over 64 consecutive
+// members are reduced as a tree of wave shuffles.  Valid while every chunk
+// has at most kRowCap runs (counters[2] stays 0); otherwise the class join
+// must be used.
+constexpr uint32_t kRowCap = 8;
+struct HitArgs {
+    const void *alias;         // [L][nchunks]
+    uint32_t nchunks;          // K
+    const uint32_t *run_base;
+    const uint32_t *run_count;
+    const uint32_t *run_final;
+    const uint32_t *content;   // [nstates][W]
+    uint32_t nmembers;         // level 0: K - 1 matrices; level >= 1: products of the level below
+    const uint64_t *prod_in;   // level >= 1: [nmembers][kRowCap]; finalize: the single product (or nullptr)
+    const uint32_t *rows_in;   // level >= 1: [nmembers]
+    uint64_t *prod_out;        // [ngroups][kRowCap]
+    uint32_t *rows_out;        // [ngroups]
+};
+hipError_t launch_hit_prod(const HitArgs &a, int W, int alias_bytes, bool level0, hipStream_t s);
+
 struct FinalArgs {
     const void *total;         // one relation [L][W] or one function [L]
     const uint32_t *fmask;     // relations: final N' states (W words)
@@ -152,6 +178,8 @@ struct FinalArgs {
 hipError_t launch_finalize_rel(const FinalArgs &a, int W, hipStream_t s);
 hipError_t launch_finalize_fun(const FinalArgs &a, hipStream_t s);
 hipError_t launch_finalize_cls(const FinalArgs &f, const ClsJoinArgs &a, int W, int alias_bytes, hipStream_t s);
+// result[2] = counters[2] (1: the hit-matrix result is not valid)
+hipError_t launch_finalize_hit(const FinalArgs &f, const HitArgs &a, int W, int alias_bytes, hipStream_t s);
 
 // Batch results, one per text, from the last join level (one group per
 // text, in text order): a class-partitioned relation or a function.

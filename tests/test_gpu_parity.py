@@ -21,9 +21,10 @@ pytestmark = pytest.mark.gpu
 
 ALGOS = ("rid", "dfa", "subset")
 
-# reach pipelines: converging (warm-up + merge) with two warm-up lengths, and plain
+# reach pipelines: converging (warm-up + merge) with two warm-up lengths and
+# the hit-matrix join, converging with the class join, and plain
 MODES = {"conv64": dict(converge=1, warmup_bytes=64), "conv16": dict(converge=1, warmup_bytes=16),
-         "plain": dict(converge=0)}
+         "cls64": dict(converge=1, warmup_bytes=64, join=1), "plain": dict(converge=0)}
 
 
 def make(pattern, mode="conv64", runs_per_lane=0):
@@ -226,6 +227,31 @@ def test_runs_that_never_converge(mode):
         x = gen.random_text(rng, b"ab", 20000)
         check_maps(rec, ref, x, "dfa", 50)
         check_maps(rec, ref, x, "rid", 50)
+    finally:
+        rec.close()
+
+
+@pytest.mark.parametrize("k", [2, 7, 8, 9, 16])
+def test_runs_per_chunk_around_the_hit_row_cap(k):
+    """Counting a's modulo k keeps k runs per chunk after merging: up to 8
+    the hit-matrix join handles them, above it the call falls back to the
+    class join.  Both must give the oracle's result."""
+    rx = b"((b*a){%d})*b*" % k
+    ref = Ref(rx)
+    rec = make(rx, "conv16")
+    try:
+        rng = gen.PCG(100 + k)
+        for n in (5000, 300001):
+            for accept in (False, True):
+                x = gen.random_text(rng, b"ab", n)
+                if accept:   # flip b's to a's until the count of a's is a multiple of k
+                    need = (-int((x == ord("a")).sum())) % k
+                    x[np.flatnonzero(x == ord("b"))[:need]] = ord("a")
+                want = ref.serial(x)
+                assert not accept or want[0]
+                for chunks in (1, 2, 64, 0):
+                    got = rec.recognize(dev(x), algo="rid", chunks=chunks)
+                    assert (got["accept"], got["final_state"]) == want, (k, n, chunks)
     finally:
         rec.close()
 
