@@ -44,9 +44,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-tune", action="store_true",
                     help="skip ri_autotune (the chunk count is then the library default)")
-    ap.add_argument("--tune-rid", metavar="TARGET:WARM:RUNS",
+    ap.add_argument("--tune-rid", metavar="TARGET:WARM:RUNS[:CONVERGE]",
                     help="use these reach settings for RID instead of ri_autotune")
-    ap.add_argument("--tune-dfa", metavar="TARGET:WARM:RUNS",
+    ap.add_argument("--tune-dfa", metavar="TARGET:WARM:RUNS[:CONVERGE]",
                     help="use these reach settings for the DFA instead of ri_autotune")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the paper-literal (non-merging) reach comparison")
@@ -132,8 +132,9 @@ def apply_setting(rec, setting):
     """setting: dict with chunk_target / warmup_bytes / runs_per_lane, or None
     (keep what ri_autotune stored in the handle)."""
     if setting:
-        for k in ("chunk_target", "warmup_bytes", "runs_per_lane"):
-            rec.set_option(k, setting[k])
+        for k in ("chunk_target", "warmup_bytes", "runs_per_lane", "converge"):
+            if k in setting:
+                rec.set_option(k, setting[k])
 
 
 def time_algo(torch, rec, t, algo, chunks, steps, warmup, want, setting=None):
@@ -400,8 +401,9 @@ def main():
     tuning, fixed = {}, {}
     for algo, spec in (("rid", args.tune_rid), ("dfa", args.tune_dfa)):
         if spec:
-            tgt, w, r = (int(v) for v in spec.split(":"))
-            fixed[algo] = dict(chunk_target=tgt, warmup_bytes=w, runs_per_lane=r)
+            vals = [int(v) for v in spec.split(":")]
+            fixed[algo] = dict(chunk_target=vals[0], warmup_bytes=vals[1], runs_per_lane=vals[2],
+                               converge=vals[3] if len(vals) > 3 else 1)
             tuning[algo] = dict(fixed[algo], trials=0, source="given")
     if not args.no_tune and args.chunks == 0:
         # setup, outside the timed region: pick chunk target / warm-up / runs
@@ -412,7 +414,7 @@ def main():
             tuning[algo] = rec.autotune(t, algo=algo)
             tuning[algo]["source"] = "ri_autotune"
             print(f"# tuned {algo}: {tuning[algo]}", file=sys.stderr, flush=True)
-            fixed[algo] = {k: tuning[algo][k] for k in ("chunk_target", "warmup_bytes", "runs_per_lane")}
+            fixed[algo] = {k: tuning[algo][k] for k in ("chunk_target", "warmup_bytes", "runs_per_lane", "converge")}
 
     rid = time_algo(torch, rec, t, "rid", args.chunks, args.steps, args.warmup, want, fixed.get("rid"))
     print(f"# rid done", file=sys.stderr, flush=True)
@@ -455,14 +457,15 @@ def main():
     # the same bytes; the run records, 12 B per run, are < 2% and left out).
     L = info["starts"][0]
     cs, c = s_rid["chunk_size"], s_rid["chunks"]
-    warm = fixed["rid"]["warmup_bytes"] if "rid" in fixed else rec.get_option("warmup_bytes")
+    conv_rid = fixed["rid"].get("converge", 1) if "rid" in fixed else rec.get_option("converge")
+    warm = (fixed["rid"]["warmup_bytes"] if "rid" in fixed else rec.get_option("warmup_bytes")) if conv_rid else 0
     long_bytes = sum(max(0, min(cs, n - i * cs) - warm) for i in range(c)) if c < 5_000_000 else n
     achieved = long_bytes / (s_rid["long_ms"] * 1e-3) / 1e9
     trec = load_traffic(wname)
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4),
                 traffic=(round(trec["traffic_bytes_per_launch"]) if trec else None),
-                kernel="long_kernel", algorithmic_bytes=int(long_bytes),
+                kernel="long_kernel" if conv_rid else "plain_kernel", algorithmic_bytes=int(long_bytes),
                 reach_phase_gbps=round(n / (s_rid["reach_ms"] * 1e-3) / 1e9, 1))
 
     cpu = None

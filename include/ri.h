@@ -201,14 +201,15 @@ int ri_set_option(ri_handle *h, int option, int64_t value);
 int ri_get_option(const ri_handle *h, int option, int64_t *value);
 
 /*
- * ri_autotune -- pick the reach-phase settings (chunk target, warm-up bytes,
- * runs per lane) for `algo` by timing a fixed grid of them on the given
- * device text (same arguments as ri_recognize_ex; every trial is a full
- * recognition whose result is checked against the first one).  The best
- * setting is stored in the handle for that algorithm and used by later
- * calls with chunks = 0 and RI_OPT_CONVERGE = 1, until ri_set_option is
- * called.  `out` (may be NULL) receives the chosen values and the best time.
- * Must not run concurrently with other calls on the same handle.
+ * ri_autotune -- pick the reach-phase settings for `algo` by timing a fixed
+ * grid of them on the given device text (same arguments as ri_recognize_ex;
+ * every trial is a full recognition whose result is checked against the
+ * first one): the converging reach over chunk targets x warm-up bytes x runs
+ * per lane, and the plain reach over chunk targets x runs per lane.  The
+ * best setting is stored in the handle for that algorithm and used by later
+ * calls with chunks = 0, until ri_set_option is called.  `out` (may be
+ * NULL) receives the chosen values and the best time.  Must not run
+ * concurrently with other calls on the same handle.
  */
 typedef struct {
     uint32_t chunk_target;
@@ -216,6 +217,7 @@ typedef struct {
     uint32_t runs_per_lane;
     uint32_t trials;
     float best_ms;
+    uint32_t converge;     /* 1: converging reach chosen; 0: plain reach */
 } ri_tuning;
 int ri_autotune(ri_handle *h, const uint8_t *text_dev, size_t n, void *stream, int algo,
                 ri_tuning *out);

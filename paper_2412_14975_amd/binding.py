@@ -52,7 +52,7 @@ class ri_result(ctypes.Structure):
 class ri_tuning(ctypes.Structure):
     _fields_ = [("chunk_target", ctypes.c_uint32), ("warmup_bytes", ctypes.c_uint32),
                 ("runs_per_lane", ctypes.c_uint32), ("trials", ctypes.c_uint32),
-                ("best_ms", ctypes.c_float)]
+                ("best_ms", ctypes.c_float), ("converge", ctypes.c_uint32)]
 
 
 class ri_info_t(ctypes.Structure):

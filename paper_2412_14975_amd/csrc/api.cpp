@@ -299,44 +299,26 @@ ri::KernelShape base_shape(const AlgoHost &H, const DeviceCopy &dc) {
     return shape;
 }
 
-// Launch configuration of the converging reach over `nchunks` chunks of at
-// most cs bytes.
+// Launch configuration of the converging reach over `nchunks` chunks.
 struct ConvCfg {
     ri::KernelShape warm_shape, long_shape;
-    uint32_t cw = 0;
     size_t lds_w = 0, lds_l = 0;
     int grid_w = 1, grid_l = 1;
-    uint32_t chunk_groups = 0;
 };
 
-int conv_config(const AlgoHost &H, const DeviceCopy &dc, const Options &opt, uint64_t cs, uint32_t nchunks,
-                ConvCfg *c) {
+constexpr uint32_t kWarmChunksPerBlock = 16;   // one wavefront per chunk
+
+int conv_config(const AlgoHost &H, const DeviceCopy &dc, const Options &opt, uint32_t nchunks, ConvCfg *c) {
     if (H.L > 65534) return fail(RI_ERR_LIMIT, "too many starts for the converging reach");
     const ri::KernelShape shape = base_shape(H, dc);
     const size_t lds_tables = H.table.size() + 512;
-    // warm-up: runs of one chunk share a lane
+    // warm-up: starts held 64 per lane register, up to 4 registers per lane
     c->warm_shape = shape;
-    uint32_t Rw = opt.runs_per_lane ? opt.runs_per_lane : 4;
-    while (Rw > 1 && Rw / 2 >= H.L) Rw /= 2;
-    c->warm_shape.runs_per_lane = (int)Rw;
-    // tile width (chunks per group): prefer >= 16 chunks within half the LDS
-    // (two blocks per CU), then anything that fits, then the table in global
-    // memory
-    const uint32_t ws = (uint32_t)std::min<uint64_t>(opt.warm, cs);
-    auto pick = [&](size_t budget, uint32_t min_cw) -> bool {
-        for (uint32_t w = 64; w >= min_cw && w >= 1; w /= 2) {
-            const size_t l = ri::warm_lds_bytes(c->warm_shape, H.L, (uint32_t)H.table.size(), w, ws);
-            if (l <= budget) { c->cw = w; c->lds_w = l; return true; }
-        }
-        return false;
-    };
-    if (!(c->warm_shape.table_in_lds && (pick(dc.max_lds / 2, 16) || pick(dc.max_lds, 1)))) {
-        c->warm_shape.table_in_lds = false;
-        if (!pick(dc.max_lds, 1)) return fail(RI_ERR_LIMIT, "too many starts for the warm-up tile");
-    }
-    c->chunk_groups = (nchunks + c->cw - 1) / c->cw;
+    c->warm_shape.runs_per_lane = H.L <= 64 ? 1 : H.L <= 128 ? 2 : 4;
+    c->lds_w = ri::warm_lds_bytes(c->warm_shape, (uint32_t)H.table.size());
+    const uint32_t iters = (nchunks + kWarmChunksPerBlock - 1) / kWarmChunksPerBlock;
     const int per_cu_w = std::max(1, ri::blocks_per_cu(1, c->warm_shape, c->lds_w));
-    c->grid_w = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)dc.cus * per_cu_w, c->chunk_groups));
+    c->grid_w = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)dc.cus * per_cu_w, iters));
     // long runs: one run per lane unless set
     c->long_shape = shape;
     c->long_shape.runs_per_lane = (int)(opt.runs_per_lane ? opt.runs_per_lane : 1);
@@ -361,8 +343,6 @@ int launch_conv(const ConvCfg &c, const ri::ScanArgs &sa, const Options &opt, co
     ri::WarmArgs wa{};
     wa.s = sa;
     wa.warm = opt.warm;
-    wa.cw = c.cw;
-    wa.chunk_groups = c.chunk_groups;
     wa.alias = rb.alias;
     wa.run_base = rb.run_base;
     wa.run_count = rb.run_count;
@@ -431,7 +411,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     uint32_t target = h->opt.chunk_target;
     {
         std::lock_guard<std::mutex> lk(h->mu);
-        if (chunks == 0 && h->opt.converge && h->tuned_valid[algo]) target = h->tuned[algo].chunk_target;
+        if (chunks == 0 && h->tuned_valid[algo]) target = h->tuned[algo].chunk_target;
     }
     int rc = plan_chunks(H, n, chunks, target, &plan);
     if (rc) return rc;
@@ -453,7 +433,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     Options opt;
     {
         std::lock_guard<std::mutex> lk(h->mu);
-        opt = (chunks == 0 && h->opt.converge && h->tuned_valid[algo]) ? h->tuned[algo] : h->opt;
+        opt = (chunks == 0 && h->tuned_valid[algo]) ? h->tuned[algo] : h->opt;
     }
     const bool conv = opt.converge != 0;
     const uint32_t g0 = tile_group(H);
@@ -466,7 +446,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     const size_t lds_tables = H.table.size() + 512;
     ConvCfg cc;
     if (conv) {
-        rc = conv_config(H, dc, opt, plan.cs, plan.nchunks, &cc);
+        rc = conv_config(H, dc, opt, plan.nchunks, &cc);
         if (rc) return rc;
     }
 
@@ -603,6 +583,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         // groups of 64 products until one is left
         ri::HitArgs ha{};
         ha.alias = ws->alias.p;
+        ha.L = H.L;
         ha.nchunks = plan.nchunks;
         ha.run_base = ja.run_base;
         ha.run_count = static_cast<const uint32_t *>(ws->run_count.p);
@@ -857,7 +838,7 @@ int plan_group(ri_batch *b, BatchGroup &g) {
         }
         const size_t pairs = (size_t)H.L * g.slots;
         const size_t row_words = H.relational ? H.W : 1;
-        int rc = conv_config(H, dc, g.opt, cs, g.slots, &g.cc);
+        int rc = conv_config(H, dc, g.opt, g.slots, &g.cc);
         if (!rc) rc = grow(g.alias, pairs * alias_bytes);
         if (!rc) rc = grow(g.run_base, (size_t)g.slots * 4);
         if (!rc) rc = grow(g.run_chunk, pairs * 4);
@@ -1231,53 +1212,59 @@ int ri_autotune(ri_handle *h, const uint8_t *text, size_t n, void *stream, int a
         h->tuned_valid[algo] = false;
     }
     static const uint32_t kTargets[] = {32768, 65536, 131072, 262144};
-    static const uint32_t kWarm[] = {16, 32, 64};
+    static const uint32_t kWarm[] = {16, 32, 64, 128};
     static const uint32_t kRuns[] = {1, 2};
+    // the grid: converging reach over targets x warm-up x runs per lane, then
+    // the plain reach over targets x runs per lane
+    std::vector<Options> grid;
+    for (int conv = 1; conv >= 0; --conv)
+        for (uint32_t tgt : kTargets)
+            for (uint32_t w : (conv ? std::vector<uint32_t>(std::begin(kWarm), std::end(kWarm)) : std::vector<uint32_t>{saved.warm}))
+                for (uint32_t R : kRuns) {
+                    Options o = saved;
+                    o.converge = conv;
+                    o.chunk_target = tgt;
+                    o.warm = w;
+                    o.runs_per_lane = R;
+                    grid.push_back(o);
+                }
     ri_result first{}, r{};
     int rc = recognize(h, text, n, stream, algo, 0, &first, nullptr, 0);
     if (rc) return rc;
     Options best = saved;
     double best_ms = 1e30;
     uint32_t trials = 0;
-    uint32_t prev_chunks = 0;
-    for (uint32_t tgt : kTargets) {
-        for (uint32_t w : kWarm) {
-            for (uint32_t R : kRuns) {
-                {
-                    std::lock_guard<std::mutex> lk(h->mu);
-                    h->opt = saved;
-                    h->opt.converge = 1;
-                    h->opt.chunk_target = tgt;
-                    h->opt.warm = w;
-                    h->opt.runs_per_lane = R;
-                }
-                rc = recognize(h, text, n, stream, algo, 0, &r, nullptr, 0);   // warm
-                if (rc) break;
-                double t[3];
-                for (double &ti : t) {
-                    auto t0 = std::chrono::steady_clock::now();
-                    rc = recognize(h, text, n, stream, algo, 0, &r, nullptr, 0);
-                    ti = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-                    if (rc) break;
-                }
-                if (rc) break;
-                if (r.accept != first.accept || r.final_state != first.final_state) {
-                    std::lock_guard<std::mutex> lk(h->mu);
-                    h->opt = saved;
-                    return fail(RI_ERR_DEVICE, "internal: results differ between tuning trials");
-                }
-                std::sort(t, t + 3);
-                ++trials;
-                if (t[1] < best_ms) {
-                    best_ms = t[1];
-                    best = h->opt;
-                }
-            }
+    auto timed = [&](double *ms) -> int {
+        auto t0 = std::chrono::steady_clock::now();
+        const int e = recognize(h, text, n, stream, algo, 0, &r, nullptr, 0);
+        *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return e;
+    };
+    for (const Options &o : grid) {
+        {
+            std::lock_guard<std::mutex> lk(h->mu);
+            h->opt = o;
+        }
+        double t[3];
+        rc = timed(&t[0]);   // warm-up call; a setting far slower than the best is not timed further
+        if (rc) break;
+        if (t[0] > 4 * best_ms) continue;
+        for (double &ti : t) {
+            rc = timed(&ti);
             if (rc) break;
         }
         if (rc) break;
-        if (r.chunks == prev_chunks) break;   // text too short for more chunks
-        prev_chunks = r.chunks;
+        if (r.accept != first.accept || r.final_state != first.final_state) {
+            std::lock_guard<std::mutex> lk(h->mu);
+            h->opt = saved;
+            return fail(RI_ERR_DEVICE, "internal: results differ between tuning trials");
+        }
+        std::sort(t, t + 3);
+        ++trials;
+        if (t[1] < best_ms) {
+            best_ms = t[1];
+            best = o;
+        }
     }
     std::lock_guard<std::mutex> lk(h->mu);
     h->opt = saved;
@@ -1290,6 +1277,7 @@ int ri_autotune(ri_handle *h, const uint8_t *text, size_t n, void *stream, int a
         out->runs_per_lane = best.runs_per_lane;
         out->trials = trials;
         out->best_ms = (float)best_ms;
+        out->converge = (uint32_t)best.converge;
     }
     return RI_OK;
 }

@@ -231,217 +231,213 @@ __global__ void __launch_bounds__(1024) plain_kernel(PlainArgs a) {
 // converging reach, step 1: warm-up and merging
 // ---------------------------------------------------------------------------
 //
-// A block takes groups of CW consecutive chunks (CW a power of two <= 64,
-// chosen so that the LDS tiles fit).  Its waves share out the start groups:
-// lane l scans chunk (l % CW) from R starts of sub-group (l / CW), for the
-// first `warm` bytes of the chunk; state ids go to an LDS tile [L][CW].
-// Merging then takes one chunk per wave, lanes over the starts: a leader
-// loop (one ballot per distinct state) gives every live start the index of
-// its state's class, in order of first appearance.  A chunk with more than
-// 64 distinct states keeps every live start as its own run.  Run slots are
-// allocated with one atomic per group, so the runs of a chunk are
-// consecutive; the alias tile is written out coalesced over chunks.
-// Row strides of the LDS tiles, padded so that a wave reading one column
-// (lanes over starts) hits distinct banks: the stride in 4-byte words is odd.
+// One wavefront per chunk; a block of 16 waves takes 16 consecutive chunks
+// at a time (static grid-stride schedule).  The lanes hold the starts, R per
+// lane (start s = base + r * 64 + lane), in blocks of 64 R starts.  The
+// chunk's first `warm` bytes are loaded once, 64 per register, as byte codes;
+// step j broadcasts code j to the wave with readlane, so every lookup of the
+// warm-up is a table access.  After the warm-up the runs of the chunk that
+// are in the same state form one class (one merged run): a leader loop finds
+// the distinct states (one ballot each), lane i keeps the state of class i.
+// A chunk with more than 64 distinct states keeps every live start as its own
+// run (numbered in start order).  The run slots of the block's 16 chunks come
+// from one atomic; the alias row of a chunk ([nchunks][L], class of every
+// start) is written contiguously.
 template <typename T> __host__ __device__ constexpr uint32_t tile_stride(uint32_t cols) {
     return cols + (sizeof(T) == 1 ? 4u : sizeof(T) == 2 ? 2u : 1u);
 }
 
-template <typename TE, typename TL, typename TA, int R, bool LDS>
+constexpr uint32_t kWarmWaves = 16;
+
+// Warm-up of the start block at `base` over codes[0..wlen) (codes of bytes
+// 64 q + lane in register q).
+template <typename TE, int R>
+__device__ __forceinline__ void warm_block(uint32_t (&st)[R], const uint32_t (&code)[4], uint32_t wlen,
+                                           const TE *tab, uint32_t dead) {
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+        const uint32_t j0 = q * kWave;
+        if (j0 >= wlen) break;
+        const uint32_t jn = wlen - j0 < kWave ? wlen - j0 : kWave;
+        for (uint32_t j = 0; j < jn; j += 16) {
+            if (__ballot(any_alive<R>(st, dead)) == 0) return;
+            if (j + 16 <= jn) {
+#pragma unroll
+                for (uint32_t k = 0; k < 16; ++k) {
+                    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)code[q], (int)(j + k));
+#pragma unroll
+                    for (int r = 0; r < R; ++r) st[r] = next_state<TE>(tab, st[r], c);
+                }
+            } else {
+                for (uint32_t k = j; k < jn; ++k) {
+                    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)code[q], (int)k);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) st[r] = next_state<TE>(tab, st[r], c);
+                }
+            }
+        }
+    }
+}
+
+template <typename TE, typename TA, int R, bool LDS>
 __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
-    __shared__ uint32_t s_job, s_base;
+    __shared__ uint32_t s_cnt[kWarmWaves], s_base;
     const TE *tab;
     const uint16_t *cls;
     stage_tables<TE, LDS>(a.s, smem, tab, cls);
+    __syncthreads();   // tables staged
     const uint32_t L = a.s.L;
-    const uint32_t CW = a.cw;
-    const uint32_t WS = a.warm < a.s.cs ? a.warm : (uint32_t)a.s.cs;   // staged bytes per chunk
-    const uint32_t TS = tile_stride<TL>(CW), AS = tile_stride<TA>(CW);
-    const uint32_t spl = kWave / CW;                   // start sub-groups per wave
-    uint8_t *area = smem + tables_lds<TE, LDS>(a.s.table_bytes);
-    uint32_t *cstate = reinterpret_cast<uint32_t *>(area);                // [CW][64] class states
-    uint32_t *dcount = cstate + (size_t)CW * kWave;                       // [CW] runs per chunk (+ spill flag)
-    uint32_t *dfirst = dcount + CW;                                       // [CW] first run (group-relative)
-    uint16_t *scode = reinterpret_cast<uint16_t *>(dfirst + CW);          // [WS][CW] byte codes
-    TL *tile = reinterpret_cast<TL *>(
-        reinterpret_cast<uint8_t *>(scode) + (((size_t)WS * CW * 2 + 15) & ~(size_t)15));   // [L][TS]
-    TA *atile = reinterpret_cast<TA *>(
-        reinterpret_cast<uint8_t *>(tile) + (((size_t)L * TS * sizeof(TL) + 15) & ~(size_t)15));  // [L][AS]
+    const uint32_t dead = a.s.dead;
     const uint32_t lane = threadIdx.x % kWave;
     const uint32_t wave = threadIdx.x / kWave;
-    const uint32_t nwaves = blockDim.x / kWave;
-    const uint32_t col = lane % CW, sub = lane / CW;
-    const uint32_t groups = (L + spl * R - 1) / (spl * R);
-    constexpr uint32_t kSpill = 0x80000000u;
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    const uint32_t per_block = (uint32_t)kWave * R;          // starts per start block
+    const uint32_t nblk = (L + per_block - 1) / per_block;
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    TA *alias = reinterpret_cast<TA *>(a.alias);
+    const uint32_t iters = (a.s.nchunks + kWarmWaves - 1) / kWarmWaves;
 
-    // chunk groups cost about the same: static grid-stride schedule
-    for (uint32_t cg = blockIdx.x; cg < a.chunk_groups; cg += gridDim.x) {
-        __syncthreads();   // tables staged / previous group done with the tiles
-        if (threadIdx.x == 0) s_job = 0;
-        // stage the warm-up bytes of the group's chunks as byte codes,
-        // step-major so that lanes (chunks) read consecutive entries
-        for (uint32_t i = threadIdx.x; i < CW * (WS / 16); i += blockDim.x) {
-            const uint32_t c = i % CW, q = i / CW;
-            const uint32_t chunk = cg * CW + c;
-            uint32_t w4[4] = {0, 0, 0, 0};
-            if (chunk < a.s.nchunks) {
-                uint64_t b, e;
-                bool first;
-                chunk_bounds(a.s, chunk, b, e, first);
-                const uint64_t b0 = b + q * 16;
-                if (b0 + 16 <= e) {
-                    const uint4 v = *reinterpret_cast<const uint4 *>(at(b0));
-                    w4[0] = v.x; w4[1] = v.y; w4[2] = v.z; w4[3] = v.w;
-                } else {
-                    for (uint32_t k = 0; b0 + k < e; ++k) w4[k / 4] |= (uint32_t)*at(b0 + k) << (8 * (k % 4));
-                }
-            }
+    for (uint32_t it = blockIdx.x; it < iters; it += gridDim.x) {
+        const uint32_t chunk = it * kWarmWaves + wave;
+        const bool ok = chunk < a.s.nchunks;
+        uint64_t b = 0, e = 0;
+        bool first = false;
+        if (ok) chunk_bounds(a.s, chunk, b, e, first);
+        const uint32_t wlen = ok ? (uint32_t)(e - b < a.warm ? e - b : a.warm) : 0u;
+        // byte codes of the warm-up bytes, 64 per register
+        uint32_t code[4] = {0, 0, 0, 0};
 #pragma unroll
-            for (int k = 0; k < 16; ++k) scode[(q * 16 + k) * CW + c] = cls[(w4[k / 4] >> (8 * (k % 4))) & 0xffu];
+        for (uint32_t q = 0; q < 4; ++q) {
+            const uint32_t j = q * kWave + lane;
+            if (j < wlen) code[q] = cls[*at(b + j)];
         }
-        __syncthreads();
-
-        // warm-up of every start from the staged codes
-        {
-            const uint32_t chunk = cg * CW + col;
-            const bool ok = chunk < a.s.nchunks;
-            uint32_t wlen = 0;
-            bool first = false;
-            if (ok) {
-                uint64_t b, e;
-                chunk_bounds(a.s, chunk, b, e, first);
-                wlen = e - b < WS ? (uint32_t)(e - b) : WS;
+        // warm-up and classes, start block by start block
+        uint32_t cs = dead;        // lane i: state (row offset) of class i
+        uint32_t D = 0;            // classes, or live starts once spilled
+        bool spill = false;
+        uint32_t st[R];
+        uint32_t al[R];
+        for (uint32_t blk = 0; blk < nblk; ++blk) {
+            const uint32_t base = blk * per_block;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t s = base + r * kWave + lane;
+                st[r] = (ok && s < L && (!first || s == 0)) ? a.s.starts[s] : dead;
             }
-            for (;;) {
-                uint32_t g = 0;
-                if (lane == 0) g = atomicAdd(&s_job, 1u);
-                g = __shfl(g, 0);
-                if (g >= groups) break;
-                const uint32_t s0 = (g * spl + sub) * R;
-                uint32_t st[R];
+            warm_block<TE, R>(st, code, wlen, tab, dead);
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const uint32_t s = s0 + r;
-                    st[r] = (ok && s < L && (!first || s == 0)) ? a.s.starts[s] : a.s.dead;
+            for (int r = 0; r < R; ++r) {
+                al[r] = kNone;
+                const bool live = st[r] != dead;
+                if (spill) {
+                    const uint64_t m = __ballot(live);
+                    D += (uint32_t)__builtin_popcountll(m);
+                    continue;
                 }
-                for (uint32_t j0 = 0; j0 < WS; j0 += 16) {
-                    if (__ballot(any_alive<R>(st, a.s.dead) && j0 < wlen) == 0) break;
-                    if (j0 + 16 <= wlen) {
-#pragma unroll
-                        for (int k = 0; k < 16; ++k) {
-                            const uint32_t c = scode[(j0 + k) * CW + col];
-#pragma unroll
-                            for (int r = 0; r < R; ++r) st[r] = next_state<TE>(tab, st[r], c);
-                        }
-                    } else {
-                        for (uint32_t j = j0; j < wlen; ++j) {
-                            const uint32_t c = scode[j * CW + col];
-#pragma unroll
-                            for (int r = 0; r < R; ++r) st[r] = next_state<TE>(tab, st[r], c);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const uint32_t s = s0 + r;
-                    if (s < L) tile[s * TS + col] = st[r] == a.s.dead ? all_ones<TL>() : (TL)(st[r] / a.s.row_bytes);
-                }
-            }
-        }
-        __syncthreads();
-
-        // merge: one chunk per wave, lanes over starts
-        for (uint32_t c = wave; c < CW; c += nwaves) {
-            uint32_t D = 0;           // classes so far (wave-uniform)
-            bool spill = false;
-            for (uint32_t s0 = 0; s0 < L && !spill; s0 += kWave) {
-                const uint32_t s = s0 + lane;
-                const uint32_t v = s < L ? (uint32_t)tile[s * TS + c] : (uint32_t)all_ones<TL>();
-                const bool live = v != (uint32_t)all_ones<TL>();
-                uint32_t al = (uint32_t)all_ones<TA>();
-                for (uint32_t i = 0; i < D; ++i)
-                    if (live && v == cstate[c * kWave + i]) al = i;
-                uint64_t open = __ballot(live && al == (uint32_t)all_ones<TA>());
+                uint64_t open = __ballot(live);
                 while (open) {
                     const int leader = __builtin_ctzll(open);
-                    const uint32_t lv = (uint32_t)__shfl((int)v, leader);
-                    if (D == kWave) { spill = true; break; }
-                    const uint64_t same = __ballot(live && v == lv);
-                    if (live && v == lv) al = D;
-                    if (lane == 0) cstate[c * kWave + D] = lv;
-                    ++D;
+                    const uint32_t lv = (uint32_t)__builtin_amdgcn_readlane((int)st[r], leader);
+                    const uint64_t hit = __ballot(lane < D && cs == lv);
+                    uint32_t ci;
+                    if (hit) {
+                        ci = (uint32_t)__builtin_ctzll(hit);
+                    } else {
+                        if (D == kWave) { spill = true; break; }
+                        ci = D;
+                        if (lane == D) cs = lv;
+                        ++D;
+                    }
+                    const uint64_t same = __ballot(live && st[r] == lv);
+                    if (live && st[r] == lv) al[r] = ci;
                     open &= ~same;
                 }
-                if (!spill && s < L) atile[s * AS + c] = (TA)al;
-            }
-            if (spill) {
-                // every live start is its own run, numbered in start order
-                D = 0;
-                for (uint32_t s0 = 0; s0 < L; s0 += kWave) {
-                    const uint32_t s = s0 + lane;
-                    const bool live = s < L && tile[s * TS + c] != all_ones<TL>();
-                    const uint64_t m = __ballot(live);
-                    if (s < L) atile[s * AS + c] = live ? (TA)(D + __builtin_popcountll(m & lane_lt)) : all_ones<TA>();
-                    D += __builtin_popcountll(m);
+                if (spill) {
+                    // count the live starts of every start seen so far
+                    D = 0;
+                    for (uint32_t b2 = 0; b2 <= blk; ++b2) {
+                        uint32_t s2[R];
+#pragma unroll
+                        for (int r2 = 0; r2 < R; ++r2) {
+                            const uint32_t s = b2 * per_block + r2 * kWave + lane;
+                            s2[r2] = (ok && s < L && (!first || s == 0)) ? a.s.starts[s] : dead;
+                        }
+                        warm_block<TE, R>(s2, code, wlen, tab, dead);
+#pragma unroll
+                        for (int r2 = 0; r2 < R; ++r2)
+                            if (b2 < blk || r2 <= r) D += (uint32_t)__builtin_popcountll(__ballot(s2[r2] != dead));
+                    }
+                    continue;
+                }
+                if (nblk > 1 && ok) {
+                    const uint32_t s = base + r * kWave + lane;
+                    if (s < L) alias[(uint64_t)chunk * L + s] = al[r] == kNone ? all_ones<TA>() : (TA)al[r];
                 }
             }
-            if (lane == 0) dcount[c] = D | (spill ? kSpill : 0u);
         }
+        // run slots of the block's chunks: one atomic
+        if (lane == 0) s_cnt[wave] = ok ? D : 0u;
         __syncthreads();
-
-        // run slots: prefix over the group's chunks, one global atomic
         if (wave == 0) {
-            const uint32_t d = lane < CW ? (dcount[lane] & ~kSpill) : 0u;
+            const uint32_t d = lane < kWarmWaves ? s_cnt[lane] : 0u;
             uint32_t incl = d;
 #pragma unroll
-            for (int k = 1; k < kWave; k <<= 1) {
+            for (int k = 1; k < (int)kWarmWaves; k <<= 1) {
                 const uint32_t o = __shfl_up(incl, k);
                 if ((int)lane >= k) incl += o;
             }
-            if (lane < CW) dfirst[lane] = incl - d;
-            if (lane == kWave - 1) s_base = atomicAdd(&a.counters[1], incl);
+            if (lane == kWarmWaves - 1) s_base = atomicAdd(&a.counters[1], incl);
+            if (lane < kWarmWaves) s_cnt[lane] = incl - d;
         }
         __syncthreads();
-        const uint32_t base = s_base;
-
-        // run records: one chunk per wave
-        for (uint32_t c = wave; c < CW; c += nwaves) {
-            const uint32_t chunk = cg * CW + c;
-            if (chunk >= a.s.nchunks) continue;
-            const uint32_t first = base + dfirst[c];
-            const uint32_t dc = dcount[c];
+        if (ok) {
+            const uint32_t firstrun = s_base + s_cnt[wave];
             if (lane == 0) {
-                a.run_base[chunk] = first;
-                if (a.run_count) a.run_count[chunk] = dc & ~kSpill;
-                if ((dc & ~kSpill) > kRowCap) atomicOr(&a.counters[2], 1u);
+                a.run_base[chunk] = firstrun;
+                if (a.run_count) a.run_count[chunk] = D;
+                if (D > kRowCap) atomicOr(&a.counters[2], 1u);
             }
-            if (!(dc & kSpill)) {
-                if (lane < dc) {
-                    a.run_chunk[first + lane] = chunk;
-                    a.run_state[first + lane] = cstate[c * kWave + lane];
+            if (!spill) {
+                if (lane < D) {
+                    a.run_chunk[firstrun + lane] = chunk;
+                    a.run_state[firstrun + lane] = cs / a.s.row_bytes;
+                }
+                if (nblk == 1) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const uint32_t s = r * kWave + lane;
+                        if (s < L) alias[(uint64_t)chunk * L + s] = al[r] == kNone ? all_ones<TA>() : (TA)al[r];
+                    }
                 }
             } else {
-                for (uint32_t s0 = 0; s0 < L; s0 += kWave) {
-                    const uint32_t s = s0 + lane;
-                    if (s < L) {
-                        const TA al = atile[s * AS + c];
-                        if (al != all_ones<TA>()) {
-                            a.run_chunk[first + al] = chunk;
-                            a.run_state[first + al] = tile[s * TS + c];
+                // every live start is its own run, in start order
+                uint32_t idx = 0;
+                for (uint32_t blk = 0; blk < nblk; ++blk) {
+                    const uint32_t base = blk * per_block;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const uint32_t s = base + r * kWave + lane;
+                        st[r] = (s < L && (!first || s == 0)) ? a.s.starts[s] : dead;
+                    }
+                    warm_block<TE, R>(st, code, wlen, tab, dead);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const uint32_t s = base + r * kWave + lane;
+                        const bool live = st[r] != dead;
+                        const uint64_t m = __ballot(live);
+                        const uint32_t my = idx + (uint32_t)__builtin_popcountll(m & lane_lt);
+                        if (live) {
+                            a.run_chunk[firstrun + my] = chunk;
+                            a.run_state[firstrun + my] = st[r] / a.s.row_bytes;
                         }
+                        if (s < L) alias[(uint64_t)chunk * L + s] = live ? (TA)my : all_ones<TA>();
+                        idx += (uint32_t)__builtin_popcountll(m);
                     }
                 }
             }
         }
-        // alias tile out, coalesced over chunks
-        TA *alias = reinterpret_cast<TA *>(a.alias);
-        for (uint32_t i = threadIdx.x; i < L * CW; i += blockDim.x) {
-            const uint32_t s = i / CW, c = i - s * CW;
-            const uint32_t chunk = cg * CW + c;
-            if (chunk < a.s.nchunks) alias[(uint64_t)s * a.s.nchunks + chunk] = atile[s * AS + c];
-        }
+        __syncthreads();   // s_cnt / s_base reused by the next chunks
     }
 }
 
@@ -573,12 +569,12 @@ struct PlainView {
 
 template <typename TA>
 struct ConvView {
-    const TA *alias;
+    const TA *alias;           // [nchunks][L]
     const uint32_t *base;
     const uint32_t *fin;
-    uint32_t nchunks;
+    uint32_t L;
     __device__ __forceinline__ uint32_t get(uint32_t s, uint32_t c) const {
-        const TA v = alias[(uint64_t)s * nchunks + c];
+        const TA v = alias[(uint64_t)c * L + s];
         return v == all_ones<TA>() ? kNoState : fin[base[c] + v];
     }
 };
@@ -590,8 +586,8 @@ hipError_t with_view(const JoinArgs &a, F &&f) {
         return f(PlainView<uint32_t>{(const uint32_t *)a.lam, a.nchunks});
     }
     if (a.alias_bytes == 1)
-        return f(ConvView<uint8_t>{(const uint8_t *)a.alias, a.run_base, a.run_final, a.nchunks});
-    return f(ConvView<uint16_t>{(const uint16_t *)a.alias, a.run_base, a.run_final, a.nchunks});
+        return f(ConvView<uint8_t>{(const uint8_t *)a.alias, a.run_base, a.run_final, a.L});
+    return f(ConvView<uint16_t>{(const uint16_t *)a.alias, a.run_base, a.run_final, a.L});
 }
 
 // ---------------------------------------------------------------------------
@@ -750,7 +746,7 @@ __global__ void __launch_bounds__(256) join_cls_kernel(ClsJoinArgs a) {
         TA v = all_ones<TA>();
         if (k < gn) {
             const uint64_t c = a.member_chunk ? a.member_chunk[m0 + k] : (uint64_t)(m0 + k) * a.span;
-            v = alias[(uint64_t)t * a.nchunks + c];
+            v = alias[c * L + t];
             if (LEVEL0 && v != all_ones<TA>()) atomicMax(&sncls[k], (uint32_t)v + 1);
         }
         salias[t * GS + k] = v;
@@ -877,7 +873,7 @@ __global__ void __launch_bounds__(256) hit_prod0_kernel(HitArgs a) {
                 for (uint32_t w = 0; w < (uint32_t)W; ++w) {
                     for (uint32_t bits = cw[w]; bits; bits &= bits - 1) {
                         const uint32_t t = w * 32 + __builtin_ctz(bits);
-                        const TA j = alias[(uint64_t)t * a.nchunks + k + 1];
+                        const TA j = alias[(uint64_t)(k + 1) * a.L + t];
                         if (j != all_ones<TA>() && (uint32_t)j < 64) m |= 1ull << j;
                     }
                 }
@@ -1093,7 +1089,7 @@ __global__ void batch_final_cls_kernel(BatchFinalArgs b, FinalArgs f, ClsJoinArg
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t == 0) reset_counters(f.counters);
     if (t >= b.ntexts) return;
-    const TA c0 = reinterpret_cast<const TA *>(a.alias)[b.text_slot[t]];   // start 0's class
+    const TA c0 = reinterpret_cast<const TA *>(a.alias)[(uint64_t)b.text_slot[t] * a.L];   // start 0's class
     uint32_t x[W];
     load_row<W>(x, c0 != all_ones<TA>() ? a.cont_in + ((uint64_t)t * a.L + c0) * W : nullptr);
     decide<W>(x, f, b.results + (uint64_t)b.text_out[t] * 2);
@@ -1191,31 +1187,21 @@ hipError_t launch_plain(const PlainArgs &a, const KernelShape &k, int grid, size
 
 hipError_t launch_warm(const WarmArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st) {
     return dispatch_te(k.entry_bytes, [&](auto te) {
-        return dispatch_tl(k.tile_bytes, [&](auto tl) {
-            return dispatch_ta(k.alias_bytes, [&](auto ta) {
-                return dispatch_r(k.runs_per_lane, [&](auto r) {
-                    return dispatch_b(k.table_in_lds, [&](auto lds_t) {
-                        auto fn = warm_kernel<decltype(te), decltype(tl), decltype(ta), decltype(r)::value,
-                                              decltype(lds_t)::value>;
-                        if (grid == 0) { g_fn = reinterpret_cast<const void *>(fn); return hipSuccess; }
-                        hipLaunchKernelGGL(fn, dim3(grid), dim3(k.block_threads), lds, st, a);
-                        return hipGetLastError();
-                    });
+        return dispatch_ta(k.alias_bytes, [&](auto ta) {
+            return dispatch_r(k.runs_per_lane, [&](auto r) {
+                return dispatch_b(k.table_in_lds, [&](auto lds_t) {
+                    auto fn = warm_kernel<decltype(te), decltype(ta), decltype(r)::value, decltype(lds_t)::value>;
+                    if (grid == 0) { g_fn = reinterpret_cast<const void *>(fn); return hipSuccess; }
+                    hipLaunchKernelGGL(fn, dim3(grid), dim3(k.block_threads), lds, st, a);
+                    return hipGetLastError();
                 });
             });
         });
     });
 }
 
-size_t warm_lds_bytes(const KernelShape &k, uint32_t L, uint32_t table_bytes, uint32_t cw, uint32_t ws) {
-    const size_t tables = (k.table_in_lds ? table_bytes : 0) + 512;
-    const size_t head = (size_t)cw * kWave * 4 + (size_t)cw * 8;
-    const size_t codes = ((size_t)ws * cw * 2 + 15) & ~(size_t)15;
-    const uint32_t ts = k.tile_bytes == 2 ? tile_stride<uint16_t>(cw) : tile_stride<uint32_t>(cw);
-    const uint32_t as = k.alias_bytes == 1 ? tile_stride<uint8_t>(cw) : tile_stride<uint16_t>(cw);
-    const size_t tile = ((size_t)L * ts * k.tile_bytes + 15) & ~(size_t)15;
-    const size_t atile = (size_t)L * as * k.alias_bytes;
-    return tables + head + codes + tile + atile;
+size_t warm_lds_bytes(const KernelShape &k, uint32_t table_bytes) {
+    return (k.table_in_lds ? table_bytes : 0) + 512;
 }
 
 hipError_t launch_long(const LongArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st) {

@@ -51,22 +51,19 @@ hipError_t launch_plain(const PlainArgs &a, const KernelShape &k, int grid, size
 
 // ---- converging reach, step 1: warm-up of every run, then merging of runs
 // of one chunk that are in the same state (state convergence) ----
-constexpr uint32_t kDedupCap = 32;   // distinct states searched per chunk
 struct WarmArgs {
     ScanArgs s;
-    uint32_t warm;             // bytes scanned by every run before merging (multiple of 16, <= 256)
-    uint32_t cw;               // chunks per group: power of two <= 64
-    uint32_t chunk_groups;     // ceil(nchunks / cw)
-    void *alias;               // [L][nchunks] local run index, all-ones = no run
+    uint32_t warm;             // bytes scanned by every run before merging (<= 256)
+    void *alias;               // [nchunks][L] class (merged run) of every start, all-ones = no run
     uint32_t *run_base;        // [nchunks] first run of the chunk
     uint32_t *run_count;       // [nchunks] runs of the chunk (nullptr: not needed)
     uint32_t *run_chunk;       // [cap]
-    uint32_t *run_state;       // [cap] state id after the warm-up, kNoState if none
+    uint32_t *run_state;       // [cap] state id after the warm-up
     uint32_t *counters;        // [1] runs allocated; [2] set to 1 when a chunk has more
                                // than kRowCap runs
 };
 hipError_t launch_warm(const WarmArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st);
-size_t warm_lds_bytes(const KernelShape &k, uint32_t L, uint32_t table_bytes, uint32_t cw, uint32_t ws);
+size_t warm_lds_bytes(const KernelShape &k, uint32_t table_bytes);
 
 // ---- converging reach, step 2: the merged runs to the chunk end ----
 struct LongArgs {
@@ -87,7 +84,7 @@ struct JoinArgs {
     // level 0 input: either plain chunk maps or the converged form
     bool converged;
     const void *lam;           // plain: [L][nchunks]
-    const void *alias;         // converged: [L][nchunks]
+    const void *alias;         // converged: [nchunks][L]
     const uint32_t *run_base;  // converged
     const uint32_t *run_final; // converged
     int tile_bytes;
@@ -117,7 +114,7 @@ hipError_t launch_materialize(const JoinArgs &a, int32_t *out, hipStream_t s);
 // runs of the chunk); level >= 1 members are relations of the level below
 // (span = chunks per member; classes of a member = runs of its first chunk).
 struct ClsJoinArgs {
-    const void *alias;         // [L][nchunks] local run index, all-ones = no run
+    const void *alias;         // [nchunks][L] local run index, all-ones = no run
     uint32_t nchunks;
     uint32_t L;
     uint32_t G;                // members per group
@@ -151,7 +148,8 @@ hipError_t launch_join_cls(const ClsJoinArgs &a, int W, int alias_bytes, bool le
 // must be used.
 constexpr uint32_t kRowCap = 8;
 struct HitArgs {
-    const void *alias;         // [L][nchunks]
+    const void *alias;         // [nchunks][L]
+    uint32_t L;
     uint32_t nchunks;          // K
     const uint32_t *run_base;
     const uint32_t *run_count;
