@@ -27,16 +27,20 @@ int fail(int code, const std::string &msg) {
 constexpr uint32_t kJoinGroup = 64;          // members per join group
 constexpr uint64_t kMinAutoChunk = 256;      // smallest automatic chunk size (bytes)
 constexpr uint64_t kMaxLamBytes = 1ull << 31;
+constexpr uint64_t kMaxAutoPairs = 1ull << 25;   // (start, chunk) pairs of an automatic chunking
 constexpr int kMaxDevices = 64;
 
 uint64_t round_up(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
 
-// FNV-1a over words; the finalize kernel uses the same function.
-uint32_t hash_words(const uint32_t *x, uint32_t W) {
+// FNV-1a over the members of a set in ascending order; the finalize kernels
+// use the same function.
+uint32_t hash_members(const std::vector<uint32_t> &m) {
     uint32_t h = 2166136261u;
-    for (uint32_t w = 0; w < W; ++w) { h ^= x[w]; h *= 16777619u; }
+    for (uint32_t x : m) { h ^= x; h *= 16777619u; }
     return h;
 }
+
+constexpr uint32_t kMaxDenseWords = 64;   // dense content bitsets up to 2048 interface states
 
 struct AlgoHost {
     bool relational = false;
@@ -46,9 +50,10 @@ struct AlgoHost {
     uint16_t code[256] = {};                   // byte -> class * entry_bytes
     std::vector<uint8_t> table;                // padded to 16 bytes
     std::vector<uint32_t> starts;              // entry offsets of the start states
-    std::vector<uint32_t> content;             // relations: [nstates][W]
-    std::vector<uint32_t> fmask;               // relations: [W]
-    std::vector<uint32_t> hash;                // relations: [cap][W + 1]
+    std::vector<uint32_t> content;             // relations, W <= kMaxDenseWords: [nstates][W] bitsets
+    std::vector<uint32_t> csr_off, csr_idx;    // relations: content as sorted member lists
+    std::vector<uint32_t> fmask;               // relations: [W] final states of N'
+    std::vector<uint32_t> hash;                // relations: [cap][2] = (state, final id), state ~0 = empty
     uint32_t hash_cap = 0;
     std::vector<int32_t> final_of_state;       // functions
     std::vector<uint8_t> accept_of_state;      // functions
@@ -57,6 +62,7 @@ struct AlgoHost {
 struct AlgoDevice {
     void *table = nullptr;
     uint32_t *starts = nullptr, *content = nullptr, *fmask = nullptr, *hash = nullptr;
+    uint32_t *csr_off = nullptr, *csr_idx = nullptr;
     uint16_t *code = nullptr;
     int32_t *final_of_state = nullptr;
     uint8_t *accept_of_state = nullptr;
@@ -150,9 +156,16 @@ void pack_all(ri_handle *h) {
     r.W = W;
     r.starts.resize(r.L);
     for (uint32_t q = 0; q < r.L; ++q) r.starts[q] = A.Bq.initial[q] * K * r.entry_bytes;
-    r.content.assign((size_t)A.Bq.n * W, 0);
-    for (uint32_t p = 0; p < A.Bq.n; ++p)
-        for (uint32_t q : A.Bq.content[p]) r.content[(size_t)p * W + q / 32] |= 1u << (q % 32);
+    if (W <= kMaxDenseWords) {
+        r.content.assign((size_t)A.Bq.n * W, 0);
+        for (uint32_t p = 0; p < A.Bq.n; ++p)
+            for (uint32_t q : A.Bq.content[p]) r.content[(size_t)p * W + q / 32] |= 1u << (q % 32);
+    }
+    r.csr_off.assign(A.Bq.n + 1, 0);
+    for (uint32_t p = 0; p < A.Bq.n; ++p) {
+        r.csr_off[p + 1] = r.csr_off[p] + (uint32_t)A.Bq.content[p].size();
+        r.csr_idx.insert(r.csr_idx.end(), A.Bq.content[p].begin(), A.Bq.content[p].end());   // ascending
+    }
     r.fmask.assign(W, 0);
     for (uint32_t q = 0; q < A.nq.n; ++q)
         if (A.nq.final[q]) r.fmask[q / 32] |= 1u << (q % 32);
@@ -161,15 +174,13 @@ void pack_all(ri_handle *h) {
     uint32_t cap = 1;
     while (cap < 2 * nkeys + 2) cap *= 2;
     r.hash_cap = cap;
-    r.hash.assign((size_t)cap * (W + 1), 0);
-    for (uint32_t s = 0; s < cap; ++s) r.hash[(size_t)s * (W + 1) + W] = (uint32_t)-2;
+    r.hash.assign((size_t)cap * 2, 0xFFFFFFFFu);
     for (uint32_t p = 0; p < A.Bq.n; ++p) {
         if (A.final_id[p] < 0) continue;
-        const uint32_t *key = &r.content[(size_t)p * W];
-        uint32_t slot = hash_words(key, W) & (cap - 1);
-        while (r.hash[(size_t)slot * (W + 1) + W] != (uint32_t)-2) slot = (slot + 1) & (cap - 1);
-        std::memcpy(&r.hash[(size_t)slot * (W + 1)], key, W * sizeof(uint32_t));
-        r.hash[(size_t)slot * (W + 1) + W] = (uint32_t)A.final_id[p];
+        uint32_t slot = hash_members(A.Bq.content[p]) & (cap - 1);
+        while (r.hash[(size_t)slot * 2] != 0xFFFFFFFFu) slot = (slot + 1) & (cap - 1);
+        r.hash[(size_t)slot * 2] = p;
+        r.hash[(size_t)slot * 2 + 1] = (uint32_t)A.final_id[p];
     }
 
     // RI_ALGO_DFA: minimal DFA, all states as starts; functional join
@@ -227,6 +238,8 @@ int ensure_device(ri_handle *h, int device) {
         HIP_TRY(upload(&D.starts, H.starts.data(), H.starts.size() * 4));
         if (H.relational) {
             HIP_TRY(upload(&D.content, H.content.data(), H.content.size() * 4));
+            HIP_TRY(upload(&D.csr_off, H.csr_off.data(), H.csr_off.size() * 4));
+            HIP_TRY(upload(&D.csr_idx, H.csr_idx.data(), H.csr_idx.size() * 4));
             HIP_TRY(upload(&D.fmask, H.fmask.data(), H.fmask.size() * 4));
             HIP_TRY(upload(&D.hash, H.hash.data(), H.hash.size() * 4));
         } else {
@@ -274,7 +287,7 @@ int plan_chunks(const AlgoHost &H, uint64_t n, uint32_t chunks, uint32_t target,
     uint64_t cs;
     if (chunks == 0) {
         cs = std::max<uint64_t>(round_up((n + target - 1) / target, 16), kMinAutoChunk);
-        while ((uint64_t)H.L * ((n + cs - 1) / cs) * H.lam_bytes > kMaxLamBytes) cs *= 2;
+        while ((uint64_t)H.L * ((n + cs - 1) / cs) > kMaxAutoPairs) cs *= 2;
     } else {
         cs = round_up((n + chunks - 1) / chunks, 16);
         if ((uint64_t)H.L * ((n + cs - 1) / cs) * H.lam_bytes > kMaxLamBytes)
@@ -400,8 +413,8 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         return RI_OK;
     }
     const AlgoHost &H = h->algo[algo];
-    if (H.relational && H.W > 64)
-        return fail(RI_ERR_LIMIT, "interface larger than 2048 states is not supported by the device join");
+    if (H.relational && H.W > ri::kPropMaxWords)
+        return fail(RI_ERR_LIMIT, "interface larger than 32768 states is not supported by the device join");
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
     int device = 0;
     HIP_TRY(hipGetDevice(&device));
@@ -436,6 +449,8 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         opt = (chunks == 0 && h->tuned_valid[algo]) ? h->tuned[algo] : h->opt;
     }
     const bool conv = opt.converge != 0;
+    if (!conv && H.relational && H.W > kMaxDenseWords)
+        return fail(RI_ERR_LIMIT, "the plain reach joins interfaces of at most 2048 states; use RI_OPT_CONVERGE = 1");
     const uint32_t g0 = tile_group(H);
     const uint32_t ng0 = (plan.nchunks + (g0 ? g0 : kJoinGroup) - 1) / (g0 ? g0 : kJoinGroup);
     const size_t row_words = H.relational ? H.W : 1;
@@ -534,6 +549,9 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     fa.fmask = D.fmask;
     fa.hash = D.hash;
     fa.hash_cap = H.hash_cap;
+    fa.csr_off = D.csr_off;
+    fa.csr_idx = D.csr_idx;
+    fa.content = H.relational && H.W <= kMaxDenseWords ? D.content : nullptr;
     fa.final_of_state = D.final_of_state;
     fa.accept_of_state = D.accept_of_state;
     fa.result = ws->dres;
@@ -548,8 +566,9 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     ca.run_base = ja.run_base;
     ca.run_final = ja.run_final;
     ca.content = D.content;
-    const uint32_t gc = conv && H.relational ? cls_group(H, shape.alias_bytes) : 0;
-    const bool hit = gc && opt.join == 0;
+    const bool rel_conv = conv && H.relational;
+    const uint32_t gc = rel_conv && H.W <= kMaxDenseWords ? cls_group(H, shape.alias_bytes) : 0;
+    const bool hit = rel_conv && (opt.join == 0 || gc == 0);
     auto cls_join = [&]() -> int {
         ca.G = gc;
         ca.nmembers = plan.nchunks;
@@ -578,24 +597,26 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         HIP_TRY(ri::launch_finalize_cls(fa, ca, (int)H.W, shape.alias_bytes, stream));
         return RI_OK;
     };
+    ri::HitArgs ha{};
     if (hit) {
         // products of hit matrices: level 0 over the K - 1 matrices, then
         // groups of 64 products until one is left
-        ri::HitArgs ha{};
         ha.alias = ws->alias.p;
         ha.L = H.L;
         ha.nchunks = plan.nchunks;
         ha.run_base = ja.run_base;
         ha.run_count = static_cast<const uint32_t *>(ws->run_count.p);
         ha.run_final = ja.run_final;
-        ha.content = D.content;
+        ha.csr_off = D.csr_off;
+        ha.csr_idx = D.csr_idx;
+        ha.content = H.W <= kMaxDenseWords ? D.content : nullptr;
         ha.prod_in = nullptr;
         if (plan.nchunks > 1) {
             int cur = 0;
             ha.nmembers = plan.nchunks - 1;
             ha.prod_out = static_cast<uint64_t *>(ws->hprod[0].p);
             ha.rows_out = static_cast<uint32_t *>(ws->hrows[0].p);
-            HIP_TRY(ri::launch_hit_prod(ha, (int)H.W, shape.alias_bytes, true, stream));
+            HIP_TRY(ri::launch_hit_prod(ha, H.W <= kMaxDenseWords ? (int)H.W : 0, shape.alias_bytes, true, stream));
             uint32_t nm = (ha.nmembers + 63) / 64;
             while (nm > 1) {
                 ha.nmembers = nm;
@@ -603,14 +624,14 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
                 ha.rows_in = static_cast<const uint32_t *>(ws->hrows[cur].p);
                 ha.prod_out = static_cast<uint64_t *>(ws->hprod[cur ^ 1].p);
                 ha.rows_out = static_cast<uint32_t *>(ws->hrows[cur ^ 1].p);
-                HIP_TRY(ri::launch_hit_prod(ha, (int)H.W, shape.alias_bytes, false, stream));
+                HIP_TRY(ri::launch_hit_prod(ha, 0, shape.alias_bytes, false, stream));
                 cur ^= 1;
                 nm = (nm + 63) / 64;
             }
             ha.prod_in = static_cast<const uint64_t *>(ws->hprod[cur].p);
         }
         if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(ws->dbg.p), stream));
-        HIP_TRY(ri::launch_finalize_hit(fa, ha, (int)H.W, shape.alias_bytes, stream));
+        HIP_TRY(ri::launch_finalize_hit(fa, ha, H.W <= kMaxDenseWords ? (int)H.W : 0, shape.alias_bytes, stream));
     } else if (gc) {
         if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(ws->dbg.p), stream));
         rc = cls_join();
@@ -652,9 +673,14 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     HIP_TRY(hipStreamSynchronize(stream));
     if (hit && ws->hres[2] != 0) {
         // some chunk kept more runs than a hit-matrix row can index: join
-        // again with the class join (the reach results are still in place)
-        rc = cls_join();
-        if (rc) return rc;
+        // again (the reach results are still in place) with the class join,
+        // or by propagation when the interface is too large for it
+        if (gc) {
+            rc = cls_join();
+            if (rc) return rc;
+        } else {
+            HIP_TRY(ri::launch_propagate(fa, ha, H.W, shape.alias_bytes, stream));
+        }
         HIP_TRY(hipMemcpyAsync(ws->hres, ws->dres, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
     }
@@ -902,6 +928,9 @@ int run_group(ri_batch *b, const BatchGroup &g, hipStream_t stream, int32_t *res
     fa.fmask = D.fmask;
     fa.hash = D.hash;
     fa.hash_cap = H.hash_cap;
+    fa.csr_off = D.csr_off;
+    fa.csr_idx = D.csr_idx;
+    fa.content = H.relational && H.W <= kMaxDenseWords ? D.content : nullptr;
     fa.final_of_state = D.final_of_state;
     fa.accept_of_state = D.accept_of_state;
     fa.counters = g.counters;
@@ -1064,6 +1093,8 @@ void ri_free(ri_handle *h) {
             (void)hipFree(D.code);
             (void)hipFree(D.starts);
             (void)hipFree(D.content);
+            (void)hipFree(D.csr_off);
+            (void)hipFree(D.csr_idx);
             (void)hipFree(D.fmask);
             (void)hipFree(D.hash);
             (void)hipFree(D.final_of_state);

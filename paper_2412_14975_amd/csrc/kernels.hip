@@ -869,11 +869,17 @@ __global__ void __launch_bounds__(256) hit_prod0_kernel(HitArgs a) {
         if (r < R) {
             const uint32_t f = a.run_final[a.run_base[k] + r];
             if (f != kNoState) {
-                const uint32_t *cw = a.content + (uint64_t)f * W;
-                for (uint32_t w = 0; w < (uint32_t)W; ++w) {
-                    for (uint32_t bits = cw[w]; bits; bits &= bits - 1) {
-                        const uint32_t t = w * 32 + __builtin_ctz(bits);
-                        const TA j = alias[(uint64_t)(k + 1) * a.L + t];
+                const TA *row = alias + (uint64_t)(k + 1) * a.L;
+                if constexpr (W > 0) {
+                    const uint32_t *cw = a.content + (uint64_t)f * W;
+                    for (uint32_t w = 0; w < (uint32_t)W; ++w)
+                        for (uint32_t bits = cw[w]; bits; bits &= bits - 1) {
+                            const TA j = row[w * 32 + __builtin_ctz(bits)];
+                            if (j != all_ones<TA>() && (uint32_t)j < 64) m |= 1ull << j;
+                        }
+                } else {
+                    for (uint32_t i = a.csr_off[f], ie = a.csr_off[f + 1]; i < ie; ++i) {
+                        const TA j = row[a.csr_idx[i]];
                         if (j != all_ones<TA>() && (uint32_t)j < 64) m |= 1ull << j;
                     }
                 }
@@ -985,46 +991,116 @@ __global__ void __launch_bounds__(256) materialize_kernel(JoinArgs a, View view,
 // finalize
 // ---------------------------------------------------------------------------
 
-// FNV-1a over the words of a content bitset; the host fills the table with
-// the same function.
-template <int W>
-__device__ __forceinline__ uint32_t hash_words(const uint32_t (&x)[W]) {
-    uint32_t h = 2166136261u;
-#pragma unroll
-    for (int w = 0; w < W; ++w) { h ^= x[w]; h *= 16777619u; }
-    return h;
-}
-
 __device__ __forceinline__ void reset_counters(uint32_t *c) {
     c[0] = 0; c[1] = 0; c[2] = 0; c[3] = 0;
 }
 
-// Acceptance and final state of the union content x of the relation row of
-// the initial state: accept iff x meets the final states of N', final state =
-// canonical minimal-DFA id stored under x in the hash table (-1: x empty).
+// Acceptance and final state of a set X of N' states (the union content of
+// the relation row of the initial state): accept iff X meets the final
+// states of N'; final state = the canonical minimal-DFA id stored for the
+// RI-DFA state whose content is X (found by the hash of X's members, then a
+// comparison of member lists); -1 when X is empty.
+__device__ __forceinline__ uint32_t fnv_step(uint32_t h, uint32_t m) { return (h ^ m) * 16777619u; }
+
+// Probe for the state whose members equal X: `same(p)` compares.
+template <class Same>
+__device__ int32_t lookup_set(uint32_t h, Same same, const FinalArgs &f) {
+    uint32_t slot = h & (f.hash_cap - 1);
+    for (uint32_t probe = 0; probe < f.hash_cap; ++probe) {
+        const uint32_t p = f.hash[(uint64_t)slot * 2];
+        if (p == 0xFFFFFFFFu) break;   // empty slot
+        if (same(p)) return (int32_t)f.hash[(uint64_t)slot * 2 + 1];
+        slot = (slot + 1) & (f.hash_cap - 1);
+    }
+    return -3;   // not found: cannot happen for a reachable subset
+}
+
+// member list of p has exactly cnt members, all in X
+template <class Has>
+__device__ __forceinline__ bool same_list(uint32_t p, uint32_t cnt, Has has, const FinalArgs &f) {
+    const uint32_t b = f.csr_off[p], e = f.csr_off[p + 1];
+    if (e - b != cnt) return false;
+    bool eq = true;
+    for (uint32_t i = b; i < e && eq; ++i) eq = has(f.csr_idx[i]);
+    return eq;
+}
+
+// X as a bitset of nw words (any memory)
+__device__ void decide_bits(const uint32_t *x, uint32_t nw, const FinalArgs &f, int32_t *res) {
+    uint32_t acc = 0, cnt = 0, h = 2166136261u;
+    for (uint32_t w = 0; w < nw; ++w) {
+        acc |= x[w] & f.fmask[w];
+        cnt += __builtin_popcount(x[w]);
+        for (uint32_t bits = x[w]; bits; bits &= bits - 1) h = fnv_step(h, w * 32 + __builtin_ctz(bits));
+    }
+    int32_t fin = -1;
+    if (cnt)
+        fin = lookup_set(h, [&](uint32_t p) {
+            return same_list(p, cnt, [&](uint32_t m) { return ((x[m >> 5] >> (m & 31)) & 1u) != 0; }, f);
+        }, f);
+    res[0] = acc != 0;
+    res[1] = fin;
+}
+
+// X as W <= 64 words in registers; candidates compared with their dense rows
 template <int W>
 __device__ __forceinline__ void decide(const uint32_t (&x)[W], const FinalArgs &f, int32_t *res) {
-    uint32_t acc = 0, any = 0;
+    uint32_t acc = 0, any = 0, h = 2166136261u;
 #pragma unroll
     for (int w = 0; w < W; ++w) {
         acc |= x[w] & f.fmask[w];
         any |= x[w];
+        for (uint32_t bits = x[w]; bits; bits &= bits - 1) h = fnv_step(h, w * 32 + __builtin_ctz(bits));
     }
     int32_t fin = -1;
-    if (any) {
-        fin = -3;   // not found: cannot happen for a reachable subset
-        uint32_t slot = hash_words<W>(x) & (f.hash_cap - 1);
-        for (uint32_t probe = 0; probe < f.hash_cap; ++probe) {
-            const uint32_t *e = f.hash + (uint64_t)slot * (W + 1);
-            const int32_t val = (int32_t)e[W];
-            if (val == -2) break;   // empty slot
+    if (any)
+        fin = lookup_set(h, [&](uint32_t p) {
+            const uint32_t *row = f.content + (uint64_t)p * W;
             bool eq = true;
 #pragma unroll
-            for (int w = 0; w < W; ++w) eq &= e[w] == x[w];
-            if (eq) { fin = val; break; }
-            slot = (slot + 1) & (f.hash_cap - 1);
+            for (int w = 0; w < W; ++w) eq &= row[w] == x[w];
+            return eq;
+        }, f);
+    res[0] = acc != 0;
+    res[1] = fin;
+}
+
+// X as the union of up to kRowCap sorted member lists
+struct ListUnion {
+    const uint32_t *b[kRowCap];
+    const uint32_t *e[kRowCap];
+    uint32_t k;
+    __device__ bool has(uint32_t m) const {
+        for (uint32_t i = 0; i < k; ++i) {
+            const uint32_t *lo = b[i], *hi = e[i];
+            while (lo < hi) {
+                const uint32_t *mid = lo + (hi - lo) / 2;
+                if (*mid < m) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < e[i] && *lo == m) return true;
         }
+        return false;
     }
+};
+
+__device__ void decide_lists(const ListUnion &u, const FinalArgs &f, int32_t *res) {
+    const uint32_t *pos[kRowCap];
+    for (uint32_t i = 0; i < u.k; ++i) pos[i] = u.b[i];
+    uint32_t acc = 0, cnt = 0, h = 2166136261u;
+    for (;;) {   // ascending merge without repeats
+        uint32_t m = 0xFFFFFFFFu;
+        for (uint32_t i = 0; i < u.k; ++i)
+            if (pos[i] < u.e[i] && *pos[i] < m) m = *pos[i];
+        if (m == 0xFFFFFFFFu) break;
+        for (uint32_t i = 0; i < u.k; ++i)
+            if (pos[i] < u.e[i] && *pos[i] == m) ++pos[i];
+        acc |= (f.fmask[m >> 5] >> (m & 31)) & 1u;
+        ++cnt;
+        h = fnv_step(h, m);
+    }
+    int32_t fin = -1;
+    if (cnt) fin = lookup_set(h, [&](uint32_t p) { return same_list(p, cnt, [&](uint32_t m) { return u.has(m); }, f); }, f);
     res[0] = acc != 0;
     res[1] = fin;
 }
@@ -1067,20 +1143,92 @@ __global__ void finalize_hit_kernel(FinalArgs f, HitArgs a) {
     if (a0 != all_ones<TA>() && (uint32_t)a0 < kRowCap) v = a.prod_in ? a.prod_in[a0] : 1ull << a0;
     const uint32_t last = a.nchunks - 1;
     const uint32_t R = a.run_count[last];
-    uint32_t x[W];
+    if constexpr (W > 0) {
+        uint32_t x[W];
 #pragma unroll
-    for (int w = 0; w < W; ++w) x[w] = 0;
-    for (; v; v &= v - 1) {
-        const uint32_t c = __builtin_ctzll(v);
-        if (c >= R) continue;
-        const uint32_t fs = a.run_final[a.run_base[last] + c];
-        if (fs == kNoState) continue;
+        for (int w = 0; w < W; ++w) x[w] = 0;
+        for (; v; v &= v - 1) {
+            const uint32_t c = __builtin_ctzll(v);
+            if (c >= R) continue;
+            const uint32_t fs = a.run_final[a.run_base[last] + c];
+            if (fs == kNoState) continue;
 #pragma unroll
-        for (int w = 0; w < W; ++w) x[w] |= a.content[(uint64_t)fs * W + w];
+            for (int w = 0; w < W; ++w) x[w] |= a.content[(uint64_t)fs * W + w];
+        }
+        decide<W>(x, f, f.result);
+    } else {
+        ListUnion u;
+        u.k = 0;
+        for (; v && u.k < kRowCap; v &= v - 1) {
+            const uint32_t c = __builtin_ctzll(v);
+            if (c >= R) continue;
+            const uint32_t fs = a.run_final[a.run_base[last] + c];
+            if (fs == kNoState) continue;
+            u.b[u.k] = a.csr_idx + a.csr_off[fs];
+            u.e[u.k] = a.csr_idx + a.csr_off[fs + 1];
+            ++u.k;
+        }
+        decide_lists(u, f, f.result);
     }
-    decide<W>(x, f, f.result);
     f.result[2] = (int32_t)f.counters[2];
     reset_counters(f.counters);
+}
+
+// One block: the set X of N' states (a bitset in LDS) is carried from chunk
+// to chunk: the classes of chunk k hit by X are {alias[k][t] : t in X}, and
+// the new X is the union of the contents of their end states.  Exact for any
+// number of runs per chunk.
+template <typename TA>
+__global__ void __launch_bounds__(1024) propagate_kernel(FinalArgs f, HitArgs a, uint32_t W) {
+    extern __shared__ __align__(16) uint32_t sm[];
+    uint32_t *X = sm;               // [W]
+    uint32_t *Y = sm + W;           // [W]
+    uint32_t *H = sm + 2 * W;       // [W] classes hit (a chunk has at most L runs)
+    const TA *alias = reinterpret_cast<const TA *>(a.alias);
+    for (uint32_t w = threadIdx.x; w < W; w += blockDim.x) X[w] = 0;
+    __syncthreads();
+    // chunk 0: start 0 only
+    {
+        const TA c0 = alias[0];
+        if (c0 != all_ones<TA>()) {
+            const uint32_t fs = a.run_final[a.run_base[0] + c0];
+            if (fs != kNoState)
+                for (uint32_t i = a.csr_off[fs] + threadIdx.x; i < a.csr_off[fs + 1]; i += blockDim.x) {
+                    const uint32_t m = a.csr_idx[i];
+                    atomicOr(&X[m >> 5], 1u << (m & 31));
+                }
+        }
+    }
+    __syncthreads();
+    for (uint32_t k = 1; k < a.nchunks; ++k) {
+        for (uint32_t w = threadIdx.x; w < W; w += blockDim.x) { H[w] = 0; Y[w] = 0; }
+        __syncthreads();
+        const TA *row = alias + (uint64_t)k * a.L;
+        for (uint32_t w = threadIdx.x; w < W; w += blockDim.x)
+            for (uint32_t bits = X[w]; bits; bits &= bits - 1) {
+                const TA c = row[w * 32 + __builtin_ctz(bits)];
+                if (c != all_ones<TA>()) atomicOr(&H[(uint32_t)c >> 5], 1u << ((uint32_t)c & 31));
+            }
+        __syncthreads();
+        const uint32_t base = a.run_base[k];
+        for (uint32_t w = threadIdx.x; w < W; w += blockDim.x)
+            for (uint32_t bits = H[w]; bits; bits &= bits - 1) {
+                const uint32_t fs = a.run_final[base + w * 32 + __builtin_ctz(bits)];
+                if (fs == kNoState) continue;
+                for (uint32_t i = a.csr_off[fs]; i < a.csr_off[fs + 1]; ++i) {
+                    const uint32_t m = a.csr_idx[i];
+                    atomicOr(&Y[m >> 5], 1u << (m & 31));
+                }
+            }
+        __syncthreads();
+        for (uint32_t w = threadIdx.x; w < W; w += blockDim.x) X[w] = Y[w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        decide_bits(X, W, f, f.result);
+        f.result[2] = 0;
+        reset_counters(f.counters);
+    }
 }
 
 // Batch: thread per text; group t of the last level holds text t's relation.
@@ -1347,6 +1495,10 @@ hipError_t launch_hit_prod(const HitArgs &a, int W, int alias_bytes, bool level0
         return hipGetLastError();
     }
     return dispatch_ta(alias_bytes, [&](auto ta) {
+        if (W == 0) {
+            hipLaunchKernelGGL((hit_prod0_kernel<0, decltype(ta)>), dim3(blocks), dim3(256), 0, s, a);
+            return hipGetLastError();
+        }
 #define CALLH(w) hipLaunchKernelGGL((hit_prod0_kernel<w, decltype(ta)>), dim3(blocks), dim3(256), 0, s, a);
         RI_DISPATCH_W(W, CALLH)
 #undef CALLH
@@ -1356,9 +1508,21 @@ hipError_t launch_hit_prod(const HitArgs &a, int W, int alias_bytes, bool level0
 
 hipError_t launch_finalize_hit(const FinalArgs &f, const HitArgs &a, int W, int alias_bytes, hipStream_t s) {
     return dispatch_ta(alias_bytes, [&](auto ta) {
+        if (W == 0) {
+            hipLaunchKernelGGL((finalize_hit_kernel<0, decltype(ta)>), dim3(1), dim3(64), 0, s, f, a);
+            return hipGetLastError();
+        }
 #define CALLFH(w) hipLaunchKernelGGL((finalize_hit_kernel<w, decltype(ta)>), dim3(1), dim3(64), 0, s, f, a);
         RI_DISPATCH_W(W, CALLFH)
 #undef CALLFH
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_propagate(const FinalArgs &f, const HitArgs &a, uint32_t W, int alias_bytes, hipStream_t s) {
+    if (W > kPropMaxWords) return hipErrorInvalidValue;
+    return dispatch_ta(alias_bytes, [&](auto ta) {
+        hipLaunchKernelGGL((propagate_kernel<decltype(ta)>), dim3(1), dim3(1024), (size_t)W * 12, s, f, a, W);
         return hipGetLastError();
     });
 }

@@ -154,20 +154,27 @@ struct HitArgs {
     const uint32_t *run_base;
     const uint32_t *run_count;
     const uint32_t *run_final;
-    const uint32_t *content;   // [nstates][W]
+    const uint32_t *csr_off;   // member lists of the RI-DFA states (see FinalArgs)
+    const uint32_t *csr_idx;
+    const uint32_t *content;   // the same as [nstates][W] bitsets when W <= 64, else nullptr
     uint32_t nmembers;         // level 0: K - 1 matrices; level >= 1: products of the level below
     const uint64_t *prod_in;   // level >= 1: [nmembers][kRowCap]; finalize: the single product (or nullptr)
     const uint32_t *rows_in;   // level >= 1: [nmembers]
     uint64_t *prod_out;        // [ngroups][kRowCap]
     uint32_t *rows_out;        // [ngroups]
 };
+// W: words of the dense content bitsets, 0 = member lists
 hipError_t launch_hit_prod(const HitArgs &a, int W, int alias_bytes, bool level0, hipStream_t s);
 
 struct FinalArgs {
     const void *total;         // one relation [L][W] or one function [L]
     const uint32_t *fmask;     // relations: final N' states (W words)
-    const uint32_t *hash;      // relations: cap slots of (W key words, 1 value word)
+    const uint32_t *hash;      // relations: cap slots of (RI-DFA state, final id); state ~0 = empty;
+                               // slot of a state = FNV-1a of its members in ascending order
     uint32_t hash_cap;
+    const uint32_t *csr_off;   // relations: member list of RI-DFA state p = csr_idx[csr_off[p] ..
+    const uint32_t *csr_idx;   //   csr_off[p + 1]), ascending
+    const uint32_t *content;   // relations with W <= 64: the same as [nstates][W] bitsets, else nullptr
     const int32_t *final_of_state;   // functions
     const uint8_t *accept_of_state;  // functions
     int32_t *result;           // [0] accept, [1] final state
@@ -178,6 +185,10 @@ hipError_t launch_finalize_fun(const FinalArgs &a, hipStream_t s);
 hipError_t launch_finalize_cls(const FinalArgs &f, const ClsJoinArgs &a, int W, int alias_bytes, hipStream_t s);
 // result[2] = counters[2] (1: the hit-matrix result is not valid)
 hipError_t launch_finalize_hit(const FinalArgs &f, const HitArgs &a, int W, int alias_bytes, hipStream_t s);
+// Join by propagating the set of N' states chunk after chunk (one block; any
+// number of runs per chunk, any interface size up to kPropMaxWords * 32).
+constexpr uint32_t kPropMaxWords = 1024;
+hipError_t launch_propagate(const FinalArgs &f, const HitArgs &a, uint32_t W, int alias_bytes, hipStream_t s);
 
 // Batch results, one per text, from the last join level (one group per
 // text, in text order): a class-partitioned relation or a function.

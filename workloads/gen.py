@@ -511,3 +511,80 @@ def c4_text(seed: int, i: int, tree, alphabet: bytes, n: int):
         others = [b for b in alphabet if b != x[p]]
         x[p] = others[int(rng.integers(0, len(others)))]
     return np.ascontiguousarray(x, dtype=np.uint8), changed
+
+
+# ---------------------------------------------------------------------------
+# serving workload: keyword unions .*(k1|...|kn).*
+# ---------------------------------------------------------------------------
+#
+# A keyword is a list of positions, each a set of printable bytes with a
+# repeat range: a literal (p = 0.9), a class of 2-5 bytes (p = 0.08) or a
+# class repeated 1-3 times (p = 0.02).  Keywords are dropped from the end
+# until the keyword positions (a repeat counted at its upper bound) are at
+# most `max_positions`: that is the size of the expression's position NFA
+# and about the size of its keyword trie.
+
+PRINTABLE = bytes(range(0x20, 0x7F))
+
+
+def _c5_keyword(rng: np.random.Generator):
+    n = int(rng.integers(4, 17))
+    out = []
+    for _ in range(n):
+        u = rng.random()
+        if u < 0.9:
+            out.append((bytes([PRINTABLE[int(rng.integers(0, len(PRINTABLE)))]]), 1, 1))
+        else:
+            k = int(rng.integers(2, 6))
+            idx = np.sort(rng.choice(len(PRINTABLE), size=k, replace=False))
+            members = bytes(PRINTABLE[i] for i in idx)
+            out.append((members, 1, 1) if u < 0.98 else (members, 1, 3))
+    return out
+
+
+def _keyword_positions(kw) -> int:
+    return sum(hi for _, _, hi in kw)
+
+
+def _render_keyword(kw) -> bytes:
+    out = b""
+    for members, lo, hi in kw:
+        body = _lit_bytes(members[0]) if len(members) == 1 else b"[" + b"".join(_lit_bytes(b) for b in members) + b"]"
+        out += body if (lo, hi) == (1, 1) else body + b"{%d,%d}" % (lo, hi)
+    return out
+
+
+def c5_automaton(seed: int, index: int, nkw: int = 0, max_positions: int = 20000):
+    """Expression `index` of the serving pool: (regex, keywords).  nkw = 0
+    draws the keyword count from U{200..2000}."""
+    rng = PCG((int(seed) << 16) + 977 * int(index) + 5)
+    n = int(nkw) if nkw else int(rng.integers(200, 2001))
+    kws = [_c5_keyword(rng) for _ in range(n)]
+    while len(kws) > 1 and sum(_keyword_positions(k) for k in kws) > max_positions:
+        kws.pop()
+    rx = b".*(" + b"|".join(_render_keyword(k) for k in kws) + b").*"
+    return rx, kws
+
+
+def keyword_instance(rng: np.random.Generator, kw) -> bytes:
+    out = b""
+    for members, lo, hi in kw:
+        for _ in range(int(rng.integers(lo, hi + 1))):
+            out += bytes([members[int(rng.integers(0, len(members)))]])
+    return out
+
+
+def c5_text(rng: np.random.Generator, kws, n: int, plant: bool) -> np.ndarray:
+    """n uniform printable bytes; with plant, one instance of a random keyword
+    at a uniform position."""
+    x = random_text(rng, PRINTABLE, n)
+    if plant and kws and n > 0:
+        k = keyword_instance(rng, kws[int(rng.integers(0, len(kws)))])
+        if len(k) <= n:
+            p = int(rng.integers(0, n - len(k) + 1))
+            x[p:p + len(k)] = np.frombuffer(k, np.uint8)
+    return x
+
+
+def c5_length(rng: np.random.Generator, median: int = 1 << 16, sigma: float = 1.0, cap: int = 1 << 26) -> int:
+    return int(min(cap, max(1, round(float(rng.lognormal(np.log(median), sigma))))))
