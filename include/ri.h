@@ -250,6 +250,7 @@ typedef struct {
     uint64_t device_bytes;     /* device memory held by the batch (not the tables)    */
     uint32_t kernels;          /* kernel launches per run                             */
     uint32_t captured;         /* 1 after a successful ri_batch_capture               */
+    uint32_t fused;            /* 1: fused plan (RI_BATCH_FUSED), 0: grouped          */
 } ri_batch_info;
 
 typedef struct {
@@ -285,6 +286,37 @@ typedef struct {
  */
 int ri_batch_create(const ri_request *reqs, uint32_t count, uint32_t chunk_bytes, ri_batch **out);
 
+/*
+ * ri_batch_create_ex -- ri_batch_create with options (opts may be NULL):
+ *   chunk_bytes   as for ri_batch_create;
+ *   mode          RI_BATCH_GROUPED: one launch sequence per (handle, algo)
+ *                 group, tables staged in LDS, per-group tuning (interfaces
+ *                 up to 2048 states);
+ *                 RI_BATCH_FUSED: one launch sequence for every text of every
+ *                 automaton: each chunk slot and text names its automaton,
+ *                 tables are read from global memory (L2), every automaton
+ *                 (RI-DFA, DFA, powerset DFA) is joined by hit matrices over
+ *                 member lists, and texts whose chunks keep more than 8 runs
+ *                 are joined by propagation.  A text gets at most 2^22
+ *                 (start, chunk) pairs: its chunks grow beyond chunk_bytes when
+ *                 needed;
+ *                 RI_BATCH_AUTO (0): fused when there are more than 4 groups or
+ *                 an interface beyond 2048 states, else grouped;
+ *   warmup_bytes  0 (the handles' settings; 64 for fused) or a multiple of 16
+ *                 in [16, 256];
+ *   reserved      must be 0.
+ */
+#define RI_BATCH_AUTO     0
+#define RI_BATCH_GROUPED  1
+#define RI_BATCH_FUSED    2
+typedef struct {
+    uint32_t chunk_bytes;
+    uint32_t mode;
+    uint32_t warmup_bytes;
+    uint32_t reserved;
+} ri_batch_opts;
+int ri_batch_create_ex(const ri_request *reqs, uint32_t count, const ri_batch_opts *opts, ri_batch **out);
+
 /* ri_batch_free -- release the batch (not the handles); NULL is a no-op.
  * No run or graph launch of the batch may be in flight. */
 void ri_batch_free(ri_batch *b);
@@ -314,10 +346,10 @@ int ri_batch_get_info(const ri_batch *b, ri_batch_info *out);
 int ri_batch_get_group(const ri_batch *b, uint32_t index, ri_batch_group *out);
 
 /*
- * ri_batch_autotune -- for every group independently, time the batch under
- * a fixed grid of chunk sizes (unless chunk_bytes was given at creation) and
- * warm-up lengths, keep for each group its fastest setting and re-plan with
- * it.  Every trial's results must equal the first trial's (RI_ERR_DEVICE
+ * ri_batch_autotune -- time the batch under a fixed grid of chunk sizes
+ * (unless chunk_bytes was given at creation) and warm-up lengths and re-plan
+ * with the fastest: per group for a grouped batch, for the whole batch for a
+ * fused one.  Every trial's results must equal the first trial's (RI_ERR_DEVICE
  * otherwise).  Synchronizes `stream`; allocates.  out may be NULL.
  */
 int ri_batch_autotune(ri_batch *b, void *stream, ri_batch_tuning *out);

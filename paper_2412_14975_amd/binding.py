@@ -26,7 +26,10 @@ SYMBOLS = ("ri_build", "ri_free", "ri_info", "ri_recognize", "ri_recognize_ex",
            "ri_chunk_maps", "ri_state_content", "ri_set_profiling", "ri_last_timings",
            "ri_set_option", "ri_get_option", "ri_autotune", "ri_last_error",
            "ri_batch_create", "ri_batch_free", "ri_batch_run", "ri_batch_capture",
-           "ri_batch_launch", "ri_batch_get_info", "ri_batch_get_group", "ri_batch_autotune")
+           "ri_batch_launch", "ri_batch_get_info", "ri_batch_get_group", "ri_batch_autotune",
+           "ri_batch_create_ex")
+RI_BATCH_AUTO, RI_BATCH_GROUPED, RI_BATCH_FUSED = 0, 1, 2
+BATCH_MODES = {"auto": RI_BATCH_AUTO, "grouped": RI_BATCH_GROUPED, "fused": RI_BATCH_FUSED}
 RI_OPT_CONVERGE, RI_OPT_WARMUP_BYTES, RI_OPT_RUNS_PER_LANE, RI_OPT_CHUNK_TARGET, RI_OPT_JOIN = 1, 2, 3, 4, 5
 OPTIONS = {"converge": RI_OPT_CONVERGE, "warmup_bytes": RI_OPT_WARMUP_BYTES,
            "runs_per_lane": RI_OPT_RUNS_PER_LANE, "chunk_target": RI_OPT_CHUNK_TARGET,
@@ -73,7 +76,12 @@ class ri_request(ctypes.Structure):
 class ri_batch_info(ctypes.Structure):
     _fields_ = [("texts", ctypes.c_uint32), ("groups", ctypes.c_uint32), ("slots", ctypes.c_uint64),
                 ("bytes", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
-                ("kernels", ctypes.c_uint32), ("captured", ctypes.c_uint32)]
+                ("kernels", ctypes.c_uint32), ("captured", ctypes.c_uint32), ("fused", ctypes.c_uint32)]
+
+
+class ri_batch_opts(ctypes.Structure):
+    _fields_ = [("chunk_bytes", ctypes.c_uint32), ("mode", ctypes.c_uint32),
+                ("warmup_bytes", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class ri_batch_group(ctypes.Structure):
@@ -114,6 +122,7 @@ def lib() -> ctypes.CDLL:
     L.ri_get_option.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64)]
     L.ri_autotune.argtypes = [vp, vp, sz, vp, i32, ctypes.POINTER(ri_tuning)]
     L.ri_batch_create.argtypes = [ctypes.POINTER(ri_request), u32, u32, ctypes.POINTER(vp)]
+    L.ri_batch_create_ex.argtypes = [ctypes.POINTER(ri_request), u32, ctypes.POINTER(ri_batch_opts), ctypes.POINTER(vp)]
     L.ri_batch_free.argtypes = [vp]
     L.ri_batch_free.restype = None
     L.ri_batch_run.argtypes = [vp, vp, vp]
@@ -269,15 +278,27 @@ def _results_ptr(results: torch.Tensor, count: int) -> int:
     return results.data_ptr()
 
 
-def ri_batch_create(requests, chunk_bytes: int = 0) -> int:
-    """requests: sequence of (handle, text tensor, algo).  The texts must stay
-    alive and unchanged while the batch is used."""
+def _requests(requests):
     arr = (ri_request * max(1, len(requests)))()
     for i, (h, text, algo) in enumerate(requests):
         ptr, n = _text_ptr(text)
         arr[i] = ri_request(h, ptr if n else None, n, _algo(algo), 0)
+    return arr
+
+
+def ri_batch_create(requests, chunk_bytes: int = 0) -> int:
+    """requests: sequence of (handle, text tensor, algo).  The texts must stay
+    alive and unchanged while the batch is used."""
     b = ctypes.c_void_p()
-    _check(lib().ri_batch_create(arr, len(requests), int(chunk_bytes), ctypes.byref(b)))
+    _check(lib().ri_batch_create(_requests(requests), len(requests), int(chunk_bytes), ctypes.byref(b)))
+    return b.value
+
+
+def ri_batch_create_ex(requests, chunk_bytes: int = 0, mode="auto", warmup_bytes: int = 0) -> int:
+    opts = ri_batch_opts(int(chunk_bytes), BATCH_MODES[mode] if isinstance(mode, str) else int(mode),
+                         int(warmup_bytes), 0)
+    b = ctypes.c_void_p()
+    _check(lib().ri_batch_create_ex(_requests(requests), len(requests), ctypes.byref(opts), ctypes.byref(b)))
     return b.value
 
 
@@ -325,11 +346,11 @@ class Batch:
     """Owns one batch: ``Batch([(recognizer, text, "rid"), ...]).run()`` returns
     an int32 GPU tensor [count, 2] of (accept, final state)."""
 
-    def __init__(self, requests, chunk_bytes: int = 0):
+    def __init__(self, requests, chunk_bytes: int = 0, mode="auto", warmup_bytes: int = 0):
         reqs = [(r.handle if isinstance(r, Recognizer) else r, t, a) for r, t, a in requests]
         self._texts = [t for _, t, _ in reqs]     # keep the texts alive
         self.count = len(reqs)
-        self.handle = ri_batch_create(reqs, chunk_bytes)
+        self.handle = ri_batch_create_ex(reqs, chunk_bytes, mode, warmup_bytes)
         dev = self._texts[0].device if self._texts else torch.device("cuda")
         self.results = torch.zeros(max(1, self.count) * 2, dtype=torch.int32, device=dev)
 

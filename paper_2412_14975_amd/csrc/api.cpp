@@ -749,12 +749,39 @@ struct BatchGroup {
 
 }  // namespace
 
+namespace {
+
+constexpr uint64_t kFusedTextPairs = 1ull << 22;   // (start, chunk) pairs of one text in a fused batch
+
+// Plan of a fused batch: all texts, all automata, one launch sequence.
+struct FusedPlan {
+    uint32_t cs = 0, warm = 64;
+    uint32_t nslots = 0, ntexts = 0, max_words = 1;
+    uint64_t alias_entries = 0;
+    size_t off_addr = 0, off_len = 0, off_sauto = 0, off_stext = 0, off_arow = 0;
+    size_t off_tslot = 0, off_tn = 0, off_tauto = 0, off_tout = 0, off_tprod = 0;
+    struct Level {
+        uint32_t ngroups = 0, prod_out = 0;
+        size_t first = 0, count = 0;
+    };
+    std::vector<Level> levels;
+    uint32_t nprod = 0;
+    Workspace::Buf blob, autos, alias, run_base, run_count, run_chunk, run_state, run_final, prod, prod_rows,
+        text_flag, counters;
+    int grid_w = 1, grid_l = 1;
+    float tuned_ms = 0;
+};
+
+}  // namespace
+
 struct ri_batch {
     int device = 0;
     std::vector<ri_request> reqs;
     std::vector<BatchGroup> groups;
     uint64_t bytes = 0;
     uint32_t fixed_chunk = 0;
+    bool fused = false;
+    FusedPlan fz;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int32_t *graph_results = nullptr;
@@ -1011,11 +1038,266 @@ int check_device(const ri_batch *b) {
     return RI_OK;
 }
 
-int batch_setup(ri_batch *b, const ri_request *reqs, uint32_t count, uint32_t chunk_bytes) {
+// Automaton descriptor of a group for the fused kernels.
+ri::AutoDesc auto_desc(const BatchGroup &g, int device) {
+    ri::AutoDesc d{};
+    if (g.empty) return d;
+    const AlgoHost &H = g.h->algo[g.algo];
+    const AlgoDevice &D = g.h->dev[device].algo[g.algo];
+    d.table = D.table;
+    d.code = D.code;
+    d.starts = D.starts;
+    d.L = H.L;
+    d.row_bytes = H.K * H.entry_bytes;
+    d.dead = H.dead;
+    d.entry_bytes = H.entry_bytes;
+    d.functional = H.relational ? 0u : 1u;
+    d.W = H.relational ? H.W : (H.L + 31) / 32;
+    d.csr_off = D.csr_off;
+    d.csr_idx = D.csr_idx;
+    d.fmask = D.fmask;
+    d.hash = D.hash;
+    d.hash_cap = H.hash_cap;
+    d.final_of_state = D.final_of_state;
+    d.accept_of_state = D.accept_of_state;
+    return d;
+}
+
+int plan_fused(ri_batch *b) {
+    FusedPlan &z = b->fz;
+    std::vector<ri::AutoDesc> descs;
+    z.max_words = 1;
+    for (const auto &g : b->groups) {
+        descs.push_back(auto_desc(g, b->device));
+        if (descs.back().W > ri::kPropMaxWords) return fail(RI_ERR_LIMIT, "automaton too large for the fused batch join");
+        z.max_words = std::max(z.max_words, descs.back().W);
+    }
+    std::vector<uint64_t> addr, arow;
+    std::vector<uint32_t> len, sauto, stext, tslot, tn, tauto, tout, tprod;
+    uint64_t alias_entries = 0;
+    for (uint32_t gi = 0; gi < b->groups.size(); ++gi) {
+        const uint32_t L = descs[gi].L;
+        for (uint32_t r : b->groups[gi].req) {
+            const ri_request &q = b->reqs[r];
+            uint64_t cs = z.cs;
+            const uint64_t maxc = std::max<uint64_t>(1, kFusedTextPairs / std::max<uint32_t>(L, 1));
+            if (q.n && (q.n + cs - 1) / cs > maxc) cs = round_up((q.n + maxc - 1) / maxc, 16);
+            const uint64_t nc = q.n ? (q.n + cs - 1) / cs : 1;
+            if (addr.size() + nc > 0x7fffffffull) return fail(RI_ERR_LIMIT, "too many chunks in one batch");
+            const uint32_t t = (uint32_t)tslot.size();
+            tslot.push_back((uint32_t)addr.size());
+            tn.push_back((uint32_t)nc);
+            tauto.push_back(gi);
+            tout.push_back(r);
+            for (uint64_t j = 0; j < nc; ++j) {
+                const uint64_t o = j * cs;
+                addr.push_back(reinterpret_cast<uint64_t>(q.text_dev) + (q.n ? o : 0));
+                const uint64_t l = q.n ? std::min<uint64_t>(cs, q.n - o) : 0;
+                len.push_back((uint32_t)l | (j == 0 ? 0x80000000u : 0u));
+                sauto.push_back(gi);
+                stext.push_back(t);
+                arow.push_back(alias_entries);
+                alias_entries += L;
+            }
+        }
+    }
+    z.nslots = (uint32_t)addr.size();
+    z.ntexts = (uint32_t)tslot.size();
+    z.alias_entries = alias_entries;
+    // join levels: level 0 groups the matrices (slot k -> k + 1) of one text,
+    // higher levels group the products of one text, until each text has one
+    std::vector<uint8_t> blob;
+    tprod.assign(z.ntexts, 0xFFFFFFFFu);
+    std::vector<uint32_t> pfirst(z.ntexts, 0), pn(z.ntexts, 0);
+    z.levels.clear();
+    z.nprod = 0;
+    std::vector<std::vector<uint32_t>> firsts, counts;
+    for (int level = 0;; ++level) {
+        std::vector<uint32_t> first, count;
+        const uint32_t out0 = z.nprod;
+        for (uint32_t t = 0; t < z.ntexts; ++t) {
+            uint32_t m0, mn;
+            if (level == 0) {
+                if (tn[t] < 2) continue;
+                m0 = tslot[t];
+                mn = tn[t] - 1;
+            } else {
+                if (pn[t] < 2) continue;
+                m0 = pfirst[t];
+                mn = pn[t];
+            }
+            const uint32_t f0 = z.nprod;
+            uint32_t k = 0;
+            for (uint32_t j = 0; j < mn; j += 64, ++k) {
+                first.push_back(m0 + j);
+                count.push_back(std::min<uint32_t>(64, mn - j));
+                ++z.nprod;
+            }
+            pfirst[t] = f0;
+            pn[t] = k;
+            if (k == 1) tprod[t] = f0;
+        }
+        if (first.empty()) break;
+        FusedPlan::Level lv;
+        lv.ngroups = (uint32_t)first.size();
+        lv.prod_out = out0;
+        firsts.push_back(first);
+        counts.push_back(count);
+        z.levels.push_back(lv);
+    }
+    z.off_addr = put_array(blob, addr);
+    z.off_arow = put_array(blob, arow);
+    z.off_len = put_array(blob, len);
+    z.off_sauto = put_array(blob, sauto);
+    z.off_stext = put_array(blob, stext);
+    z.off_tslot = put_array(blob, tslot);
+    z.off_tn = put_array(blob, tn);
+    z.off_tauto = put_array(blob, tauto);
+    z.off_tout = put_array(blob, tout);
+    z.off_tprod = put_array(blob, tprod);
+    for (size_t l = 0; l < z.levels.size(); ++l) {
+        z.levels[l].first = put_array(blob, firsts[l]);
+        z.levels[l].count = put_array(blob, counts[l]);
+    }
+    int rc = grow(z.blob, std::max<size_t>(blob.size(), 16));
+    if (!rc) rc = grow(z.autos, std::max<size_t>(descs.size(), 1) * sizeof(ri::AutoDesc));
+    if (!rc) rc = grow(z.alias, std::max<uint64_t>(alias_entries, 1) * 2);
+    if (!rc) rc = grow(z.run_base, std::max<size_t>(z.nslots, 1) * 4);
+    if (!rc) rc = grow(z.run_count, std::max<size_t>(z.nslots, 1) * 4);
+    if (!rc) rc = grow(z.run_chunk, std::max<uint64_t>(alias_entries, 1) * 4);
+    if (!rc) rc = grow(z.run_state, std::max<uint64_t>(alias_entries, 1) * 4);
+    if (!rc) rc = grow(z.run_final, std::max<uint64_t>(alias_entries, 1) * 4);
+    if (!rc) rc = grow(z.prod, std::max<size_t>(z.nprod, 1) * ri::kRowCap * 8);
+    if (!rc) rc = grow(z.prod_rows, std::max<size_t>(z.nprod, 1) * 4);
+    if (!rc) rc = grow(z.text_flag, std::max<size_t>(z.ntexts, 1) * 4);
+    if (!rc) rc = grow(z.counters, 64);
+    if (rc) return rc;
+    if (!blob.empty()) HIP_TRY(hipMemcpy(z.blob.p, blob.data(), blob.size(), hipMemcpyHostToDevice));
+    if (!descs.empty())
+        HIP_TRY(hipMemcpy(z.autos.p, descs.data(), descs.size() * sizeof(ri::AutoDesc), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(z.text_flag.p, 0, z.text_flag.cap));
+    HIP_TRY(hipMemset(z.counters.p, 0, 64));
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
+    const uint32_t iters = (z.nslots + kWarmChunksPerBlock - 1) / kWarmChunksPerBlock;
+    z.grid_w = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)cus * std::max(1, ri::multi_blocks_per_cu(1)), iters));
+    z.grid_l = std::max(1, cus * std::max(1, ri::multi_blocks_per_cu(2)));
+    return RI_OK;
+}
+
+int run_fused(ri_batch *b, hipStream_t stream, int32_t *results) {
+    const FusedPlan &z = b->fz;
+    if (z.ntexts == 0) return RI_OK;
+    auto at8 = [&](size_t off) { return static_cast<const uint8_t *>(z.blob.p) + off; };
+    ri::MultiArgs a{};
+    a.autos = static_cast<const ri::AutoDesc *>(z.autos.p);
+    a.nslots = z.nslots;
+    a.ntexts = z.ntexts;
+    a.chunk_addr = reinterpret_cast<const uint64_t *>(at8(z.off_addr));
+    a.chunk_len = reinterpret_cast<const uint32_t *>(at8(z.off_len));
+    a.slot_auto = reinterpret_cast<const uint32_t *>(at8(z.off_sauto));
+    a.slot_text = reinterpret_cast<const uint32_t *>(at8(z.off_stext));
+    a.alias_row = reinterpret_cast<const uint64_t *>(at8(z.off_arow));
+    a.alias = static_cast<uint16_t *>(z.alias.p);
+    a.warm = z.warm;
+    a.run_base = static_cast<uint32_t *>(z.run_base.p);
+    a.run_count = static_cast<uint32_t *>(z.run_count.p);
+    a.run_chunk = static_cast<uint32_t *>(z.run_chunk.p);
+    a.run_state = static_cast<uint32_t *>(z.run_state.p);
+    a.run_final = static_cast<uint32_t *>(z.run_final.p);
+    a.counters = static_cast<uint32_t *>(z.counters.p);
+    a.text_flag = static_cast<uint32_t *>(z.text_flag.p);
+    a.text_slot = reinterpret_cast<const uint32_t *>(at8(z.off_tslot));
+    a.text_nslots = reinterpret_cast<const uint32_t *>(at8(z.off_tn));
+    a.text_auto = reinterpret_cast<const uint32_t *>(at8(z.off_tauto));
+    a.text_out = reinterpret_cast<const uint32_t *>(at8(z.off_tout));
+    a.text_prod = reinterpret_cast<const uint32_t *>(at8(z.off_tprod));
+    a.results = results;
+    a.prod = static_cast<uint64_t *>(z.prod.p);
+    a.prod_rows = static_cast<uint32_t *>(z.prod_rows.p);
+    HIP_TRY(ri::launch_mwarm(a, z.grid_w, stream));
+    HIP_TRY(ri::launch_mlong(a, z.grid_l, stream));
+    for (size_t l = 0; l < z.levels.size(); ++l) {
+        a.grp_first = reinterpret_cast<const uint32_t *>(at8(z.levels[l].first));
+        a.grp_count = reinterpret_cast<const uint32_t *>(at8(z.levels[l].count));
+        a.ngroups = z.levels[l].ngroups;
+        a.prod_out = z.levels[l].prod_out;
+        HIP_TRY(ri::launch_mhit(a, l == 0, stream));
+    }
+    HIP_TRY(ri::launch_mfinal(a, stream));
+    HIP_TRY(ri::launch_mprop(a, z.max_words, stream));
+    return RI_OK;
+}
+
+void release_fused(FusedPlan &z) {
+    for (Workspace::Buf *x : {&z.blob, &z.autos, &z.alias, &z.run_base, &z.run_count, &z.run_chunk, &z.run_state,
+                              &z.run_final, &z.prod, &z.prod_rows, &z.text_flag, &z.counters})
+        release(*x);
+}
+
+// Whole-batch grid search of (chunk size, warm-up) for a fused batch.
+int autotune_fused(ri_batch *b, hipStream_t stream, const uint32_t *chunks, size_t nchunks, const uint32_t *warms,
+                   size_t nwarms, ri_batch_tuning *out) {
+    FusedPlan &z = b->fz;
+    const size_t nr = b->reqs.size();
+    int32_t *dres = nullptr;
+    HIP_TRY(hipMalloc(reinterpret_cast<void **>(&dres), std::max<size_t>(nr, 1) * 8));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = RI_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(RI_ERR_DEVICE, "hipEventCreate");
+    std::vector<int32_t> ref, got(nr * 2);
+    float best = 1e30f;
+    uint32_t best_cs = z.cs, best_warm = z.warm, trials = 0;
+    for (size_t ci = 0; ci < nchunks && !rc; ++ci) {
+        if (b->fixed_chunk && ci > 0) break;
+        for (size_t wi = 0; wi < nwarms && !rc; ++wi) {
+            z.cs = b->fixed_chunk ? b->fixed_chunk : chunks[ci];
+            z.warm = warms[wi];
+            rc = plan_fused(b);
+            float ms = 0;
+            for (int it = 0; it < 3 && !rc; ++it) {   // first pass is a warm-up
+                if (hipEventRecord(e0, stream) != hipSuccess) rc = fail(RI_ERR_DEVICE, "hipEventRecord");
+                if (!rc) rc = run_fused(b, stream, dres);
+                if (!rc && hipEventRecord(e1, stream) != hipSuccess) rc = fail(RI_ERR_DEVICE, "hipEventRecord");
+                if (!rc && hipStreamSynchronize(stream) != hipSuccess) rc = fail(RI_ERR_DEVICE, "hipStreamSynchronize");
+                float t = 0;
+                if (!rc && it > 0 && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = fail(RI_ERR_DEVICE, "hipEventElapsedTime");
+                ms += it > 0 ? t / 2 : 0.f;
+            }
+            if (!rc && nr && hipMemcpy(got.data(), dres, nr * 8, hipMemcpyDeviceToHost) != hipSuccess)
+                rc = fail(RI_ERR_DEVICE, "hipMemcpy");
+            if (rc) break;
+            if (ref.empty()) ref = got;
+            else if (got != ref) rc = fail(RI_ERR_DEVICE, "internal: results differ between tuning trials");
+            ++trials;
+            if (!rc && ms < best) {
+                best = ms;
+                best_cs = z.cs;
+                best_warm = z.warm;
+            }
+        }
+    }
+    (void)hipFree(dres);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    z.cs = best_cs;
+    z.warm = best_warm;
+    z.tuned_ms = best;
+    rc = plan_fused(b);
+    if (rc) return rc;
+    if (out) {
+        out->trials = trials;
+        out->best_ms = best;
+    }
+    return RI_OK;
+}
+
+int batch_setup(ri_batch *b, const ri_request *reqs, uint32_t count, const ri_batch_opts &o) {
     HIP_TRY(hipGetDevice(&b->device));
     if (b->device < 0 || b->device >= kMaxDevices) return fail(RI_ERR_DEVICE, "device index out of range");
     b->reqs.assign(reqs, reqs + count);
-    b->fixed_chunk = chunk_bytes;
+    b->fixed_chunk = o.chunk_bytes;
     for (uint32_t i = 0; i < count; ++i) {
         ri_handle *h = const_cast<ri_handle *>(reqs[i].h);
         BatchGroup *g = nullptr;
@@ -1034,21 +1316,30 @@ int batch_setup(ri_batch *b, const ri_request *reqs, uint32_t count, uint32_t ch
     for (auto &s : b->side) HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
     for (auto &e : b->joins) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    bool wide = false;   // an interface beyond the grouped path's dense join
     for (auto &g : b->groups) {
-        {
-            std::lock_guard<std::mutex> lk(g.h->mu);
-            g.opt = g.h->tuned_valid[g.algo] ? g.h->tuned[g.algo] : g.h->opt;
-            if (!g.empty) {
-                const int rc = ensure_device(g.h, b->device);
-                if (rc) return rc;
-            }
+        std::lock_guard<std::mutex> lk(g.h->mu);
+        g.opt = g.h->tuned_valid[g.algo] ? g.h->tuned[g.algo] : g.h->opt;
+        if (o.warmup_bytes) g.opt.warm = o.warmup_bytes;
+        if (!g.empty) {
+            const int rc = ensure_device(g.h, b->device);
+            if (rc) return rc;
+            wide |= g.h->algo[g.algo].relational && g.h->algo[g.algo].W > kMaxDenseWords;
         }
+    }
+    b->fused = o.mode == RI_BATCH_FUSED || (o.mode == RI_BATCH_AUTO && (b->groups.size() > 4 || wide));
+    if (b->fused) {
+        b->fz.cs = o.chunk_bytes ? o.chunk_bytes : 4096;
+        b->fz.warm = o.warmup_bytes ? o.warmup_bytes : 64;
+        return plan_fused(b);
+    }
+    for (auto &g : b->groups) {
         uint64_t bytes = 0;
         for (uint32_t r : g.req) bytes += b->reqs[r].n;
-        g.cs = chunk_bytes ? chunk_bytes
-                           : std::min(kBatchMaxChunk,
-                                      std::max(kBatchMinChunk, round_up((bytes + kBatchAutoChunkTarget - 1) /
-                                                                            kBatchAutoChunkTarget, 16)));
+        g.cs = o.chunk_bytes ? o.chunk_bytes
+                             : std::min(kBatchMaxChunk,
+                                        std::max(kBatchMinChunk, round_up((bytes + kBatchAutoChunkTarget - 1) /
+                                                                              kBatchAutoChunkTarget, 16)));
         const int rc = plan_group(b, g);
         if (rc) return rc;
     }
@@ -1313,11 +1604,17 @@ int ri_autotune(ri_handle *h, const uint8_t *text, size_t n, void *stream, int a
     return RI_OK;
 }
 
-int ri_batch_create(const ri_request *reqs, uint32_t count, uint32_t chunk_bytes, ri_batch **out) {
+int ri_batch_create_ex(const ri_request *reqs, uint32_t count, const ri_batch_opts *opts, ri_batch **out) {
     if (!out || (count > 0 && !reqs)) return fail(RI_ERR_ARG, "NULL argument");
     *out = nullptr;
-    if (chunk_bytes % 16) return fail(RI_ERR_ARG, "chunk_bytes must be a multiple of 16");
-    if (chunk_bytes > (1u << 30)) return fail(RI_ERR_ARG, "chunk_bytes too large");
+    ri_batch_opts o{};
+    if (opts) o = *opts;
+    if (o.chunk_bytes % 16) return fail(RI_ERR_ARG, "chunk_bytes must be a multiple of 16");
+    if (o.chunk_bytes > (1u << 30)) return fail(RI_ERR_ARG, "chunk_bytes too large");
+    if (o.mode > RI_BATCH_FUSED) return fail(RI_ERR_ARG, "unknown batch mode");
+    if (o.warmup_bytes && (o.warmup_bytes < 16 || o.warmup_bytes > 256 || o.warmup_bytes % 16))
+        return fail(RI_ERR_ARG, "bad warm-up length");
+    if (o.reserved) return fail(RI_ERR_ARG, "reserved must be 0");
     for (uint32_t i = 0; i < count; ++i) {
         const ri_request &q = reqs[i];
         if (!q.h) return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": NULL handle");
@@ -1328,13 +1625,19 @@ int ri_batch_create(const ri_request *reqs, uint32_t count, uint32_t chunk_bytes
             return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": text must be 16-byte aligned");
     }
     ri_batch *b = new ri_batch();
-    const int rc = batch_setup(b, reqs, count, chunk_bytes);
+    const int rc = batch_setup(b, reqs, count, o);
     if (rc) {
         ri_batch_free(b);
         return rc;
     }
     *out = b;
     return RI_OK;
+}
+
+int ri_batch_create(const ri_request *reqs, uint32_t count, uint32_t chunk_bytes, ri_batch **out) {
+    ri_batch_opts o{};
+    o.chunk_bytes = chunk_bytes;
+    return ri_batch_create_ex(reqs, count, &o, out);
 }
 
 void ri_batch_free(ri_batch *b) {
@@ -1349,6 +1652,7 @@ void ri_batch_free(ri_batch *b) {
             release(*x);
         if (g.counters) (void)hipFree(g.counters);
     }
+    release_fused(b->fz);
     for (auto s : b->side)
         if (s) (void)hipStreamDestroy(s);
     if (b->fork) (void)hipEventDestroy(b->fork);
@@ -1363,6 +1667,7 @@ int ri_batch_run(ri_batch *b, void *stream_v, int32_t *results_dev) {
     int rc = check_device(b);
     if (rc) return rc;
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
+    if (b->fused) return run_fused(b, stream, results_dev);
     for (const auto &g : b->groups) {
         rc = run_group(b, g, stream, results_dev);
         if (rc) return rc;
@@ -1385,7 +1690,8 @@ int ri_batch_capture(ri_batch *b, int32_t *results_dev) {
     // groups are independent: spread them over concurrent branches
     e = hipEventRecord(b->fork, cap);
     for (int k = 0; k < kBatchSide && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->side[k], b->fork, 0);
-    for (size_t i = 0; i < b->groups.size() && e == hipSuccess && rc == RI_OK; ++i)
+    if (b->fused && e == hipSuccess) rc = run_fused(b, b->side[0], results_dev);
+    for (size_t i = 0; !b->fused && i < b->groups.size() && e == hipSuccess && rc == RI_OK; ++i)
         rc = run_group(b, b->groups[i], b->side[i % kBatchSide], results_dev);
     for (int k = 0; k < kBatchSide && e == hipSuccess; ++k) {
         e = hipEventRecord(b->joins[k], b->side[k]);
@@ -1424,7 +1730,16 @@ int ri_batch_get_info(const ri_batch *b, ri_batch_info *out) {
     out->texts = (uint32_t)b->reqs.size();
     out->groups = (uint32_t)b->groups.size();
     out->bytes = b->bytes;
+    if (b->fused) {
+        const FusedPlan &z = b->fz;
+        out->slots = z.nslots;
+        out->kernels = z.ntexts ? 4 + (uint32_t)z.levels.size() : 0;
+        for (const Workspace::Buf *x : {&z.blob, &z.autos, &z.alias, &z.run_base, &z.run_count, &z.run_chunk,
+                                        &z.run_state, &z.run_final, &z.prod, &z.prod_rows, &z.text_flag, &z.counters})
+            out->device_bytes += x->cap;
+    }
     for (const auto &g : b->groups) {
+        if (b->fused) break;
         out->slots += g.slots;
         out->kernels += g.empty ? 1 : 2 + (uint32_t)g.levels.size() + 1;
         for (const Workspace::Buf *x : {&g.desc, &g.alias, &g.run_base, &g.run_chunk, &g.run_state, &g.run_final,
@@ -1432,6 +1747,7 @@ int ri_batch_get_info(const ri_batch *b, ri_batch_info *out) {
             out->device_bytes += x->cap;
     }
     out->captured = b->exec != nullptr;
+    out->fused = b->fused ? 1u : 0u;
     return RI_OK;
 }
 
@@ -1443,6 +1759,15 @@ int ri_batch_get_group(const ri_batch *b, uint32_t index, ri_batch_group *out) {
     out->h = g.h;
     out->algo = g.algo;
     out->texts = (uint32_t)g.req.size();
+    if (b->fused) {
+        const FusedPlan &z = b->fz;
+        for (uint32_t r : g.req) out->bytes += b->reqs[r].n;
+        out->chunk_bytes = z.cs;
+        out->warmup_bytes = z.warm;
+        out->join_levels = (uint32_t)z.levels.size();
+        out->tuned_ms = z.tuned_ms;
+        return RI_OK;
+    }
     out->slots = g.slots;
     out->bytes = g.bytes;
     out->chunk_bytes = (uint32_t)g.cs;
@@ -1461,6 +1786,7 @@ int ri_batch_autotune(ri_batch *b, void *stream_v, ri_batch_tuning *out) {
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
     static const uint32_t kChunk[] = {1024, 2048, 4096, 8192, 16384, 65536};
     static const uint32_t kWarm[] = {32, 64, 128};
+    if (b->fused) return autotune_fused(b, stream, kChunk, sizeof(kChunk) / 4, kWarm, sizeof(kWarm) / 4, out);
     const size_t ng = b->groups.size();
     const size_t nr = b->reqs.size();
     int32_t *dres = nullptr;

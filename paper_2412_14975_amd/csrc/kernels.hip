@@ -279,6 +279,155 @@ __device__ __forceinline__ void warm_block(uint32_t (&st)[R], const uint32_t (&c
     }
 }
 
+// Warm-up and classes of one chunk (all lanes of the wave).  al[r]: class of
+// start base + r * 64 + lane of the last start block; with several start
+// blocks the alias row is written as classes are found.  Once more than 64
+// distinct states are seen the chunk spills: D counts its live starts.
+template <typename TE, typename TA, int R>
+__device__ __forceinline__ void warm_classes(const TE *tab, const uint32_t *starts, uint32_t L, uint32_t dead,
+                                             bool ok, bool first, const uint32_t (&code)[4], uint32_t wlen,
+                                             TA *arow, uint32_t lane, uint32_t (&al)[R], uint32_t &D,
+                                             uint32_t &cs, bool &spill) {
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    const uint32_t per_block = (uint32_t)kWave * R;
+    const uint32_t nblk = (L + per_block - 1) / per_block;
+    cs = dead;
+    D = 0;
+    spill = false;
+    uint32_t st[R];
+    for (uint32_t blk = 0; blk < nblk; ++blk) {
+        const uint32_t base = blk * per_block;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t s = base + r * kWave + lane;
+            st[r] = (ok && s < L && (!first || s == 0)) ? starts[s] : dead;
+        }
+        warm_block<TE, R>(st, code, wlen, tab, dead);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            al[r] = kNone;
+            const bool live = st[r] != dead;
+            if (spill) {
+                D += (uint32_t)__builtin_popcountll(__ballot(live));
+                continue;
+            }
+            uint64_t open = __ballot(live);
+            while (open) {
+                const int leader = __builtin_ctzll(open);
+                const uint32_t lv = (uint32_t)__builtin_amdgcn_readlane((int)st[r], leader);
+                const uint64_t hit = __ballot(lane < D && cs == lv);
+                uint32_t ci;
+                if (hit) {
+                    ci = (uint32_t)__builtin_ctzll(hit);
+                } else {
+                    if (D == kWave) { spill = true; break; }
+                    ci = D;
+                    if (lane == D) cs = lv;
+                    ++D;
+                }
+                const uint64_t same = __ballot(live && st[r] == lv);
+                if (live && st[r] == lv) al[r] = ci;
+                open &= ~same;
+            }
+            if (spill) {
+                // count the live starts of every start seen so far
+                D = 0;
+                for (uint32_t b2 = 0; b2 <= blk; ++b2) {
+                    uint32_t s2[R];
+#pragma unroll
+                    for (int r2 = 0; r2 < R; ++r2) {
+                        const uint32_t s = b2 * per_block + r2 * kWave + lane;
+                        s2[r2] = (ok && s < L && (!first || s == 0)) ? starts[s] : dead;
+                    }
+                    warm_block<TE, R>(s2, code, wlen, tab, dead);
+#pragma unroll
+                    for (int r2 = 0; r2 < R; ++r2)
+                        if (b2 < blk || r2 <= r) D += (uint32_t)__builtin_popcountll(__ballot(s2[r2] != dead));
+                }
+                continue;
+            }
+            if (nblk > 1 && ok) {
+                const uint32_t s = base + r * kWave + lane;
+                if (s < L) arow[s] = al[r] == kNone ? all_ones<TA>() : (TA)al[r];
+            }
+        }
+    }
+}
+
+// Run records of one chunk from slot `firstrun` on, and its alias row (when
+// not written yet).  A spilled chunk's runs are recomputed: every live start
+// is its own run, in start order.
+template <typename TE, typename TA, int R>
+__device__ __forceinline__ void warm_records(const TE *tab, const uint32_t *starts, uint32_t L, uint32_t dead,
+                                             uint32_t row_bytes, bool first, const uint32_t (&code)[4],
+                                             uint32_t wlen, TA *arow, uint32_t lane, uint64_t lane_lt,
+                                             const uint32_t (&al)[R], uint32_t D, uint32_t cs, bool spill,
+                                             uint32_t firstrun, uint32_t chunk, uint32_t *run_chunk,
+                                             uint32_t *run_state) {
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    const uint32_t per_block = (uint32_t)kWave * R;
+    const uint32_t nblk = (L + per_block - 1) / per_block;
+    if (!spill) {
+        if (lane < D) {
+            run_chunk[firstrun + lane] = chunk;
+            run_state[firstrun + lane] = cs / row_bytes;
+        }
+        if (nblk == 1) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t s = r * kWave + lane;
+                if (s < L) arow[s] = al[r] == kNone ? all_ones<TA>() : (TA)al[r];
+            }
+        }
+        return;
+    }
+    uint32_t idx = 0;
+    uint32_t st[R];
+    for (uint32_t blk = 0; blk < nblk; ++blk) {
+        const uint32_t base = blk * per_block;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t s = base + r * kWave + lane;
+            st[r] = (s < L && (!first || s == 0)) ? starts[s] : dead;
+        }
+        warm_block<TE, R>(st, code, wlen, tab, dead);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t s = base + r * kWave + lane;
+            const bool live = st[r] != dead;
+            const uint64_t m = __ballot(live);
+            const uint32_t my = idx + (uint32_t)__builtin_popcountll(m & lane_lt);
+            if (live) {
+                run_chunk[firstrun + my] = chunk;
+                run_state[firstrun + my] = st[r] / row_bytes;
+            }
+            if (s < L) arow[s] = live ? (TA)my : all_ones<TA>();
+            idx += (uint32_t)__builtin_popcountll(m);
+        }
+    }
+}
+
+// Run slots of the block's chunks (one per wave): one atomic.  Returns the
+// first slot of this wave's chunk.
+__device__ __forceinline__ uint32_t warm_slots(uint32_t *s_cnt, uint32_t &s_base, uint32_t lane, uint32_t wave,
+                                               uint32_t D, uint32_t *counter) {
+    if (lane == 0) s_cnt[wave] = D;
+    __syncthreads();
+    if (wave == 0) {
+        const uint32_t d = lane < kWarmWaves ? s_cnt[lane] : 0u;
+        uint32_t incl = d;
+#pragma unroll
+        for (int k = 1; k < (int)kWarmWaves; k <<= 1) {
+            const uint32_t o = __shfl_up(incl, k);
+            if ((int)lane >= k) incl += o;
+        }
+        if (lane == kWarmWaves - 1) s_base = atomicAdd(counter, incl);
+        if (lane < kWarmWaves) s_cnt[lane] = incl - d;
+    }
+    __syncthreads();
+    return s_base + s_cnt[wave];
+}
+
 template <typename TE, typename TA, int R, bool LDS>
 __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -292,9 +441,6 @@ __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
     const uint32_t lane = threadIdx.x % kWave;
     const uint32_t wave = threadIdx.x / kWave;
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-    const uint32_t per_block = (uint32_t)kWave * R;          // starts per start block
-    const uint32_t nblk = (L + per_block - 1) / per_block;
-    constexpr uint32_t kNone = 0xFFFFFFFFu;
     TA *alias = reinterpret_cast<TA *>(a.alias);
     const uint32_t iters = (a.s.nchunks + kWarmWaves - 1) / kWarmWaves;
 
@@ -312,130 +458,19 @@ __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
             const uint32_t j = q * kWave + lane;
             if (j < wlen) code[q] = cls[*at(b + j)];
         }
-        // warm-up and classes, start block by start block
-        uint32_t cs = dead;        // lane i: state (row offset) of class i
-        uint32_t D = 0;            // classes, or live starts once spilled
-        bool spill = false;
-        uint32_t st[R];
-        uint32_t al[R];
-        for (uint32_t blk = 0; blk < nblk; ++blk) {
-            const uint32_t base = blk * per_block;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const uint32_t s = base + r * kWave + lane;
-                st[r] = (ok && s < L && (!first || s == 0)) ? a.s.starts[s] : dead;
-            }
-            warm_block<TE, R>(st, code, wlen, tab, dead);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                al[r] = kNone;
-                const bool live = st[r] != dead;
-                if (spill) {
-                    const uint64_t m = __ballot(live);
-                    D += (uint32_t)__builtin_popcountll(m);
-                    continue;
-                }
-                uint64_t open = __ballot(live);
-                while (open) {
-                    const int leader = __builtin_ctzll(open);
-                    const uint32_t lv = (uint32_t)__builtin_amdgcn_readlane((int)st[r], leader);
-                    const uint64_t hit = __ballot(lane < D && cs == lv);
-                    uint32_t ci;
-                    if (hit) {
-                        ci = (uint32_t)__builtin_ctzll(hit);
-                    } else {
-                        if (D == kWave) { spill = true; break; }
-                        ci = D;
-                        if (lane == D) cs = lv;
-                        ++D;
-                    }
-                    const uint64_t same = __ballot(live && st[r] == lv);
-                    if (live && st[r] == lv) al[r] = ci;
-                    open &= ~same;
-                }
-                if (spill) {
-                    // count the live starts of every start seen so far
-                    D = 0;
-                    for (uint32_t b2 = 0; b2 <= blk; ++b2) {
-                        uint32_t s2[R];
-#pragma unroll
-                        for (int r2 = 0; r2 < R; ++r2) {
-                            const uint32_t s = b2 * per_block + r2 * kWave + lane;
-                            s2[r2] = (ok && s < L && (!first || s == 0)) ? a.s.starts[s] : dead;
-                        }
-                        warm_block<TE, R>(s2, code, wlen, tab, dead);
-#pragma unroll
-                        for (int r2 = 0; r2 < R; ++r2)
-                            if (b2 < blk || r2 <= r) D += (uint32_t)__builtin_popcountll(__ballot(s2[r2] != dead));
-                    }
-                    continue;
-                }
-                if (nblk > 1 && ok) {
-                    const uint32_t s = base + r * kWave + lane;
-                    if (s < L) alias[(uint64_t)chunk * L + s] = al[r] == kNone ? all_ones<TA>() : (TA)al[r];
-                }
-            }
-        }
-        // run slots of the block's chunks: one atomic
-        if (lane == 0) s_cnt[wave] = ok ? D : 0u;
-        __syncthreads();
-        if (wave == 0) {
-            const uint32_t d = lane < kWarmWaves ? s_cnt[lane] : 0u;
-            uint32_t incl = d;
-#pragma unroll
-            for (int k = 1; k < (int)kWarmWaves; k <<= 1) {
-                const uint32_t o = __shfl_up(incl, k);
-                if ((int)lane >= k) incl += o;
-            }
-            if (lane == kWarmWaves - 1) s_base = atomicAdd(&a.counters[1], incl);
-            if (lane < kWarmWaves) s_cnt[lane] = incl - d;
-        }
-        __syncthreads();
+        TA *arow = alias + (uint64_t)(ok ? chunk : 0) * L;
+        uint32_t al[R], D, cs;
+        bool spill;
+        warm_classes<TE, TA, R>(tab, a.s.starts, L, dead, ok, first, code, wlen, arow, lane, al, D, cs, spill);
+        const uint32_t firstrun = warm_slots(s_cnt, s_base, lane, wave, ok ? D : 0u, &a.counters[1]);
         if (ok) {
-            const uint32_t firstrun = s_base + s_cnt[wave];
             if (lane == 0) {
                 a.run_base[chunk] = firstrun;
                 if (a.run_count) a.run_count[chunk] = D;
                 if (D > kRowCap) atomicOr(&a.counters[2], 1u);
             }
-            if (!spill) {
-                if (lane < D) {
-                    a.run_chunk[firstrun + lane] = chunk;
-                    a.run_state[firstrun + lane] = cs / a.s.row_bytes;
-                }
-                if (nblk == 1) {
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const uint32_t s = r * kWave + lane;
-                        if (s < L) alias[(uint64_t)chunk * L + s] = al[r] == kNone ? all_ones<TA>() : (TA)al[r];
-                    }
-                }
-            } else {
-                // every live start is its own run, in start order
-                uint32_t idx = 0;
-                for (uint32_t blk = 0; blk < nblk; ++blk) {
-                    const uint32_t base = blk * per_block;
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const uint32_t s = base + r * kWave + lane;
-                        st[r] = (s < L && (!first || s == 0)) ? a.s.starts[s] : dead;
-                    }
-                    warm_block<TE, R>(st, code, wlen, tab, dead);
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const uint32_t s = base + r * kWave + lane;
-                        const bool live = st[r] != dead;
-                        const uint64_t m = __ballot(live);
-                        const uint32_t my = idx + (uint32_t)__builtin_popcountll(m & lane_lt);
-                        if (live) {
-                            a.run_chunk[firstrun + my] = chunk;
-                            a.run_state[firstrun + my] = st[r] / a.s.row_bytes;
-                        }
-                        if (s < L) alias[(uint64_t)chunk * L + s] = live ? (TA)my : all_ones<TA>();
-                        idx += (uint32_t)__builtin_popcountll(m);
-                    }
-                }
-            }
+            warm_records<TE, TA, R>(tab, a.s.starts, L, dead, a.s.row_bytes, first, code, wlen, arow, lane, lane_lt,
+                                    al, D, cs, spill, firstrun, chunk, a.run_chunk, a.run_state);
         }
         __syncthreads();   // s_cnt / s_base reused by the next chunks
     }
@@ -1271,6 +1306,264 @@ __global__ void finalize_fun_kernel(FinalArgs a) {
 
 uint32_t blocks_for(uint64_t threads, uint32_t per) { return (uint32_t)((threads + per - 1) / per); }
 
+// ---------------------------------------------------------------------------
+// fused batches: every slot and text names its automaton
+// ---------------------------------------------------------------------------
+
+template <class F>
+__device__ __forceinline__ void with_entry(uint32_t eb, F &&f) {
+    if (eb == 1) f((uint8_t)0);
+    else if (eb == 2) f((uint16_t)0);
+    else f((uint32_t)0);
+}
+
+__device__ __forceinline__ void slot_bounds(const MultiArgs &a, uint32_t slot, uint64_t &b, uint64_t &e, bool &first) {
+    const uint32_t l = a.chunk_len[slot];
+    b = a.chunk_addr[slot];
+    e = b + (l & 0x7fffffffu);
+    first = (l >> 31) != 0;
+}
+
+// warm-up and merging: one wavefront per slot, 16 slots per block iteration
+__global__ void __launch_bounds__(1024) mwarm_kernel(MultiArgs a) {
+    __shared__ uint32_t s_cnt[kWarmWaves], s_base;
+    constexpr int R = 4;
+    const uint32_t lane = threadIdx.x % kWave;
+    const uint32_t wave = threadIdx.x / kWave;
+    const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    const uint32_t iters = (a.nslots + kWarmWaves - 1) / kWarmWaves;
+    for (uint32_t it = blockIdx.x; it < iters; it += gridDim.x) {
+        const uint32_t slot = it * kWarmWaves + wave;
+        const bool ok = slot < a.nslots;
+        const AutoDesc &d = a.autos[ok ? a.slot_auto[slot] : 0];
+        const bool okl = ok && d.L > 0;
+        uint64_t b = 0, e = 0;
+        bool first = false;
+        if (ok) slot_bounds(a, slot, b, e, first);
+        const uint32_t wlen = okl ? (uint32_t)(e - b < a.warm ? e - b : a.warm) : 0u;
+        uint32_t code[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+            const uint32_t j = q * kWave + lane;
+            if (j < wlen) code[q] = d.code[*at(b + j)];
+        }
+        uint16_t *arow = a.alias + (ok ? a.alias_row[slot] : 0);
+        uint32_t al[R], D = 0, cs = 0;
+        bool spill = false;
+        if (okl)
+            with_entry(d.entry_bytes, [&](auto te) {
+                using TE = decltype(te);
+                warm_classes<TE, uint16_t, R>(reinterpret_cast<const TE *>(d.table), d.starts, d.L, d.dead, true,
+                                              first, code, wlen, arow, lane, al, D, cs, spill);
+            });
+        const uint32_t firstrun = warm_slots(s_cnt, s_base, lane, wave, ok ? D : 0u, &a.counters[1]);
+        if (ok) {
+            if (lane == 0) {
+                a.run_base[slot] = firstrun;
+                a.run_count[slot] = D;
+                if (D > kRowCap) a.text_flag[a.slot_text[slot]] = 1u;
+            }
+            if (okl)
+                with_entry(d.entry_bytes, [&](auto te) {
+                    using TE = decltype(te);
+                    warm_records<TE, uint16_t, R>(reinterpret_cast<const TE *>(d.table), d.starts, d.L, d.dead,
+                                                  d.row_bytes, first, code, wlen, arow, lane, lane_lt, al, D, cs,
+                                                  spill, firstrun, slot, a.run_chunk, a.run_state);
+                });
+        }
+        __syncthreads();
+    }
+}
+
+// merged runs to the end of their chunks: one run per lane, grid-stride
+__global__ void __launch_bounds__(256) mlong_kernel(MultiArgs a) {
+    const uint32_t nruns = *reinterpret_cast<volatile uint32_t *>(&a.counters[1]);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nruns; i += gridDim.x * blockDim.x) {
+        const uint32_t slot = a.run_chunk[i];
+        const AutoDesc &d = a.autos[a.slot_auto[slot]];
+        uint64_t b, e;
+        bool first;
+        slot_bounds(a, slot, b, e, first);
+        const uint64_t p = b + a.warm < e ? b + a.warm : e;
+        const uint64_t vend = p + ((e - p) & ~(uint64_t)15);
+        uint32_t f = 0;
+        with_entry(d.entry_bytes, [&](auto te) {
+            using TE = decltype(te);
+            f = scan_lane<TE>(a.run_state[i] * d.row_bytes, p, vend, e, reinterpret_cast<const TE *>(d.table), d.code,
+                              d.dead);
+        });
+        a.run_final[i] = f == d.dead ? kNoState : f / d.row_bytes;
+    }
+}
+
+// Members of the set a state stands for: its content (RI-DFA) or itself.
+template <class F>
+__device__ __forceinline__ void for_members(const AutoDesc &d, uint32_t st, F &&f) {
+    if (d.functional) {
+        f(st);
+        return;
+    }
+    for (uint32_t i = d.csr_off[st], ie = d.csr_off[st + 1]; i < ie; ++i) f(d.csr_idx[i]);
+}
+
+// Hit products.  Level 0: wave per group of matrices M_k (slots k and k + 1
+// of one text); level >= 1: wave per group of products of the level below.
+template <bool LEVEL0>
+__global__ void __launch_bounds__(256) mhit_kernel(MultiArgs a) {
+    const uint32_t lane = threadIdx.x % kWave;
+    const uint32_t g = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (g >= a.ngroups) return;
+    const uint32_t m0 = a.grp_first[g], gn = a.grp_count[g];
+    uint64_t rows[kRowCap];
+    uint32_t R = 0;
+#pragma unroll
+    for (uint32_t r = 0; r < kRowCap; ++r) rows[r] = 0;
+    if (lane < gn) {
+        const uint32_t m = m0 + lane;
+        if (LEVEL0) {
+            const AutoDesc &d = a.autos[a.slot_auto[m]];
+            R = a.run_count[m];
+            R = R < kRowCap ? R : kRowCap;
+            const uint16_t *row = a.alias + a.alias_row[m + 1];
+            for (uint32_t r = 0; r < R; ++r) {
+                const uint32_t fs = a.run_final[a.run_base[m] + r];
+                uint64_t bits = 0;
+                if (fs != kNoState)
+                    for_members(d, fs, [&](uint32_t t) {
+                        const uint16_t j = row[t];
+                        if (j != 0xFFFFu && j < 64) bits |= 1ull << j;
+                    });
+#pragma unroll
+                for (uint32_t rr = 0; rr < kRowCap; ++rr)
+                    if (rr == r) rows[rr] = bits;
+            }
+        } else {
+#pragma unroll
+            for (uint32_t r = 0; r < kRowCap; ++r) rows[r] = a.prod[(uint64_t)m * kRowCap + r];
+            R = a.prod_rows[m];
+        }
+    }
+    wave_tree_product(rows, lane, gn);
+    if (lane == 0) {
+        const uint64_t o = (uint64_t)(a.prod_out + g);
+#pragma unroll
+        for (uint32_t r = 0; r < kRowCap; ++r) a.prod[o * kRowCap + r] = rows[r];
+        a.prod_rows[o] = R;
+    }
+}
+
+__device__ __forceinline__ FinalArgs final_args(const AutoDesc &d) {
+    FinalArgs f{};
+    f.fmask = d.fmask;
+    f.hash = d.hash;
+    f.hash_cap = d.hash_cap;
+    f.csr_off = d.csr_off;
+    f.csr_idx = d.csr_idx;
+    return f;
+}
+
+// thread per text: classes of the last slot reached from start 0 of the first
+__global__ void __launch_bounds__(256) mfinal_kernel(MultiArgs a) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) reset_counters(a.counters);   // every reader of the counters has run
+    if (t >= a.ntexts) return;
+    const AutoDesc &d = a.autos[a.text_auto[t]];
+    int32_t *res = a.results + (uint64_t)a.text_out[t] * 2;
+    res[0] = 0;
+    res[1] = -1;
+    if (d.L == 0) return;
+    const uint32_t s0 = a.text_slot[t], c = a.text_nslots[t], last = s0 + c - 1;
+    const uint16_t a0 = a.alias[a.alias_row[s0]];
+    uint64_t v = 0;
+    if (a0 != 0xFFFFu && a0 < kRowCap) v = c == 1 ? 1ull << a0 : a.prod[(uint64_t)a.text_prod[t] * kRowCap + a0];
+    const uint32_t R = a.run_count[last];
+    if (d.functional) {
+        for (; v; v &= v - 1) {
+            const uint32_t ci = __builtin_ctzll(v);
+            if (ci >= R) continue;
+            const uint32_t fs = a.run_final[a.run_base[last] + ci];
+            if (fs == kNoState) continue;
+            res[0] = d.accept_of_state[fs];
+            res[1] = d.final_of_state[fs];
+            break;
+        }
+        return;
+    }
+    ListUnion u;
+    u.k = 0;
+    for (; v && u.k < kRowCap; v &= v - 1) {
+        const uint32_t ci = __builtin_ctzll(v);
+        if (ci >= R) continue;
+        const uint32_t fs = a.run_final[a.run_base[last] + ci];
+        if (fs == kNoState) continue;
+        u.b[u.k] = d.csr_idx + d.csr_off[fs];
+        u.e[u.k] = d.csr_idx + d.csr_off[fs + 1];
+        ++u.k;
+    }
+    decide_lists(u, final_args(d), res);
+}
+
+// block per text whose chunks kept more than kRowCap runs: the set of starts
+// (members) is carried slot by slot, as in propagate_kernel
+__global__ void __launch_bounds__(1024) mprop_kernel(MultiArgs a) {
+    extern __shared__ __align__(16) uint32_t sm[];
+    const uint32_t t = blockIdx.x;
+    if (a.text_flag[t] == 0) return;
+    const AutoDesc &d = a.autos[a.text_auto[t]];
+    const uint32_t W = d.functional ? (d.L + 31) / 32 : d.W;
+    uint32_t *X = sm, *Y = sm + W, *H = sm + 2 * W;
+    const uint32_t s0 = a.text_slot[t], c = a.text_nslots[t];
+    for (uint32_t w = threadIdx.x; w < W; w += blockDim.x) X[w] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint16_t c0 = a.alias[a.alias_row[s0]];
+        if (c0 != 0xFFFFu) {
+            const uint32_t fs = a.run_final[a.run_base[s0] + c0];
+            if (fs != kNoState) for_members(d, fs, [&](uint32_t m) { X[m >> 5] |= 1u << (m & 31); });
+        }
+    }
+    __syncthreads();
+    for (uint32_t k = s0 + 1; k < s0 + c; ++k) {
+        for (uint32_t w = threadIdx.x; w < W; w += blockDim.x) { H[w] = 0; Y[w] = 0; }
+        __syncthreads();
+        const uint16_t *row = a.alias + a.alias_row[k];
+        for (uint32_t w = threadIdx.x; w < W; w += blockDim.x)
+            for (uint32_t bits = X[w]; bits; bits &= bits - 1) {
+                const uint16_t ci = row[w * 32 + __builtin_ctz(bits)];
+                if (ci != 0xFFFFu) atomicOr(&H[ci >> 5], 1u << (ci & 31));
+            }
+        __syncthreads();
+        const uint32_t base = a.run_base[k];
+        for (uint32_t w = threadIdx.x; w < W; w += blockDim.x)
+            for (uint32_t bits = H[w]; bits; bits &= bits - 1) {
+                const uint32_t fs = a.run_final[base + w * 32 + __builtin_ctz(bits)];
+                if (fs != kNoState) for_members(d, fs, [&](uint32_t m) { atomicOr(&Y[m >> 5], 1u << (m & 31)); });
+            }
+        __syncthreads();
+        for (uint32_t w = threadIdx.x; w < W; w += blockDim.x) X[w] = Y[w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        int32_t *res = a.results + (uint64_t)a.text_out[t] * 2;
+        if (d.functional) {
+            res[0] = 0;
+            res[1] = -1;
+            for (uint32_t w = 0; w < W; ++w)
+                if (X[w]) {
+                    const uint32_t st = w * 32 + __builtin_ctz(X[w]);
+                    res[0] = d.accept_of_state[st];
+                    res[1] = d.final_of_state[st];
+                    break;
+                }
+        } else {
+            decide_bits(X, W, final_args(d), res);
+        }
+        a.text_flag[t] = 0;
+    }
+}
+
+
+
 // ---- template dispatch ----------------------------------------------------
 
 template <class F>
@@ -1547,6 +1840,43 @@ hipError_t launch_batch_final_fun(const BatchFinalArgs &b, const FinalArgs &f, u
 hipError_t launch_batch_fill(const BatchFinalArgs &b, hipStream_t s) {
     hipLaunchKernelGGL(batch_fill_kernel, dim3(blocks_for(b.ntexts ? b.ntexts : 1, 256)), dim3(256), 0, s, b);
     return hipGetLastError();
+}
+
+hipError_t launch_mwarm(const MultiArgs &a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(mwarm_kernel, dim3(grid), dim3(1024), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlong(const MultiArgs &a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(mlong_kernel, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mhit(const MultiArgs &a, bool level0, hipStream_t s) {
+    const uint32_t blocks = (a.ngroups + 3) / 4;
+    if (blocks == 0) return hipSuccess;
+    if (level0) hipLaunchKernelGGL(mhit_kernel<true>, dim3(blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(mhit_kernel<false>, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfinal(const MultiArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(mfinal_kernel, dim3(blocks_for(a.ntexts ? a.ntexts : 1, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mprop(const MultiArgs &a, uint32_t max_words, hipStream_t s) {
+    if (max_words > kPropMaxWords) return hipErrorInvalidValue;
+    if (a.ntexts == 0) return hipSuccess;
+    hipLaunchKernelGGL(mprop_kernel, dim3(a.ntexts), dim3(1024), (size_t)max_words * 12, s, a);
+    return hipGetLastError();
+}
+
+int multi_blocks_per_cu(int which) {
+    int n = 0;
+    if (which == 1) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mwarm_kernel, 1024, 0);
+    else (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mlong_kernel, 256, 0);
+    return n;
 }
 
 }  // namespace ri

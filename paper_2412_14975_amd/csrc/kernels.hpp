@@ -205,4 +205,53 @@ hipError_t launch_batch_final_fun(const BatchFinalArgs &b, const FinalArgs &f, u
 // results of texts whose automaton accepts nothing: (0, -1)
 hipError_t launch_batch_fill(const BatchFinalArgs &b, hipStream_t s);
 
+// ---- fused batches: many automata in one launch sequence ----
+//
+// Every chunk slot names its automaton; tables stay in global memory (L2),
+// entry widths are read at run time, alias rows are 16-bit.  Every automaton
+// is joined by hit matrices over member lists: an RI-DFA state stands for
+// its content, a DFA state s (functional automata) for {s}.
+struct AutoDesc {
+    const void *table;
+    const uint16_t *code;          // byte -> class * entry_bytes
+    const uint32_t *starts;        // row offsets of the L starts
+    uint32_t L, row_bytes, dead, entry_bytes;
+    uint32_t functional;           // 1: content(s) = {s}, results from the tables below
+    uint32_t W;                    // words of a set of starts
+    const uint32_t *csr_off, *csr_idx, *fmask, *hash;
+    uint32_t hash_cap;
+    const int32_t *final_of_state;
+    const uint8_t *accept_of_state;
+};
+
+struct MultiArgs {
+    const AutoDesc *autos;
+    uint32_t nslots, ntexts;
+    const uint64_t *chunk_addr;    // per slot (see ScanArgs)
+    const uint32_t *chunk_len;
+    const uint32_t *slot_auto;     // automaton of each slot
+    const uint32_t *slot_text;     // text of each slot
+    const uint64_t *alias_row;     // per slot: first entry of its alias row (uint16 entries)
+    uint16_t *alias;
+    uint32_t warm;
+    uint32_t *run_base, *run_count, *run_chunk, *run_state, *run_final;
+    uint32_t *counters;            // [1] runs; reset by the final kernel
+    uint32_t *text_flag;           // per text: 1 when a chunk kept more than kRowCap runs
+    // texts
+    const uint32_t *text_slot, *text_nslots, *text_auto, *text_out, *text_prod;
+    int32_t *results;              // [rows][2]
+    // hit products: every level in one buffer
+    uint64_t *prod;                // [groups][kRowCap]
+    uint32_t *prod_rows;           // [groups]
+    const uint32_t *grp_first, *grp_count;   // the level being launched
+    uint32_t ngroups;
+    uint32_t prod_out;             // first product index of the level being launched
+};
+hipError_t launch_mwarm(const MultiArgs &a, int grid, hipStream_t s);
+hipError_t launch_mlong(const MultiArgs &a, int grid, hipStream_t s);
+hipError_t launch_mhit(const MultiArgs &a, bool level0, hipStream_t s);
+hipError_t launch_mfinal(const MultiArgs &a, hipStream_t s);
+hipError_t launch_mprop(const MultiArgs &a, uint32_t max_words, hipStream_t s);
+int multi_blocks_per_cu(int which);
+
 }  // namespace ri

@@ -71,9 +71,12 @@ def mixed_requests(seed):
     return out
 
 
-def check_batch(reqs, chunk_bytes, refs, recs, launch="run"):
+MODES = ("grouped", "fused")
+
+
+def check_batch(reqs, chunk_bytes, refs, recs, launch="run", mode="auto"):
     texts = [dev(x) for _, x, _ in reqs]
-    b = ri.Batch([(recs[p], t, a) for (p, _, a), t in zip(reqs, texts)], chunk_bytes=chunk_bytes)
+    b = ri.Batch([(recs[p], t, a) for (p, _, a), t in zip(reqs, texts)], chunk_bytes=chunk_bytes, mode=mode)
     try:
         if launch == "run":
             got = b.run().cpu().numpy()
@@ -105,21 +108,25 @@ def mixed():
         r.close()
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("chunk_bytes", [0, 16, 48, 256, 4096])
-def test_mixed_batch(mixed, chunk_bytes):
+def test_mixed_batch(mixed, chunk_bytes, mode):
     reqs, refs, recs = mixed
-    info = check_batch(reqs, chunk_bytes, refs, recs)
+    info = check_batch(reqs, chunk_bytes, refs, recs, mode=mode)
     assert info["texts"] == len(reqs)
     assert info["bytes"] == sum(len(x) for _, x, _ in reqs)
+    assert info["fused"] == (mode == "fused")
 
 
-def test_mixed_batch_graph(mixed):
+@pytest.mark.parametrize("mode", MODES)
+def test_mixed_batch_graph(mixed, mode):
     reqs, refs, recs = mixed
-    info = check_batch(reqs, 64, refs, recs, launch="graph")
+    info = check_batch(reqs, 64, refs, recs, launch="graph", mode=mode)
     assert info["captured"] == 1
 
 
-def test_deep_join_trees():
+@pytest.mark.parametrize("mode", MODES)
+def test_deep_join_trees(mode):
     """16-byte chunks: a 300 KB text has ~19k chunks, so the per-text join
     tree has three or more levels; texts of one chunk sit beside it."""
     p = gen.c1_regex()
@@ -132,7 +139,7 @@ def test_deep_join_trees():
     try:
         for algo in ALGOS:
             reqs = [(p, x, algo) for x in xs]
-            b = ri.Batch([(rec, dev(x), algo) for x in xs], chunk_bytes=16)
+            b = ri.Batch([(rec, dev(x), algo) for x in xs], chunk_bytes=16, mode=mode)
             try:
                 assert b.group(0)["join_levels"] >= 3
                 got = b.run().cpu().numpy()
@@ -145,7 +152,8 @@ def test_deep_join_trees():
         rec.close()
 
 
-def test_graph_replays_with_eager_work_between():
+@pytest.mark.parametrize("mode", MODES)
+def test_graph_replays_with_eager_work_between(mode):
     """Replay the captured graph several times; between replays the results
     are overwritten by eager torch work, and every replay must restore them."""
     p = gen.c1_regex()
@@ -155,7 +163,7 @@ def test_graph_replays_with_eager_work_between():
     xs[0][-4:] = np.frombuffer(b"abab", np.uint8)
     want = [ref.serial(x) for x in xs]
     texts = [dev(x) for x in xs]
-    b = ri.Batch([(rec, t, a) for t, a in zip(texts, ("rid", "dfa", "rid", "subset"))], chunk_bytes=256)
+    b = ri.Batch([(rec, t, a) for t, a in zip(texts, ("rid", "dfa", "rid", "subset"))], chunk_bytes=256, mode=mode)
     try:
         b.capture()
         for rep in range(4):
@@ -170,7 +178,8 @@ def test_graph_replays_with_eager_work_between():
         rec.close()
 
 
-def test_batch_autotune_keeps_results():
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_autotune_keeps_results(mode):
     rx, motifs = gen.c2_regex_and_motifs(2)
     ref = MinRef(rx)
     rng = gen.PCG(3)
@@ -180,7 +189,7 @@ def test_batch_autotune_keeps_results():
         xs.append(x if k % 2 == 0 else rej)
     rec = ri.Recognizer(rx)
     texts = [dev(x) for x in xs]
-    b = ri.Batch([(rec, t, ("rid", "dfa")[i % 2]) for i, t in enumerate(texts)])
+    b = ri.Batch([(rec, t, ("rid", "dfa")[i % 2]) for i, t in enumerate(texts)], mode=mode)
     try:
         tun = b.autotune()
         assert tun["trials"] >= 6 and tun["best_ms"] > 0
@@ -194,7 +203,8 @@ def test_batch_autotune_keeps_results():
         rec.close()
 
 
-def test_batched_workload_sample():
+@pytest.mark.parametrize("mode", MODES)
+def test_batched_workload_sample(mode):
     """Four expressions of the batched workload, 48 texts of 1 KiB - 512 KiB,
     half derived from the expression and half changed at one byte."""
     spec = json.load(open(os.path.join(HERE, "golden", "c4_regexes.json")))
@@ -216,7 +226,7 @@ def test_batched_workload_sample():
     texts = [dev(x) for _, x, _ in items]
     try:
         for algo in ("rid", "dfa"):
-            b = ri.Batch([(recs[k], t, algo) for (k, _, _), t in zip(items, texts)])
+            b = ri.Batch([(recs[k], t, algo) for (k, _, _), t in zip(items, texts)], mode=mode)
             try:
                 got = b.run().cpu().numpy()
             finally:
@@ -260,3 +270,35 @@ def test_batch_argument_errors():
             b.close()
     finally:
         rec.close()
+
+
+def test_fused_batch_of_large_automata():
+    """Keyword unions with 20 and 300 keywords (interfaces below and beyond
+    2048 states) and the never-merging counter beside a 300-keyword union,
+    RID and DFA, in one fused batch (auto mode picks fused for them)."""
+    kw20, k20 = gen.c5_automaton(7, 1, 20)
+    kw300, k300 = gen.c5_automaton(7, 1, 300)
+    count = b"((b*a){37})*b*|z" + kw300
+    pats = [kw20, kw300, count]
+    refs = {p: MinRef(p) for p in pats}
+    recs = {p: ri.Recognizer(p) for p in pats}
+    rng = gen.PCG(77)
+    reqs = []
+    for i, n in enumerate((0, 1, 300, 5000, 65536, 200003)):
+        reqs.append((kw20, gen.c5_text(rng, k20, n, i % 2 == 0), ("rid", "dfa")[i % 2]))
+        reqs.append((kw300, gen.c5_text(rng, k300, n, i % 2 == 1), ("rid", "dfa")[(i + 1) % 2]))
+        reqs.append((count, gen.random_text(rng, b"ab", n), "rid"))
+    try:
+        texts = [dev(x) for _, x, _ in reqs]
+        b = ri.Batch([(recs[p], t, a) for (p, _, a), t in zip(reqs, texts)], chunk_bytes=256)
+        try:
+            assert b.info()["fused"] == 1
+            for rep in range(2):
+                got = b.run().cpu().numpy()
+                for i, (p, x, a) in enumerate(reqs):
+                    assert (bool(got[i, 0]), int(got[i, 1])) == refs[p].serial(x), (rep, i, len(x), a)
+        finally:
+            b.close()
+    finally:
+        for r in recs.values():
+            r.close()
