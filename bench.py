@@ -14,6 +14,12 @@ already resident in HBM.  Default workload: the motif union over {A,C,G,T}
 16 random expressions, recognized by one captured graph launch of a batch
 (ri_batch_*), RID and all-states DFA, against one ri_recognize_ex call per
 text.
+
+--workload serve: a pool of 64 resident keyword-union automata
+.*(k1|...|kn).* (n in 200..2000), requests with log-normal text lengths
+(median 64 KiB, sigma 1, cap 64 MiB), a keyword planted in half of them;
+capacity (all requests at once), then Poisson arrivals at fractions of it:
+p50/p99 latency and GB/s, RID and all-states DFA.
 """
 
 import argparse
@@ -35,7 +41,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="motif", choices=["motif", "log", "tiny", "batch"])
+    ap.add_argument("--workload", default="motif", choices=["motif", "log", "tiny", "batch", "serve"])
+    ap.add_argument("--automata", type=int, default=64, help="serve workload: automata in the pool")
+    ap.add_argument("--requests", type=int, default=2000, help="serve workload: requests per run")
+    ap.add_argument("--loads", default="0.25,0.5,0.8", help="serve workload: offered loads (fractions of capacity)")
     ap.add_argument("--texts", type=int, default=4096, help="batch workload: number of texts")
     ap.add_argument("--procs", type=int, default=8, help="batch workload: text generator processes")
     ap.add_argument("--chunks", type=int, default=0)
@@ -352,8 +361,121 @@ def main_batch(args):
         rc.close()
 
 
+# ---------------------------------------------------------------------------
+# serving workload
+# ---------------------------------------------------------------------------
+
+SERVE_SEED = 11
+
+
+def main_serve(args):
+    import torch
+    import paper_2412_14975_amd as ri
+    from concurrent.futures import ThreadPoolExecutor
+    from workloads import gen
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU", file=sys.stderr)
+        sys.exit(2)
+    t0 = time.perf_counter()
+    autos = [gen.c5_automaton(SERVE_SEED, i) for i in range(args.automata)]
+    with ThreadPoolExecutor(max_workers=max(1, args.procs)) as ex:   # ri_build runs without the interpreter lock
+        recs = list(ex.map(lambda a: ri.Recognizer(a[0]), autos))
+    infos = [r.info() for r in recs]
+    print(f"# {len(recs)} automata built ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    rng = gen.PCG(SERVE_SEED + 1)
+    reqs = []
+    for i in range(args.requests):
+        k = int(rng.integers(0, len(autos)))
+        n = gen.c5_length(rng)
+        reqs.append((k, gen.c5_text(rng, autos[k][1], n, plant=i % 2 == 0)))
+    total = sum(len(x) for _, x in reqs)
+    print(f"# {len(reqs)} requests, {total} bytes", file=sys.stderr, flush=True)
+    loads = [float(v) for v in args.loads.split(",") if v]
+    out_algo, results_by_algo = {}, {}
+    for algo in ("rid", "dfa"):
+        srv = ri.serve.Server(recs, algo=algo, slots=3, hbm_budget=32 << 30)
+        try:
+            # capacity: every request present at once
+            c0 = time.perf_counter()
+            for k, x in reqs:
+                srv.submit(k, x, arrival=c0)
+            done = srv.drain()
+            wall = time.perf_counter() - c0
+            results_by_algo[algo] = {d["id"]: (d["accept"], d["final_state"]) for d in done}
+            cap_rps = len(reqs) / wall
+            entry = dict(capacity=dict(gbps=total / wall / 1e9, req_per_s=cap_rps, wall_s=wall, steps=srv.steps))
+            # Poisson arrivals at fractions of the capacity
+            for frac in loads:
+                qps = frac * cap_rps
+                t, sched = 0.0, []
+                prng = gen.PCG(SERVE_SEED + 2)
+                for k, x in reqs:
+                    t += float(prng.exponential(1.0 / qps))
+                    sched.append((t, k, x))
+                steps0 = srv.steps
+                done, wall = ri.serve.run_open_loop(srv, sched)
+                lat = np.array([d["latency"] for d in done])
+                same = all((d["accept"], d["final_state"]) == results_by_algo[algo][d["id"] - len(reqs) * (1 + loads.index(frac))]
+                           for d in done)
+                entry[f"load_{frac:g}"] = dict(offered_req_per_s=qps, gbps=total / wall / 1e9,
+                                               p50_ms=float(np.percentile(lat, 50) * 1e3),
+                                               p99_ms=float(np.percentile(lat, 99) * 1e3),
+                                               steps=srv.steps - steps0, same_results=bool(same))
+                print(f"# serve {algo} load {frac}: p50 {entry[f'load_{frac:g}']['p50_ms']:.2f} ms "
+                      f"p99 {entry[f'load_{frac:g}']['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
+            entry["max_device_bytes_in_flight"] = srv.max_used
+        finally:
+            srv.close()
+        out_algo[algo] = entry
+    # every request: RID and DFA agree, and a sample agrees with single-text calls
+    agree = all(results_by_algo["rid"][i] == results_by_algo["dfa"][i] for i in range(len(reqs)))
+    alone_ok = True
+    for i in range(0, len(reqs), max(1, len(reqs) // 50)):
+        k, x = reqs[i]
+        if len(x) == 0:
+            continue
+        r = recs[k].recognize(torch.from_numpy(x).to("cuda"), algo="rid")
+        alone_ok &= (r["accept"], r["final_state"]) == results_by_algo["rid"][i]
+    rid = out_algo["rid"]
+    out = {
+        "metric": "GB/s of text recognized, RI-DFA vs all-states DFA speculation (bit-exact); p50/p99",
+        "value": round(rid["capacity"]["gbps"], 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.requests,
+        "warmup": 0,
+        "ms_per_step": round(rid["capacity"]["wall_s"] * 1e3 / args.requests, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"serving-{len(recs)}-keyword-automata", "requests": len(reqs), "n_bytes": total,
+                   "keyword_seed": SERVE_SEED, "interface_states": [min(i["interface_states"] for i in infos),
+                                                                     max(i["interface_states"] for i in infos)],
+                   "min_dfa_states": [min(i["min_dfa_states"] for i in infos), max(i["min_dfa_states"] for i in infos)],
+                   "slots": 3, "loads": loads},
+        "bitexact": bool(agree and alone_ok),
+        "serve": {a: {k: ({kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                          if isinstance(v, dict) else v) for k, v in e.items()} for a, e in out_algo.items()},
+        "speedup_rid_vs_dfa": round(rid["capacity"]["gbps"] / out_algo["dfa"]["capacity"]["gbps"], 4),
+        "command": " ".join(["python", "bench.py"] + sys.argv[1:]),
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    for r in recs:
+        r.close()
+
+
 def main():
     args = parse()
+    if args.workload == "serve" and not args.traffic_from:
+        if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+            print("bench.py: this recognizer runs on one GPU only; --gpus must be 1", file=sys.stderr)
+            sys.exit(2)
+        main_serve(args)
+        return
     if args.workload == "batch" and not args.traffic_from:
         if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
             print("bench.py: this recognizer runs on one GPU only; --gpus must be 1", file=sys.stderr)

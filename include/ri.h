@@ -317,6 +317,23 @@ typedef struct {
 } ri_batch_opts;
 int ri_batch_create_ex(const ri_request *reqs, uint32_t count, const ri_batch_opts *opts, ri_batch **out);
 
+/*
+ * ri_batch_update -- re-plan a fused batch for a new set of requests (same
+ * rules as ri_batch_create_ex), keeping its options and tuned chunk size and
+ * warm-up and reusing its device buffers (they grow only when the new plan
+ * needs more).  No run or graph launch of the batch may be in flight; a
+ * captured graph is dropped.  Synchronous.  RI_ERR_ARG for a grouped batch.
+ */
+int ri_batch_update(ri_batch *b, const ri_request *reqs, uint32_t count);
+
+/*
+ * ri_request_footprint -- device bytes that one request (text of n bytes,
+ * handle h, algo) occupies in a fused batch with this chunk_bytes (0 = the
+ * fused default): the text itself plus its share of the batch's buffers.
+ * Host only; for admission control.
+ */
+int ri_request_footprint(const ri_handle *h, int algo, uint64_t n, uint32_t chunk_bytes, uint64_t *bytes);
+
 /* ri_batch_free -- release the batch (not the handles); NULL is a no-op.
  * No run or graph launch of the batch may be in flight. */
 void ri_batch_free(ri_batch *b);

@@ -12,5 +12,6 @@ from .binding import (  # noqa: F401
     ri_last_timings, ri_recognize, ri_recognize_ex, ri_set_profiling, ri_state_content,
     ri_set_option, ri_get_option, ri_autotune, Batch, ri_batch_create, ri_batch_free, ri_batch_run,
     ri_batch_capture, ri_batch_launch, ri_batch_get_info, ri_batch_get_group, ri_batch_autotune,
-    ri_batch_create_ex,
+    ri_batch_create_ex, ri_batch_update, ri_request_footprint,
 )
+from . import serve  # noqa: F401,E402

@@ -27,7 +27,7 @@ SYMBOLS = ("ri_build", "ri_free", "ri_info", "ri_recognize", "ri_recognize_ex",
            "ri_set_option", "ri_get_option", "ri_autotune", "ri_last_error",
            "ri_batch_create", "ri_batch_free", "ri_batch_run", "ri_batch_capture",
            "ri_batch_launch", "ri_batch_get_info", "ri_batch_get_group", "ri_batch_autotune",
-           "ri_batch_create_ex")
+           "ri_batch_create_ex", "ri_batch_update", "ri_request_footprint")
 RI_BATCH_AUTO, RI_BATCH_GROUPED, RI_BATCH_FUSED = 0, 1, 2
 BATCH_MODES = {"auto": RI_BATCH_AUTO, "grouped": RI_BATCH_GROUPED, "fused": RI_BATCH_FUSED}
 RI_OPT_CONVERGE, RI_OPT_WARMUP_BYTES, RI_OPT_RUNS_PER_LANE, RI_OPT_CHUNK_TARGET, RI_OPT_JOIN = 1, 2, 3, 4, 5
@@ -123,6 +123,8 @@ def lib() -> ctypes.CDLL:
     L.ri_autotune.argtypes = [vp, vp, sz, vp, i32, ctypes.POINTER(ri_tuning)]
     L.ri_batch_create.argtypes = [ctypes.POINTER(ri_request), u32, u32, ctypes.POINTER(vp)]
     L.ri_batch_create_ex.argtypes = [ctypes.POINTER(ri_request), u32, ctypes.POINTER(ri_batch_opts), ctypes.POINTER(vp)]
+    L.ri_batch_update.argtypes = [vp, ctypes.POINTER(ri_request), u32]
+    L.ri_request_footprint.argtypes = [vp, i32, ctypes.c_uint64, u32, ctypes.POINTER(ctypes.c_uint64)]
     L.ri_batch_free.argtypes = [vp]
     L.ri_batch_free.restype = None
     L.ri_batch_run.argtypes = [vp, vp, vp]
@@ -300,6 +302,16 @@ def ri_batch_create_ex(requests, chunk_bytes: int = 0, mode="auto", warmup_bytes
     b = ctypes.c_void_p()
     _check(lib().ri_batch_create_ex(_requests(requests), len(requests), ctypes.byref(opts), ctypes.byref(b)))
     return b.value
+
+
+def ri_batch_update(b: int, requests) -> None:
+    _check(lib().ri_batch_update(b, _requests(requests), len(requests)))
+
+
+def ri_request_footprint(h: int, algo, n: int, chunk_bytes: int = 0) -> int:
+    v = ctypes.c_uint64(0)
+    _check(lib().ri_request_footprint(h, _algo(algo), int(n), int(chunk_bytes), ctypes.byref(v)))
+    return int(v.value)
 
 
 def ri_batch_free(b: int) -> None:

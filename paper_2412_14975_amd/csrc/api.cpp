@@ -206,11 +206,19 @@ void pack_all(ri_handle *h) {
     u.accept_of_state = A.dsub_accept;
 }
 
+// Zero device memory and wait for it: the memset runs on the null stream,
+// which does not order it before kernels on non-blocking streams.
+hipError_t zero_now(void *p, size_t bytes) {
+    hipError_t e = hipMemset(p, 0, bytes);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    return e;
+}
+
 template <typename T>
 hipError_t upload(T **dst, const void *src, size_t bytes) {
     hipError_t e = hipMalloc(reinterpret_cast<void **>(dst), bytes ? bytes : 16);
     if (e != hipSuccess) return e;
-    if (bytes == 0 || !src) return hipMemset(*dst, 0, bytes ? bytes : 16);
+    if (bytes == 0 || !src) return zero_now(*dst, bytes ? bytes : 16);
     return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
 }
 
@@ -258,7 +266,7 @@ int get_workspace(ri_handle *h, int device, hipStream_t stream, Workspace **out)
     w->device = device;
     w->stream = stream;
     HIP_TRY(hipMalloc(reinterpret_cast<void **>(&w->counters), 64));
-    HIP_TRY(hipMemset(w->counters, 0, 64));
+    HIP_TRY(zero_now(w->counters, 64));
     HIP_TRY(hipMalloc(reinterpret_cast<void **>(&w->dres), 16));
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&w->hres), 16, hipHostMallocDefault));
     for (auto &e : w->ev) HIP_TRY(hipEventCreate(&e));
@@ -481,12 +489,18 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     } else {
         rc = grow(ws->lam, pairs * H.lam_bytes);
     }
-    // join buffers: at most ceil(nchunks / 2) relations of L rows (or classes)
+    // join buffers of the dense joins (class join, relations, functions): at
+    // most ceil(nchunks / 2) relations of L rows (or classes); the hit-matrix
+    // join and the join by propagation do not use them
+    const bool rel_conv = conv && H.relational;
+    const uint32_t gc = rel_conv && H.W <= kMaxDenseWords ? cls_group(H, shape.alias_bytes) : 0;
+    const bool hit = rel_conv && (opt.join == 0 || gc == 0);
+    const bool dense_join = !rel_conv || gc != 0;
     const size_t nrel_max = std::max<size_t>(ng0, (plan.nchunks + 1) / 2);
-    if (!rc) rc = grow(ws->join[0], nrel_max * H.L * row_words * 4);
-    if (!rc) rc = grow(ws->join[1], nrel_max * H.L * row_words * 4);
-    if (!rc) rc = grow(ws->ncls[0], nrel_max * 4);
-    if (!rc) rc = grow(ws->ncls[1], nrel_max * 4);
+    if (!rc && dense_join) rc = grow(ws->join[0], nrel_max * H.L * row_words * 4);
+    if (!rc && dense_join) rc = grow(ws->join[1], nrel_max * H.L * row_words * 4);
+    if (!rc && dense_join) rc = grow(ws->ncls[0], nrel_max * 4);
+    if (!rc && dense_join) rc = grow(ws->ncls[1], nrel_max * 4);
     if (!rc && maps) rc = grow(ws->dbg, pairs * 4);
     if (rc) return rc;
 
@@ -566,9 +580,6 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     ca.run_base = ja.run_base;
     ca.run_final = ja.run_final;
     ca.content = D.content;
-    const bool rel_conv = conv && H.relational;
-    const uint32_t gc = rel_conv && H.W <= kMaxDenseWords ? cls_group(H, shape.alias_bytes) : 0;
-    const bool hit = rel_conv && (opt.join == 0 || gc == 0);
     auto cls_join = [&]() -> int {
         ca.G = gc;
         ca.nmembers = plan.nchunks;
@@ -904,7 +915,7 @@ int plan_group(ri_batch *b, BatchGroup &g) {
         if (rc) return rc;
         if (!g.counters) {
             HIP_TRY(hipMalloc(reinterpret_cast<void **>(&g.counters), 64));
-            HIP_TRY(hipMemset(g.counters, 0, 64));
+            HIP_TRY(zero_now(g.counters, 64));
         }
     }
     int rc = grow(g.desc, blob.size());
@@ -1038,6 +1049,27 @@ int check_device(const ri_batch *b) {
     return RI_OK;
 }
 
+// Chunking of one text in a fused batch: (chunk bytes, chunks).
+void fused_chunking(uint64_t n, uint32_t L, uint64_t cs, uint64_t *cs_out, uint64_t *nc_out) {
+    const uint64_t maxc = std::max<uint64_t>(1, kFusedTextPairs / std::max<uint32_t>(L, 1));
+    if (n && (n + cs - 1) / cs > maxc) cs = round_up((n + maxc - 1) / maxc, 16);
+    *cs_out = cs;
+    *nc_out = n ? (n + cs - 1) / cs : 1;
+}
+
+int check_requests(const ri_request *reqs, uint32_t count) {
+    for (uint32_t i = 0; i < count; ++i) {
+        const ri_request &q = reqs[i];
+        if (!q.h) return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": NULL handle");
+        if (q.algo < 0 || q.algo >= RI_NUM_ALGOS) return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": unknown algorithm");
+        if (q.reserved != 0) return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": reserved must be 0");
+        if (q.n > 0 && !q.text_dev) return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": NULL text pointer");
+        if (q.n > 0 && (reinterpret_cast<uintptr_t>(q.text_dev) & 15))
+            return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": text must be 16-byte aligned");
+    }
+    return RI_OK;
+}
+
 // Automaton descriptor of a group for the fused kernels.
 ri::AutoDesc auto_desc(const BatchGroup &g, int device) {
     ri::AutoDesc d{};
@@ -1079,10 +1111,8 @@ int plan_fused(ri_batch *b) {
         const uint32_t L = descs[gi].L;
         for (uint32_t r : b->groups[gi].req) {
             const ri_request &q = b->reqs[r];
-            uint64_t cs = z.cs;
-            const uint64_t maxc = std::max<uint64_t>(1, kFusedTextPairs / std::max<uint32_t>(L, 1));
-            if (q.n && (q.n + cs - 1) / cs > maxc) cs = round_up((q.n + maxc - 1) / maxc, 16);
-            const uint64_t nc = q.n ? (q.n + cs - 1) / cs : 1;
+            uint64_t cs, nc;
+            fused_chunking(q.n, L, z.cs, &cs, &nc);
             if (addr.size() + nc > 0x7fffffffull) return fail(RI_ERR_LIMIT, "too many chunks in one batch");
             const uint32_t t = (uint32_t)tslot.size();
             tslot.push_back((uint32_t)addr.size());
@@ -1175,8 +1205,8 @@ int plan_fused(ri_batch *b) {
     if (!blob.empty()) HIP_TRY(hipMemcpy(z.blob.p, blob.data(), blob.size(), hipMemcpyHostToDevice));
     if (!descs.empty())
         HIP_TRY(hipMemcpy(z.autos.p, descs.data(), descs.size() * sizeof(ri::AutoDesc), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemset(z.text_flag.p, 0, z.text_flag.cap));
-    HIP_TRY(hipMemset(z.counters.p, 0, 64));
+    HIP_TRY(zero_now(z.text_flag.p, z.text_flag.cap));
+    HIP_TRY(zero_now(z.counters.p, 64));
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
     const uint32_t iters = (z.nslots + kWarmChunksPerBlock - 1) / kWarmChunksPerBlock;
@@ -1615,15 +1645,8 @@ int ri_batch_create_ex(const ri_request *reqs, uint32_t count, const ri_batch_op
     if (o.warmup_bytes && (o.warmup_bytes < 16 || o.warmup_bytes > 256 || o.warmup_bytes % 16))
         return fail(RI_ERR_ARG, "bad warm-up length");
     if (o.reserved) return fail(RI_ERR_ARG, "reserved must be 0");
-    for (uint32_t i = 0; i < count; ++i) {
-        const ri_request &q = reqs[i];
-        if (!q.h) return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": NULL handle");
-        if (q.algo < 0 || q.algo >= RI_NUM_ALGOS) return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": unknown algorithm");
-        if (q.reserved != 0) return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": reserved must be 0");
-        if (q.n > 0 && !q.text_dev) return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": NULL text pointer");
-        if (q.n > 0 && (reinterpret_cast<uintptr_t>(q.text_dev) & 15))
-            return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": text must be 16-byte aligned");
-    }
+    int rc0 = check_requests(reqs, count);
+    if (rc0) return rc0;
     ri_batch *b = new ri_batch();
     const int rc = batch_setup(b, reqs, count, o);
     if (rc) {
@@ -1638,6 +1661,52 @@ int ri_batch_create(const ri_request *reqs, uint32_t count, uint32_t chunk_bytes
     ri_batch_opts o{};
     o.chunk_bytes = chunk_bytes;
     return ri_batch_create_ex(reqs, count, &o, out);
+}
+
+int ri_batch_update(ri_batch *b, const ri_request *reqs, uint32_t count) {
+    if (!b || (count > 0 && !reqs)) return fail(RI_ERR_ARG, "NULL argument");
+    if (!b->fused) return fail(RI_ERR_ARG, "only fused batches can be updated");
+    int rc = check_device(b);
+    if (!rc) rc = check_requests(reqs, count);
+    if (rc) return rc;
+    drop_graph(b);
+    b->reqs.assign(reqs, reqs + count);
+    b->groups.clear();
+    b->bytes = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        ri_handle *h = const_cast<ri_handle *>(reqs[i].h);
+        BatchGroup *g = nullptr;
+        for (auto &x : b->groups)
+            if (x.h == h && x.algo == reqs[i].algo) g = &x;
+        if (!g) {
+            b->groups.emplace_back();
+            g = &b->groups.back();
+            g->h = h;
+            g->algo = reqs[i].algo;
+            g->empty = h->A.empty_language;
+            if (!g->empty) {
+                std::lock_guard<std::mutex> lk(h->mu);
+                rc = ensure_device(h, b->device);
+                if (rc) return rc;
+            }
+        }
+        g->req.push_back(i);
+        b->bytes += reqs[i].n;
+    }
+    return plan_fused(b);
+}
+
+int ri_request_footprint(const ri_handle *h, int algo, uint64_t n, uint32_t chunk_bytes, uint64_t *bytes) {
+    if (!h || !bytes) return fail(RI_ERR_ARG, "NULL argument");
+    if (algo < 0 || algo >= RI_NUM_ALGOS) return fail(RI_ERR_ARG, "unknown algorithm");
+    if (chunk_bytes % 16) return fail(RI_ERR_ARG, "chunk_bytes must be a multiple of 16");
+    const uint32_t L = h->A.empty_language ? 0 : h->algo[algo].L;
+    uint64_t cs, nc;
+    fused_chunking(n, L, chunk_bytes ? chunk_bytes : 4096, &cs, &nc);
+    // text, alias rows (2 B), run records (chunk, state, final: 12 B) per
+    // (start, chunk) pair, per-chunk descriptors and run counts, products
+    *bytes = round_up(n, 16) + nc * (uint64_t)L * 14 + nc * 40 + (nc / 64 + 2) * (ri::kRowCap * 8 + 4) + 64;
+    return RI_OK;
 }
 
 void ri_batch_free(ri_batch *b) {

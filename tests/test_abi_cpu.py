@@ -99,6 +99,23 @@ def test_batch_argument_checks_before_any_device_call():
         ri.ri_free(hh)
 
 
+def test_request_footprint_is_host_only_and_grows_with_the_text():
+    hh = ri.ri_build(gen.c5_automaton(3, 0, 20)[0])
+    try:
+        f = [ri.ri_request_footprint(hh, algo, n) for algo in ("rid", "dfa") for n in (0, 100, 1 << 16, 1 << 24)]
+        assert all(v > 0 for v in f)
+        assert f[0] < f[1] < f[2] < f[3] and f[4] < f[5] < f[6] < f[7]
+        assert f[3] >= 1 << 24
+        lib = ri.binding.lib()
+        v = ctypes.c_uint64()
+        assert lib.ri_request_footprint(None, 0, 10, 0, ctypes.byref(v)) == ri.binding.RI_ERR_ARG
+        assert lib.ri_request_footprint(hh, 9, 10, 0, ctypes.byref(v)) == ri.binding.RI_ERR_ARG
+        assert lib.ri_request_footprint(hh, 0, 10, 24, ctypes.byref(v)) == ri.binding.RI_ERR_ARG
+        assert lib.ri_batch_update(None, None, 0) == ri.binding.RI_ERR_ARG
+    finally:
+        ri.ri_free(hh)
+
+
 def _compare_with_oracle(pattern):
     ref = oracle.build(pattern)
     h = ri.ri_build(pattern)
