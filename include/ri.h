@@ -300,8 +300,8 @@ int ri_batch_create(const ri_request *reqs, uint32_t count, uint32_t chunk_bytes
  *                 are joined by propagation.  A text gets at most 2^22
  *                 (start, chunk) pairs: its chunks grow beyond chunk_bytes when
  *                 needed;
- *                 RI_BATCH_AUTO (0): fused when there are more than 4 groups or
- *                 an interface beyond 2048 states, else grouped;
+ *                 RI_BATCH_AUTO (0): fused when an interface exceeds 2048 states
+ *                 or the groups average less than 4 MiB of text, else grouped;
  *   warmup_bytes  0 (the handles' settings; 64 for fused) or a multiple of 16
  *                 in [16, 256];
  *   reserved      must be 0.

@@ -733,6 +733,7 @@ constexpr uint64_t kBatchAutoChunkTarget = 131072;   // chunks aimed at per grou
 constexpr uint64_t kBatchMinChunk = 256;
 constexpr uint64_t kBatchMaxChunk = 1ull << 20;
 constexpr int kBatchSide = 4;                         // concurrent branches of a captured batch
+constexpr uint64_t kGroupedMinBytes = 4ull << 20;     // text per group for the automatic grouped mode
 
 struct BatchLevel {
     uint32_t ngroups = 0;
@@ -1357,7 +1358,10 @@ int batch_setup(ri_batch *b, const ri_request *reqs, uint32_t count, const ri_ba
             wide |= g.h->algo[g.algo].relational && g.h->algo[g.algo].W > kMaxDenseWords;
         }
     }
-    b->fused = o.mode == RI_BATCH_FUSED || (o.mode == RI_BATCH_AUTO && (b->groups.size() > 4 || wide));
+    // automatic mode: the grouped path (tables in LDS, one launch sequence per
+    // group) when every group has enough text to fill the GPU; else fused
+    const bool small_groups = b->groups.size() > 0 && b->bytes / b->groups.size() < kGroupedMinBytes;
+    b->fused = o.mode == RI_BATCH_FUSED || (o.mode == RI_BATCH_AUTO && (wide || small_groups));
     if (b->fused) {
         b->fz.cs = o.chunk_bytes ? o.chunk_bytes : 4096;
         b->fz.warm = o.warmup_bytes ? o.warmup_bytes : 64;

@@ -256,6 +256,31 @@ def test_runs_per_chunk_around_the_hit_row_cap(k):
         rec.close()
 
 
+@pytest.mark.parametrize("k", [6, 10, 12])
+def test_regexp_family_sweep(k):
+    """(a|b)*a(a|b)^k: the minimal DFA has 2^(k+1) states (all speculated by
+    the baseline), the interface k + 2.  Accepted and rejected texts, both
+    algorithms, converging and plain reach."""
+    rx = gen.regexp_family(k)
+    ref = Ref(rx)
+    acc, rej = gen.c1_texts(300 + k, n=(1 << 20) + 9)
+    for mode in ("conv16", "plain"):
+        rec = make(rx, mode)
+        try:
+            assert rec.info()["min_dfa_states"] == 2 ** (k + 1)
+            assert rec.info()["interface_states"] == k + 2
+            for x in (acc, rej):
+                want = ref.serial(x)
+                for algo in ("rid", "dfa"):
+                    for chunks in (64, 0):
+                        got = rec.recognize(dev(x), algo=algo, chunks=chunks)
+                        assert (got["accept"], got["final_state"]) == want, (k, mode, algo, chunks)
+            if k == 10:
+                check_maps(rec, ref, acc[:40000], "rid", 16)
+        finally:
+            rec.close()
+
+
 # ---------------------------------------------------------------------------
 # edge cases
 # ---------------------------------------------------------------------------
