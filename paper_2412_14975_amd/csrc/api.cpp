@@ -85,7 +85,7 @@ struct Workspace {
     int32_t *hres = nullptr;        // pinned
     struct Buf { void *p = nullptr; size_t cap = 0; };
     Buf lam, alias, run_base, run_count, run_chunk, run_state, run_final, dbg, join[2], ncls[2], hprod[2],
-        hrows[2];
+        hrows[2], block_count;
     hipEvent_t ev[6] = {};
 };
 
@@ -325,9 +325,8 @@ struct ConvCfg {
     ri::KernelShape warm_shape, long_shape;
     size_t lds_w = 0, lds_l = 0;
     int grid_w = 1, grid_l = 1;
+    uint64_t run_cap = 0;   // run slots of all warm-up blocks' regions
 };
-
-constexpr uint32_t kWarmChunksPerBlock = 16;   // one wavefront per chunk
 
 int conv_config(const AlgoHost &H, const DeviceCopy &dc, const Options &opt, uint32_t nchunks, ConvCfg *c) {
     if (H.L > 65534) return fail(RI_ERR_LIMIT, "too many starts for the converging reach");
@@ -336,14 +335,25 @@ int conv_config(const AlgoHost &H, const DeviceCopy &dc, const Options &opt, uin
     // warm-up: starts held 64 per lane register, up to 4 registers per lane
     c->warm_shape = shape;
     c->warm_shape.runs_per_lane = H.L <= 64 ? 1 : H.L <= 128 ? 2 : 4;
-    c->lds_w = ri::warm_lds_bytes(c->warm_shape, (uint32_t)H.table.size());
-    const uint32_t iters = (nchunks + kWarmChunksPerBlock - 1) / kWarmChunksPerBlock;
+    c->lds_w = ri::warm_lds_bytes(c->warm_shape, (uint32_t)H.table.size(), H.L);
+    if (c->lds_w > dc.max_lds) {   // table and starts do not fit together: table from global memory
+        c->warm_shape.table_in_lds = false;
+        c->lds_w = ri::warm_lds_bytes(c->warm_shape, (uint32_t)H.table.size(), H.L);
+    }
+    const uint32_t iters = (nchunks + ri::kWarmChunksPerBlock - 1) / ri::kWarmChunksPerBlock;
     const int per_cu_w = std::max(1, ri::blocks_per_cu(1, c->warm_shape, c->lds_w));
     c->grid_w = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)dc.cus * per_cu_w, iters));
-    // long runs: one run per lane unless set
+    c->run_cap = (uint64_t)iters * ri::kWarmChunksPerBlock * H.L;   // every block's region
+    // long runs: one run per lane unless set; LDS also holds the prefix of
+    // the warm-up blocks' run counts
     c->long_shape = shape;
     c->long_shape.runs_per_lane = (int)(opt.runs_per_lane ? opt.runs_per_lane : 1);
-    c->lds_l = shape.table_in_lds ? lds_tables : 512;
+    const size_t pre = round_up(((size_t)c->grid_w + 1) * 4, 16);
+    c->lds_l = (shape.table_in_lds ? lds_tables : 512) + pre;
+    if (c->lds_l > dc.max_lds) {
+        c->long_shape.table_in_lds = false;
+        c->lds_l = 512 + pre;
+    }
     const uint64_t pairs = (uint64_t)H.L * nchunks;
     const int per_cu_l = std::max(1, ri::blocks_per_cu(2, c->long_shape, c->lds_l));
     const uint64_t max_jobs = (pairs + 64ull * c->long_shape.runs_per_lane - 1) / (64ull * c->long_shape.runs_per_lane);
@@ -355,6 +365,7 @@ struct ReachBufs {
     void *alias;
     uint32_t *run_base, *run_chunk, *run_state, *run_final, *counters;
     uint32_t *run_count;
+    uint32_t *block_count;   // [warm-up grid]
 };
 
 // Warm-up and merging, then the merged runs to the chunk ends; `mid`
@@ -370,6 +381,7 @@ int launch_conv(const ConvCfg &c, const ri::ScanArgs &sa, const Options &opt, co
     wa.run_chunk = rb.run_chunk;
     wa.run_state = rb.run_state;
     wa.counters = rb.counters;
+    wa.block_count = rb.block_count;
     HIP_TRY(ri::launch_warm(wa, c.warm_shape, c.grid_w, c.lds_w, stream));
     if (mid) HIP_TRY(hipEventRecord(mid, stream));
     ri::LongArgs la{};
@@ -378,7 +390,8 @@ int launch_conv(const ConvCfg &c, const ri::ScanArgs &sa, const Options &opt, co
     la.run_chunk = rb.run_chunk;
     la.run_state = rb.run_state;
     la.run_final = rb.run_final;
-    la.counters = rb.counters;
+    la.block_count = rb.block_count;
+    la.warm_blocks = (uint32_t)c.grid_w;
     HIP_TRY(ri::launch_long(la, c.long_shape, c.grid_l, c.lds_l, stream));
     return RI_OK;
 }
@@ -477,10 +490,11 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     if (conv) {
         rc = grow(ws->alias, pairs * shape.alias_bytes);
         if (!rc) rc = grow(ws->run_base, (size_t)plan.nchunks * 4);
-        if (!rc) rc = grow(ws->run_chunk, pairs * 4);
-        if (!rc) rc = grow(ws->run_state, pairs * 4);
-        if (!rc) rc = grow(ws->run_final, pairs * 4);
+        if (!rc) rc = grow(ws->run_chunk, cc.run_cap * 4);
+        if (!rc) rc = grow(ws->run_state, cc.run_cap * 4);
+        if (!rc) rc = grow(ws->run_final, cc.run_cap * 4);
         if (!rc) rc = grow(ws->run_count, (size_t)plan.nchunks * 4);
+        if (!rc) rc = grow(ws->block_count, (size_t)cc.grid_w * 4);
         const size_t nh = std::max<size_t>(1, (plan.nchunks + 62) / 64);   // level-0 hit products
         for (int i = 0; i < 2 && !rc; ++i) {
             rc = grow(ws->hprod[i], nh * ri::kRowCap * 8);
@@ -536,7 +550,8 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     } else {
         ReachBufs rb{ws->alias.p, static_cast<uint32_t *>(ws->run_base.p), static_cast<uint32_t *>(ws->run_chunk.p),
                      static_cast<uint32_t *>(ws->run_state.p), static_cast<uint32_t *>(ws->run_final.p),
-                     ws->counters, static_cast<uint32_t *>(ws->run_count.p)};
+                     ws->counters, static_cast<uint32_t *>(ws->run_count.p),
+                     static_cast<uint32_t *>(ws->block_count.p)};
         rc = launch_conv(cc, sa, opt, rb, stream, h->profiling ? ws->ev[5] : nullptr);
         if (rc) return rc;
         if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[4], stream));
@@ -754,7 +769,7 @@ struct BatchGroup {
     ConvCfg cc;
     std::vector<BatchLevel> levels;
     size_t off_addr = 0, off_len = 0, off_slot = 0, off_out = 0;
-    Workspace::Buf desc, alias, run_base, run_chunk, run_state, run_final, join[2], ncls[2];
+    Workspace::Buf desc, alias, run_base, run_chunk, run_state, run_final, join[2], ncls[2], block_count;
     uint32_t *counters = nullptr;
     float tuned_ms = 0;
 };
@@ -906,9 +921,10 @@ int plan_group(ri_batch *b, BatchGroup &g) {
         int rc = conv_config(H, dc, g.opt, g.slots, &g.cc);
         if (!rc) rc = grow(g.alias, pairs * alias_bytes);
         if (!rc) rc = grow(g.run_base, (size_t)g.slots * 4);
-        if (!rc) rc = grow(g.run_chunk, pairs * 4);
-        if (!rc) rc = grow(g.run_state, pairs * 4);
-        if (!rc) rc = grow(g.run_final, pairs * 4);
+        if (!rc) rc = grow(g.run_chunk, g.cc.run_cap * 4);
+        if (!rc) rc = grow(g.run_state, g.cc.run_cap * 4);
+        if (!rc) rc = grow(g.run_final, g.cc.run_cap * 4);
+        if (!rc) rc = grow(g.block_count, (size_t)g.cc.grid_w * 4);
         for (int i = 0; i < 2 && !rc; ++i) {
             rc = grow(g.join[i], max_groups * H.L * row_words * 4);
             if (!rc) rc = grow(g.ncls[i], max_groups * 4);
@@ -958,7 +974,8 @@ int run_group(ri_batch *b, const BatchGroup &g, hipStream_t stream, int32_t *res
     sa.row_bytes = H.K * H.entry_bytes;
     sa.dead = H.dead;
     ReachBufs rb{g.alias.p, static_cast<uint32_t *>(g.run_base.p), static_cast<uint32_t *>(g.run_chunk.p),
-                 static_cast<uint32_t *>(g.run_state.p), static_cast<uint32_t *>(g.run_final.p), g.counters};
+                 static_cast<uint32_t *>(g.run_state.p), static_cast<uint32_t *>(g.run_final.p), g.counters, nullptr,
+                 static_cast<uint32_t *>(g.block_count.p)};
     int rc = launch_conv(g.cc, sa, g.opt, rb, stream, nullptr);
     if (rc) return rc;
 
@@ -1210,7 +1227,7 @@ int plan_fused(ri_batch *b) {
     HIP_TRY(zero_now(z.counters.p, 64));
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
-    const uint32_t iters = (z.nslots + kWarmChunksPerBlock - 1) / kWarmChunksPerBlock;
+    const uint32_t iters = (z.nslots + ri::kWarmChunksPerBlock - 1) / ri::kWarmChunksPerBlock;
     z.grid_w = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)cus * std::max(1, ri::multi_blocks_per_cu(1)), iters));
     z.grid_l = std::max(1, cus * std::max(1, ri::multi_blocks_per_cu(2)));
     return RI_OK;
@@ -1434,7 +1451,7 @@ void ri_free(ri_handle *h) {
         (void)hipFree(w->counters);
         (void)hipFree(w->dres);
         (void)hipHostFree(w->hres);
-        for (Workspace::Buf *b : {&w->lam, &w->alias, &w->run_base, &w->run_count, &w->hprod[0], &w->hprod[1],
+        for (Workspace::Buf *b : {&w->lam, &w->alias, &w->run_base, &w->run_count, &w->hprod[0], &w->hprod[1], &w->block_count,
                                   &w->hrows[0], &w->hrows[1], &w->run_chunk, &w->run_state,
                                   &w->run_final, &w->dbg, &w->join[0], &w->join[1], &w->ncls[0],
                                   &w->ncls[1]})
@@ -1721,7 +1738,7 @@ void ri_batch_free(ri_batch *b) {
     drop_graph(b);
     for (auto &g : b->groups) {
         for (Workspace::Buf *x : {&g.desc, &g.alias, &g.run_base, &g.run_chunk, &g.run_state, &g.run_final,
-                                  &g.join[0], &g.join[1], &g.ncls[0], &g.ncls[1]})
+                                  &g.join[0], &g.join[1], &g.ncls[0], &g.ncls[1], &g.block_count})
             release(*x);
         if (g.counters) (void)hipFree(g.counters);
     }

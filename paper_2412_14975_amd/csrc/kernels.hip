@@ -247,7 +247,7 @@ template <typename T> __host__ __device__ constexpr uint32_t tile_stride(uint32_
     return cols + (sizeof(T) == 1 ? 4u : sizeof(T) == 2 ? 2u : 1u);
 }
 
-constexpr uint32_t kWarmWaves = 16;
+constexpr uint32_t kWarmWaves = kWarmChunksPerBlock;
 
 // Warm-up of the start block at `base` over codes[0..wlen) (codes of bytes
 // 64 q + lane in register q).
@@ -409,8 +409,11 @@ __device__ __forceinline__ void warm_records(const TE *tab, const uint32_t *star
 
 // Run slots of the block's chunks (one per wave): one atomic.  Returns the
 // first slot of this wave's chunk.
-__device__ __forceinline__ uint32_t warm_slots(uint32_t *s_cnt, uint32_t &s_base, uint32_t lane, uint32_t wave,
-                                               uint32_t D, uint32_t *counter) {
+// s_cnt [kWarmWaves + 1] is used on alternate iterations from two buffers, so
+// no barrier is needed after the last read: the next writes go to the other
+// buffer, and the one after that follows this iteration's first barrier.
+__device__ __forceinline__ uint32_t warm_slots(uint32_t *s_cnt, uint32_t lane, uint32_t wave, uint32_t D,
+                                               uint32_t *counter) {
     if (lane == 0) s_cnt[wave] = D;
     __syncthreads();
     if (wave == 0) {
@@ -421,22 +424,32 @@ __device__ __forceinline__ uint32_t warm_slots(uint32_t *s_cnt, uint32_t &s_base
             const uint32_t o = __shfl_up(incl, k);
             if ((int)lane >= k) incl += o;
         }
-        if (lane == kWarmWaves - 1) s_base = atomicAdd(counter, incl);
+        if (lane == kWarmWaves - 1) s_cnt[kWarmWaves] = atomicAdd(counter, incl);
         if (lane < kWarmWaves) s_cnt[lane] = incl - d;
     }
     __syncthreads();
-    return s_base + s_cnt[wave];
+    return s_cnt[kWarmWaves] + s_cnt[wave];
 }
+
+// Starts staged in LDS by the warm-up kernel when they fit.
+constexpr uint32_t kStageStarts = 4096;
 
 template <typename TE, typename TA, int R, bool LDS>
 __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
-    __shared__ uint32_t s_cnt[kWarmWaves], s_base;
+    __shared__ uint32_t s_count;   // runs placed in this block's region
     const TE *tab;
     const uint16_t *cls;
     stage_tables<TE, LDS>(a.s, smem, tab, cls);
-    __syncthreads();   // tables staged
     const uint32_t L = a.s.L;
+    const uint32_t *starts = a.s.starts;
+    if (L <= kStageStarts) {
+        uint32_t *ss = reinterpret_cast<uint32_t *>(smem + tables_lds<TE, LDS>(a.s.table_bytes));
+        for (uint32_t i = threadIdx.x; i < L; i += blockDim.x) ss[i] = a.s.starts[i];
+        starts = ss;
+    }
+    if (threadIdx.x == 0) s_count = 0;
+    __syncthreads();   // tables and starts staged
     const uint32_t dead = a.s.dead;
     const uint32_t lane = threadIdx.x % kWave;
     const uint32_t wave = threadIdx.x / kWave;
@@ -444,36 +457,59 @@ __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
     TA *alias = reinterpret_cast<TA *>(a.alias);
     const uint32_t iters = (a.s.nchunks + kWarmWaves - 1) / kWarmWaves;
 
-    for (uint32_t it = blockIdx.x; it < iters; it += gridDim.x) {
+    // the warm-up bytes of this wave's chunk in iteration `it` (raw, 64 per
+    // register); loaded one iteration ahead
+    auto fetch = [&](uint32_t it, uint32_t (&raw)[4], uint64_t &b, uint32_t &wlen, bool &first) {
         const uint32_t chunk = it * kWarmWaves + wave;
-        const bool ok = chunk < a.s.nchunks;
-        uint64_t b = 0, e = 0;
-        bool first = false;
-        if (ok) chunk_bounds(a.s, chunk, b, e, first);
-        const uint32_t wlen = ok ? (uint32_t)(e - b < a.warm ? e - b : a.warm) : 0u;
-        // byte codes of the warm-up bytes, 64 per register
-        uint32_t code[4] = {0, 0, 0, 0};
+        uint64_t e = 0;
+        b = 0;
+        first = false;
+        wlen = 0;
+        if (it < iters && chunk < a.s.nchunks) {
+            chunk_bounds(a.s, chunk, b, e, first);
+            wlen = (uint32_t)(e - b < a.warm ? e - b : a.warm);
+        }
 #pragma unroll
         for (uint32_t q = 0; q < 4; ++q) {
             const uint32_t j = q * kWave + lane;
-            if (j < wlen) code[q] = cls[*at(b + j)];
+            raw[q] = j < wlen ? (uint32_t)*at(b + j) : 0u;
         }
+    };
+    uint32_t raw[4];
+    uint64_t b;
+    uint32_t wlen;
+    bool first;
+    fetch(blockIdx.x, raw, b, wlen, first);
+    const uint64_t region = warm_region(blockIdx.x, gridDim.x, iters, L);
+    for (uint32_t it = blockIdx.x; it < iters; it += gridDim.x) {
+        const uint32_t chunk = it * kWarmWaves + wave;
+        const bool ok = chunk < a.s.nchunks;
+        uint32_t code[4];
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) code[q] = q * kWave + lane < wlen ? cls[raw[q]] : 0u;
+        const uint32_t cur_wlen = wlen;
+        const bool cur_first = first;
+        fetch(it + gridDim.x, raw, b, wlen, first);   // next iteration's bytes, in flight meanwhile
         TA *arow = alias + (uint64_t)(ok ? chunk : 0) * L;
         uint32_t al[R], D, cs;
         bool spill;
-        warm_classes<TE, TA, R>(tab, a.s.starts, L, dead, ok, first, code, wlen, arow, lane, al, D, cs, spill);
-        const uint32_t firstrun = warm_slots(s_cnt, s_base, lane, wave, ok ? D : 0u, &a.counters[1]);
+        warm_classes<TE, TA, R>(tab, starts, L, dead, ok, cur_first, code, cur_wlen, arow, lane, al, D, cs, spill);
+        // slots from the block's region: an LDS counter, no barrier
+        uint32_t base = 0;
+        if (lane == 0 && ok) base = atomicAdd(&s_count, D);
+        const uint32_t firstrun = (uint32_t)(region + (uint32_t)__shfl((int)base, 0));
         if (ok) {
             if (lane == 0) {
                 a.run_base[chunk] = firstrun;
                 if (a.run_count) a.run_count[chunk] = D;
                 if (D > kRowCap) atomicOr(&a.counters[2], 1u);
             }
-            warm_records<TE, TA, R>(tab, a.s.starts, L, dead, a.s.row_bytes, first, code, wlen, arow, lane, lane_lt,
-                                    al, D, cs, spill, firstrun, chunk, a.run_chunk, a.run_state);
+            warm_records<TE, TA, R>(tab, starts, L, dead, a.s.row_bytes, cur_first, code, cur_wlen, arow, lane,
+                                    lane_lt, al, D, cs, spill, firstrun, chunk, a.run_chunk, a.run_state);
         }
-        __syncthreads();   // s_cnt / s_base reused by the next chunks
     }
+    __syncthreads();
+    if (threadIdx.x == 0) a.block_count[blockIdx.x] = s_count;
 }
 
 // ---------------------------------------------------------------------------
@@ -492,9 +528,40 @@ __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
     const TE *tab;
     const uint16_t *cls;
     stage_tables<TE, LDS>(a.s, smem, tab, cls);
+    // exclusive prefix of the warm-up blocks' run counts: run i of the dense
+    // numbering is in the region of the block b with pre[b] <= i < pre[b + 1]
+    const uint32_t G = a.warm_blocks;
+    uint32_t *pre = reinterpret_cast<uint32_t *>(smem + tables_lds<TE, LDS>(a.s.table_bytes));
+    for (uint32_t i = threadIdx.x; i < G; i += blockDim.x) pre[i + 1] = a.block_count[i];
     __syncthreads();
     const uint32_t lane = threadIdx.x % kWave;
-    const uint32_t nruns = *reinterpret_cast<volatile uint32_t *>(&a.counters[1]);
+    if (threadIdx.x < kWave) {
+        uint32_t carry = 0;
+        for (uint32_t b0 = 0; b0 < G; b0 += kWave) {
+            const uint32_t v = b0 + lane < G ? pre[b0 + lane + 1] : 0u;
+            uint32_t incl = v;
+#pragma unroll
+            for (int k = 1; k < kWave; k <<= 1) {
+                const uint32_t o = __shfl_up(incl, k);
+                if ((int)lane >= k) incl += o;
+            }
+            if (b0 + lane < G) pre[b0 + lane + 1] = carry + incl;
+            carry += (uint32_t)__shfl((int)incl, kWave - 1);
+        }
+        if (lane == 0) pre[0] = 0;
+    }
+    __syncthreads();
+    const uint32_t iters = (a.s.nchunks + kWarmChunksPerBlock - 1) / kWarmChunksPerBlock;
+    auto phys = [&](uint32_t i) -> uint32_t {
+        uint32_t lo = 0, hi = G;   // pre[lo] <= i < pre[hi]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (pre[mid] <= i) lo = mid;
+            else hi = mid;
+        }
+        return (uint32_t)(warm_region(lo, G, iters, a.s.L) + (i - pre[lo]));
+    };
+    const uint32_t nruns = pre[G];
     const uint32_t per_job = kWave * R;
     const uint32_t njobs = (nruns + per_job - 1) / per_job;
     const uint32_t dead = a.s.dead;
@@ -505,20 +572,23 @@ __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
         uint64_t p[R], vend[R], end[R];
         uint32_t st[R];
         bool ok[R];
+        uint32_t ri[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t i = job * per_job + r * kWave + lane;
             ok[r] = i < nruns;
             p[r] = vend[r] = end[r] = 0;
             st[r] = dead;
+            ri[r] = 0;
             if (ok[r]) {
+                ri[r] = phys(i);
                 uint64_t b, e;
                 bool first;
-                chunk_bounds(a.s, a.run_chunk[i], b, e, first);
+                chunk_bounds(a.s, a.run_chunk[ri[r]], b, e, first);
                 p[r] = b + a.warm < e ? b + a.warm : e;
                 vend[r] = p[r] + ((e - p[r]) & ~(uint64_t)15);
                 end[r] = e;
-                st[r] = a.run_state[i] * a.s.row_bytes;
+                st[r] = a.run_state[ri[r]] * a.s.row_bytes;
             }
         }
         // lockstep 64-byte block loop with one block of read-ahead per run.
@@ -582,7 +652,7 @@ __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
         for (int r = 0; r < R; ++r) {
             if (ok[r]) {
                 const uint32_t f = scan_lane<TE>(st[r], p[r], vend[r], end[r], tab, cls, dead);
-                a.run_final[job * per_job + r * kWave + lane] = f == dead ? kNoState : f / a.s.row_bytes;
+                a.run_final[ri[r]] = f == dead ? kNoState : f / a.s.row_bytes;
             }
         }
     }
@@ -1326,13 +1396,14 @@ __device__ __forceinline__ void slot_bounds(const MultiArgs &a, uint32_t slot, u
 
 // warm-up and merging: one wavefront per slot, 16 slots per block iteration
 __global__ void __launch_bounds__(1024) mwarm_kernel(MultiArgs a) {
-    __shared__ uint32_t s_cnt[kWarmWaves], s_base;
+    __shared__ uint32_t s_cnt[2][kWarmWaves + 1];
+    uint32_t buf = 0;
     constexpr int R = 4;
     const uint32_t lane = threadIdx.x % kWave;
     const uint32_t wave = threadIdx.x / kWave;
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     const uint32_t iters = (a.nslots + kWarmWaves - 1) / kWarmWaves;
-    for (uint32_t it = blockIdx.x; it < iters; it += gridDim.x) {
+    for (uint32_t it = blockIdx.x; it < iters; it += gridDim.x, buf ^= 1) {
         const uint32_t slot = it * kWarmWaves + wave;
         const bool ok = slot < a.nslots;
         const AutoDesc &d = a.autos[ok ? a.slot_auto[slot] : 0];
@@ -1356,7 +1427,7 @@ __global__ void __launch_bounds__(1024) mwarm_kernel(MultiArgs a) {
                 warm_classes<TE, uint16_t, R>(reinterpret_cast<const TE *>(d.table), d.starts, d.L, d.dead, true,
                                               first, code, wlen, arow, lane, al, D, cs, spill);
             });
-        const uint32_t firstrun = warm_slots(s_cnt, s_base, lane, wave, ok ? D : 0u, &a.counters[1]);
+        const uint32_t firstrun = warm_slots(s_cnt[buf], lane, wave, ok ? D : 0u, &a.counters[1]);
         if (ok) {
             if (lane == 0) {
                 a.run_base[slot] = firstrun;
@@ -1371,7 +1442,6 @@ __global__ void __launch_bounds__(1024) mwarm_kernel(MultiArgs a) {
                                                   spill, firstrun, slot, a.run_chunk, a.run_state);
                 });
         }
-        __syncthreads();
     }
 }
 
@@ -1641,8 +1711,8 @@ hipError_t launch_warm(const WarmArgs &a, const KernelShape &k, int grid, size_t
     });
 }
 
-size_t warm_lds_bytes(const KernelShape &k, uint32_t table_bytes) {
-    return (k.table_in_lds ? table_bytes : 0) + 512;
+size_t warm_lds_bytes(const KernelShape &k, uint32_t table_bytes, uint32_t L) {
+    return (k.table_in_lds ? table_bytes : 0) + 512 + (L <= kStageStarts ? (size_t)L * 4 : 0);
 }
 
 hipError_t launch_long(const LongArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st) {

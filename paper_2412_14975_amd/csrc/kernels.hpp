@@ -51,6 +51,16 @@ hipError_t launch_plain(const PlainArgs &a, const KernelShape &k, int grid, size
 
 // ---- converging reach, step 1: warm-up of every run, then merging of runs
 // of one chunk that are in the same state (state convergence) ----
+//
+// Run slots: warm-up block b (of G, each taking kWarmChunksPerBlock chunks
+// per iteration of `iters`) owns the region of the run arrays that holds L
+// runs for each of its chunks, starting at warm_region(b); it fills its
+// region from the front and reports the count in block_count[b].
+constexpr uint32_t kWarmChunksPerBlock = 16;
+__host__ __device__ inline uint64_t warm_region(uint32_t b, uint32_t G, uint32_t iters, uint32_t L) {
+    const uint64_t q = iters / G, r = iters % G;
+    return (uint64_t)kWarmChunksPerBlock * L * ((uint64_t)b * q + (b < r ? b : r));
+}
 struct WarmArgs {
     ScanArgs s;
     uint32_t warm;             // bytes scanned by every run before merging (<= 256)
@@ -59,11 +69,11 @@ struct WarmArgs {
     uint32_t *run_count;       // [nchunks] runs of the chunk (nullptr: not needed)
     uint32_t *run_chunk;       // [cap]
     uint32_t *run_state;       // [cap] state id after the warm-up
-    uint32_t *counters;        // [1] runs allocated; [2] set to 1 when a chunk has more
-                               // than kRowCap runs
+    uint32_t *counters;        // [2] set to 1 when a chunk has more than kRowCap runs
+    uint32_t *block_count;     // [grid] runs in each block's region
 };
 hipError_t launch_warm(const WarmArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st);
-size_t warm_lds_bytes(const KernelShape &k, uint32_t table_bytes);
+size_t warm_lds_bytes(const KernelShape &k, uint32_t table_bytes, uint32_t L);
 
 // ---- converging reach, step 2: the merged runs to the chunk end ----
 struct LongArgs {
@@ -72,7 +82,8 @@ struct LongArgs {
     const uint32_t *run_chunk;
     const uint32_t *run_state;
     uint32_t *run_final;       // state id at the chunk end, kNoState if the run died
-    uint32_t *counters;        // [1] runs allocated (read)
+    const uint32_t *block_count;   // runs of each warm-up block's region
+    uint32_t warm_blocks;      // grid of the warm-up kernel
 };
 hipError_t launch_long(const LongArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st);
 
