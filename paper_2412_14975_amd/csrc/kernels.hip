@@ -953,8 +953,9 @@ __device__ __forceinline__ void wave_tree_product(uint64_t (&rows)[kRowCap], uin
 // Level 0, fused with the hit rows: wave per group of 64 matrices; lane l
 // builds M_k (k = 64 g + l) from the end states of chunk k's runs and the
 // alias column of chunk k + 1.
-template <int W, typename TA>
+template <int W, typename TA, bool STAGE>
 __global__ void __launch_bounds__(256) hit_prod0_kernel(HitArgs a) {
+    extern __shared__ __align__(16) uint8_t hsm[];
     const uint32_t lane = threadIdx.x % kWave;
     const uint32_t g = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     const uint32_t ngroups = (a.nmembers + kWave - 1) / kWave;
@@ -962,6 +963,14 @@ __global__ void __launch_bounds__(256) hit_prod0_kernel(HitArgs a) {
     const uint32_t gn = g * kWave + kWave <= a.nmembers ? kWave : a.nmembers - g * kWave;
     const uint32_t k = g * kWave + lane;
     const TA *alias = reinterpret_cast<const TA *>(a.alias);
+    // STAGE: the wave's next-chunk rows (chunks 64 g + 1 .. 64 g + gn, one
+    // contiguous span) are copied to LDS first, lanes over elements
+    TA *srow = reinterpret_cast<TA *>(hsm) + (size_t)(threadIdx.x / kWave) * kWave * a.L;
+    if constexpr (STAGE) {
+        const TA *src = alias + (uint64_t)(g * kWave + 1) * a.L;
+        for (uint32_t i = lane; i < gn * a.L; i += kWave) srow[i] = src[i];
+        __builtin_amdgcn_wave_barrier();   // the rows are read by other lanes of this wave
+    }
     uint64_t rows[kRowCap];
     uint32_t R = 0;
     if (lane < gn) {
@@ -974,7 +983,7 @@ __global__ void __launch_bounds__(256) hit_prod0_kernel(HitArgs a) {
         if (r < R) {
             const uint32_t f = a.run_final[a.run_base[k] + r];
             if (f != kNoState) {
-                const TA *row = alias + (uint64_t)(k + 1) * a.L;
+                const TA *row = STAGE ? srow + (size_t)lane * a.L : alias + (uint64_t)(k + 1) * a.L;
                 if constexpr (W > 0) {
                     const uint32_t *cw = a.content + (uint64_t)f * W;
                     for (uint32_t w = 0; w < (uint32_t)W; ++w)
@@ -1857,15 +1866,22 @@ hipError_t launch_hit_prod(const HitArgs &a, int W, int alias_bytes, bool level0
         hipLaunchKernelGGL(hit_prodN_kernel, dim3(blocks), dim3(256), 0, s, a);
         return hipGetLastError();
     }
+    // next-chunk rows staged in LDS when 4 waves x 64 rows fit in 64 KiB
+    const size_t stage = (size_t)4 * kWave * a.L * alias_bytes;
+    const bool st = stage <= 65536;
     return dispatch_ta(alias_bytes, [&](auto ta) {
-        if (W == 0) {
-            hipLaunchKernelGGL((hit_prod0_kernel<0, decltype(ta)>), dim3(blocks), dim3(256), 0, s, a);
-            return hipGetLastError();
-        }
-#define CALLH(w) hipLaunchKernelGGL((hit_prod0_kernel<w, decltype(ta)>), dim3(blocks), dim3(256), 0, s, a);
-        RI_DISPATCH_W(W, CALLH)
+        return dispatch_b(st, [&](auto stg) {
+            constexpr bool S = decltype(stg)::value;
+            const size_t lds = S ? stage : 0;
+            if (W == 0) {
+                hipLaunchKernelGGL((hit_prod0_kernel<0, decltype(ta), S>), dim3(blocks), dim3(256), lds, s, a);
+                return hipGetLastError();
+            }
+#define CALLH(w) hipLaunchKernelGGL((hit_prod0_kernel<w, decltype(ta), S>), dim3(blocks), dim3(256), lds, s, a);
+            RI_DISPATCH_W(W, CALLH)
 #undef CALLH
-        return hipGetLastError();
+            return hipGetLastError();
+        });
     });
 }
 
