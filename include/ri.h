@@ -138,6 +138,30 @@ int ri_recognize_ex(const ri_handle *h, const uint8_t *text_dev, size_t n, void 
                     int algo, uint32_t chunks, ri_result *out);
 
 /*
+ * ri_recognize_async -- the recognition of ri_recognize_ex (chunking of
+ * Sect. 2, reach, join and acceptance of Sect. 3.2), enqueued on `stream`
+ * without a host wait; the result stays in device memory.
+ *
+ * result_dev : int32[2] in device memory, 4-byte aligned, owned by the
+ *              caller; when the stream reaches the end of the call it holds
+ *              {accept (0/1), final state} with the meaning of ri_result
+ *              (final state -3: internal inconsistency).  Nothing else is
+ *              written to it.
+ * text_dev, n, algo, chunks : as for ri_recognize_ex; the text and result_dev
+ *              must stay valid until the stream has passed the call.
+ * Calls on one stream run in order and reuse that stream's scratch memory;
+ * the handle's options and last tuning apply as for ri_recognize_ex;
+ * profiling timings are not recorded.  Scratch that has to grow for a longer
+ * text is reallocated after a device-wide synchronization.
+ * Errors found before anything is enqueued (RI_ERR_ARG: NULL or misaligned
+ * pointers; RI_ERR_LIMIT; RI_ERR_NOMEM) are returned and nothing is written;
+ * a launch failure returns RI_ERR_DEVICE.  Faults during execution surface
+ * at the caller's next synchronization.
+ */
+int ri_recognize_async(const ri_handle *h, const uint8_t *text_dev, size_t n, void *stream,
+                       int algo, uint32_t chunks, int32_t *result_dev);
+
+/*
  * ri_chunk_maps -- the reach phase only, for inspection: like ri_recognize_ex,
  * and in addition copies the chunk maps lambda_i (Sects. 2 and 3.2) to the
  * host array maps[c * starts + s] (int32, caller-owned, `cap` entries), where

@@ -9,7 +9,7 @@ include/ri.h (libri.so).  ``binding`` is the ctypes layer with the C names.
 
 from .binding import (  # noqa: F401
     ALGOS, RIError, Recognizer, ri_build, ri_chunk_maps, ri_free, ri_info, ri_last_error,
-    ri_last_timings, ri_recognize, ri_recognize_ex, ri_set_profiling, ri_state_content,
+    ri_last_timings, ri_recognize, ri_recognize_ex, ri_recognize_async, ri_set_profiling, ri_state_content,
     ri_set_option, ri_get_option, ri_autotune, Batch, ri_batch_create, ri_batch_free, ri_batch_run,
     ri_batch_capture, ri_batch_launch, ri_batch_get_info, ri_batch_get_group, ri_batch_autotune,
     ri_batch_create_ex, ri_batch_update, ri_request_footprint,

@@ -23,7 +23,7 @@ RI_NUM_ALGOS = 3
 ALGOS = {"rid": RI_ALGO_RID, "dfa": RI_ALGO_DFA, "subset": RI_ALGO_SUBSET}
 
 SYMBOLS = ("ri_build", "ri_free", "ri_info", "ri_recognize", "ri_recognize_ex",
-           "ri_chunk_maps", "ri_state_content", "ri_set_profiling", "ri_last_timings",
+           "ri_recognize_async", "ri_chunk_maps", "ri_state_content", "ri_set_profiling", "ri_last_timings",
            "ri_set_option", "ri_get_option", "ri_autotune", "ri_last_error",
            "ri_batch_create", "ri_batch_free", "ri_batch_run", "ri_batch_capture",
            "ri_batch_launch", "ri_batch_get_info", "ri_batch_get_group", "ri_batch_autotune",
@@ -114,6 +114,7 @@ def lib() -> ctypes.CDLL:
     L.ri_info.argtypes = [vp, ctypes.POINTER(ri_info_t)]
     L.ri_recognize.argtypes = [vp, vp, sz, vp, ctypes.POINTER(ri_result)]
     L.ri_recognize_ex.argtypes = [vp, vp, sz, vp, i32, u32, ctypes.POINTER(ri_result)]
+    L.ri_recognize_async.argtypes = [vp, vp, sz, vp, i32, u32, vp]
     L.ri_chunk_maps.argtypes = [vp, vp, sz, vp, i32, u32, vp, sz, ctypes.POINTER(ri_result)]
     L.ri_state_content.argtypes = [vp, i32, u32, ctypes.POINTER(u32), u32, ctypes.POINTER(u32)]
     L.ri_set_profiling.argtypes = [vp, i32]
@@ -212,6 +213,15 @@ def ri_recognize_ex(h: int, text: torch.Tensor, stream=None, algo="rid", chunks:
     _check(lib().ri_recognize_ex(h, ptr, n, _stream_ptr(stream), _algo(algo), int(chunks),
                                  ctypes.byref(r)))
     return _result(r)
+
+
+def ri_recognize_async(h: int, text: torch.Tensor, result: torch.Tensor, stream=None, algo="rid",
+                       chunks: int = 0) -> None:
+    """Enqueues the recognition on the stream; result (int32 GPU tensor of at
+    least 2 entries) receives [accept, final_state] in stream order."""
+    ptr, n = _text_ptr(text)
+    _check(lib().ri_recognize_async(h, ptr, n, _stream_ptr(stream), _algo(algo), int(chunks),
+                                    _results_ptr(result, 1)))
 
 
 def ri_chunk_maps(h: int, text: torch.Tensor, stream=None, algo="rid", chunks: int = 0):
@@ -409,6 +419,9 @@ class Recognizer:
 
     def recognize(self, text, algo="rid", chunks: int = 0, stream=None) -> dict:
         return ri_recognize_ex(self.handle, text, stream, algo, chunks)
+
+    def recognize_async(self, text, result, algo="rid", chunks: int = 0, stream=None) -> None:
+        ri_recognize_async(self.handle, text, result, stream, algo, chunks)
 
     def chunk_maps(self, text, algo="rid", chunks: int = 0, stream=None):
         return ri_chunk_maps(self.handle, text, stream, algo, chunks)

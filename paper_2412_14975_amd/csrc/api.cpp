@@ -277,6 +277,8 @@ int get_workspace(ri_handle *h, int device, hipStream_t stream, Workspace **out)
 
 int grow(Workspace::Buf &b, size_t need) {
     if (need <= b.cap) return RI_OK;
+    // work enqueued without a host wait may still use the old buffer
+    if (b.p) HIP_TRY(hipDeviceSynchronize());
     if (b.p) HIP_TRY(hipFree(b.p));
     b.p = nullptr;
     b.cap = 0;
@@ -417,10 +419,14 @@ uint32_t tile_group(const AlgoHost &H) {
     return g0;
 }
 
+// result_dev != nullptr: everything is enqueued on the stream and the
+// result is left in result_dev[0..1]; no host wait, no profiling, no maps.
 int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v, int algo,
-              uint32_t chunks, ri_result *out, int32_t *maps, size_t maps_cap) {
+              uint32_t chunks, ri_result *out, int32_t *maps, size_t maps_cap, int32_t *result_dev = nullptr) {
     ri_handle *h = const_cast<ri_handle *>(hc);
     if (!h || !out) return fail(RI_ERR_ARG, "NULL handle or result pointer");
+    if (result_dev && (reinterpret_cast<uintptr_t>(result_dev) & 3))
+        return fail(RI_ERR_ARG, "result must be 4-byte aligned");
     if (algo < 0 || algo >= RI_NUM_ALGOS) return fail(RI_ERR_ARG, "unknown algorithm");
     if (n > 0 && !text) return fail(RI_ERR_ARG, "NULL text pointer");
     if (n > 0 && (reinterpret_cast<uintptr_t>(text) & 15)) return fail(RI_ERR_ARG, "text must be 16-byte aligned");
@@ -431,6 +437,11 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         out->accept = (n == 0 && !A.empty_language && A.accepts_empty) ? 1 : 0;
         out->final_state = (n == 0 && !A.empty_language) ? 0 : -1;
         if (maps && maps_cap > 0) std::memset(maps, 0xff, sizeof(int32_t) * maps_cap);
+        if (result_dev) {
+            hipError_t e = ri::launch_store_result(result_dev, out->accept, out->final_state,
+                                                   reinterpret_cast<hipStream_t>(stream_v));
+            if (e != hipSuccess) return fail(RI_ERR_DEVICE, std::string("store result: ") + hipGetErrorString(e));
+        }
         return RI_OK;
     }
     const AlgoHost &H = h->algo[algo];
@@ -463,6 +474,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     std::lock_guard<std::mutex> wlk(ws->mu);
     DeviceCopy &dc = h->dev[device];
     const AlgoDevice &D = dc.algo[algo];
+    const bool prof = h->profiling && !result_dev;
 
     Options opt;
     {
@@ -532,7 +544,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     sa.dead = H.dead;
     const uint32_t chunk_groups = (plan.nchunks + 63) / 64;
 
-    if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[0], stream));
+    if (prof) HIP_TRY(hipEventRecord(ws->ev[0], stream));
     if (!conv) {
         while (R > 1 && R / 2 >= H.L) R /= 2;
         shape.runs_per_lane = (int)R;
@@ -546,17 +558,17 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         const int per_cu = std::max(1, ri::blocks_per_cu(0, shape, lds));
         const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)dc.cus * per_cu, (pa.njobs + 15) / 16));
         HIP_TRY(ri::launch_plain(pa, shape, grid, lds, stream));
-        if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[4], stream));
+        if (prof) HIP_TRY(hipEventRecord(ws->ev[4], stream));
     } else {
         ReachBufs rb{ws->alias.p, static_cast<uint32_t *>(ws->run_base.p), static_cast<uint32_t *>(ws->run_chunk.p),
                      static_cast<uint32_t *>(ws->run_state.p), static_cast<uint32_t *>(ws->run_final.p),
                      ws->counters, static_cast<uint32_t *>(ws->run_count.p),
                      static_cast<uint32_t *>(ws->block_count.p)};
-        rc = launch_conv(cc, sa, opt, rb, stream, h->profiling ? ws->ev[5] : nullptr);
+        rc = launch_conv(cc, sa, opt, rb, stream, prof ? ws->ev[5] : nullptr);
         if (rc) return rc;
-        if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[4], stream));
+        if (prof) HIP_TRY(hipEventRecord(ws->ev[4], stream));
     }
-    if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[1], stream));
+    if (prof) HIP_TRY(hipEventRecord(ws->ev[1], stream));
 
     // join tree
     ri::JoinArgs ja{};
@@ -583,7 +595,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     fa.content = H.relational && H.W <= kMaxDenseWords ? D.content : nullptr;
     fa.final_of_state = D.final_of_state;
     fa.accept_of_state = D.accept_of_state;
-    fa.result = ws->dres;
+    fa.result = result_dev && !hit ? result_dev : ws->dres;   // the hit join needs result[2]
     fa.counters = ws->counters;
 
     // class-partitioned join for merged runs of a relational chunk automaton:
@@ -688,14 +700,24 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         if (H.relational) HIP_TRY(ri::launch_finalize_rel(fa, (int)H.W, stream));
         else HIP_TRY(ri::launch_finalize_fun(fa, stream));
     }
-    if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[2], stream));
+    if (result_dev) {
+        // the result stays on the device; a hit-matrix result that a chunk
+        // with too many runs made invalid is redone by the gated propagation
+        if (hit) HIP_TRY(ri::launch_propagate(fa, ha, H.W, shape.alias_bytes, stream, result_dev));
+        out->chunks = plan.nchunks;
+        out->chunk_size = (uint32_t)plan.cs;
+        out->accept = -1;
+        out->final_state = -1;
+        return RI_OK;
+    }
+    if (prof) HIP_TRY(hipEventRecord(ws->ev[2], stream));
     HIP_TRY(hipMemcpyAsync(ws->hres, ws->dres, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     std::vector<int32_t> lam_host;
     if (maps) {
         lam_host.resize(pairs);
         HIP_TRY(hipMemcpyAsync(lam_host.data(), ws->dbg.p, pairs * 4, hipMemcpyDeviceToHost, stream));
     }
-    if (h->profiling) HIP_TRY(hipEventRecord(ws->ev[3], stream));
+    if (prof) HIP_TRY(hipEventRecord(ws->ev[3], stream));
     HIP_TRY(hipStreamSynchronize(stream));
     if (hit && ws->hres[2] != 0) {
         // some chunk kept more runs than a hit-matrix row can index: join
@@ -716,7 +738,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     out->chunks = plan.nchunks;
     out->chunk_size = (uint32_t)plan.cs;
     if (out->final_state == -3) return fail(RI_ERR_DEVICE, "internal: final subset not found");
-    if (h->profiling) {
+    if (prof) {
         float ms[5] = {0, 0, 0, 0, 0};
         HIP_TRY(hipEventElapsedTime(&ms[0], ws->ev[0], ws->ev[1]));
         HIP_TRY(hipEventElapsedTime(&ms[1], ws->ev[1], ws->ev[2]));
@@ -1489,6 +1511,13 @@ int ri_recognize(const ri_handle *h, const uint8_t *text_dev, size_t n, void *st
 int ri_recognize_ex(const ri_handle *h, const uint8_t *text_dev, size_t n, void *stream, int algo,
                     uint32_t chunks, ri_result *out) {
     return recognize(h, text_dev, n, stream, algo, chunks, out, nullptr, 0);
+}
+
+int ri_recognize_async(const ri_handle *h, const uint8_t *text_dev, size_t n, void *stream, int algo,
+                       uint32_t chunks, int32_t *result_dev) {
+    if (!result_dev) return fail(RI_ERR_ARG, "NULL result pointer");
+    ri_result r;
+    return recognize(h, text_dev, n, stream, algo, chunks, &r, nullptr, 0, result_dev);
 }
 
 int ri_chunk_maps(const ri_handle *h, const uint8_t *text_dev, size_t n, void *stream, int algo,

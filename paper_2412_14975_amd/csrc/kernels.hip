@@ -27,7 +27,9 @@
 // the acceptance test and the minimal-DFA state of the result.
 #include "kernels.hpp"
 
+#include <mutex>
 #include <type_traits>
+#include <unordered_map>
 
 namespace ri {
 namespace {
@@ -1292,8 +1294,18 @@ __global__ void finalize_hit_kernel(FinalArgs f, HitArgs a) {
 // to chunk: the classes of chunk k hit by X are {alias[k][t] : t in X}, and
 // the new X is the union of the contents of their end states.  Exact for any
 // number of runs per chunk.
+// With out != nullptr the kernel follows the hit-matrix join on the same
+// stream: it joins only when that join flagged its result invalid
+// (f.result[2] != 0) and copies the result to out in either case.
 template <typename TA>
-__global__ void __launch_bounds__(1024) propagate_kernel(FinalArgs f, HitArgs a, uint32_t W) {
+__global__ void __launch_bounds__(1024) propagate_kernel(FinalArgs f, HitArgs a, uint32_t W, int32_t *out) {
+    if (out && f.result[2] == 0) {
+        if (threadIdx.x == 0) {
+            out[0] = f.result[0];
+            out[1] = f.result[1];
+        }
+        return;
+    }
     extern __shared__ __align__(16) uint32_t sm[];
     uint32_t *X = sm;               // [W]
     uint32_t *Y = sm + W;           // [W]
@@ -1342,6 +1354,17 @@ __global__ void __launch_bounds__(1024) propagate_kernel(FinalArgs f, HitArgs a,
         decide_bits(X, W, f, f.result);
         f.result[2] = 0;
         reset_counters(f.counters);
+        if (out) {
+            out[0] = f.result[0];
+            out[1] = f.result[1];
+        }
+    }
+}
+
+__global__ void store_result_kernel(int32_t *out, int32_t accept, int32_t final_state) {
+    if (threadIdx.x == 0) {
+        out[0] = accept;
+        out[1] = final_state;
     }
 }
 
@@ -1737,7 +1760,23 @@ hipError_t launch_long(const LongArgs &a, const KernelShape &k, int grid, size_t
     });
 }
 
+// Occupancy does not change for a kernel instance, its block size, LDS size
+// and device: the answers are kept so that a call queries each shape once.
 int blocks_per_cu(int which, const KernelShape &k, size_t lds) {
+    static std::mutex mu;
+    static std::unordered_map<uint64_t, int> known;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return 0;
+    const uint64_t key = (uint64_t)which | (uint64_t)k.entry_bytes << 2 | (uint64_t)k.tile_bytes << 5 |
+                         (uint64_t)k.alias_bytes << 8 | (uint64_t)k.runs_per_lane << 11 |
+                         (uint64_t)k.table_in_lds << 14 | (uint64_t)(k.block_threads / 64) << 15 |
+                         (uint64_t)(lds & 0x3ffffff) << 22 | (uint64_t)(device & 0xffff) << 48;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = known.find(key);
+        if (it != known.end()) return it->second;
+    }
+    std::lock_guard<std::mutex> lk(mu);
     g_fn = nullptr;
     hipError_t e = hipSuccess;
     if (which == 0) e = launch_plain(PlainArgs{}, k, 0, lds, nullptr);
@@ -1746,6 +1785,7 @@ int blocks_per_cu(int which, const KernelShape &k, size_t lds) {
     if (e != hipSuccess || !g_fn) return 0;
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, g_fn, k.block_threads, lds) != hipSuccess) return 0;
+    if (nb > 0) known[key] = nb;
     return nb;
 }
 
@@ -1898,12 +1938,18 @@ hipError_t launch_finalize_hit(const FinalArgs &f, const HitArgs &a, int W, int 
     });
 }
 
-hipError_t launch_propagate(const FinalArgs &f, const HitArgs &a, uint32_t W, int alias_bytes, hipStream_t s) {
+hipError_t launch_propagate(const FinalArgs &f, const HitArgs &a, uint32_t W, int alias_bytes, hipStream_t s,
+                            int32_t *out) {
     if (W > kPropMaxWords) return hipErrorInvalidValue;
     return dispatch_ta(alias_bytes, [&](auto ta) {
-        hipLaunchKernelGGL((propagate_kernel<decltype(ta)>), dim3(1), dim3(1024), (size_t)W * 12, s, f, a, W);
+        hipLaunchKernelGGL((propagate_kernel<decltype(ta)>), dim3(1), dim3(1024), (size_t)W * 12, s, f, a, W, out);
         return hipGetLastError();
     });
+}
+
+hipError_t launch_store_result(int32_t *out, int32_t accept, int32_t final_state, hipStream_t s) {
+    hipLaunchKernelGGL(store_result_kernel, dim3(1), dim3(64), 0, s, out, accept, final_state);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch_final_cls(const BatchFinalArgs &b, const FinalArgs &f, const ClsJoinArgs &a, int W,
@@ -1959,9 +2005,18 @@ hipError_t launch_mprop(const MultiArgs &a, uint32_t max_words, hipStream_t s) {
 }
 
 int multi_blocks_per_cu(int which) {
+    static std::mutex mu;
+    static std::unordered_map<int, int> known;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return 0;
+    const int key = device * 4 + (which == 1);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = known.find(key);
+    if (it != known.end()) return it->second;
     int n = 0;
     if (which == 1) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mwarm_kernel, 1024, 0);
     else (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mlong_kernel, 256, 0);
+    if (n > 0) known[key] = n;
     return n;
 }
 

@@ -199,7 +199,12 @@ hipError_t launch_finalize_hit(const FinalArgs &f, const HitArgs &a, int W, int 
 // Join by propagating the set of N' states chunk after chunk (one block; any
 // number of runs per chunk, any interface size up to kPropMaxWords * 32).
 constexpr uint32_t kPropMaxWords = 1024;
-hipError_t launch_propagate(const FinalArgs &f, const HitArgs &a, uint32_t W, int alias_bytes, hipStream_t s);
+// out != nullptr: gated form that runs after launch_finalize_hit on the same
+// stream, joins only when f.result[2] != 0, and writes {accept, final} to out.
+hipError_t launch_propagate(const FinalArgs &f, const HitArgs &a, uint32_t W, int alias_bytes, hipStream_t s,
+                            int32_t *out = nullptr);
+// out[0] = accept, out[1] = final_state, in stream order
+hipError_t launch_store_result(int32_t *out, int32_t accept, int32_t final_state, hipStream_t s);
 
 // Batch results, one per text, from the last join level (one group per
 // text, in text order): a class-partitioned relation or a function.
