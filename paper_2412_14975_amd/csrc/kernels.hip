@@ -98,9 +98,21 @@ __device__ __forceinline__ void step16_each(uint32_t (&st)[R], const uint4 (&v)[
     }
 }
 
-__device__ __forceinline__ void load64(uint4 (&b)[4], const uint8_t *p) {
-    const uint4 *q = reinterpret_cast<const uint4 *>(p);
-    b[0] = q[0]; b[1] = q[1]; b[2] = q[2]; b[3] = q[3];
+// Text bytes are read through global (address space 1) pointers: the loads
+// are then global loads, tracked by the vector-memory counter only, so a wait
+// for an LDS table lookup does not also wait for text loads still in flight
+// (generic pointers give flat loads, which count against both counters).
+typedef const __attribute__((address_space(1))) uint8_t gbyte;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) u32x4 gu32x4;
+
+__device__ __forceinline__ uint4 load16(gbyte *p) {
+    const u32x4 v = *(gu32x4 *)p;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ void load64(uint4 (&b)[4], gbyte *p) {
+    b[0] = load16(p); b[1] = load16(p + 16); b[2] = load16(p + 32); b[3] = load16(p + 48);
 }
 
 // Chunk `chunk` as absolute addresses [b, e), and whether it begins its text
@@ -121,7 +133,17 @@ __device__ __forceinline__ void chunk_bounds(const ScanArgs &s, uint32_t chunk, 
     }
 }
 
-__device__ __forceinline__ const uint8_t *at(uint64_t p) { return reinterpret_cast<const uint8_t *>(p); }
+__device__ __forceinline__ gbyte *at(uint64_t p) { return (gbyte *)p; }
+
+// Values that are equal on every lane of the wave, marked as such so that the
+// compiler keeps them in scalar registers and branches on them with scalar
+// branches instead of exec masks.
+__device__ __forceinline__ uint32_t wave_uniform(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+__device__ __forceinline__ uint64_t wave_uniform(uint64_t x) {
+    return (uint64_t)wave_uniform((uint32_t)x) | (uint64_t)wave_uniform((uint32_t)(x >> 32)) << 32;
+}
 
 template <int R>
 __device__ __forceinline__ bool any_alive(const uint32_t (&st)[R], uint32_t dead) {
@@ -149,6 +171,7 @@ __device__ __forceinline__ void scan_shared(uint32_t (&st)[R], uint64_t p, uint6
         if (work) {
             uint4 nxt[4];
             load64(nxt, at(p + 64 < bend ? p + 64 : p));
+            __builtin_amdgcn_sched_barrier(0);   // keep the read-ahead ahead of the lookups
 #pragma unroll
             for (int q = 0; q < 4; ++q) step16_shared<TE, R>(st, cur[q], tab, cls);
 #pragma unroll
@@ -157,7 +180,7 @@ __device__ __forceinline__ void scan_shared(uint32_t (&st)[R], uint64_t p, uint6
         }
     }
     for (; p < vend && any_alive<R>(st, dead); p += 16)
-        step16_shared<TE, R>(st, *reinterpret_cast<const uint4 *>(at(p)), tab, cls);
+        step16_shared<TE, R>(st, load16(at(p)), tab, cls);
     for (p = p < vend ? vend : p; p < end && any_alive<R>(st, dead); ++p) {
         const uint32_t c = cls[*at(p)];
 #pragma unroll
@@ -171,7 +194,7 @@ __device__ __forceinline__ uint32_t scan_lane(uint32_t st, uint64_t p, uint64_t 
                                               const TE *tab, const uint16_t *cls, uint32_t dead) {
     uint32_t s1[1] = {st};
     for (; p < vend && s1[0] != dead; p += 16)
-        step16_shared<TE, 1>(s1, *reinterpret_cast<const uint4 *>(at(p)), tab, cls);
+        step16_shared<TE, 1>(s1, load16(at(p)), tab, cls);
     for (p = p < vend ? vend : p; p < end && s1[0] != dead; ++p) s1[0] = next_state<TE>(tab, s1[0], cls[*at(p)]);
     return s1[0];
 }
@@ -245,6 +268,19 @@ __global__ void __launch_bounds__(1024) plain_kernel(PlainArgs a) {
 // run (numbered in start order).  The run slots of the block's 16 chunks come
 // from one atomic; the alias row of a chunk ([nchunks][L], class of every
 // start) is written contiguously.
+// Starts staged in LDS by the warm-up kernel when they fit.
+constexpr uint32_t kStageStarts = 4096;
+
+// The start list, read from LDS when staged and from global memory otherwise,
+// through pointers of the matching address space (never a flat load, whose
+// wait would also wait for the text read ahead for the next chunk).
+struct StartList {
+    const __attribute__((address_space(3))) uint32_t *lds;
+    const __attribute__((address_space(1))) uint32_t *glb;
+    bool staged;
+    __device__ __forceinline__ uint32_t operator[](uint32_t s) const { return staged ? lds[s] : glb[s]; }
+};
+
 template <typename T> __host__ __device__ constexpr uint32_t tile_stride(uint32_t cols) {
     return cols + (sizeof(T) == 1 ? 4u : sizeof(T) == 2 ? 2u : 1u);
 }
@@ -286,7 +322,7 @@ __device__ __forceinline__ void warm_block(uint32_t (&st)[R], const uint32_t (&c
 // blocks the alias row is written as classes are found.  Once more than 64
 // distinct states are seen the chunk spills: D counts its live starts.
 template <typename TE, typename TA, int R>
-__device__ __forceinline__ void warm_classes(const TE *tab, const uint32_t *starts, uint32_t L, uint32_t dead,
+__device__ __forceinline__ void warm_classes(const TE *tab, const StartList &starts, uint32_t L, uint32_t dead,
                                              bool ok, bool first, const uint32_t (&code)[4], uint32_t wlen,
                                              TA *arow, uint32_t lane, uint32_t (&al)[R], uint32_t &D,
                                              uint32_t &cs, bool &spill) {
@@ -360,7 +396,7 @@ __device__ __forceinline__ void warm_classes(const TE *tab, const uint32_t *star
 // not written yet).  A spilled chunk's runs are recomputed: every live start
 // is its own run, in start order.
 template <typename TE, typename TA, int R>
-__device__ __forceinline__ void warm_records(const TE *tab, const uint32_t *starts, uint32_t L, uint32_t dead,
+__device__ __forceinline__ void warm_records(const TE *tab, const StartList &starts, uint32_t L, uint32_t dead,
                                              uint32_t row_bytes, bool first, const uint32_t (&code)[4],
                                              uint32_t wlen, TA *arow, uint32_t lane, uint64_t lane_lt,
                                              const uint32_t (&al)[R], uint32_t D, uint32_t cs, bool spill,
@@ -433,28 +469,30 @@ __device__ __forceinline__ uint32_t warm_slots(uint32_t *s_cnt, uint32_t lane, u
     return s_cnt[kWarmWaves] + s_cnt[wave];
 }
 
-// Starts staged in LDS by the warm-up kernel when they fit.
-constexpr uint32_t kStageStarts = 4096;
 
+// Occupancy: a block is 16 waves (4 per SIMD), so two blocks per CU need 8
+// waves per SIMD; without the attribute the kernel's SGPR use allows 7 and
+// only one block fits.  With 4 start registers (R = 4) the VGPRs would spill.
 template <typename TE, typename TA, int R, bool LDS>
-__global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(R <= 2 ? 8 : 4))) warm_kernel(WarmArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ uint32_t s_count;   // runs placed in this block's region
     const TE *tab;
     const uint16_t *cls;
     stage_tables<TE, LDS>(a.s, smem, tab, cls);
     const uint32_t L = a.s.L;
-    const uint32_t *starts = a.s.starts;
-    if (L <= kStageStarts) {
-        uint32_t *ss = reinterpret_cast<uint32_t *>(smem + tables_lds<TE, LDS>(a.s.table_bytes));
+    uint32_t *ss = reinterpret_cast<uint32_t *>(smem + tables_lds<TE, LDS>(a.s.table_bytes));
+    StartList starts;
+    starts.lds = (const __attribute__((address_space(3))) uint32_t *)ss;
+    starts.glb = (const __attribute__((address_space(1))) uint32_t *)a.s.starts;
+    starts.staged = L <= kStageStarts;
+    if (starts.staged)
         for (uint32_t i = threadIdx.x; i < L; i += blockDim.x) ss[i] = a.s.starts[i];
-        starts = ss;
-    }
     if (threadIdx.x == 0) s_count = 0;
     __syncthreads();   // tables and starts staged
     const uint32_t dead = a.s.dead;
     const uint32_t lane = threadIdx.x % kWave;
-    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t wave = wave_uniform(threadIdx.x / kWave);
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     TA *alias = reinterpret_cast<TA *>(a.alias);
     const uint32_t iters = (a.s.nchunks + kWarmWaves - 1) / kWarmWaves;
@@ -471,6 +509,9 @@ __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
             chunk_bounds(a.s, chunk, b, e, first);
             wlen = (uint32_t)(e - b < a.warm ? e - b : a.warm);
         }
+        b = wave_uniform(b);
+        wlen = wave_uniform(wlen);
+        first = wave_uniform((uint32_t)first) != 0;
 #pragma unroll
         for (uint32_t q = 0; q < 4; ++q) {
             const uint32_t j = q * kWave + lane;
@@ -524,17 +565,11 @@ __global__ void __launch_bounds__(1024) warm_kernel(WarmArgs a) {
 // R independent chains in flight.  Runs of equal length (all but the last
 // chunk's) advance in lockstep; a lane whose runs differ finishes them one
 // by one.
-template <typename TE, int R, bool LDS>
-__global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    const TE *tab;
-    const uint16_t *cls;
-    stage_tables<TE, LDS>(a.s, smem, tab, cls);
-    // exclusive prefix of the warm-up blocks' run counts: run i of the dense
-    // numbering is in the region of the block b with pre[b] <= i < pre[b + 1]
-    const uint32_t G = a.warm_blocks;
-    uint32_t *pre = reinterpret_cast<uint32_t *>(smem + tables_lds<TE, LDS>(a.s.table_bytes));
-    for (uint32_t i = threadIdx.x; i < G; i += blockDim.x) pre[i + 1] = a.block_count[i];
+// Exclusive prefix of the warm-up blocks' run counts in LDS: run i of the
+// dense numbering is in the region of block b with pre[b] <= i < pre[b + 1].
+// Ends with a barrier.
+__device__ __forceinline__ void run_prefix(uint32_t *pre, const uint32_t *block_count, uint32_t G) {
+    for (uint32_t i = threadIdx.x; i < G; i += blockDim.x) pre[i + 1] = block_count[i];
     __syncthreads();
     const uint32_t lane = threadIdx.x % kWave;
     if (threadIdx.x < kWave) {
@@ -553,16 +588,32 @@ __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
         if (lane == 0) pre[0] = 0;
     }
     __syncthreads();
+}
+
+// Slot of dense run i (binary search of the prefix).
+__device__ __forceinline__ uint32_t run_slot(const uint32_t *pre, uint32_t G, uint32_t iters, uint32_t L,
+                                             uint32_t i) {
+    uint32_t lo = 0, hi = G;   // pre[lo] <= i < pre[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (pre[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return (uint32_t)(warm_region(lo, G, iters, L) + (i - pre[lo]));
+}
+
+template <typename TE, int R, bool LDS>
+__global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const TE *tab;
+    const uint16_t *cls;
+    stage_tables<TE, LDS>(a.s, smem, tab, cls);
+    const uint32_t G = a.warm_blocks;
+    uint32_t *pre = reinterpret_cast<uint32_t *>(smem + tables_lds<TE, LDS>(a.s.table_bytes));
+    run_prefix(pre, a.block_count, G);
+    const uint32_t lane = threadIdx.x % kWave;
     const uint32_t iters = (a.s.nchunks + kWarmChunksPerBlock - 1) / kWarmChunksPerBlock;
-    auto phys = [&](uint32_t i) -> uint32_t {
-        uint32_t lo = 0, hi = G;   // pre[lo] <= i < pre[hi]
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) / 2;
-            if (pre[mid] <= i) lo = mid;
-            else hi = mid;
-        }
-        return (uint32_t)(warm_region(lo, G, iters, a.s.L) + (i - pre[lo]));
-    };
+    auto phys = [&](uint32_t i) -> uint32_t { return run_slot(pre, G, iters, a.s.L, i); };
     const uint32_t nruns = pre[G];
     const uint32_t per_job = kWave * R;
     const uint32_t njobs = (nruns + per_job - 1) / per_job;
@@ -631,6 +682,7 @@ __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
                     if (act[r]) load64(nxt[r], at(q));
                     else nxt[r][0] = nxt[r][1] = nxt[r][2] = nxt[r][3] = make_uint4(0, 0, 0, 0);
                 }
+                __builtin_amdgcn_sched_barrier(0);   // keep the read-ahead ahead of the lookups
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     uint4 v[R];
@@ -1427,12 +1479,13 @@ __device__ __forceinline__ void slot_bounds(const MultiArgs &a, uint32_t slot, u
 }
 
 // warm-up and merging: one wavefront per slot, 16 slots per block iteration
-__global__ void __launch_bounds__(1024) mwarm_kernel(MultiArgs a) {
+// (8 waves per SIMD: two 16-wave blocks per CU, as for warm_kernel)
+__global__ void __launch_bounds__(1024, 8) mwarm_kernel(MultiArgs a) {
     __shared__ uint32_t s_cnt[2][kWarmWaves + 1];
     uint32_t buf = 0;
     constexpr int R = 4;
     const uint32_t lane = threadIdx.x % kWave;
-    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t wave = wave_uniform(threadIdx.x / kWave);
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     const uint32_t iters = (a.nslots + kWarmWaves - 1) / kWarmWaves;
     for (uint32_t it = blockIdx.x; it < iters; it += gridDim.x, buf ^= 1) {
@@ -1443,7 +1496,13 @@ __global__ void __launch_bounds__(1024) mwarm_kernel(MultiArgs a) {
         uint64_t b = 0, e = 0;
         bool first = false;
         if (ok) slot_bounds(a, slot, b, e, first);
-        const uint32_t wlen = okl ? (uint32_t)(e - b < a.warm ? e - b : a.warm) : 0u;
+        b = wave_uniform(b);
+        first = wave_uniform((uint32_t)first) != 0;
+        const uint32_t wlen = wave_uniform(okl ? (uint32_t)(e - b < a.warm ? e - b : a.warm) : 0u);
+        StartList starts;
+        starts.lds = nullptr;
+        starts.glb = (const __attribute__((address_space(1))) uint32_t *)d.starts;
+        starts.staged = false;
         uint32_t code[4] = {0, 0, 0, 0};
 #pragma unroll
         for (uint32_t q = 0; q < 4; ++q) {
@@ -1456,7 +1515,7 @@ __global__ void __launch_bounds__(1024) mwarm_kernel(MultiArgs a) {
         if (okl)
             with_entry(d.entry_bytes, [&](auto te) {
                 using TE = decltype(te);
-                warm_classes<TE, uint16_t, R>(reinterpret_cast<const TE *>(d.table), d.starts, d.L, d.dead, true,
+                warm_classes<TE, uint16_t, R>(reinterpret_cast<const TE *>(d.table), starts, d.L, d.dead, true,
                                               first, code, wlen, arow, lane, al, D, cs, spill);
             });
         const uint32_t firstrun = warm_slots(s_cnt[buf], lane, wave, ok ? D : 0u, &a.counters[1]);
@@ -1469,7 +1528,7 @@ __global__ void __launch_bounds__(1024) mwarm_kernel(MultiArgs a) {
             if (okl)
                 with_entry(d.entry_bytes, [&](auto te) {
                     using TE = decltype(te);
-                    warm_records<TE, uint16_t, R>(reinterpret_cast<const TE *>(d.table), d.starts, d.L, d.dead,
+                    warm_records<TE, uint16_t, R>(reinterpret_cast<const TE *>(d.table), starts, d.L, d.dead,
                                                   d.row_bytes, first, code, wlen, arow, lane, lane_lt, al, D, cs,
                                                   spill, firstrun, slot, a.run_chunk, a.run_state);
                 });
@@ -1767,10 +1826,14 @@ int blocks_per_cu(int which, const KernelShape &k, size_t lds) {
     static std::unordered_map<uint64_t, int> known;
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) return 0;
-    const uint64_t key = (uint64_t)which | (uint64_t)k.entry_bytes << 2 | (uint64_t)k.tile_bytes << 5 |
-                         (uint64_t)k.alias_bytes << 8 | (uint64_t)k.runs_per_lane << 11 |
-                         (uint64_t)k.table_in_lds << 14 | (uint64_t)(k.block_threads / 64) << 15 |
-                         (uint64_t)(lds & 0x3ffffff) << 22 | (uint64_t)(device & 0xffff) << 48;
+    // fields: which 3 bits, entry/tile/alias bytes and runs per lane 3 bits
+    // each (values <= 4), LDS flag, waves per block 5 bits, LDS bytes 18 bits
+    // (<= 160 KiB), device 12 bits
+    const uint64_t key = (uint64_t)(which & 7) | (uint64_t)(k.entry_bytes & 7) << 3 |
+                         (uint64_t)(k.tile_bytes & 7) << 6 | (uint64_t)(k.alias_bytes & 7) << 9 |
+                         (uint64_t)(k.runs_per_lane & 7) << 12 | (uint64_t)(k.table_in_lds ? 1 : 0) << 15 |
+                         (uint64_t)((k.block_threads / 64) & 31) << 16 | (uint64_t)(lds & 0x3ffff) << 21 |
+                         (uint64_t)(device & 0xfff) << 39;
     {
         std::lock_guard<std::mutex> lk(mu);
         auto it = known.find(key);

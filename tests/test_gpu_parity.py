@@ -196,12 +196,13 @@ def test_accepted_texts_of_random_expressions():
         x = np.frombuffer(bytes(out + dist[s]), dtype=np.uint8)
         want = ref.serial(x)
         assert want[0] is True
-        rec = make(pattern, ("conv64", "conv16", "plain")[_ % 3])
+        mode = ("conv64", "conv16", "plain")[_ % 3]
+        rec = make(pattern, mode)
         try:
             for algo in ALGOS:
                 for chunks in (1, 7, 100, 0):
                     got = rec.recognize(dev(x), algo=algo, chunks=chunks)
-                    assert (got["accept"], got["final_state"]) == want
+                    assert (got["accept"], got["final_state"]) == want, (pattern, mode, algo, chunks, got)
         finally:
             rec.close()
 
