@@ -638,7 +638,8 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     ri::HitArgs ha{};
     if (hit) {
         // products of hit matrices: level 0 over the K - 1 matrices, then
-        // groups of 64 products until one is left
+        // groups of 64 products until at most 64 are left; the last level and
+        // the final step run in one wave
         ha.alias = ws->alias.p;
         ha.L = H.L;
         ha.nchunks = plan.nchunks;
@@ -649,6 +650,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         ha.csr_idx = D.csr_idx;
         ha.content = H.W <= kMaxDenseWords ? D.content : nullptr;
         ha.prod_in = nullptr;
+        ha.nmembers = 0;
         if (plan.nchunks > 1) {
             int cur = 0;
             ha.nmembers = plan.nchunks - 1;
@@ -656,7 +658,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
             ha.rows_out = static_cast<uint32_t *>(ws->hrows[0].p);
             HIP_TRY(ri::launch_hit_prod(ha, H.W <= kMaxDenseWords ? (int)H.W : 0, shape.alias_bytes, true, stream));
             uint32_t nm = (ha.nmembers + 63) / 64;
-            while (nm > 1) {
+            while (nm > ri::kHitTailMax) {
                 ha.nmembers = nm;
                 ha.prod_in = static_cast<const uint64_t *>(ws->hprod[cur].p);
                 ha.rows_in = static_cast<const uint32_t *>(ws->hrows[cur].p);
@@ -667,6 +669,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
                 nm = (nm + 63) / 64;
             }
             ha.prod_in = static_cast<const uint64_t *>(ws->hprod[cur].p);
+            ha.nmembers = nm;
         }
         if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(ws->dbg.p), stream));
         HIP_TRY(ri::launch_finalize_hit(fa, ha, H.W <= kMaxDenseWords ? (int)H.W : 0, shape.alias_bytes, stream));

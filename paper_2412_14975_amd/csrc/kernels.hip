@@ -171,7 +171,6 @@ __device__ __forceinline__ void scan_shared(uint32_t (&st)[R], uint64_t p, uint6
         if (work) {
             uint4 nxt[4];
             load64(nxt, at(p + 64 < bend ? p + 64 : p));
-            __builtin_amdgcn_sched_barrier(0);   // keep the read-ahead ahead of the lookups
 #pragma unroll
             for (int q = 0; q < 4; ++q) step16_shared<TE, R>(st, cur[q], tab, cls);
 #pragma unroll
@@ -682,7 +681,6 @@ __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
                     if (act[r]) load64(nxt[r], at(q));
                     else nxt[r][0] = nxt[r][1] = nxt[r][2] = nxt[r][3] = make_uint4(0, 0, 0, 0);
                 }
-                __builtin_amdgcn_sched_barrier(0);   // keep the read-ahead ahead of the lookups
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     uint4 v[R];
@@ -1303,12 +1301,13 @@ __global__ void finalize_cls_kernel(FinalArgs f, ClsJoinArgs a) {
 // Classes of the last chunk reached from start 0 (row a0 of the product, a0
 // = class of start 0 in chunk 0), union of their end-state contents, then
 // acceptance and final state.
+// prod: the whole product M_0 ... M_{K-2} (kRowCap rows), nullptr for a
+// single chunk.  One thread.
 template <int W, typename TA>
-__global__ void finalize_hit_kernel(FinalArgs f, HitArgs a) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void finalize_hit_one(const FinalArgs &f, const HitArgs &a, const uint64_t *prod) {
     const TA a0 = reinterpret_cast<const TA *>(a.alias)[0];
     uint64_t v = 0;
-    if (a0 != all_ones<TA>() && (uint32_t)a0 < kRowCap) v = a.prod_in ? a.prod_in[a0] : 1ull << a0;
+    if (a0 != all_ones<TA>() && (uint32_t)a0 < kRowCap) v = prod ? prod[a0] : 1ull << a0;
     const uint32_t last = a.nchunks - 1;
     const uint32_t R = a.run_count[last];
     if constexpr (W > 0) {
@@ -1340,6 +1339,27 @@ __global__ void finalize_hit_kernel(FinalArgs f, HitArgs a) {
     }
     f.result[2] = (int32_t)f.counters[2];
     reset_counters(f.counters);
+}
+
+// The last level of the hit-matrix product (at most 64 products, a.nmembers
+// of them in a.prod_in; 0 for a single chunk) and the final step, in one wave.
+template <int W, typename TA>
+__global__ void __launch_bounds__(64) hit_tail_kernel(FinalArgs f, HitArgs a) {
+    __shared__ uint64_t top[kRowCap];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t nm = a.nmembers;
+    const uint64_t *prod = nm ? a.prod_in : nullptr;
+    if (nm > 1) {
+        uint64_t rows[kRowCap];
+#pragma unroll
+        for (uint32_t r = 0; r < kRowCap; ++r) rows[r] = lane < nm ? a.prod_in[(uint64_t)lane * kRowCap + r] : 0ull;
+        wave_tree_product(rows, lane, nm);
+        if (lane == 0)
+#pragma unroll
+            for (uint32_t r = 0; r < kRowCap; ++r) top[r] = rows[r];
+        prod = top;
+    }
+    if (lane == 0) finalize_hit_one<W, TA>(f, a, prod);
 }
 
 // One block: the set X of N' states (a bitset in LDS) is carried from chunk
@@ -1989,12 +2009,13 @@ hipError_t launch_hit_prod(const HitArgs &a, int W, int alias_bytes, bool level0
 }
 
 hipError_t launch_finalize_hit(const FinalArgs &f, const HitArgs &a, int W, int alias_bytes, hipStream_t s) {
+    if (a.nmembers > kHitTailMax) return hipErrorInvalidValue;
     return dispatch_ta(alias_bytes, [&](auto ta) {
         if (W == 0) {
-            hipLaunchKernelGGL((finalize_hit_kernel<0, decltype(ta)>), dim3(1), dim3(64), 0, s, f, a);
+            hipLaunchKernelGGL((hit_tail_kernel<0, decltype(ta)>), dim3(1), dim3(kWave), 0, s, f, a);
             return hipGetLastError();
         }
-#define CALLFH(w) hipLaunchKernelGGL((finalize_hit_kernel<w, decltype(ta)>), dim3(1), dim3(64), 0, s, f, a);
+#define CALLFH(w) hipLaunchKernelGGL((hit_tail_kernel<w, decltype(ta)>), dim3(1), dim3(kWave), 0, s, f, a);
         RI_DISPATCH_W(W, CALLFH)
 #undef CALLFH
         return hipGetLastError();

@@ -194,7 +194,10 @@ struct FinalArgs {
 hipError_t launch_finalize_rel(const FinalArgs &a, int W, hipStream_t s);
 hipError_t launch_finalize_fun(const FinalArgs &a, hipStream_t s);
 hipError_t launch_finalize_cls(const FinalArgs &f, const ClsJoinArgs &a, int W, int alias_bytes, hipStream_t s);
+// The last level (a.nmembers <= kHitTailMax products in a.prod_in, 0 for a
+// single chunk) and the final step, in one launch.
 // result[2] = counters[2] (1: the hit-matrix result is not valid)
+constexpr uint32_t kHitTailMax = 64;
 hipError_t launch_finalize_hit(const FinalArgs &f, const HitArgs &a, int W, int alias_bytes, hipStream_t s);
 // Join by propagating the set of N' states chunk after chunk (one block; any
 // number of runs per chunk, any interface size up to kPropMaxWords * 32).
