@@ -672,7 +672,10 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
             ha.nmembers = nm;
         }
         if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(ws->dbg.p), stream));
-        HIP_TRY(ri::launch_finalize_hit(fa, ha, H.W <= kMaxDenseWords ? (int)H.W : 0, shape.alias_bytes, stream));
+        // queued calls: a result that a chunk with too many runs made invalid
+        // is redone by propagation in the same launch, then copied out
+        HIP_TRY(ri::launch_finalize_hit(fa, ha, H.W <= kMaxDenseWords ? (int)H.W : 0, shape.alias_bytes, stream,
+                                        result_dev, result_dev ? H.W : 0));
     } else if (gc) {
         if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(ws->dbg.p), stream));
         rc = cls_join();
@@ -704,9 +707,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         else HIP_TRY(ri::launch_finalize_fun(fa, stream));
     }
     if (result_dev) {
-        // the result stays on the device; a hit-matrix result that a chunk
-        // with too many runs made invalid is redone by the gated propagation
-        if (hit) HIP_TRY(ri::launch_propagate(fa, ha, H.W, shape.alias_bytes, stream, result_dev));
+        // the result stays on the device (written by the final kernel)
         out->chunks = plan.nchunks;
         out->chunk_size = (uint32_t)plan.cs;
         out->accept = -1;

@@ -1301,10 +1301,15 @@ __global__ void finalize_cls_kernel(FinalArgs f, ClsJoinArgs a) {
 // Classes of the last chunk reached from start 0 (row a0 of the product, a0
 // = class of start 0 in chunk 0), union of their end-state contents, then
 // acceptance and final state.
+// The join by propagation (defined below) run by the calling block; sm holds
+// 3 W words.
+template <typename TA>
+__device__ void propagate_block(const FinalArgs &f, const HitArgs &a, uint32_t W, uint32_t *sm);
+
 // prod: the whole product M_0 ... M_{K-2} (kRowCap rows), nullptr for a
 // single chunk.  One thread.
 template <int W, typename TA>
-__device__ void finalize_hit_one(const FinalArgs &f, const HitArgs &a, const uint64_t *prod) {
+__device__ uint32_t finalize_hit_one(const FinalArgs &f, const HitArgs &a, const uint64_t *prod) {
     const TA a0 = reinterpret_cast<const TA *>(a.alias)[0];
     uint64_t v = 0;
     if (a0 != all_ones<TA>() && (uint32_t)a0 < kRowCap) v = prod ? prod[a0] : 1ull << a0;
@@ -1337,14 +1342,19 @@ __device__ void finalize_hit_one(const FinalArgs &f, const HitArgs &a, const uin
         }
         decide_lists(u, f, f.result);
     }
-    f.result[2] = (int32_t)f.counters[2];
+    const uint32_t flag = f.counters[2];
+    f.result[2] = (int32_t)flag;
     reset_counters(f.counters);
+    return flag;
 }
 
 // The last level of the hit-matrix product (at most 64 products, a.nmembers
 // of them in a.prod_in; 0 for a single chunk) and the final step, in one wave.
+// With out != nullptr the result is also copied to out; when a chunk kept
+// more runs than a hit row holds, the wave first joins again by propagation
+// (prop_words words per set of N' states, 12 bytes per word of dynamic LDS).
 template <int W, typename TA>
-__global__ void __launch_bounds__(64) hit_tail_kernel(FinalArgs f, HitArgs a) {
+__global__ void __launch_bounds__(64) hit_tail_kernel(FinalArgs f, HitArgs a, uint32_t prop_words, int32_t *out) {
     __shared__ uint64_t top[kRowCap];
     const uint32_t lane = threadIdx.x;
     const uint32_t nm = a.nmembers;
@@ -1359,26 +1369,26 @@ __global__ void __launch_bounds__(64) hit_tail_kernel(FinalArgs f, HitArgs a) {
             for (uint32_t r = 0; r < kRowCap; ++r) top[r] = rows[r];
         prod = top;
     }
-    if (lane == 0) finalize_hit_one<W, TA>(f, a, prod);
+    uint32_t redo = 0;
+    if (lane == 0) redo = finalize_hit_one<W, TA>(f, a, prod);
+    if (!out) return;
+    redo = (uint32_t)__shfl((int)redo, 0);
+    if (redo) {
+        extern __shared__ __align__(16) uint32_t tsm[];
+        propagate_block<TA>(f, a, prop_words, tsm);   // ends with the result in f.result
+    }
+    if (lane == 0) {
+        out[0] = f.result[0];
+        out[1] = f.result[1];
+    }
 }
 
 // One block: the set X of N' states (a bitset in LDS) is carried from chunk
 // to chunk: the classes of chunk k hit by X are {alias[k][t] : t in X}, and
 // the new X is the union of the contents of their end states.  Exact for any
 // number of runs per chunk.
-// With out != nullptr the kernel follows the hit-matrix join on the same
-// stream: it joins only when that join flagged its result invalid
-// (f.result[2] != 0) and copies the result to out in either case.
 template <typename TA>
-__global__ void __launch_bounds__(1024) propagate_kernel(FinalArgs f, HitArgs a, uint32_t W, int32_t *out) {
-    if (out && f.result[2] == 0) {
-        if (threadIdx.x == 0) {
-            out[0] = f.result[0];
-            out[1] = f.result[1];
-        }
-        return;
-    }
-    extern __shared__ __align__(16) uint32_t sm[];
+__device__ void propagate_block(const FinalArgs &f, const HitArgs &a, uint32_t W, uint32_t *sm) {
     uint32_t *X = sm;               // [W]
     uint32_t *Y = sm + W;           // [W]
     uint32_t *H = sm + 2 * W;       // [W] classes hit (a chunk has at most L runs)
@@ -1426,11 +1436,13 @@ __global__ void __launch_bounds__(1024) propagate_kernel(FinalArgs f, HitArgs a,
         decide_bits(X, W, f, f.result);
         f.result[2] = 0;
         reset_counters(f.counters);
-        if (out) {
-            out[0] = f.result[0];
-            out[1] = f.result[1];
-        }
     }
+}
+
+template <typename TA>
+__global__ void __launch_bounds__(1024) propagate_kernel(FinalArgs f, HitArgs a, uint32_t W) {
+    extern __shared__ __align__(16) uint32_t sm[];
+    propagate_block<TA>(f, a, W, sm);
 }
 
 __global__ void store_result_kernel(int32_t *out, int32_t accept, int32_t final_state) {
@@ -2008,25 +2020,26 @@ hipError_t launch_hit_prod(const HitArgs &a, int W, int alias_bytes, bool level0
     });
 }
 
-hipError_t launch_finalize_hit(const FinalArgs &f, const HitArgs &a, int W, int alias_bytes, hipStream_t s) {
-    if (a.nmembers > kHitTailMax) return hipErrorInvalidValue;
+hipError_t launch_finalize_hit(const FinalArgs &f, const HitArgs &a, int W, int alias_bytes, hipStream_t s,
+                               int32_t *out, uint32_t prop_words) {
+    if (a.nmembers > kHitTailMax || (out && prop_words > kPropMaxWords)) return hipErrorInvalidValue;
+    const size_t lds = out ? (size_t)prop_words * 12 : 0;
     return dispatch_ta(alias_bytes, [&](auto ta) {
         if (W == 0) {
-            hipLaunchKernelGGL((hit_tail_kernel<0, decltype(ta)>), dim3(1), dim3(kWave), 0, s, f, a);
+            hipLaunchKernelGGL((hit_tail_kernel<0, decltype(ta)>), dim3(1), dim3(kWave), lds, s, f, a, prop_words, out);
             return hipGetLastError();
         }
-#define CALLFH(w) hipLaunchKernelGGL((hit_tail_kernel<w, decltype(ta)>), dim3(1), dim3(kWave), 0, s, f, a);
+#define CALLFH(w) hipLaunchKernelGGL((hit_tail_kernel<w, decltype(ta)>), dim3(1), dim3(kWave), lds, s, f, a, prop_words, out);
         RI_DISPATCH_W(W, CALLFH)
 #undef CALLFH
         return hipGetLastError();
     });
 }
 
-hipError_t launch_propagate(const FinalArgs &f, const HitArgs &a, uint32_t W, int alias_bytes, hipStream_t s,
-                            int32_t *out) {
+hipError_t launch_propagate(const FinalArgs &f, const HitArgs &a, uint32_t W, int alias_bytes, hipStream_t s) {
     if (W > kPropMaxWords) return hipErrorInvalidValue;
     return dispatch_ta(alias_bytes, [&](auto ta) {
-        hipLaunchKernelGGL((propagate_kernel<decltype(ta)>), dim3(1), dim3(1024), (size_t)W * 12, s, f, a, W, out);
+        hipLaunchKernelGGL((propagate_kernel<decltype(ta)>), dim3(1), dim3(1024), (size_t)W * 12, s, f, a, W);
         return hipGetLastError();
     });
 }

@@ -196,16 +196,16 @@ hipError_t launch_finalize_fun(const FinalArgs &a, hipStream_t s);
 hipError_t launch_finalize_cls(const FinalArgs &f, const ClsJoinArgs &a, int W, int alias_bytes, hipStream_t s);
 // The last level (a.nmembers <= kHitTailMax products in a.prod_in, 0 for a
 // single chunk) and the final step, in one launch.
-// result[2] = counters[2] (1: the hit-matrix result is not valid)
+// result[2] = counters[2] (1: the hit-matrix result is not valid).  With
+// out != nullptr an invalid result is redone by propagation in the same
+// launch (prop_words <= kPropMaxWords) and {accept, final} is copied to out.
 constexpr uint32_t kHitTailMax = 64;
-hipError_t launch_finalize_hit(const FinalArgs &f, const HitArgs &a, int W, int alias_bytes, hipStream_t s);
+hipError_t launch_finalize_hit(const FinalArgs &f, const HitArgs &a, int W, int alias_bytes, hipStream_t s,
+                               int32_t *out = nullptr, uint32_t prop_words = 0);
 // Join by propagating the set of N' states chunk after chunk (one block; any
 // number of runs per chunk, any interface size up to kPropMaxWords * 32).
 constexpr uint32_t kPropMaxWords = 1024;
-// out != nullptr: gated form that runs after launch_finalize_hit on the same
-// stream, joins only when f.result[2] != 0, and writes {accept, final} to out.
-hipError_t launch_propagate(const FinalArgs &f, const HitArgs &a, uint32_t W, int alias_bytes, hipStream_t s,
-                            int32_t *out = nullptr);
+hipError_t launch_propagate(const FinalArgs &f, const HitArgs &a, uint32_t W, int alias_bytes, hipStream_t s);
 // out[0] = accept, out[1] = final_state, in stream order
 hipError_t launch_store_result(int32_t *out, int32_t accept, int32_t final_state, hipStream_t s);
 
