@@ -976,29 +976,38 @@ __global__ void __launch_bounds__(256) join_cls_kernel(ClsJoinArgs a) {
 // join over merged runs: products of hit matrices (RI-DFA)
 // ---------------------------------------------------------------------------
 
-// Row product: rows a[r] (bitmasks over the partner's rows) times b.
-__device__ __forceinline__ void rows_times(uint64_t (&a)[kRowCap], const uint64_t (&b)[kRowCap]) {
+// A hit matrix keeps kRowCap = 8 rows and 8 columns (a chunk with more
+// classes flags the result as invalid, so wider columns are never needed):
+// row r is byte r of one 64-bit word, bit c of that byte is column c.
+constexpr uint64_t kByteLsb = 0x0101010101010101ull;
+
+// Boolean product a * b: row r of the result is the union of the rows j of b
+// for which a[r][j] is set.  For each j, bit j of every row of a is widened
+// to a byte mask and selects a copy of row j of b; no data-dependent loop.
+__device__ __forceinline__ uint64_t mat8_times(uint64_t a, uint64_t b) {
+    uint64_t c = 0;
 #pragma unroll
-    for (uint32_t r = 0; r < kRowCap; ++r) {
-        uint64_t x = a[r], y = 0;
-        while (x) {
-            const uint32_t j = __builtin_ctzll(x);
-            x &= x - 1;
-            if (j < kRowCap) y |= b[j];
-        }
-        a[r] = y;
+    for (uint32_t j = 0; j < kRowCap; ++j) {
+        const uint64_t col = (a >> j) & kByteLsb;     // a[r][j] as 0 / 1 in byte r
+        const uint64_t sel = (col << 8) - col;        // 0xFF in the selected rows
+        c |= sel & (((b >> (8 * j)) & 0xFFull) * kByteLsb);
     }
+    return c;
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+    return (uint64_t)hi << 32 | lo;
 }
 
 // Tree product of the wave's gn members (lane l holds member l): after it
-// lane 0 holds the product of all of them.
-__device__ __forceinline__ void wave_tree_product(uint64_t (&rows)[kRowCap], uint32_t lane, uint32_t gn) {
+// lane 0 holds the product of all of them, in order.
+__device__ __forceinline__ void wave_tree_product(uint64_t &m, uint32_t lane, uint32_t gn) {
 #pragma unroll
     for (uint32_t d = 1; d < kWave; d <<= 1) {
-        uint64_t b[kRowCap];
-#pragma unroll
-        for (uint32_t j = 0; j < kRowCap; ++j) b[j] = __shfl(rows[j], (int)((lane + d) % kWave));
-        if ((lane & (2 * d - 1)) == 0 && lane + d < gn) rows_times(rows, b);
+        const uint64_t b = shfl64(m, (int)((lane + d) % kWave));
+        if ((lane & (2 * d - 1)) == 0 && lane + d < gn) m = mat8_times(m, b);
     }
 }
 
@@ -1023,7 +1032,7 @@ __global__ void __launch_bounds__(256) hit_prod0_kernel(HitArgs a) {
         for (uint32_t i = lane; i < gn * a.L; i += kWave) srow[i] = src[i];
         __builtin_amdgcn_wave_barrier();   // the rows are read by other lanes of this wave
     }
-    uint64_t rows[kRowCap];
+    uint64_t M = 0;
     uint32_t R = 0;
     if (lane < gn) {
         R = a.run_count[k];
@@ -1041,22 +1050,21 @@ __global__ void __launch_bounds__(256) hit_prod0_kernel(HitArgs a) {
                     for (uint32_t w = 0; w < (uint32_t)W; ++w)
                         for (uint32_t bits = cw[w]; bits; bits &= bits - 1) {
                             const TA j = row[w * 32 + __builtin_ctz(bits)];
-                            if (j != all_ones<TA>() && (uint32_t)j < 64) m |= 1ull << j;
+                            if (j != all_ones<TA>() && (uint32_t)j < kRowCap) m |= 1ull << j;
                         }
                 } else {
                     for (uint32_t i = a.csr_off[f], ie = a.csr_off[f + 1]; i < ie; ++i) {
                         const TA j = row[a.csr_idx[i]];
-                        if (j != all_ones<TA>() && (uint32_t)j < 64) m |= 1ull << j;
+                        if (j != all_ones<TA>() && (uint32_t)j < kRowCap) m |= 1ull << j;
                     }
                 }
             }
         }
-        rows[r] = m;
+        M |= m << (8 * r);
     }
-    wave_tree_product(rows, lane, gn);
+    wave_tree_product(M, lane, gn);
     if (lane == 0) {
-#pragma unroll
-        for (uint32_t r = 0; r < kRowCap; ++r) a.prod_out[(uint64_t)g * kRowCap + r] = rows[r];
+        a.prod_out[g] = M;
         a.rows_out[g] = R;
     }
 }
@@ -1069,14 +1077,11 @@ __global__ void __launch_bounds__(256) hit_prodN_kernel(HitArgs a) {
     if (g >= ngroups) return;
     const uint32_t gn = g * kWave + kWave <= a.nmembers ? kWave : a.nmembers - g * kWave;
     const uint32_t m = g * kWave + lane;
-    uint64_t rows[kRowCap];
-#pragma unroll
-    for (uint32_t r = 0; r < kRowCap; ++r) rows[r] = lane < gn ? a.prod_in[(uint64_t)m * kRowCap + r] : 0ull;
+    uint64_t M = lane < gn ? a.prod_in[m] : 0ull;
     const uint32_t R = lane < gn ? a.rows_in[m] : 0u;
-    wave_tree_product(rows, lane, gn);
+    wave_tree_product(M, lane, gn);
     if (lane == 0) {
-#pragma unroll
-        for (uint32_t r = 0; r < kRowCap; ++r) a.prod_out[(uint64_t)g * kRowCap + r] = rows[r];
+        a.prod_out[g] = M;
         a.rows_out[g] = R;
     }
 }
@@ -1306,13 +1311,13 @@ __global__ void finalize_cls_kernel(FinalArgs f, ClsJoinArgs a) {
 template <typename TA>
 __device__ void propagate_block(const FinalArgs &f, const HitArgs &a, uint32_t W, uint32_t *sm);
 
-// prod: the whole product M_0 ... M_{K-2} (kRowCap rows), nullptr for a
-// single chunk.  One thread.
+// prod: the whole product M_0 ... M_{K-2} when `have` (not for a single
+// chunk).  One thread.
 template <int W, typename TA>
-__device__ uint32_t finalize_hit_one(const FinalArgs &f, const HitArgs &a, const uint64_t *prod) {
+__device__ uint32_t finalize_hit_one(const FinalArgs &f, const HitArgs &a, bool have, uint64_t prod) {
     const TA a0 = reinterpret_cast<const TA *>(a.alias)[0];
     uint64_t v = 0;
-    if (a0 != all_ones<TA>() && (uint32_t)a0 < kRowCap) v = prod ? prod[a0] : 1ull << a0;
+    if (a0 != all_ones<TA>() && (uint32_t)a0 < kRowCap) v = have ? (prod >> (8 * (uint32_t)a0)) & 0xFFull : 1ull << a0;
     const uint32_t last = a.nchunks - 1;
     const uint32_t R = a.run_count[last];
     if constexpr (W > 0) {
@@ -1355,22 +1360,12 @@ __device__ uint32_t finalize_hit_one(const FinalArgs &f, const HitArgs &a, const
 // (prop_words words per set of N' states, 12 bytes per word of dynamic LDS).
 template <int W, typename TA>
 __global__ void __launch_bounds__(64) hit_tail_kernel(FinalArgs f, HitArgs a, uint32_t prop_words, int32_t *out) {
-    __shared__ uint64_t top[kRowCap];
     const uint32_t lane = threadIdx.x;
     const uint32_t nm = a.nmembers;
-    const uint64_t *prod = nm ? a.prod_in : nullptr;
-    if (nm > 1) {
-        uint64_t rows[kRowCap];
-#pragma unroll
-        for (uint32_t r = 0; r < kRowCap; ++r) rows[r] = lane < nm ? a.prod_in[(uint64_t)lane * kRowCap + r] : 0ull;
-        wave_tree_product(rows, lane, nm);
-        if (lane == 0)
-#pragma unroll
-            for (uint32_t r = 0; r < kRowCap; ++r) top[r] = rows[r];
-        prod = top;
-    }
+    uint64_t M = lane < nm ? a.prod_in[lane] : 0ull;
+    if (nm > 1) wave_tree_product(M, lane, nm);
     uint32_t redo = 0;
-    if (lane == 0) redo = finalize_hit_one<W, TA>(f, a, prod);
+    if (lane == 0) redo = finalize_hit_one<W, TA>(f, a, nm > 0, M);
     if (!out) return;
     redo = (uint32_t)__shfl((int)redo, 0);
     if (redo) {
@@ -1607,10 +1602,8 @@ __global__ void __launch_bounds__(256) mhit_kernel(MultiArgs a) {
     const uint32_t g = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (g >= a.ngroups) return;
     const uint32_t m0 = a.grp_first[g], gn = a.grp_count[g];
-    uint64_t rows[kRowCap];
+    uint64_t M = 0;
     uint32_t R = 0;
-#pragma unroll
-    for (uint32_t r = 0; r < kRowCap; ++r) rows[r] = 0;
     if (lane < gn) {
         const uint32_t m = m0 + lane;
         if (LEVEL0) {
@@ -1624,23 +1617,19 @@ __global__ void __launch_bounds__(256) mhit_kernel(MultiArgs a) {
                 if (fs != kNoState)
                     for_members(d, fs, [&](uint32_t t) {
                         const uint16_t j = row[t];
-                        if (j != 0xFFFFu && j < 64) bits |= 1ull << j;
+                        if (j != 0xFFFFu && j < kRowCap) bits |= 1ull << j;
                     });
-#pragma unroll
-                for (uint32_t rr = 0; rr < kRowCap; ++rr)
-                    if (rr == r) rows[rr] = bits;
+                M |= bits << (8 * r);
             }
         } else {
-#pragma unroll
-            for (uint32_t r = 0; r < kRowCap; ++r) rows[r] = a.prod[(uint64_t)m * kRowCap + r];
+            M = a.prod[m];
             R = a.prod_rows[m];
         }
     }
-    wave_tree_product(rows, lane, gn);
+    wave_tree_product(M, lane, gn);
     if (lane == 0) {
         const uint64_t o = (uint64_t)(a.prod_out + g);
-#pragma unroll
-        for (uint32_t r = 0; r < kRowCap; ++r) a.prod[o * kRowCap + r] = rows[r];
+        a.prod[o] = M;
         a.prod_rows[o] = R;
     }
 }
@@ -1668,7 +1657,7 @@ __global__ void __launch_bounds__(256) mfinal_kernel(MultiArgs a) {
     const uint32_t s0 = a.text_slot[t], c = a.text_nslots[t], last = s0 + c - 1;
     const uint16_t a0 = a.alias[a.alias_row[s0]];
     uint64_t v = 0;
-    if (a0 != 0xFFFFu && a0 < kRowCap) v = c == 1 ? 1ull << a0 : a.prod[(uint64_t)a.text_prod[t] * kRowCap + a0];
+    if (a0 != 0xFFFFu && a0 < kRowCap) v = c == 1 ? 1ull << a0 : (a.prod[a.text_prod[t]] >> (8 * a0)) & 0xFFull;
     const uint32_t R = a.run_count[last];
     if (d.functional) {
         for (; v; v &= v - 1) {

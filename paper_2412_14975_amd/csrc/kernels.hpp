@@ -169,9 +169,9 @@ struct HitArgs {
     const uint32_t *csr_idx;
     const uint32_t *content;   // the same as [nstates][W] bitsets when W <= 64, else nullptr
     uint32_t nmembers;         // level 0: K - 1 matrices; level >= 1: products of the level below
-    const uint64_t *prod_in;   // level >= 1: [nmembers][kRowCap]; finalize: the single product (or nullptr)
+    const uint64_t *prod_in;   // level >= 1 and the last level: [nmembers] products, 8 rows x 8 columns in one word
     const uint32_t *rows_in;   // level >= 1: [nmembers]
-    uint64_t *prod_out;        // [ngroups][kRowCap]
+    uint64_t *prod_out;        // [ngroups] products (row r = byte r, column c = bit c of it)
     uint32_t *rows_out;        // [ngroups]
 };
 // W: words of the dense content bitsets, 0 = member lists
@@ -260,7 +260,7 @@ struct MultiArgs {
     const uint32_t *text_slot, *text_nslots, *text_auto, *text_out, *text_prod;
     int32_t *results;              // [rows][2]
     // hit products: every level in one buffer
-    uint64_t *prod;                // [groups][kRowCap]
+    uint64_t *prod;                // [groups] products (row r = byte r, column c = bit c of it)
     uint32_t *prod_rows;           // [groups]
     const uint32_t *grp_first, *grp_count;   // the level being launched
     uint32_t ngroups;
