@@ -471,9 +471,9 @@ __device__ __forceinline__ uint32_t warm_slots(uint32_t *s_cnt, uint32_t lane, u
 
 // Occupancy: a block is 16 waves (4 per SIMD), so two blocks per CU need 8
 // waves per SIMD; without the attribute the kernel's SGPR use allows 7 and
-// only one block fits.  With 4 start registers (R = 4) the VGPRs would spill.
+// only one block fits (the SGPRs over the limit live in VGPR lanes).
 template <typename TE, typename TA, int R, bool LDS>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(R <= 2 ? 8 : 4))) warm_kernel(WarmArgs a) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) warm_kernel(WarmArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ uint32_t s_count;   // runs placed in this block's region
     const TE *tab;
