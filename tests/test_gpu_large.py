@@ -93,3 +93,26 @@ def test_runs_that_never_merge_on_a_large_interface():
                 assert (got["accept"], got["final_state"]) == want, (n, chunks)
     finally:
         rec.close()
+
+
+def test_warm_up_with_starts_read_from_global_memory():
+    """520 keywords: 4447 interface starts (RID) and 6246 minimal-DFA states,
+    more than the warm-up stages in LDS (4096), so the warm-up reads its start
+    list from global memory; the results must still be the oracle's."""
+    rx, kws = gen.c5_automaton(7, 1, 520)
+    ref = MinRef(rx)
+    rec = ri.Recognizer(rx)
+    try:
+        info = rec.info()
+        assert info["starts"][0] > 4096 and info["starts"][1] > 4096
+        rng = gen.PCG(91)
+        for n in (4097, 1 << 16, (1 << 20) + 3):
+            for plant in (False, True):
+                x = gen.c5_text(rng, kws, n, plant)
+                want = ref.serial(x)
+                for algo in ("rid", "dfa"):
+                    for chunks in (0, 64):
+                        got = rec.recognize(dev(x), algo=algo, chunks=chunks)
+                        assert (got["accept"], got["final_state"]) == want, (algo, n, chunks)
+    finally:
+        rec.close()
