@@ -117,6 +117,21 @@ def test_tiny_accept_and_final(tiny, seed, algo, chunks):
         assert got["n"] == len(x)
 
 
+@pytest.mark.parametrize("c", [4096, 4097, 4098, 4161, 4162])
+def test_join_level_boundaries(tiny, c):
+    """16-byte chunks, c of them: c - 1 = 64 x 64 (+1, ...) hit matrices, so
+    the last level of the product gets exactly 64 members or needs one more
+    level; the functional join of the DFA sees the same group boundaries."""
+    rec, ref = tiny
+    acc, rej = gen.c1_texts(70 + c % 7, n=c * 16)
+    for x in (acc, rej):
+        want = ref.serial(x)
+        for algo in ALGOS:
+            got = rec.recognize(dev(x), algo=algo, chunks=c)
+            assert got["chunks"] == c
+            assert (got["accept"], got["final_state"]) == want, (algo, c)
+
+
 @pytest.mark.parametrize("algo", ["rid", "dfa"])
 def test_tiny_chunk_maps(tiny, algo):
     rec, ref = tiny
