@@ -337,6 +337,7 @@ int conv_config(const AlgoHost &H, const DeviceCopy &dc, const Options &opt, uin
     // warm-up: starts held 64 per lane register, up to 4 registers per lane
     c->warm_shape = shape;
     c->warm_shape.runs_per_lane = H.L <= 64 ? 1 : H.L <= 128 ? 2 : 4;
+    c->warm_shape.code_regs = opt.warm <= 64 ? 1 : 4;   // registers of 64 warm-up byte codes
     c->lds_w = ri::warm_lds_bytes(c->warm_shape, (uint32_t)H.table.size(), H.L);
     if (c->lds_w > dc.max_lds) {   // table and starts do not fit together: table from global memory
         c->warm_shape.table_in_lds = false;

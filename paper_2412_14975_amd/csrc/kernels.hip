@@ -288,11 +288,11 @@ constexpr uint32_t kWarmWaves = kWarmChunksPerBlock;
 
 // Warm-up of the start block at `base` over codes[0..wlen) (codes of bytes
 // 64 q + lane in register q).
-template <typename TE, int R>
-__device__ __forceinline__ void warm_block(uint32_t (&st)[R], const uint32_t (&code)[4], uint32_t wlen,
+template <typename TE, int R, int NQ>
+__device__ __forceinline__ void warm_block(uint32_t (&st)[R], const uint32_t (&code)[NQ], uint32_t wlen,
                                            const TE *tab, uint32_t dead) {
 #pragma unroll
-    for (uint32_t q = 0; q < 4; ++q) {
+    for (uint32_t q = 0; q < (uint32_t)NQ; ++q) {
         const uint32_t j0 = q * kWave;
         if (j0 >= wlen) break;
         const uint32_t jn = wlen - j0 < kWave ? wlen - j0 : kWave;
@@ -320,9 +320,9 @@ __device__ __forceinline__ void warm_block(uint32_t (&st)[R], const uint32_t (&c
 // start base + r * 64 + lane of the last start block; with several start
 // blocks the alias row is written as classes are found.  Once more than 64
 // distinct states are seen the chunk spills: D counts its live starts.
-template <typename TE, typename TA, int R>
+template <typename TE, typename TA, int R, int NQ>
 __device__ __forceinline__ void warm_classes(const TE *tab, const StartList &starts, uint32_t L, uint32_t dead,
-                                             bool ok, bool first, const uint32_t (&code)[4], uint32_t wlen,
+                                             bool ok, bool first, const uint32_t (&code)[NQ], uint32_t wlen,
                                              TA *arow, uint32_t lane, uint32_t (&al)[R], uint32_t &D,
                                              uint32_t &cs, bool &spill) {
     constexpr uint32_t kNone = 0xFFFFFFFFu;
@@ -339,7 +339,7 @@ __device__ __forceinline__ void warm_classes(const TE *tab, const StartList &sta
             const uint32_t s = base + r * kWave + lane;
             st[r] = (ok && s < L && (!first || s == 0)) ? starts[s] : dead;
         }
-        warm_block<TE, R>(st, code, wlen, tab, dead);
+        warm_block<TE, R, NQ>(st, code, wlen, tab, dead);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             al[r] = kNone;
@@ -376,7 +376,7 @@ __device__ __forceinline__ void warm_classes(const TE *tab, const StartList &sta
                         const uint32_t s = b2 * per_block + r2 * kWave + lane;
                         s2[r2] = (ok && s < L && (!first || s == 0)) ? starts[s] : dead;
                     }
-                    warm_block<TE, R>(s2, code, wlen, tab, dead);
+                    warm_block<TE, R, NQ>(s2, code, wlen, tab, dead);
 #pragma unroll
                     for (int r2 = 0; r2 < R; ++r2)
                         if (b2 < blk || r2 <= r) D += (uint32_t)__builtin_popcountll(__ballot(s2[r2] != dead));
@@ -394,9 +394,9 @@ __device__ __forceinline__ void warm_classes(const TE *tab, const StartList &sta
 // Run records of one chunk from slot `firstrun` on, and its alias row (when
 // not written yet).  A spilled chunk's runs are recomputed: every live start
 // is its own run, in start order.
-template <typename TE, typename TA, int R>
+template <typename TE, typename TA, int R, int NQ>
 __device__ __forceinline__ void warm_records(const TE *tab, const StartList &starts, uint32_t L, uint32_t dead,
-                                             uint32_t row_bytes, bool first, const uint32_t (&code)[4],
+                                             uint32_t row_bytes, bool first, const uint32_t (&code)[NQ],
                                              uint32_t wlen, TA *arow, uint32_t lane, uint64_t lane_lt,
                                              const uint32_t (&al)[R], uint32_t D, uint32_t cs, bool spill,
                                              uint32_t firstrun, uint32_t chunk, uint32_t *run_chunk,
@@ -427,7 +427,7 @@ __device__ __forceinline__ void warm_records(const TE *tab, const StartList &sta
             const uint32_t s = base + r * kWave + lane;
             st[r] = (s < L && (!first || s == 0)) ? starts[s] : dead;
         }
-        warm_block<TE, R>(st, code, wlen, tab, dead);
+        warm_block<TE, R, NQ>(st, code, wlen, tab, dead);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t s = base + r * kWave + lane;
@@ -472,7 +472,7 @@ __device__ __forceinline__ uint32_t warm_slots(uint32_t *s_cnt, uint32_t lane, u
 // Occupancy: a block is 16 waves (4 per SIMD), so two blocks per CU need 8
 // waves per SIMD; without the attribute the kernel's SGPR use allows 7 and
 // only one block fits (the SGPRs over the limit live in VGPR lanes).
-template <typename TE, typename TA, int R, bool LDS>
+template <typename TE, typename TA, int R, bool LDS, int NQ>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) warm_kernel(WarmArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ uint32_t s_count;   // runs placed in this block's region
@@ -498,7 +498,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
 
     // the warm-up bytes of this wave's chunk in iteration `it` (raw, 64 per
     // register); loaded one iteration ahead
-    auto fetch = [&](uint32_t it, uint32_t (&raw)[4], uint64_t &b, uint32_t &wlen, bool &first) {
+    auto fetch = [&](uint32_t it, uint32_t (&raw)[NQ], uint64_t &b, uint32_t &wlen, bool &first) {
         const uint32_t chunk = it * kWarmWaves + wave;
         uint64_t e = 0;
         b = 0;
@@ -512,12 +512,12 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
         wlen = wave_uniform(wlen);
         first = wave_uniform((uint32_t)first) != 0;
 #pragma unroll
-        for (uint32_t q = 0; q < 4; ++q) {
+        for (uint32_t q = 0; q < (uint32_t)NQ; ++q) {
             const uint32_t j = q * kWave + lane;
             raw[q] = j < wlen ? (uint32_t)*at(b + j) : 0u;
         }
     };
-    uint32_t raw[4];
+    uint32_t raw[NQ];
     uint64_t b;
     uint32_t wlen;
     bool first;
@@ -526,16 +526,16 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     for (uint32_t it = blockIdx.x; it < iters; it += gridDim.x) {
         const uint32_t chunk = it * kWarmWaves + wave;
         const bool ok = chunk < a.s.nchunks;
-        uint32_t code[4];
+        uint32_t code[NQ];
 #pragma unroll
-        for (uint32_t q = 0; q < 4; ++q) code[q] = q * kWave + lane < wlen ? cls[raw[q]] : 0u;
+        for (uint32_t q = 0; q < (uint32_t)NQ; ++q) code[q] = q * kWave + lane < wlen ? cls[raw[q]] : 0u;
         const uint32_t cur_wlen = wlen;
         const bool cur_first = first;
         fetch(it + gridDim.x, raw, b, wlen, first);   // next iteration's bytes, in flight meanwhile
         TA *arow = alias + (uint64_t)(ok ? chunk : 0) * L;
         uint32_t al[R], D, cs;
         bool spill;
-        warm_classes<TE, TA, R>(tab, starts, L, dead, ok, cur_first, code, cur_wlen, arow, lane, al, D, cs, spill);
+        warm_classes<TE, TA, R, NQ>(tab, starts, L, dead, ok, cur_first, code, cur_wlen, arow, lane, al, D, cs, spill);
         // slots from the block's region: an LDS counter, no barrier
         uint32_t base = 0;
         if (lane == 0 && ok) base = atomicAdd(&s_count, D);
@@ -546,7 +546,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
                 if (a.run_count) a.run_count[chunk] = D;
                 if (D > kRowCap) atomicOr(&a.counters[2], 1u);
             }
-            warm_records<TE, TA, R>(tab, starts, L, dead, a.s.row_bytes, cur_first, code, cur_wlen, arow, lane,
+            warm_records<TE, TA, R, NQ>(tab, starts, L, dead, a.s.row_bytes, cur_first, code, cur_wlen, arow, lane,
                                     lane_lt, al, D, cs, spill, firstrun, chunk, a.run_chunk, a.run_state);
         }
     }
@@ -1542,7 +1542,7 @@ __global__ void __launch_bounds__(1024, 8) mwarm_kernel(MultiArgs a) {
         if (okl)
             with_entry(d.entry_bytes, [&](auto te) {
                 using TE = decltype(te);
-                warm_classes<TE, uint16_t, R>(reinterpret_cast<const TE *>(d.table), starts, d.L, d.dead, true,
+                warm_classes<TE, uint16_t, R, 4>(reinterpret_cast<const TE *>(d.table), starts, d.L, d.dead, true,
                                               first, code, wlen, arow, lane, al, D, cs, spill);
             });
         const uint32_t firstrun = warm_slots(s_cnt[buf], lane, wave, ok ? D : 0u, &a.counters[1]);
@@ -1555,7 +1555,7 @@ __global__ void __launch_bounds__(1024, 8) mwarm_kernel(MultiArgs a) {
             if (okl)
                 with_entry(d.entry_bytes, [&](auto te) {
                     using TE = decltype(te);
-                    warm_records<TE, uint16_t, R>(reinterpret_cast<const TE *>(d.table), starts, d.L, d.dead,
+                    warm_records<TE, uint16_t, R, 4>(reinterpret_cast<const TE *>(d.table), starts, d.L, d.dead,
                                                   d.row_bytes, first, code, wlen, arow, lane, lane_lt, al, D, cs,
                                                   spill, firstrun, slot, a.run_chunk, a.run_state);
                 });
@@ -1813,10 +1813,13 @@ hipError_t launch_warm(const WarmArgs &a, const KernelShape &k, int grid, size_t
         return dispatch_ta(k.alias_bytes, [&](auto ta) {
             return dispatch_r(k.runs_per_lane, [&](auto r) {
                 return dispatch_b(k.table_in_lds, [&](auto lds_t) {
-                    auto fn = warm_kernel<decltype(te), decltype(ta), decltype(r)::value, decltype(lds_t)::value>;
-                    if (grid == 0) { g_fn = reinterpret_cast<const void *>(fn); return hipSuccess; }
-                    hipLaunchKernelGGL(fn, dim3(grid), dim3(k.block_threads), lds, st, a);
-                    return hipGetLastError();
+                    return dispatch_b(k.code_regs == 1, [&](auto one) {
+                        constexpr int NQ = decltype(one)::value ? 1 : 4;
+                        auto fn = warm_kernel<decltype(te), decltype(ta), decltype(r)::value, decltype(lds_t)::value, NQ>;
+                        if (grid == 0) { g_fn = reinterpret_cast<const void *>(fn); return hipSuccess; }
+                        hipLaunchKernelGGL(fn, dim3(grid), dim3(k.block_threads), lds, st, a);
+                        return hipGetLastError();
+                    });
                 });
             });
         });
@@ -1849,12 +1852,12 @@ int blocks_per_cu(int which, const KernelShape &k, size_t lds) {
     if (hipGetDevice(&device) != hipSuccess) return 0;
     // fields: which 3 bits, entry/tile/alias bytes and runs per lane 3 bits
     // each (values <= 4), LDS flag, waves per block 5 bits, LDS bytes 18 bits
-    // (<= 160 KiB), device 12 bits
+    // (<= 160 KiB), device 12 bits, warm-up code registers 3 bits
     const uint64_t key = (uint64_t)(which & 7) | (uint64_t)(k.entry_bytes & 7) << 3 |
                          (uint64_t)(k.tile_bytes & 7) << 6 | (uint64_t)(k.alias_bytes & 7) << 9 |
                          (uint64_t)(k.runs_per_lane & 7) << 12 | (uint64_t)(k.table_in_lds ? 1 : 0) << 15 |
                          (uint64_t)((k.block_threads / 64) & 31) << 16 | (uint64_t)(lds & 0x3ffff) << 21 |
-                         (uint64_t)(device & 0xfff) << 39;
+                         (uint64_t)(device & 0xfff) << 39 | (uint64_t)(k.code_regs & 7) << 51;
     {
         std::lock_guard<std::mutex> lk(mu);
         auto it = known.find(key);

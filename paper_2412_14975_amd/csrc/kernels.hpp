@@ -37,6 +37,7 @@ struct KernelShape {
     int runs_per_lane;         // 1, 2, 4
     bool table_in_lds;
     int block_threads;         // 1024
+    int code_regs = 4;         // warm-up: registers of 64 byte codes (1 when the warm-up is <= 64 bytes)
 };
 
 // ---- plain reach: every (chunk, start) run to the chunk end or its death ----
