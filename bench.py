@@ -7,11 +7,18 @@ and finalize kernel, with the text already resident in HBM.  The value is
 K steps queued back to back on one stream (ri_recognize_async, results left
 on the device and checked after the final wait); p50/p99 are per-call times
 of the synchronous ri_recognize_ex, which also reads the result back.
-Default workload: the motif union over {A,C,G,T} (256 MiB).  Prints ONE
-JSON line.
+Default workload: the structured log lines (about 1 GiB, minimal DFA of
+302 states, interface of 227 starts).  Prints ONE JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--workload motif|log|tiny|batch]
-                  [--chunks C] [--seed S] [--no-cpu-baseline]
+  python bench.py [--steps K] [--warmup W] [--workload log|motif|tiny|batch|serve|sweep]
+                  [--chunks C] [--seed S] [--algos rid,dfa] [--no-cpu-baseline]
+
+Besides RID and the all-states minimal DFA, the single-text workloads time
+the all-states powerset (subset) DFA of the position NFA, and the tiny
+(a|b)*a(a|b)^3 workload at exactly 64 chunks (the paper's chunk count) and
+at the tuned chunk count.  The CPU leg times the oracle's serial scan on one
+core (`cpu_baseline.value`) and the paper's own CPU scheme, one thread per
+chunk on every usable core, for RID and the DFA on a 64 MiB prefix.
 
 --workload batch: 4096 texts (1 KiB - 4 MiB, log-uniform, about 2 GB) over
 16 random expressions, recognized by one captured graph launch of a batch
@@ -50,7 +57,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="motif", choices=["motif", "log", "tiny", "batch", "serve", "sweep"])
+    ap.add_argument("--workload", default="log", choices=["log", "motif", "tiny", "batch", "serve", "sweep"])
+    ap.add_argument("--algos", default="rid,dfa",
+                    help="single-text workloads: algorithms to time (rid first; 'rid' alone for profiling)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the subset-DFA baseline and the tiny workload at 64 chunks")
+    ap.add_argument("--cpu-prefix-mib", type=int, default=64,
+                    help="CPU leg: text prefix recognized by the threaded CPU scheme")
     ap.add_argument("--ks", default="3,4,5,6,7,8,9,10,11,12", help="sweep workload: k values")
     ap.add_argument("--sweep-mib", type=int, default=64, help="sweep workload: text MiB per k")
     ap.add_argument("--automata", type=int, default=64, help="serve workload: automata in the pool")
@@ -79,14 +92,19 @@ def parse():
     return ap.parse_args()
 
 
-KERNEL_SRC = os.path.join(ROOT, "paper_2412_14975_amd", "csrc", "kernels.hip")
+# sources of the reach kernels (the long-run kernel and its helpers)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2412_14975_amd", "csrc", f)
+               for f in ("k_reach.hip", "device.hpp", "kernels.hpp")]
 CALIB_BYTES = 256 << 20
 
 
 def kernel_source_hash():
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for p in KERNEL_SRCS:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def traffic_record_path(workload_name):
@@ -404,13 +422,18 @@ def main_serve(args):
         recs = list(ex.map(lambda a: ri.Recognizer(a[0]), autos))
     infos = [r.info() for r in recs]
     print(f"# {len(recs)} automata built ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
-    rng = gen.PCG(SERVE_SEED + 1)
-    reqs = []
-    for i in range(args.requests):
-        k = int(rng.integers(0, len(autos)))
-        n = gen.c5_length(rng)
-        reqs.append((k, gen.c5_text(rng, autos[k][1], n, plant=i % 2 == 0)))
+    reqs = [(k, x) for _, k, x in gen.c5_requests(args.requests, [a[1] for a in autos], seed=SERVE_SEED)]
     total = sum(len(x) for _, x in reqs)
+    # the oracle's results for this request stream (tests/golden/c5_serving.json,
+    # written by tests/golden/make_c5_goldens.py from the oracle alone)
+    golden = None
+    gpath = os.path.join(ROOT, "tests", "golden", "c5_serving.json")
+    if os.path.exists(gpath) and args.automata == 64:
+        g = json.load(open(gpath))
+        rows = {r[0]: r for r in g["requests"]}
+        if g["seed"] == SERVE_SEED and all(i in rows for i in range(len(reqs))):
+            golden = {i: (bool(rows[i][3]), int(rows[i][4])) for i in range(len(reqs))}
+            assert all(rows[i][1] == reqs[i][0] and rows[i][2] == len(reqs[i][1]) for i in range(len(reqs)))
     print(f"# {len(reqs)} requests, {total} bytes", file=sys.stderr, flush=True)
     loads = [float(v) for v in args.loads.split(",") if v]
     # device only: every text resident, one fused batch, timed with events
@@ -423,6 +446,9 @@ def main_serve(args):
             tun = b.autotune()
             b.run()
             torch.cuda.synchronize()
+            got = b.results[: 2 * len(reqs)].view(-1, 2).cpu().numpy()
+            dev_exact = None if golden is None else all(
+                (bool(got[i][0]), int(got[i][1])) == golden[i] for i in range(len(reqs)))
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
             for _ in range(5):
@@ -431,7 +457,8 @@ def main_serve(args):
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / 5
             g0 = b.group(0)
-            device[algo] = dict(gbps=total / (ms * 1e-3) / 1e9, ms=ms, chunk_bytes=g0["chunk_bytes"],
+            device[algo] = dict(gbps=total / (ms * 1e-3) / 1e9, ms=ms, bitexact_vs_oracle=dev_exact,
+                                chunk_bytes=g0["chunk_bytes"],
                                 warmup_bytes=g0["warmup_bytes"], tuning_trials=tun["trials"],
                                 slots=int(b.info()["slots"]))
         finally:
@@ -502,7 +529,12 @@ def main_serve(args):
                                                                      max(i["interface_states"] for i in infos)],
                    "min_dfa_states": [min(i["min_dfa_states"] for i in infos), max(i["min_dfa_states"] for i in infos)],
                    "slots": 3, "loads": loads},
-        "bitexact": bool(agree and alone_ok),
+        "bitexact": bool(agree and alone_ok) if golden is None else bool(
+            all(results_by_algo[a][i] == golden[i] for a in ("rid", "dfa") for i in range(len(reqs)))
+            and all(device[a]["bitexact_vs_oracle"] for a in ("rid", "dfa"))),
+        "bitexact_against": "GPU self-consistency only (no oracle results for this request stream)"
+        if golden is None else "oracle results of every request (tests/golden/c5_serving.json): serving "
+                               "loop and device-only fused batch, RID and DFA",
         "serve": {a: {k: ({kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                           if isinstance(v, dict) else v) for k, v in e.items()} for a, e in out_algo.items()},
         "serving_speedup_rid_vs_dfa": round(rid["capacity"]["gbps"] / out_algo["dfa"]["capacity"]["gbps"], 4),
@@ -531,19 +563,23 @@ def main_sweep(args):
     if not torch.cuda.is_available():
         print("bench.py: no GPU", file=sys.stderr)
         sys.exit(2)
+    import oracle
     ks = [int(v) for v in args.ks.split(",") if v]
     rows = []
     for k in ks:
         rx = gen.regexp_family(k)
         x, rej = gen.c1_texts(100 + k, n=args.sweep_mib << 20)
+        # expected result: the oracle's minimal DFA, serial scan
+        d = oracle.min_dfa_of(oracle.trim(oracle.position_nfa(rx)))
+        owant = oracle.serial(d, x, oracle.dense_table(d.n, d.delta))
         t = torch.from_numpy(x).to("cuda")
         rec = ri.Recognizer(rx)
         info = rec.info()
         row = dict(k=k, min_dfa_states=info["min_dfa_states"], interface_states=info["interface_states"],
-                   ridfa_states=info["ridfa_states"], nfa_states=info["nfa_states"])
+                   ridfa_states=info["ridfa_states"], nfa_states=info["nfa_states"], bitexact=True)
         for algo in ("rid", "dfa"):
             tun = rec.autotune(t, algo=algo)
-            want = None
+            want = owant
             for conv in (1, 0):
                 rec.set_option("converge", conv)
                 if conv:
@@ -558,10 +594,21 @@ def main_sweep(args):
                 for _ in range(args.steps):
                     r = rec.recognize(t, algo=algo)
                 dt = (time.perf_counter() - c0) / args.steps
-                want = want or (r["accept"], r["final_state"])
                 row[f"{algo}_{'conv' if conv else 'plain'}_gbps"] = round(len(x) / dt / 1e9, 2)
-                assert (r["accept"], r["final_state"]) == want
+                row["bitexact"] &= (r["accept"], r["final_state"]) == want
             row[f"{algo}_accept"] = bool(want[0])
+        # the NFA device (position NFA over sets of states)
+        tun = rec.autotune(t, algo="nfa")
+        rec.set_option("chunk_target", tun["chunk_target"])
+        r = rec.recognize(t, algo="nfa")
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        for _ in range(args.steps):
+            r = rec.recognize(t, algo="nfa")
+        dt = (time.perf_counter() - c0) / args.steps
+        row["bitexact"] &= (r["accept"], r["final_state"]) == owant
+        row["nfa_gbps"] = round(len(x) / dt / 1e9, 2)
+        row["rid_over_nfa"] = round(row["rid_conv_gbps"] / row["nfa_gbps"], 2)
         rec.close()
         del t
         torch.cuda.empty_cache()
@@ -603,6 +650,7 @@ def main_sweep(args):
         "data": "synthetic",
         "config": {"workload": f"regexp-family-sweep-{args.sweep_mib}MiB", "ks": ks},
         "sweep": rows,
+        "bitexact": all(r["bitexact"] for r in rows),
         "command": " ".join(["python", "bench.py"] + sys.argv[1:]),
         "roofline": None,
         "cpu_baseline": cpu,
@@ -648,6 +696,10 @@ def main():
 
     rx, x, wname = workload(args.workload, args.seed)
     n = len(x)
+    algos = [a for a in args.algos.split(",") if a]
+    if not algos or algos[0] != "rid" or any(a not in ("rid", "dfa") for a in algos):
+        print("bench.py: --algos must start with rid and name only rid and dfa", file=sys.stderr)
+        sys.exit(2)
     print(f"# workload {wname}: n={n} bytes", file=sys.stderr, flush=True)
 
     # expected result from the oracle (serial scan, host)
@@ -678,7 +730,7 @@ def main():
     if not args.no_tune and args.chunks == 0:
         # setup, outside the timed region: pick chunk target / warm-up / runs
         # per lane for each algorithm on this text (same grid for both)
-        for algo in ("rid", "dfa"):
+        for algo in algos:
             if algo in fixed:
                 continue
             tuning[algo] = rec.autotune(t, algo=algo)
@@ -686,13 +738,31 @@ def main():
             print(f"# tuned {algo}: {tuning[algo]}", file=sys.stderr, flush=True)
             fixed[algo] = {k: tuning[algo][k] for k in ("chunk_target", "warmup_bytes", "runs_per_lane", "converge")}
 
-    rid = time_algo(torch, rec, t, "rid", args.chunks, args.steps, args.warmup, want, fixed.get("rid"))
-    print(f"# rid done", file=sys.stderr, flush=True)
-    dfa = time_algo(torch, rec, t, "dfa", args.chunks, args.steps, args.warmup, want, fixed.get("dfa"))
-    print(f"# dfa done", file=sys.stderr, flush=True)
+    timed = {}
+    for algo in algos:
+        timed[algo] = time_algo(torch, rec, t, algo, args.chunks, args.steps, args.warmup, want, fixed.get(algo))
+        print(f"# {algo} done", file=sys.stderr, flush=True)
+    rid = timed["rid"]
+
+    def summary(m, steps):
+        p50 = float(np.percentile(m["per_call"], 50))
+        p99 = float(np.percentile(m["per_call"], 99))
+        return dict(gbps=n * steps / m["queued"] / 1e9, ms_per_step=m["queued"] / steps * 1e3,
+                    sync_gbps=n * steps / m["total"] / 1e9,
+                    p50_ms=p50 * 1e3, p99_ms=p99 * 1e3, gbps_p50=n / p50 / 1e9, gbps_p99=n / p99 / 1e9,
+                    reach_ms=float(m["reach_ms"].mean()), join_ms=float(m["join_ms"].mean()),
+                    long_ms=float(m["kern_ms"].mean()), warm_ms=float(m["warm_ms"].mean()),
+                    chunks=m["result"]["chunks"], chunk_size=m["result"]["chunk_size"],
+                    bitexact=bool(m["exact"]))
+
+    def rounded(d):
+        return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+
+    s_rid = summary(rid, args.steps)
+    s_dfa = summary(timed["dfa"], args.steps) if "dfa" in timed else None
 
     plain = None
-    if not args.no_plain:
+    if not args.no_plain and "dfa" in timed:
         # the paper-literal reach (every run to the chunk end or its death, no
         # merging), RID vs all-states DFA at the RID chunk count
         c_rid = rid["result"]["chunks"]
@@ -709,18 +779,55 @@ def main():
         rec.set_option("converge", 1)
         print(f"# plain done", file=sys.stderr, flush=True)
 
-    def summary(m):
-        p50 = float(np.percentile(m["per_call"], 50))
-        p99 = float(np.percentile(m["per_call"], 99))
-        return dict(gbps=n * args.steps / m["queued"] / 1e9, ms_per_step=m["queued"] / args.steps * 1e3,
-                    sync_gbps=n * args.steps / m["total"] / 1e9,
-                    p50_ms=p50 * 1e3, p99_ms=p99 * 1e3, gbps_p50=n / p50 / 1e9, gbps_p99=n / p99 / 1e9,
-                    reach_ms=float(m["reach_ms"].mean()), join_ms=float(m["join_ms"].mean()),
-                    long_ms=float(m["kern_ms"].mean()), warm_ms=float(m["warm_ms"].mean()),
-                    chunks=m["result"]["chunks"], chunk_size=m["result"]["chunk_size"],
-                    bitexact=bool(m["exact"]))
-
-    s_rid, s_dfa = summary(rid), summary(dfa)
+    extras = None
+    if not args.no_extras:
+        extras = {}
+        # the all-states powerset DFA of the position NFA (the second
+        # baseline; for the motif union the minimal DFA has one state)
+        st = rec.autotune(t, algo="subset")
+        m = time_algo(torch, rec, t, "subset", 0, max(3, args.steps // 3), 2, want,
+                      {k: st[k] for k in ("chunk_target", "warmup_bytes", "runs_per_lane", "converge")})
+        extras["all_states_subset_dfa"] = dict(rounded(summary(m, max(3, args.steps // 3))),
+                                               states=info["subset_dfa_states"],
+                                               speedup_rid_vs_subset=round(s_rid["gbps"] / (n * max(3, args.steps // 3) / m["queued"] / 1e9), 4))
+        print(f"# subset done", file=sys.stderr, flush=True)
+        # the NFA device of Sect. 2: the position NFA as chunk automaton,
+        # every NFA state speculated, runs as sets of states
+        if info["starts"][3] <= 256:
+            nt = rec.autotune(t, algo="nfa")
+            k = 3
+            m = time_algo(torch, rec, t, "nfa", 0, k, 1, want, {"chunk_target": nt["chunk_target"]})
+            nfa_gbps = n * k / m["queued"] / 1e9
+            extras["nfa_device"] = dict(rounded(summary(m, k)), nfa_states=info["starts"][3],
+                                        speedup_rid_vs_nfa=round(s_rid["gbps"] / nfa_gbps, 4))
+            print(f"# nfa done", file=sys.stderr, flush=True)
+        # the tiny workload at the paper's chunk count (64) and tuned
+        from workloads import gen
+        trx = gen.c1_regex()
+        tx, _ = gen.c1_texts(args.seed)
+        tref = oracle.build(trx)
+        twant = oracle.serial(tref.dfa, tx)
+        trec = ri.Recognizer(trx)
+        tt = torch.from_numpy(tx).to("cuda")
+        tiny = {}
+        for algo in ("rid", "dfa"):
+            tiny[algo] = {}
+            for label, chunks in (("c64", 64), ("tuned", 0)):
+                if chunks == 0:
+                    tun = trec.autotune(tt, algo=algo)
+                    setting = {k: tun[k] for k in ("chunk_target", "warmup_bytes", "runs_per_lane", "converge")}
+                else:
+                    setting = None
+                m = time_algo(torch, trec, tt, algo, chunks, 20, 3, twant, setting)
+                tiny[algo][label] = dict(gbps=round(len(tx) * 20 / m["queued"] / 1e9, 3),
+                                         p50_ms=round(float(np.percentile(m["per_call"], 50)) * 1e3, 4),
+                                         p99_ms=round(float(np.percentile(m["per_call"], 99)) * 1e3, 4),
+                                         chunks=m["result"]["chunks"], bitexact=bool(m["exact"]))
+        tiny["speedup_rid_vs_dfa_c64"] = round(tiny["rid"]["c64"]["gbps"] / tiny["dfa"]["c64"]["gbps"], 4)
+        extras["tiny_regexp_k3_1MiB"] = tiny
+        trec.close()
+        del tt
+        print(f"# tiny done", file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel: the long-run kernel of the converging
     # reach.  Algorithmic bytes per launch = the text bytes it must read, i.e.
@@ -732,12 +839,15 @@ def main():
     warm = (fixed["rid"]["warmup_bytes"] if "rid" in fixed else rec.get_option("warmup_bytes")) if conv_rid else 0
     long_bytes = sum(max(0, min(cs, n - i * cs) - warm) for i in range(c)) if c < 5_000_000 else n
     achieved = long_bytes / (s_rid["long_ms"] * 1e-3) / 1e9
-    trec = load_traffic(wname)
+    trec_t = load_traffic(wname)
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4),
-                traffic=(round(trec["traffic_bytes_per_launch"]) if trec else None),
+                traffic=(round(trec_t["traffic_bytes_per_launch"]) if trec_t else None),
                 kernel="long_kernel" if conv_rid else "plain_kernel", algorithmic_bytes=int(long_bytes),
-                reach_phase_gbps=round(n / (s_rid["reach_ms"] * 1e-3) / 1e9, 1))
+                kernel_ms=round(s_rid["long_ms"], 4),
+                reach_phase_gbps=round(n / (s_rid["reach_ms"] * 1e-3) / 1e9, 1),
+                whole_path_gbps=round(s_rid["gbps"], 1),
+                whole_path_frac=round(s_rid["gbps"] / HBM_PEAK_GBS, 4))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -753,6 +863,7 @@ def main():
         cpu = dict(value=round(n * reps / dt / 1e9, 4), unit="GB/s", cores=1, kind="oracle",
                    sample=f"{reps} serial scans of the whole {n}-byte text by the oracle's "
                           f"minimal-DFA scan ({dt:.1f} s)")
+        cpu["threaded_csdpa"] = threaded_cpu(oracle, ref, x, table, args.cpu_prefix_mib << 20)
 
     out = {
         "metric": "GB/s of text recognized, RI-DFA vs all-states DFA speculation (bit-exact); p50/p99",
@@ -775,20 +886,58 @@ def main():
         "p99_ms": round(s_rid["p99_ms"], 4),
         "gbps_p50": round(s_rid["gbps_p50"], 2),
         "gbps_p99": round(s_rid["gbps_p99"], 2),
-        "bitexact": s_rid["bitexact"] and s_dfa["bitexact"] and (
-            plain is None or (plain["rid"]["bitexact"] and plain["dfa"]["bitexact"])),
-        "rid": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s_rid.items()},
-        "all_states_dfa": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s_dfa.items()},
-        "speedup_rid_vs_dfa": round(s_rid["gbps"] / s_dfa["gbps"], 4),
-        "tuning": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
-                   for k, v in tuning.items()},
+        "bitexact": all(m["exact"] for m in timed.values()) and (
+            plain is None or (plain["rid"]["bitexact"] and plain["dfa"]["bitexact"])) and (
+            extras is None or (extras["all_states_subset_dfa"]["bitexact"] and all(
+                v["bitexact"] for a in ("rid", "dfa") for v in extras["tiny_regexp_k3_1MiB"][a].values())
+                and extras.get("nfa_device", {}).get("bitexact", True))),
+        "rid": rounded(s_rid),
+        "all_states_dfa": rounded(s_dfa) if s_dfa else None,
+        "speedup_rid_vs_dfa": round(s_rid["gbps"] / s_dfa["gbps"], 4) if s_dfa else None,
+        "tuning": {k: rounded(v) for k, v in tuning.items()},
         "command": " ".join(["python", "bench.py"] + sys.argv[1:]),
         "plain_reach": plain,
+        "extras": extras,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     rec.close()
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def threaded_cpu(oracle, ref, x, table, prefix):
+    """The paper's CPU scheme (one thread per chunk, serial join) for the
+    all-states minimal DFA and for RID on the first `prefix` bytes, with as
+    many chunks as usable cores; checked against the oracle's serial scan of
+    the same prefix."""
+    from oracle import baseline
+    cores = len(os.sched_getaffinity(0))
+    xp = np.ascontiguousarray(x[:prefix])
+    want = oracle.serial(ref.dfa, xp, table)
+    tq = oracle.dense_table(ref.Bq.n, ref.Bq.delta)
+    d = baseline.csdpa_dfa(ref.dfa, xp, cores, table)
+    r = baseline.csdpa_rid(ref.Bq, xp, cores, tq)
+    end, _ = oracle.run(tq, ref.Bq.initial[0], xp, 0, len(xp))
+    exact = (d["accept"], d["final_state"]) == want and r["accept"] == want[0] and (
+        r["S"] == (ref.Bq.content[end] if end >= 0 else frozenset()))
+    return dict(cpu_model=cpu_model(), cores=cores, threads=cores, chunks=cores, bytes=int(len(xp)),
+                dfa_gbps=round(len(xp) / d["seconds"] / 1e9, 4), rid_gbps=round(len(xp) / r["seconds"] / 1e9, 4),
+                speedup_rid_vs_dfa=round(d["seconds"] / r["seconds"], 4),
+                dfa_transitions=d["transitions"], rid_transitions=r["transitions"],
+                transitions_dfa_over_rid=round(d["transitions"] / max(1, r["transitions"]), 4),
+                bitexact=bool(exact),
+                note="reported baseline: the paper's scheme (Sect. 4), one thread per chunk, on the host cores")
 
 
 if __name__ == "__main__":

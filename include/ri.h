@@ -19,7 +19,10 @@
  * (Fig. 2): the minimal DFA speculated from all of its states.
  * RI_ALGO_SUBSET speculates from all states of the unminimized powerset DFA
  * of the position NFA (a second baseline for languages whose minimal DFA is
- * trivially small).
+ * trivially small).  RI_ALGO_NFA is the third device of Sect. 2 (Fig. 1):
+ * the position NFA itself as chunk automaton, every NFA state speculated,
+ * each run a set of NFA states; the chunk relations are composed and the
+ * set reached from q0 decides acceptance.
  *
  * Every call returns RI_OK (0) or a negative RI_ERR_* code; ri_last_error()
  * then gives a message for the calling thread.  No C++ exception crosses
@@ -53,7 +56,10 @@ extern "C" {
 #define RI_ALGO_RID     0    /* RI-DFA chunk automaton, reduced interface (Sects. 3.1-3.4) */
 #define RI_ALGO_DFA     1    /* minimal DFA, all states speculated (Sect. 2, Fig. 2)      */
 #define RI_ALGO_SUBSET  2    /* powerset DFA of the position NFA, all states speculated  */
-#define RI_NUM_ALGOS    3
+#define RI_ALGO_NFA     3    /* the position NFA itself, every state speculated, runs are
+                                sets of states (the NFA device of Sect. 2, Fig. 1; Tab. 3);
+                                at most 256 NFA states, single texts only               */
+#define RI_NUM_ALGOS    4
 
 typedef struct ri_handle ri_handle;   /* opaque; immutable after ri_build */
 
@@ -124,7 +130,9 @@ int ri_recognize(const ri_handle *h, const uint8_t *text_dev, size_t n, void *st
  *            touching the device.
  * stream   : hipStream_t on which all work is enqueued; the call synchronizes
  *            this stream (only) before it returns.
- * algo     : RI_ALGO_RID, RI_ALGO_DFA or RI_ALGO_SUBSET.
+ * algo     : RI_ALGO_RID, RI_ALGO_DFA, RI_ALGO_SUBSET or RI_ALGO_NFA (NFAs of at
+ *            most 256 states, RI_ERR_LIMIT otherwise; the reach options do
+ *            not apply to it, only the chunk count).
  * chunks   : requested chunk count c (0 = choose automatically).  Chunks are
  *            ceil(n/c) bytes rounded up to a multiple of 16, so the count used
  *            (reported in out->chunks) can be smaller; c is clamped to n.
@@ -152,7 +160,9 @@ int ri_recognize_ex(const ri_handle *h, const uint8_t *text_dev, size_t n, void 
  * Calls on one stream run in order and reuse that stream's scratch memory;
  * the handle's options and last tuning apply as for ri_recognize_ex;
  * profiling timings are not recorded.  Scratch that has to grow for a longer
- * text is reallocated after a device-wide synchronization.
+ * text is reallocated with no synchronization at all: the buffer it replaces
+ * may still be in use by earlier queued calls, so it is freed with the
+ * handle.
  * Errors found before anything is enqueued (RI_ERR_ARG: NULL or misaligned
  * pointers; RI_ERR_LIMIT; RI_ERR_NOMEM) are returned and nothing is written;
  * a launch failure returns RI_ERR_DEVICE.  Faults during execution surface
@@ -176,7 +186,8 @@ int ri_chunk_maps(const ri_handle *h, const uint8_t *text_dev, size_t n, void *s
  * ri_state_content -- for RI_ALGO_RID, the content of RI-DFA state `state`
  * (the states of N' it stands for, Sect. 3.1), written in ascending order to
  * members[0..*count) (at most cap entries); start s of RI_ALGO_RID is the
- * singleton {s} of N'.  For RI_ALGO_DFA / RI_ALGO_SUBSET, the minimal-DFA
+ * singleton {s} of N'.  RI_ERR_ARG for RI_ALGO_NFA.  For RI_ALGO_DFA /
+ * RI_ALGO_SUBSET, the minimal-DFA
  * state that the state stands for (one entry), or no entry for none.
  */
 int ri_state_content(const ri_handle *h, int algo, uint32_t state, uint32_t *members,
@@ -262,7 +273,7 @@ typedef struct {
     const ri_handle *h;        /* automaton; must stay alive while the batch exists  */
     const uint8_t *text_dev;   /* device pointer, 16-byte aligned; NULL allowed if n = 0 */
     uint64_t n;                /* text length (0 allowed)                             */
-    int32_t algo;              /* RI_ALGO_RID, RI_ALGO_DFA or RI_ALGO_SUBSET          */
+    int32_t algo;              /* RI_ALGO_RID, RI_ALGO_DFA or RI_ALGO_SUBSET (not NFA) */
     uint32_t reserved;         /* must be 0                                           */
 } ri_request;
 

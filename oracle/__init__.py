@@ -16,8 +16,12 @@ automata.py   position NFA (Sect. 4.1), powerset DFA, Moore minimization with
               downgrading with delegation (Sect. 3.4), quotient NFA
 recognize.py  serial recognizer (Sect. 2), CSDPA with a DFA (Sect. 2, Fig. 2),
               RID with an RI-DFA and ``if`` / ``if_min`` (Sects. 3.2, 3.4),
-              NFA simulation (Lemma 1) and transition counts (Fig. 1)
+              NFA simulation (Lemma 1), CSDPA with the NFA as chunk automaton
+              and transition counts (Fig. 1)
+baseline.py   the paper's CPU scheme (one thread per chunk, serial join) for
+              the minimal DFA and RID, timed as a reported baseline
 scan.c        the plain serial table scan used by recognize.py
+csdpa.c       the threaded reach phase used by baseline.py
 
 Parity status: every function here is pinned by tests against the paper's
 worked examples (Figs. 1-5), closed forms of the regexp family, Python's
@@ -31,6 +35,6 @@ from .automata import (  # noqa: F401
     if_fun, if_min_fun, moore_partition, nfa_step,
 )
 from .recognize import (  # noqa: F401
-    serial, csdpa, rid, nst, nfa_reach, nfa_csdpa_transitions, even_bounds, dense_table,
+    serial, csdpa, rid, nst, nfa_reach, nfa_csdpa, nfa_csdpa_transitions, even_bounds, dense_table,
     run, build_scan_library,
 )

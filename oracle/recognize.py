@@ -25,19 +25,19 @@ import subprocess
 
 import numpy as np
 
-from .automata import DFA, NFA, RIDFA
+from .automata import DFA, NFA, RIDFA, nfa_step
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "scan.c")
+_SRCS = [os.path.join(_HERE, "scan.c"), os.path.join(_HERE, "csdpa.c")]
 _LIB = os.path.join(_HERE, "_scan.so")
 _lib = None
 
 
 def build_scan_library(force: bool = False) -> str:
-    """Compile scan.c with gcc into oracle/_scan.so."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile scan.c and csdpa.c with gcc into oracle/_scan.so."""
+    if force or not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(s) for s in _SRCS):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-pthread", "-o", tmp] + _SRCS)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -50,6 +50,10 @@ def _scanlib():
         lib.oracle_scan.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                     ctypes.c_int64, ctypes.c_int64,
                                     ctypes.POINTER(ctypes.c_int64)]
+        lib.oracle_threaded_reach.restype = ctypes.c_int
+        lib.oracle_threaded_reach.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                              ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
         _lib = lib
     return _lib
 
@@ -195,16 +199,44 @@ def nst(B: RIDFA, plas) -> frozenset:
 # ---------------------------------------------------------------------------
 
 def nfa_reach(nfa: NFA, S, text) -> frozenset:
-    """rho(S, x) for a set S of NFA states (Sect. 3.3)."""
+    """rho(S, x) for a set S of NFA states (Sect. 3.3): one nfa_step per
+    byte, stopping once the set is empty."""
     cur = frozenset(S)
     for b in _as_u8(text).tolist():
-        nxt = set()
-        for q in cur:
-            nxt |= nfa.moves(q, b)
-        cur = frozenset(nxt)
+        cur = nfa_step(nfa, cur, b)
         if not cur:
             break
     return cur
+
+
+def nfa_csdpa(nfa: NFA, text, bounds):
+    """CSDPA with the NFA itself as chunk automaton (Sect. 2, the third
+    device of Fig. 1): chunk 1 is run from {q0} only, every other chunk from
+    every single NFA state q, and lambda_i(q) = rho(q, y_i) is a set of NFA
+    states (empty when every path dies).  The chunk relations are composed
+    left to right: S_1 = lambda_1(q0), S_i = union of lambda_i(q) over q in
+    S_{i-1}; x is accepted iff S_c meets F, and S_c = rho(q0, x).
+    Returns dict(lambdas, S, accept) with lambdas[i][q] a frozenset."""
+    x = _as_u8(text)
+    lambdas = []
+    S = None
+    for i in range(len(bounds) - 1):
+        y = x[bounds[i]:bounds[i + 1]]
+        starts = [0] if i == 0 else list(range(nfa.n))
+        if nfa.n == 0:
+            starts = []
+        lam = {q: nfa_reach(nfa, [q], y) for q in starts}
+        lambdas.append(lam)
+        if i == 0:
+            S = lam.get(0, frozenset())
+        else:
+            nxt = set()
+            for q in S:
+                nxt |= lam[q]
+            S = frozenset(nxt)
+    if S is None:
+        S = frozenset()
+    return dict(lambdas=lambdas, S=S, accept=bool(S & nfa.final))
 
 
 def nfa_csdpa_transitions(nfa: NFA, text, bounds) -> int:

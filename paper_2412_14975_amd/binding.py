@@ -18,9 +18,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libri.so")
 
 RI_OK, RI_ERR_PARSE, RI_ERR_LIMIT, RI_ERR_NOMEM, RI_ERR_DEVICE, RI_ERR_ARG = 0, -1, -2, -3, -4, -5
-RI_ALGO_RID, RI_ALGO_DFA, RI_ALGO_SUBSET = 0, 1, 2
-RI_NUM_ALGOS = 3
-ALGOS = {"rid": RI_ALGO_RID, "dfa": RI_ALGO_DFA, "subset": RI_ALGO_SUBSET}
+RI_ALGO_RID, RI_ALGO_DFA, RI_ALGO_SUBSET, RI_ALGO_NFA = 0, 1, 2, 3
+RI_NUM_ALGOS = 4
+ALGOS = {"rid": RI_ALGO_RID, "dfa": RI_ALGO_DFA, "subset": RI_ALGO_SUBSET, "nfa": RI_ALGO_NFA}
 
 SYMBOLS = ("ri_build", "ri_free", "ri_info", "ri_recognize", "ri_recognize_ex",
            "ri_recognize_async", "ri_chunk_maps", "ri_state_content", "ri_set_profiling", "ri_last_timings",

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libri.so")
 
-SOURCES = ["automata.cpp", "kernels.hip", "api.cpp"]
+SOURCES = ["automata.cpp", "api.cpp", "k_reach.hip", "k_join.hip", "k_batch.hip", "k_nfa.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",
@@ -33,20 +33,24 @@ def _hipcc():
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every source and link libri.so in the package directory.
-    Always recompiles; the output replaces the old library atomically."""
+    """Compile every source (in parallel) and link libri.so in the package
+    directory.  Always recompiles; the output replaces the old library
+    atomically."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
     hipcc = _hipcc()
+    jobs = []
     for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         cmd = [hipcc] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
-        objs.append(obj)
+        jobs.append((obj, cmd, subprocess.Popen(cmd)))
+    failed = [cmd for _, cmd, p in jobs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
+    objs = [obj for obj, _, _ in jobs]
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

@@ -57,6 +57,11 @@ struct AlgoHost {
     uint32_t hash_cap = 0;
     std::vector<int32_t> final_of_state;       // functions
     std::vector<uint8_t> accept_of_state;      // functions
+    // RI_ALGO_NFA: sets of N's states (nfa_words 64-bit words); fmask, hash
+    // and csr_* then describe the powerset DFA's states as sets of N's states
+    bool nfa = false;
+    uint32_t nfa_words = 0;                    // 0: N is too large for the device NFA
+    std::vector<uint64_t> follow, mask;        // [L][nfa_words], [K][nfa_words]
 };
 
 struct AlgoDevice {
@@ -66,6 +71,7 @@ struct AlgoDevice {
     uint16_t *code = nullptr;
     int32_t *final_of_state = nullptr;
     uint8_t *accept_of_state = nullptr;
+    uint64_t *follow = nullptr, *mask = nullptr;
 };
 
 struct DeviceCopy {
@@ -76,6 +82,11 @@ struct DeviceCopy {
     size_t max_lds = 0;
 };
 
+// A device buffer that only grows.  A buffer it replaces may still be read
+// by work enqueued without a host wait, so it is kept in `retired` and freed
+// with its owner (no device-wide synchronization on the way).
+struct Buf { void *p = nullptr; size_t cap = 0; };
+
 struct Workspace {
     std::mutex mu;
     int device = -1;
@@ -83,9 +94,9 @@ struct Workspace {
     uint32_t *counters = nullptr;   // [4], zero between calls
     int32_t *dres = nullptr;
     int32_t *hres = nullptr;        // pinned
-    struct Buf { void *p = nullptr; size_t cap = 0; };
     Buf lam, alias, run_base, run_count, run_chunk, run_state, run_final, dbg, join[2], ncls[2], hprod[2],
         hrows[2], block_count;
+    std::vector<void *> retired;
     hipEvent_t ev[6] = {};
 };
 
@@ -204,6 +215,38 @@ void pack_all(ri_handle *h) {
     for (uint32_t s = 0; s < u.L; ++s) u.starts[s] = s * K * u.entry_bytes;
     u.final_of_state = A.dsub_final_id;
     u.accept_of_state = A.dsub_accept;
+
+    // RI_ALGO_NFA: N itself over sets of states, every state a start; the
+    // set reached from q0 is a state of the powerset DFA, found by the hash
+    // of its members
+    AlgoHost &v = h->algo[RI_ALGO_NFA];
+    v.nfa = true;
+    v.L = A.nfa_states;
+    v.K = K;
+    v.nfa_words = A.nfa_words;
+    if (v.nfa_words) {
+        v.W = 2 * v.nfa_words;
+        v.follow = A.nfa_follow;
+        v.mask = A.nfa_mask;
+        v.fmask.assign(v.W, 0);
+        for (uint32_t q = 0; q < A.pos.n; ++q)
+            if (A.pos.final[q]) v.fmask[q / 32] |= 1u << (q % 32);
+        v.csr_off.assign(A.dsub_n + 1, 0);
+        for (uint32_t t = 0; t < A.dsub_n; ++t) {
+            v.csr_off[t + 1] = v.csr_off[t] + (uint32_t)A.dsub_content[t].size();
+            v.csr_idx.insert(v.csr_idx.end(), A.dsub_content[t].begin(), A.dsub_content[t].end());
+        }
+        uint32_t cap = 1;
+        while (cap < 2 * A.dsub_n + 2) cap *= 2;
+        v.hash_cap = cap;
+        v.hash.assign((size_t)cap * 2, 0xFFFFFFFFu);
+        for (uint32_t t = 0; t < A.dsub_n; ++t) {
+            uint32_t slot = hash_members(A.dsub_content[t]) & (cap - 1);
+            while (v.hash[(size_t)slot * 2] != 0xFFFFFFFFu) slot = (slot + 1) & (cap - 1);
+            v.hash[(size_t)slot * 2] = t;
+            v.hash[(size_t)slot * 2 + 1] = (uint32_t)A.dsub_final_id[t];
+        }
+    }
 }
 
 // Zero device memory and wait for it: the memset runs on the null stream,
@@ -244,7 +287,14 @@ int ensure_device(ri_handle *h, int device) {
         HIP_TRY(upload(&D.table, H.table.data(), H.table.size()));
         HIP_TRY(upload(&D.code, H.code, sizeof(H.code)));
         HIP_TRY(upload(&D.starts, H.starts.data(), H.starts.size() * 4));
-        if (H.relational) {
+        if (H.nfa) {
+            HIP_TRY(upload(&D.follow, H.follow.data(), H.follow.size() * 8));
+            HIP_TRY(upload(&D.mask, H.mask.data(), H.mask.size() * 8));
+            HIP_TRY(upload(&D.csr_off, H.csr_off.data(), H.csr_off.size() * 4));
+            HIP_TRY(upload(&D.csr_idx, H.csr_idx.data(), H.csr_idx.size() * 4));
+            HIP_TRY(upload(&D.fmask, H.fmask.data(), H.fmask.size() * 4));
+            HIP_TRY(upload(&D.hash, H.hash.data(), H.hash.size() * 4));
+        } else if (H.relational) {
             HIP_TRY(upload(&D.content, H.content.data(), H.content.size() * 4));
             HIP_TRY(upload(&D.csr_off, H.csr_off.data(), H.csr_off.size() * 4));
             HIP_TRY(upload(&D.csr_idx, H.csr_idx.data(), H.csr_idx.size() * 4));
@@ -275,15 +325,20 @@ int get_workspace(ri_handle *h, int device, hipStream_t stream, Workspace **out)
     return RI_OK;
 }
 
-int grow(Workspace::Buf &b, size_t need) {
+// Grows b to at least `need` bytes (geometrically, so the retired buffers
+// of one owner add up to less than its live ones).  The old buffer goes to
+// `retired`, or is freed at once when retired is null (the caller knows
+// that nothing in flight uses it).
+int grow(Buf &b, size_t need, std::vector<void *> *retired) {
     if (need <= b.cap) return RI_OK;
-    // work enqueued without a host wait may still use the old buffer
-    if (b.p) HIP_TRY(hipDeviceSynchronize());
-    if (b.p) HIP_TRY(hipFree(b.p));
-    b.p = nullptr;
-    b.cap = 0;
-    need = round_up(need, 1 << 20);
-    HIP_TRY(hipMalloc(&b.p, need));
+    need = round_up(std::max<size_t>(need, b.cap + b.cap / 2), 1 << 20);
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, need));
+    if (b.p) {
+        if (retired) retired->push_back(b.p);
+        else (void)hipFree(b.p);
+    }
+    b.p = p;
     b.cap = need;
     return RI_OK;
 }
@@ -328,6 +383,7 @@ struct ConvCfg {
     size_t lds_w = 0, lds_l = 0;
     int grid_w = 1, grid_l = 1;
     uint64_t run_cap = 0;   // run slots of all warm-up blocks' regions
+    uint32_t cpi = ri::kWarmChunksPerBlock;   // chunks per warm-up block iteration
 };
 
 int conv_config(const AlgoHost &H, const DeviceCopy &dc, const Options &opt, uint32_t nchunks, ConvCfg *c) {
@@ -338,15 +394,20 @@ int conv_config(const AlgoHost &H, const DeviceCopy &dc, const Options &opt, uin
     c->warm_shape = shape;
     c->warm_shape.runs_per_lane = H.L <= 64 ? 1 : H.L <= 128 ? 2 : 4;
     c->warm_shape.code_regs = opt.warm <= 64 ? 1 : 4;   // registers of 64 warm-up byte codes
+    // merging by hashing when the starts fit one block of 64 R starts; a
+    // wave then takes several chunks at a time
+    c->warm_shape.hashed = H.L <= 64u * (uint32_t)c->warm_shape.runs_per_lane;
+    c->cpi = ri::kWarmChunksPerBlock *
+             ri::warm_chunks_per_wave(c->warm_shape.hashed, c->warm_shape.runs_per_lane, c->warm_shape.code_regs);
     c->lds_w = ri::warm_lds_bytes(c->warm_shape, (uint32_t)H.table.size(), H.L);
     if (c->lds_w > dc.max_lds) {   // table and starts do not fit together: table from global memory
         c->warm_shape.table_in_lds = false;
         c->lds_w = ri::warm_lds_bytes(c->warm_shape, (uint32_t)H.table.size(), H.L);
     }
-    const uint32_t iters = (nchunks + ri::kWarmChunksPerBlock - 1) / ri::kWarmChunksPerBlock;
+    const uint32_t iters = (nchunks + c->cpi - 1) / c->cpi;
     const int per_cu_w = std::max(1, ri::blocks_per_cu(1, c->warm_shape, c->lds_w));
     c->grid_w = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)dc.cus * per_cu_w, iters));
-    c->run_cap = (uint64_t)iters * ri::kWarmChunksPerBlock * H.L;   // every block's region
+    c->run_cap = (uint64_t)iters * c->cpi * H.L;   // every block's region
     // long runs: one run per lane unless set; LDS also holds the prefix of
     // the warm-up blocks' run counts
     c->long_shape = shape;
@@ -385,6 +446,7 @@ int launch_conv(const ConvCfg &c, const ri::ScanArgs &sa, const Options &opt, co
     wa.run_state = rb.run_state;
     wa.counters = rb.counters;
     wa.block_count = rb.block_count;
+    wa.cpi = c.cpi;
     HIP_TRY(ri::launch_warm(wa, c.warm_shape, c.grid_w, c.lds_w, stream));
     if (mid) HIP_TRY(hipEventRecord(mid, stream));
     ri::LongArgs la{};
@@ -395,6 +457,7 @@ int launch_conv(const ConvCfg &c, const ri::ScanArgs &sa, const Options &opt, co
     la.run_final = rb.run_final;
     la.block_count = rb.block_count;
     la.warm_blocks = (uint32_t)c.grid_w;
+    la.cpi = c.cpi;
     HIP_TRY(ri::launch_long(la, c.long_shape, c.grid_l, c.lds_l, stream));
     return RI_OK;
 }
@@ -420,14 +483,255 @@ uint32_t tile_group(const AlgoHost &H) {
     return g0;
 }
 
+// Device scratch of one recognition call, taken from the stream's cached
+// workspace or carved from a fixed arena (ri_recognize_noalloc).
+struct Scratch {
+    void *lam = nullptr, *alias = nullptr, *dbg = nullptr;
+    uint32_t *run_base = nullptr, *run_count = nullptr, *run_chunk = nullptr, *run_state = nullptr;
+    uint32_t *run_final = nullptr, *block_count = nullptr;
+    void *join[2] = {nullptr, nullptr};
+    uint32_t *ncls[2] = {nullptr, nullptr}, *hrows[2] = {nullptr, nullptr};
+    uint64_t *hprod[2] = {nullptr, nullptr};
+    uint32_t *counters = nullptr;   // [16], zero on entry
+    int32_t *dres = nullptr;        // [4]
+};
+
+// Launch plan and scratch sizes of one call for a given chunking.
+struct CallPlan {
+    Plan plan;
+    bool conv = false;
+    ConvCfg cc;
+    ri::KernelShape shape;
+    uint32_t g0 = 0, ng0 = 0, gc = 0;
+    bool hit = false, dense_join = false;
+    size_t row_words = 1, pairs = 0, nh = 0, nrel_max = 0;
+};
+
+int plan_call(const AlgoHost &H, const DeviceCopy &dc, const Options &opt, const Plan &plan, CallPlan *cp) {
+    cp->plan = plan;
+    cp->conv = opt.converge != 0;
+    if (!cp->conv && H.relational && H.W > kMaxDenseWords)
+        return fail(RI_ERR_LIMIT, "the plain reach joins interfaces of at most 2048 states; use RI_OPT_CONVERGE = 1");
+    cp->g0 = tile_group(H);
+    cp->ng0 = (plan.nchunks + (cp->g0 ? cp->g0 : kJoinGroup) - 1) / (cp->g0 ? cp->g0 : kJoinGroup);
+    cp->row_words = H.relational ? H.W : 1;
+    cp->pairs = (size_t)H.L * plan.nchunks;
+    cp->shape = base_shape(H, dc);
+    if (cp->conv) {
+        int rc = conv_config(H, dc, opt, plan.nchunks, &cp->cc);
+        if (rc) return rc;
+    }
+    cp->nh = std::max<size_t>(1, (plan.nchunks + 62) / 64);   // level-0 hit products
+    // join buffers of the dense joins (class join, relations, functions): at
+    // most ceil(nchunks / 2) relations of L rows (or classes); the hit-matrix
+    // join and the join by propagation do not use them
+    const bool rel_conv = cp->conv && H.relational;
+    cp->gc = rel_conv && H.W <= kMaxDenseWords ? cls_group(H, cp->shape.alias_bytes) : 0;
+    cp->hit = rel_conv && (opt.join == 0 || cp->gc == 0);
+    cp->dense_join = !rel_conv || cp->gc != 0;
+    cp->nrel_max = std::max<size_t>(cp->ng0, (plan.nchunks + 1) / 2);
+    return RI_OK;
+}
+
+// The buffers of a call in a fixed order: (pointer slot, bytes).
+template <class F>
+void for_each_buffer(const AlgoHost &H, const CallPlan &cp, bool maps, Scratch &sc, F &&f) {
+    if (cp.conv) {
+        f(reinterpret_cast<void **>(&sc.alias), cp.pairs * cp.shape.alias_bytes);
+        f(reinterpret_cast<void **>(&sc.run_base), (size_t)cp.plan.nchunks * 4);
+        f(reinterpret_cast<void **>(&sc.run_chunk), cp.cc.run_cap * 4);
+        f(reinterpret_cast<void **>(&sc.run_state), cp.cc.run_cap * 4);
+        f(reinterpret_cast<void **>(&sc.run_final), cp.cc.run_cap * 4);
+        f(reinterpret_cast<void **>(&sc.run_count), (size_t)cp.plan.nchunks * 4);
+        f(reinterpret_cast<void **>(&sc.block_count), (size_t)cp.cc.grid_w * 4);
+        for (int i = 0; i < 2; ++i) {
+            f(reinterpret_cast<void **>(&sc.hprod[i]), cp.nh * ri::kRowCap * 8);
+            f(reinterpret_cast<void **>(&sc.hrows[i]), cp.nh * 4);
+        }
+    } else {
+        f(reinterpret_cast<void **>(&sc.lam), cp.pairs * H.lam_bytes);
+    }
+    if (cp.dense_join) {
+        for (int i = 0; i < 2; ++i) {
+            f(reinterpret_cast<void **>(&sc.join[i]), cp.nrel_max * H.L * cp.row_words * 4);
+            f(reinterpret_cast<void **>(&sc.ncls[i]), cp.nrel_max * 4);
+        }
+    }
+    if (maps) f(reinterpret_cast<void **>(&sc.dbg), cp.pairs * 4);
+}
+
+constexpr size_t kArenaAlign = 256;
+
+// Bytes of the arena a call needs: counters and result, then every buffer.
+size_t arena_bytes(const AlgoHost &H, const CallPlan &cp) {
+    size_t total = 2 * kArenaAlign;
+    Scratch tmp;
+    for_each_buffer(H, cp, false, tmp, [&](void **, size_t bytes) { total += round_up(bytes ? bytes : 1, kArenaAlign); });
+    return total;
+}
+
+}  // namespace
+
+namespace ri {
+// A fixed device region that a call carves its scratch from; the caller of
+// recognize() provides it and guarantees that no other call uses it meanwhile.
+struct Arena {
+    uint8_t *base;
+    size_t bytes;
+};
+}  // namespace ri
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// RI_ALGO_NFA: the position NFA as chunk automaton over sets of states
+// ---------------------------------------------------------------------------
+
+constexpr uint64_t kNfaMapBytes = 1ull << 29;   // chunk maps of one call
+
+int nfa_plan(const AlgoHost &H, uint64_t n, uint32_t chunks, uint32_t target, Plan *p) {
+    const uint64_t row = (uint64_t)H.L * H.nfa_words * 8;   // one chunk's map
+    uint64_t cs;
+    if (chunks == 0) {
+        cs = std::max<uint64_t>(round_up((n + target - 1) / target, 16), kMinAutoChunk);
+        while (((n + cs - 1) / cs) * row > kNfaMapBytes) cs *= 2;
+    } else {
+        cs = round_up((n + chunks - 1) / chunks, 16);
+        if (((n + cs - 1) / cs) * row > kNfaMapBytes)
+            return fail(RI_ERR_LIMIT, "NFA chunk maps for this chunk count exceed the device budget");
+    }
+    const uint64_t nc = (n + cs - 1) / cs;
+    if (nc * H.L > 0x7fffffffull) return fail(RI_ERR_LIMIT, "too many chunks");
+    p->cs = cs;
+    p->nchunks = (uint32_t)nc;
+    return RI_OK;
+}
+
+// Scratch of an NFA call: maps [c][L][W] and two join buffers of
+// ceil(c / 64) relations.
+void nfa_buffer_sizes(const AlgoHost &H, const Plan &plan, size_t *maps, size_t *join) {
+    const size_t row = (size_t)H.L * H.nfa_words * 8;
+    *maps = (size_t)plan.nchunks * row;
+    *join = (size_t)((plan.nchunks + 63) / 64) * row;
+}
+
+size_t nfa_arena_bytes(const AlgoHost &H, const Plan &plan) {
+    size_t m, j;
+    nfa_buffer_sizes(H, plan, &m, &j);
+    return 2 * kArenaAlign + round_up(m, kArenaAlign) + 2 * round_up(j, kArenaAlign);
+}
+
+int recognize_nfa(ri_handle *h, const AlgoHost &H, const DeviceCopy &dc, const AlgoDevice &D, const uint8_t *text,
+                  size_t n, hipStream_t stream, const Plan &plan, Workspace *ws, const ri::Arena *arena,
+                  int32_t *result_dev, ri_result *out) {
+    size_t mbytes, jbytes;
+    nfa_buffer_sizes(H, plan, &mbytes, &jbytes);
+    uint64_t *maps, *join[2];
+    uint32_t *counters;
+    int32_t *dres;
+    if (arena) {
+        uint8_t *p = arena->base;
+        counters = reinterpret_cast<uint32_t *>(p);
+        dres = reinterpret_cast<int32_t *>(p + kArenaAlign);
+        p += 2 * kArenaAlign;
+        maps = reinterpret_cast<uint64_t *>(p);
+        p += round_up(mbytes, kArenaAlign);
+        join[0] = reinterpret_cast<uint64_t *>(p);
+        p += round_up(jbytes, kArenaAlign);
+        join[1] = reinterpret_cast<uint64_t *>(p);
+        HIP_TRY(ri::launch_zero_words(counters, 16, stream));
+    } else {
+        int rc = grow(ws->lam, mbytes, &ws->retired);
+        if (!rc) rc = grow(ws->join[0], jbytes, &ws->retired);
+        if (!rc) rc = grow(ws->join[1], jbytes, &ws->retired);
+        if (rc) return rc;
+        maps = static_cast<uint64_t *>(ws->lam.p);
+        join[0] = static_cast<uint64_t *>(ws->join[0].p);
+        join[1] = static_cast<uint64_t *>(ws->join[1].p);
+        counters = ws->counters;
+        dres = ws->dres;
+    }
+    const bool prof = h->profiling && !result_dev;
+    if (prof) HIP_TRY(hipEventRecord(ws->ev[0], stream));
+    ri::NfaArgs na{};
+    na.text = text;
+    na.n = n;
+    na.cs = plan.cs;
+    na.nchunks = plan.nchunks;
+    na.follow = D.follow;
+    na.mask = D.mask;
+    na.cls = dc.cls;
+    na.L = H.L;
+    na.K = H.K;
+    na.W = H.nfa_words;
+    na.maps = maps;
+    na.job_counter = counters + 3;
+    na.chunk_groups = (plan.nchunks + 63) / 64;
+    na.njobs = H.L * na.chunk_groups;
+    // 256-thread blocks, 8 per CU, persistent over the jobs
+    const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)dc.cus * 8, (na.njobs + 3) / 4));
+    HIP_TRY(ri::launch_nfa_reach(na, grid, stream));
+    if (prof) {
+        HIP_TRY(hipEventRecord(ws->ev[4], stream));
+        HIP_TRY(hipEventRecord(ws->ev[1], stream));
+    }
+    const uint64_t *total = maps;
+    uint32_t nin = plan.nchunks;
+    int cur = 0;
+    while (nin > 1) {
+        ri::NfaJoinArgs ja{total, nin, join[cur], H.L, H.nfa_words, kJoinGroup};
+        HIP_TRY(ri::launch_nfa_join(ja, stream));
+        total = join[cur];
+        cur ^= 1;
+        nin = (nin + kJoinGroup - 1) / kJoinGroup;
+    }
+    ri::FinalArgs fa{};
+    fa.fmask = D.fmask;
+    fa.hash = D.hash;
+    fa.hash_cap = H.hash_cap;
+    fa.csr_off = D.csr_off;
+    fa.csr_idx = D.csr_idx;
+    fa.result = result_dev ? result_dev : dres;
+    fa.counters = counters;
+    HIP_TRY(ri::launch_nfa_final(fa, total, H.nfa_words, nullptr, stream));
+    out->chunks = plan.nchunks;
+    out->chunk_size = (uint32_t)plan.cs;
+    if (result_dev) {
+        out->accept = -1;
+        out->final_state = -1;
+        return RI_OK;
+    }
+    if (prof) HIP_TRY(hipEventRecord(ws->ev[2], stream));
+    HIP_TRY(hipMemcpyAsync(ws->hres, ws->dres, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    if (prof) HIP_TRY(hipEventRecord(ws->ev[3], stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    out->accept = ws->hres[0];
+    out->final_state = ws->hres[1];
+    if (out->final_state == -3) return fail(RI_ERR_DEVICE, "internal: final subset not found");
+    if (prof) {
+        float ms[5] = {0, 0, 0, 0, 0};
+        HIP_TRY(hipEventElapsedTime(&ms[0], ws->ev[0], ws->ev[1]));
+        HIP_TRY(hipEventElapsedTime(&ms[1], ws->ev[1], ws->ev[2]));
+        HIP_TRY(hipEventElapsedTime(&ms[2], ws->ev[0], ws->ev[3]));
+        HIP_TRY(hipEventElapsedTime(&ms[3], ws->ev[0], ws->ev[4]));
+        std::lock_guard<std::mutex> lk(h->mu);
+        std::memcpy(h->last_ms, ms, sizeof(ms));
+    }
+    return RI_OK;
+}
+
 // result_dev != nullptr: everything is enqueued on the stream and the
 // result is left in result_dev[0..1]; no host wait, no profiling, no maps.
+// arena != nullptr (with result_dev): scratch is carved from the arena, the
+// chunk count is lowered until it fits, and nothing is allocated.
 int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v, int algo,
-              uint32_t chunks, ri_result *out, int32_t *maps, size_t maps_cap, int32_t *result_dev = nullptr) {
+              uint32_t chunks, ri_result *out, int32_t *maps, size_t maps_cap, int32_t *result_dev = nullptr,
+              const ri::Arena *arena = nullptr) {
     ri_handle *h = const_cast<ri_handle *>(hc);
     if (!h || !out) return fail(RI_ERR_ARG, "NULL handle or result pointer");
     if (result_dev && (reinterpret_cast<uintptr_t>(result_dev) & 3))
         return fail(RI_ERR_ARG, "result must be 4-byte aligned");
+    if (arena && (!result_dev || maps)) return fail(RI_ERR_ARG, "internal: arena calls are queued calls");
     if (algo < 0 || algo >= RI_NUM_ALGOS) return fail(RI_ERR_ARG, "unknown algorithm");
     if (n > 0 && !text) return fail(RI_ERR_ARG, "NULL text pointer");
     if (n > 0 && (reinterpret_cast<uintptr_t>(text) & 15)) return fail(RI_ERR_ARG, "text must be 16-byte aligned");
@@ -446,6 +750,8 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         return RI_OK;
     }
     const AlgoHost &H = h->algo[algo];
+    if (H.nfa && maps) return fail(RI_ERR_ARG, "RI_ALGO_NFA: chunk maps are sets of NFA states, not state ids");
+    if (H.nfa && !H.nfa_words) return fail(RI_ERR_LIMIT, "RI_ALGO_NFA: the NFA has more than 256 states");
     if (H.relational && H.W > ri::kPropMaxWords)
         return fail(RI_ERR_LIMIT, "interface larger than 32768 states is not supported by the device join");
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
@@ -453,83 +759,106 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     HIP_TRY(hipGetDevice(&device));
     if (device < 0 || device >= kMaxDevices) return fail(RI_ERR_DEVICE, "device index out of range");
 
-    Plan plan;
+    Options opt;
     uint32_t target = h->opt.chunk_target;
     {
         std::lock_guard<std::mutex> lk(h->mu);
         if (chunks == 0 && h->tuned_valid[algo]) target = h->tuned[algo].chunk_target;
+        opt = (chunks == 0 && h->tuned_valid[algo]) ? h->tuned[algo] : h->opt;
     }
-    int rc = plan_chunks(H, n, chunks, target, &plan);
+    Plan plan;
+    int rc = H.nfa ? nfa_plan(H, n, chunks, target, &plan) : plan_chunks(H, n, chunks, target, &plan);
     if (rc) return rc;
     if (maps && maps_cap < (size_t)plan.nchunks * H.L)
         return fail(RI_ERR_ARG, "maps buffer too small");
 
     Workspace *ws = nullptr;
-    {
+    std::unique_lock<std::mutex> wlk;
+    if (arena) {
+        std::lock_guard<std::mutex> lk(h->mu);
+        if (!h->dev[device].ready)
+            return fail(RI_ERR_ARG, "the handle's tables are not on the current device yet: make one "
+                                    "ri_recognize* call on this device first");
+    } else {
         std::lock_guard<std::mutex> lk(h->mu);
         rc = ensure_device(h, device);
         if (rc) return rc;
         rc = get_workspace(h, device, stream, &ws);
         if (rc) return rc;
     }
-    std::lock_guard<std::mutex> wlk(ws->mu);
+    if (ws) wlk = std::unique_lock<std::mutex>(ws->mu);
     DeviceCopy &dc = h->dev[device];
     const AlgoDevice &D = dc.algo[algo];
     const bool prof = h->profiling && !result_dev;
 
-    Options opt;
-    {
-        std::lock_guard<std::mutex> lk(h->mu);
-        opt = (chunks == 0 && h->tuned_valid[algo]) ? h->tuned[algo] : h->opt;
+    if (H.nfa) {
+        if (arena) {
+            while (nfa_arena_bytes(H, plan) > arena->bytes) {
+                if (chunks != 0 || plan.nchunks <= 1)
+                    return fail(RI_ERR_LIMIT, "the text does not fit the fixed scratch memory with this chunk count "
+                                              "(" + std::to_string(nfa_arena_bytes(H, plan)) + " bytes needed, " +
+                                              std::to_string(arena->bytes) + " available)");
+                rc = nfa_plan(H, n, 0, std::max<uint32_t>(1, plan.nchunks / 2), &plan);
+                if (rc) return rc;
+            }
+        }
+        return recognize_nfa(h, H, dc, D, text, n, stream, plan, ws, arena, result_dev, out);
     }
-    const bool conv = opt.converge != 0;
-    if (!conv && H.relational && H.W > kMaxDenseWords)
-        return fail(RI_ERR_LIMIT, "the plain reach joins interfaces of at most 2048 states; use RI_OPT_CONVERGE = 1");
-    const uint32_t g0 = tile_group(H);
-    const uint32_t ng0 = (plan.nchunks + (g0 ? g0 : kJoinGroup) - 1) / (g0 ? g0 : kJoinGroup);
-    const size_t row_words = H.relational ? H.W : 1;
-    const size_t pairs = (size_t)H.L * plan.nchunks;
-
-    ri::KernelShape shape = base_shape(H, dc);
+    CallPlan cp;
+    rc = plan_call(H, dc, opt, plan, &cp);
+    if (rc) return rc;
+    Scratch sc;
+    if (arena) {
+        // fewer, longer chunks until the call fits the arena
+        while (arena_bytes(H, cp) > arena->bytes) {
+            if (chunks != 0 || plan.nchunks <= 1)
+                return fail(RI_ERR_LIMIT, "the text does not fit the fixed scratch memory with this chunk count "
+                                          "(" + std::to_string(arena_bytes(H, cp)) + " bytes needed, " +
+                                          std::to_string(arena->bytes) + " available)");
+            target = std::max<uint32_t>(1, plan.nchunks / 2);
+            rc = plan_chunks(H, n, 0, target, &plan);
+            if (!rc) rc = plan_call(H, dc, opt, plan, &cp);
+            if (rc) return rc;
+        }
+        uint8_t *p = arena->base;
+        sc.counters = reinterpret_cast<uint32_t *>(p);
+        sc.dres = reinterpret_cast<int32_t *>(p + kArenaAlign);
+        p += 2 * kArenaAlign;
+        for_each_buffer(H, cp, false, sc, [&](void **slot, size_t bytes) {
+            *slot = p;
+            p += round_up(bytes ? bytes : 1, kArenaAlign);
+        });
+        // the counters start at zero (a fill kernel: capturable, unlike a memset)
+        HIP_TRY(ri::launch_zero_words(sc.counters, 16, stream));
+    } else {
+        // the workspace buffer that backs each scratch pointer
+        const std::pair<void *, Buf *> backing[] = {
+            {&sc.lam, &ws->lam}, {&sc.alias, &ws->alias}, {&sc.dbg, &ws->dbg}, {&sc.run_base, &ws->run_base},
+            {&sc.run_count, &ws->run_count}, {&sc.run_chunk, &ws->run_chunk}, {&sc.run_state, &ws->run_state},
+            {&sc.run_final, &ws->run_final}, {&sc.block_count, &ws->block_count}, {&sc.join[0], &ws->join[0]},
+            {&sc.join[1], &ws->join[1]}, {&sc.ncls[0], &ws->ncls[0]}, {&sc.ncls[1], &ws->ncls[1]},
+            {&sc.hrows[0], &ws->hrows[0]}, {&sc.hrows[1], &ws->hrows[1]}, {&sc.hprod[0], &ws->hprod[0]},
+            {&sc.hprod[1], &ws->hprod[1]}};
+        for_each_buffer(H, cp, maps != nullptr, sc, [&](void **slot, size_t bytes) {
+            Buf *b = nullptr;
+            for (const auto &e : backing)
+                if (e.first == static_cast<void *>(slot)) b = e.second;
+            if (!b) { rc = fail(RI_ERR_DEVICE, "internal: scratch slot without a buffer"); return; }
+            if (!rc) rc = grow(*b, bytes, &ws->retired);
+            *slot = b->p;
+        });
+        if (rc) return rc;
+        sc.counters = ws->counters;
+        sc.dres = ws->dres;
+    }
+    const bool conv = cp.conv;
+    const ConvCfg &cc = cp.cc;
+    ri::KernelShape shape = cp.shape;
+    const uint32_t g0 = cp.g0, ng0 = cp.ng0, gc = cp.gc;
+    const bool hit = cp.hit;
+    const size_t pairs = cp.pairs;
     uint32_t R = opt.runs_per_lane ? opt.runs_per_lane : 4;
     const size_t lds_tables = H.table.size() + 512;
-    ConvCfg cc;
-    if (conv) {
-        rc = conv_config(H, dc, opt, plan.nchunks, &cc);
-        if (rc) return rc;
-    }
-
-    // buffers
-    if (conv) {
-        rc = grow(ws->alias, pairs * shape.alias_bytes);
-        if (!rc) rc = grow(ws->run_base, (size_t)plan.nchunks * 4);
-        if (!rc) rc = grow(ws->run_chunk, cc.run_cap * 4);
-        if (!rc) rc = grow(ws->run_state, cc.run_cap * 4);
-        if (!rc) rc = grow(ws->run_final, cc.run_cap * 4);
-        if (!rc) rc = grow(ws->run_count, (size_t)plan.nchunks * 4);
-        if (!rc) rc = grow(ws->block_count, (size_t)cc.grid_w * 4);
-        const size_t nh = std::max<size_t>(1, (plan.nchunks + 62) / 64);   // level-0 hit products
-        for (int i = 0; i < 2 && !rc; ++i) {
-            rc = grow(ws->hprod[i], nh * ri::kRowCap * 8);
-            if (!rc) rc = grow(ws->hrows[i], nh * 4);
-        }
-    } else {
-        rc = grow(ws->lam, pairs * H.lam_bytes);
-    }
-    // join buffers of the dense joins (class join, relations, functions): at
-    // most ceil(nchunks / 2) relations of L rows (or classes); the hit-matrix
-    // join and the join by propagation do not use them
-    const bool rel_conv = conv && H.relational;
-    const uint32_t gc = rel_conv && H.W <= kMaxDenseWords ? cls_group(H, shape.alias_bytes) : 0;
-    const bool hit = rel_conv && (opt.join == 0 || gc == 0);
-    const bool dense_join = !rel_conv || gc != 0;
-    const size_t nrel_max = std::max<size_t>(ng0, (plan.nchunks + 1) / 2);
-    if (!rc && dense_join) rc = grow(ws->join[0], nrel_max * H.L * row_words * 4);
-    if (!rc && dense_join) rc = grow(ws->join[1], nrel_max * H.L * row_words * 4);
-    if (!rc && dense_join) rc = grow(ws->ncls[0], nrel_max * 4);
-    if (!rc && dense_join) rc = grow(ws->ncls[1], nrel_max * 4);
-    if (!rc && maps) rc = grow(ws->dbg, pairs * 4);
-    if (rc) return rc;
 
     ri::ScanArgs sa{};
     sa.text = text;
@@ -552,8 +881,8 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         const size_t lds = shape.table_in_lds ? lds_tables : 512;
         ri::PlainArgs pa{};
         pa.s = sa;
-        pa.lam = ws->lam.p;
-        pa.job_counter = ws->counters + 3;
+        pa.lam = sc.lam;
+        pa.job_counter = sc.counters + 3;
         pa.chunk_groups = chunk_groups;
         pa.njobs = ((H.L + R - 1) / R) * chunk_groups;
         const int per_cu = std::max(1, ri::blocks_per_cu(0, shape, lds));
@@ -561,10 +890,8 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         HIP_TRY(ri::launch_plain(pa, shape, grid, lds, stream));
         if (prof) HIP_TRY(hipEventRecord(ws->ev[4], stream));
     } else {
-        ReachBufs rb{ws->alias.p, static_cast<uint32_t *>(ws->run_base.p), static_cast<uint32_t *>(ws->run_chunk.p),
-                     static_cast<uint32_t *>(ws->run_state.p), static_cast<uint32_t *>(ws->run_final.p),
-                     ws->counters, static_cast<uint32_t *>(ws->run_count.p),
-                     static_cast<uint32_t *>(ws->block_count.p)};
+        ReachBufs rb{sc.alias, sc.run_base, sc.run_chunk, sc.run_state, sc.run_final, sc.counters, sc.run_count,
+                     sc.block_count};
         rc = launch_conv(cc, sa, opt, rb, stream, prof ? ws->ev[5] : nullptr);
         if (rc) return rc;
         if (prof) HIP_TRY(hipEventRecord(ws->ev[4], stream));
@@ -574,10 +901,10 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     // join tree
     ri::JoinArgs ja{};
     ja.converged = conv;
-    ja.lam = ws->lam.p;
-    ja.alias = ws->alias.p;
-    ja.run_base = static_cast<const uint32_t *>(ws->run_base.p);
-    ja.run_final = static_cast<const uint32_t *>(ws->run_final.p);
+    ja.lam = sc.lam;
+    ja.alias = sc.alias;
+    ja.run_base = sc.run_base;
+    ja.run_final = sc.run_final;
     ja.tile_bytes = (int)H.lam_bytes;
     ja.alias_bytes = shape.alias_bytes;
     ja.nchunks = plan.nchunks;
@@ -586,7 +913,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     ja.G = kJoinGroup;
     ja.in = nullptr;
     ja.nin = 0;
-    ja.out = ws->join[0].p;
+    ja.out = sc.join[0];
     ri::FinalArgs fa{};
     fa.fmask = D.fmask;
     fa.hash = D.hash;
@@ -596,13 +923,13 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     fa.content = H.relational && H.W <= kMaxDenseWords ? D.content : nullptr;
     fa.final_of_state = D.final_of_state;
     fa.accept_of_state = D.accept_of_state;
-    fa.result = result_dev && !hit ? result_dev : ws->dres;   // the hit join needs result[2]
-    fa.counters = ws->counters;
+    fa.result = result_dev && !hit ? result_dev : sc.dres;   // the hit join needs result[2]
+    fa.counters = sc.counters;
 
     // class-partitioned join for merged runs of a relational chunk automaton:
     // the group size is the widest power of two <= 64 whose LDS stays in 64 KiB
     ri::ClsJoinArgs ca{};
-    ca.alias = ws->alias.p;
+    ca.alias = sc.alias;
     ca.nchunks = plan.nchunks;
     ca.L = H.L;
     ca.run_base = ja.run_base;
@@ -614,8 +941,8 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         ca.span = 1;
         ca.ncls_in = nullptr;
         ca.cont_in = nullptr;
-        ca.ncls_out = static_cast<uint32_t *>(ws->ncls[0].p);
-        ca.cont_out = static_cast<uint32_t *>(ws->join[0].p);
+        ca.ncls_out = sc.ncls[0];
+        ca.cont_out = static_cast<uint32_t *>(sc.join[0]);
         HIP_TRY(ri::launch_join_cls(ca, (int)H.W, shape.alias_bytes, true, stream));
         int cur = 0;
         uint32_t nm = (plan.nchunks + gc - 1) / gc;
@@ -623,16 +950,16 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         while (nm > 1) {
             ca.nmembers = nm;
             ca.span = span;
-            ca.ncls_in = static_cast<const uint32_t *>(ws->ncls[cur].p);
-            ca.cont_in = static_cast<const uint32_t *>(ws->join[cur].p);
-            ca.ncls_out = static_cast<uint32_t *>(ws->ncls[cur ^ 1].p);
-            ca.cont_out = static_cast<uint32_t *>(ws->join[cur ^ 1].p);
+            ca.ncls_in = sc.ncls[cur];
+            ca.cont_in = static_cast<const uint32_t *>(sc.join[cur]);
+            ca.ncls_out = sc.ncls[cur ^ 1];
+            ca.cont_out = static_cast<uint32_t *>(sc.join[cur ^ 1]);
             HIP_TRY(ri::launch_join_cls(ca, (int)H.W, shape.alias_bytes, false, stream));
             cur ^= 1;
             span *= gc;
             nm = (nm + gc - 1) / gc;
         }
-        ca.cont_in = static_cast<const uint32_t *>(ws->join[cur].p);
+        ca.cont_in = static_cast<const uint32_t *>(sc.join[cur]);
         HIP_TRY(ri::launch_finalize_cls(fa, ca, (int)H.W, shape.alias_bytes, stream));
         return RI_OK;
     };
@@ -641,11 +968,11 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         // products of hit matrices: level 0 over the K - 1 matrices, then
         // groups of 64 products until at most 64 are left; the last level and
         // the final step run in one wave
-        ha.alias = ws->alias.p;
+        ha.alias = sc.alias;
         ha.L = H.L;
         ha.nchunks = plan.nchunks;
         ha.run_base = ja.run_base;
-        ha.run_count = static_cast<const uint32_t *>(ws->run_count.p);
+        ha.run_count = sc.run_count;
         ha.run_final = ja.run_final;
         ha.csr_off = D.csr_off;
         ha.csr_idx = D.csr_idx;
@@ -655,30 +982,39 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         if (plan.nchunks > 1) {
             int cur = 0;
             ha.nmembers = plan.nchunks - 1;
-            ha.prod_out = static_cast<uint64_t *>(ws->hprod[0].p);
-            ha.rows_out = static_cast<uint32_t *>(ws->hrows[0].p);
+            ha.prod_out = sc.hprod[0];
+            ha.rows_out = sc.hrows[0];
             HIP_TRY(ri::launch_hit_prod(ha, H.W <= kMaxDenseWords ? (int)H.W : 0, shape.alias_bytes, true, stream));
             uint32_t nm = (ha.nmembers + 63) / 64;
             while (nm > ri::kHitTailMax) {
                 ha.nmembers = nm;
-                ha.prod_in = static_cast<const uint64_t *>(ws->hprod[cur].p);
-                ha.rows_in = static_cast<const uint32_t *>(ws->hrows[cur].p);
-                ha.prod_out = static_cast<uint64_t *>(ws->hprod[cur ^ 1].p);
-                ha.rows_out = static_cast<uint32_t *>(ws->hrows[cur ^ 1].p);
+                ha.prod_in = sc.hprod[cur];
+                ha.rows_in = sc.hrows[cur];
+                ha.prod_out = sc.hprod[cur ^ 1];
+                ha.rows_out = sc.hrows[cur ^ 1];
                 HIP_TRY(ri::launch_hit_prod(ha, 0, shape.alias_bytes, false, stream));
                 cur ^= 1;
                 nm = (nm + 63) / 64;
             }
-            ha.prod_in = static_cast<const uint64_t *>(ws->hprod[cur].p);
+            ha.prod_in = sc.hprod[cur];
             ha.nmembers = nm;
         }
-        if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(ws->dbg.p), stream));
+        if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(sc.dbg), stream));
         // queued calls: a result that a chunk with too many runs made invalid
-        // is redone by propagation in the same launch, then copied out
+        // is redone by the class join, whose kernels are enqueued behind the
+        // hit join and return at once unless the flag is set (interfaces of at
+        // most 2048 states), or else by propagation inside the final kernel
+        const bool gated_cls = result_dev && gc != 0;
         HIP_TRY(ri::launch_finalize_hit(fa, ha, H.W <= kMaxDenseWords ? (int)H.W : 0, shape.alias_bytes, stream,
-                                        result_dev, result_dev ? H.W : 0));
+                                        result_dev, result_dev && !gated_cls ? H.W : 0, gated_cls));
+        if (gated_cls) {
+            ca.gate = sc.counters + 2;
+            fa.result = result_dev;
+            rc = cls_join();
+            if (rc) return rc;
+        }
     } else if (gc) {
-        if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(ws->dbg.p), stream));
+        if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(sc.dbg), stream));
         rc = cls_join();
         if (rc) return rc;
     } else {
@@ -694,16 +1030,16 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         int cur = 0;
         uint32_t nin = ng0;
         while (nin > 1) {
-            ja.in = ws->join[cur].p;
+            ja.in = sc.join[cur];
             ja.nin = nin;
-            ja.out = ws->join[cur ^ 1].p;
+            ja.out = sc.join[cur ^ 1];
             if (H.relational) HIP_TRY(ri::launch_joinN_rel(ja, (int)H.W, stream));
             else HIP_TRY(ri::launch_joinN_fun(ja, stream));
             cur ^= 1;
             nin = (nin + kJoinGroup - 1) / kJoinGroup;
         }
-        if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(ws->dbg.p), stream));
-        fa.total = ws->join[cur].p;
+        if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(sc.dbg), stream));
+        fa.total = sc.join[cur];
         if (H.relational) HIP_TRY(ri::launch_finalize_rel(fa, (int)H.W, stream));
         else HIP_TRY(ri::launch_finalize_fun(fa, stream));
     }
@@ -720,7 +1056,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     std::vector<int32_t> lam_host;
     if (maps) {
         lam_host.resize(pairs);
-        HIP_TRY(hipMemcpyAsync(lam_host.data(), ws->dbg.p, pairs * 4, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(lam_host.data(), sc.dbg, pairs * 4, hipMemcpyDeviceToHost, stream));
     }
     if (prof) HIP_TRY(hipEventRecord(ws->ev[3], stream));
     HIP_TRY(hipStreamSynchronize(stream));
@@ -796,7 +1132,7 @@ struct BatchGroup {
     ConvCfg cc;
     std::vector<BatchLevel> levels;
     size_t off_addr = 0, off_len = 0, off_slot = 0, off_out = 0;
-    Workspace::Buf desc, alias, run_base, run_chunk, run_state, run_final, join[2], ncls[2], block_count;
+    Buf desc, alias, run_base, run_chunk, run_state, run_final, join[2], ncls[2], block_count;
     uint32_t *counters = nullptr;
     float tuned_ms = 0;
 };
@@ -820,7 +1156,7 @@ struct FusedPlan {
     };
     std::vector<Level> levels;
     uint32_t nprod = 0;
-    Workspace::Buf blob, autos, alias, run_base, run_count, run_chunk, run_state, run_final, prod, prod_rows,
+    Buf blob, autos, alias, run_base, run_count, run_chunk, run_state, run_final, prod, prod_rows,
         text_flag, counters;
     int grid_w = 1, grid_l = 1;
     float tuned_ms = 0;
@@ -841,6 +1177,7 @@ struct ri_batch {
     int32_t *graph_results = nullptr;
     hipStream_t side[kBatchSide] = {};
     hipEvent_t fork = nullptr, joins[kBatchSide] = {};
+    std::vector<void *> retired;    // buffers replaced by a re-plan, freed with the batch
 };
 
 namespace {
@@ -853,7 +1190,7 @@ size_t put_array(std::vector<uint8_t> &blob, const std::vector<T> &v) {
     return off;
 }
 
-void release(Workspace::Buf &b) {
+void release(Buf &b) {
     if (b.p) (void)hipFree(b.p);
     b.p = nullptr;
     b.cap = 0;
@@ -946,15 +1283,15 @@ int plan_group(ri_batch *b, BatchGroup &g) {
         const size_t pairs = (size_t)H.L * g.slots;
         const size_t row_words = H.relational ? H.W : 1;
         int rc = conv_config(H, dc, g.opt, g.slots, &g.cc);
-        if (!rc) rc = grow(g.alias, pairs * alias_bytes);
-        if (!rc) rc = grow(g.run_base, (size_t)g.slots * 4);
-        if (!rc) rc = grow(g.run_chunk, g.cc.run_cap * 4);
-        if (!rc) rc = grow(g.run_state, g.cc.run_cap * 4);
-        if (!rc) rc = grow(g.run_final, g.cc.run_cap * 4);
-        if (!rc) rc = grow(g.block_count, (size_t)g.cc.grid_w * 4);
+        if (!rc) rc = grow(g.alias, pairs * alias_bytes, &b->retired);
+        if (!rc) rc = grow(g.run_base, (size_t)g.slots * 4, &b->retired);
+        if (!rc) rc = grow(g.run_chunk, g.cc.run_cap * 4, &b->retired);
+        if (!rc) rc = grow(g.run_state, g.cc.run_cap * 4, &b->retired);
+        if (!rc) rc = grow(g.run_final, g.cc.run_cap * 4, &b->retired);
+        if (!rc) rc = grow(g.block_count, (size_t)g.cc.grid_w * 4, &b->retired);
         for (int i = 0; i < 2 && !rc; ++i) {
-            rc = grow(g.join[i], max_groups * H.L * row_words * 4);
-            if (!rc) rc = grow(g.ncls[i], max_groups * 4);
+            rc = grow(g.join[i], max_groups * H.L * row_words * 4, &b->retired);
+            if (!rc) rc = grow(g.ncls[i], max_groups * 4, &b->retired);
         }
         if (rc) return rc;
         if (!g.counters) {
@@ -962,7 +1299,7 @@ int plan_group(ri_batch *b, BatchGroup &g) {
             HIP_TRY(zero_now(g.counters, 64));
         }
     }
-    int rc = grow(g.desc, blob.size());
+    int rc = grow(g.desc, blob.size(), &b->retired);
     if (rc) return rc;
     HIP_TRY(hipMemcpy(g.desc.p, blob.data(), blob.size(), hipMemcpyHostToDevice));
     return RI_OK;
@@ -1107,6 +1444,8 @@ int check_requests(const ri_request *reqs, uint32_t count) {
         const ri_request &q = reqs[i];
         if (!q.h) return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": NULL handle");
         if (q.algo < 0 || q.algo >= RI_NUM_ALGOS) return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": unknown algorithm");
+        if (q.algo == RI_ALGO_NFA)
+            return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": RI_ALGO_NFA is not available in batches");
         if (q.reserved != 0) return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": reserved must be 0");
         if (q.n > 0 && !q.text_dev) return fail(RI_ERR_ARG, "request " + std::to_string(i) + ": NULL text pointer");
         if (q.n > 0 && (reinterpret_cast<uintptr_t>(q.text_dev) & 15))
@@ -1234,18 +1573,18 @@ int plan_fused(ri_batch *b) {
         z.levels[l].first = put_array(blob, firsts[l]);
         z.levels[l].count = put_array(blob, counts[l]);
     }
-    int rc = grow(z.blob, std::max<size_t>(blob.size(), 16));
-    if (!rc) rc = grow(z.autos, std::max<size_t>(descs.size(), 1) * sizeof(ri::AutoDesc));
-    if (!rc) rc = grow(z.alias, std::max<uint64_t>(alias_entries, 1) * 2);
-    if (!rc) rc = grow(z.run_base, std::max<size_t>(z.nslots, 1) * 4);
-    if (!rc) rc = grow(z.run_count, std::max<size_t>(z.nslots, 1) * 4);
-    if (!rc) rc = grow(z.run_chunk, std::max<uint64_t>(alias_entries, 1) * 4);
-    if (!rc) rc = grow(z.run_state, std::max<uint64_t>(alias_entries, 1) * 4);
-    if (!rc) rc = grow(z.run_final, std::max<uint64_t>(alias_entries, 1) * 4);
-    if (!rc) rc = grow(z.prod, std::max<size_t>(z.nprod, 1) * ri::kRowCap * 8);
-    if (!rc) rc = grow(z.prod_rows, std::max<size_t>(z.nprod, 1) * 4);
-    if (!rc) rc = grow(z.text_flag, std::max<size_t>(z.ntexts, 1) * 4);
-    if (!rc) rc = grow(z.counters, 64);
+    int rc = grow(z.blob, std::max<size_t>(blob.size(), 16), &b->retired);
+    if (!rc) rc = grow(z.autos, std::max<size_t>(descs.size(), 1) * sizeof(ri::AutoDesc), &b->retired);
+    if (!rc) rc = grow(z.alias, std::max<uint64_t>(alias_entries, 1) * 2, &b->retired);
+    if (!rc) rc = grow(z.run_base, std::max<size_t>(z.nslots, 1) * 4, &b->retired);
+    if (!rc) rc = grow(z.run_count, std::max<size_t>(z.nslots, 1) * 4, &b->retired);
+    if (!rc) rc = grow(z.run_chunk, std::max<uint64_t>(alias_entries, 1) * 4, &b->retired);
+    if (!rc) rc = grow(z.run_state, std::max<uint64_t>(alias_entries, 1) * 4, &b->retired);
+    if (!rc) rc = grow(z.run_final, std::max<uint64_t>(alias_entries, 1) * 4, &b->retired);
+    if (!rc) rc = grow(z.prod, std::max<size_t>(z.nprod, 1) * ri::kRowCap * 8, &b->retired);
+    if (!rc) rc = grow(z.prod_rows, std::max<size_t>(z.nprod, 1) * 4, &b->retired);
+    if (!rc) rc = grow(z.text_flag, std::max<size_t>(z.ntexts, 1) * 4, &b->retired);
+    if (!rc) rc = grow(z.counters, 64, &b->retired);
     if (rc) return rc;
     if (!blob.empty()) HIP_TRY(hipMemcpy(z.blob.p, blob.data(), blob.size(), hipMemcpyHostToDevice));
     if (!descs.empty())
@@ -1305,7 +1644,7 @@ int run_fused(ri_batch *b, hipStream_t stream, int32_t *results) {
 }
 
 void release_fused(FusedPlan &z) {
-    for (Workspace::Buf *x : {&z.blob, &z.autos, &z.alias, &z.run_base, &z.run_count, &z.run_chunk, &z.run_state,
+    for (Buf *x : {&z.blob, &z.autos, &z.alias, &z.run_base, &z.run_count, &z.run_chunk, &z.run_state,
                               &z.run_final, &z.prod, &z.prod_rows, &z.text_flag, &z.counters})
         release(*x);
 }
@@ -1426,6 +1765,18 @@ int batch_setup(ri_batch *b, const ri_request *reqs, uint32_t count, const ri_ba
 
 }  // namespace
 
+namespace ri {
+// Entry points in other translation units of the library (not part of ri.h).
+int set_error(int code, const char *msg) { return fail(code, msg); }
+int recognize_in_arena(const ri_handle *h, const uint8_t *text, size_t n, void *stream, int algo,
+                       uint32_t chunks, int32_t *result_dev, void *arena, size_t arena_bytes) {
+    if (!result_dev) return fail(RI_ERR_ARG, "NULL result pointer");
+    ri_result r;
+    const Arena a{static_cast<uint8_t *>(arena), arena_bytes};
+    return recognize(h, text, n, stream, algo, chunks, &r, nullptr, 0, result_dev, &a);
+}
+}  // namespace ri
+
 extern "C" {
 
 int ri_build(const char *re, size_t re_len, const ri_build_opts *opts, ri_handle **out) {
@@ -1468,6 +1819,8 @@ void ri_free(ri_handle *h) {
             (void)hipFree(D.hash);
             (void)hipFree(D.final_of_state);
             (void)hipFree(D.accept_of_state);
+            (void)hipFree(D.follow);
+            (void)hipFree(D.mask);
         }
         (void)hipSetDevice(prev);
     }
@@ -1478,11 +1831,12 @@ void ri_free(ri_handle *h) {
         (void)hipFree(w->counters);
         (void)hipFree(w->dres);
         (void)hipHostFree(w->hres);
-        for (Workspace::Buf *b : {&w->lam, &w->alias, &w->run_base, &w->run_count, &w->hprod[0], &w->hprod[1], &w->block_count,
+        for (Buf *b : {&w->lam, &w->alias, &w->run_base, &w->run_count, &w->hprod[0], &w->hprod[1], &w->block_count,
                                   &w->hrows[0], &w->hrows[1], &w->run_chunk, &w->run_state,
                                   &w->run_final, &w->dbg, &w->join[0], &w->join[1], &w->ncls[0],
                                   &w->ncls[1]})
             (void)hipFree(b->p);
+        for (void *p : w->retired) (void)hipFree(p);
         for (auto e : w->ev) (void)hipEventDestroy(e);
         (void)hipSetDevice(prev);
     }
@@ -1503,8 +1857,9 @@ int ri_info(const ri_handle *h, ri_info_t *out) {
     out->accepts_empty = A.accepts_empty ? 1 : 0;
     for (int a = 0; a < RI_NUM_ALGOS; ++a) {
         out->starts[a] = h->algo[a].L;
-        out->entry_bytes[a] = h->algo[a].entry_bytes;
-        out->table_bytes[a] = h->algo[a].table.size();
+        out->entry_bytes[a] = h->algo[a].nfa ? 8 * h->algo[a].nfa_words : h->algo[a].entry_bytes;
+        out->table_bytes[a] = h->algo[a].nfa ? 8 * (h->algo[a].follow.size() + h->algo[a].mask.size())
+                                             : h->algo[a].table.size();
     }
     return RI_OK;
 }
@@ -1543,9 +1898,11 @@ int ri_state_content(const ri_handle *h, int algo, uint32_t state, uint32_t *mem
     } else if (algo == RI_ALGO_DFA) {
         if (state >= A.dmin_n) return fail(RI_ERR_ARG, "state out of range");
         v.push_back(state);
-    } else {
+    } else if (algo == RI_ALGO_SUBSET) {
         if (state >= A.dsub_n) return fail(RI_ERR_ARG, "state out of range");
         if (A.dsub_final_id[state] >= 0) v.push_back((uint32_t)A.dsub_final_id[state]);
+    } else {
+        return fail(RI_ERR_ARG, "RI_ALGO_NFA has no state ids (its runs are sets of NFA states)");
     }
     *count = (uint32_t)v.size();
     if (v.size() > cap) return fail(RI_ERR_ARG, "members buffer too small");
@@ -1624,7 +1981,14 @@ int ri_autotune(ri_handle *h, const uint8_t *text, size_t n, void *stream, int a
     // the grid: converging reach over targets x warm-up x runs per lane, then
     // the plain reach over targets x runs per lane
     std::vector<Options> grid;
-    for (int conv = 1; conv >= 0; --conv)
+    if (algo == RI_ALGO_NFA) {   // chunk count only: the NFA runs neither merge nor share lanes
+        for (uint32_t tgt : {4096u, 16384u, 65536u, 131072u, 262144u}) {
+            Options o = saved;
+            o.chunk_target = tgt;
+            grid.push_back(o);
+        }
+    }
+    for (int conv = 1; conv >= 0 && algo != RI_ALGO_NFA; --conv)
         for (uint32_t tgt : kTargets)
             for (uint32_t w : (conv ? std::vector<uint32_t>(std::begin(kWarm), std::end(kWarm)) : std::vector<uint32_t>{saved.warm}))
                 for (uint32_t R : kRuns) {
@@ -1771,12 +2135,13 @@ void ri_batch_free(ri_batch *b) {
     (void)hipSetDevice(b->device);
     drop_graph(b);
     for (auto &g : b->groups) {
-        for (Workspace::Buf *x : {&g.desc, &g.alias, &g.run_base, &g.run_chunk, &g.run_state, &g.run_final,
+        for (Buf *x : {&g.desc, &g.alias, &g.run_base, &g.run_chunk, &g.run_state, &g.run_final,
                                   &g.join[0], &g.join[1], &g.ncls[0], &g.ncls[1], &g.block_count})
             release(*x);
         if (g.counters) (void)hipFree(g.counters);
     }
     release_fused(b->fz);
+    for (void *p : b->retired) (void)hipFree(p);
     for (auto s : b->side)
         if (s) (void)hipStreamDestroy(s);
     if (b->fork) (void)hipEventDestroy(b->fork);
@@ -1858,7 +2223,7 @@ int ri_batch_get_info(const ri_batch *b, ri_batch_info *out) {
         const FusedPlan &z = b->fz;
         out->slots = z.nslots;
         out->kernels = z.ntexts ? 4 + (uint32_t)z.levels.size() : 0;
-        for (const Workspace::Buf *x : {&z.blob, &z.autos, &z.alias, &z.run_base, &z.run_count, &z.run_chunk,
+        for (const Buf *x : {&z.blob, &z.autos, &z.alias, &z.run_base, &z.run_count, &z.run_chunk,
                                         &z.run_state, &z.run_final, &z.prod, &z.prod_rows, &z.text_flag, &z.counters})
             out->device_bytes += x->cap;
     }
@@ -1866,7 +2231,7 @@ int ri_batch_get_info(const ri_batch *b, ri_batch_info *out) {
         if (b->fused) break;
         out->slots += g.slots;
         out->kernels += g.empty ? 1 : 2 + (uint32_t)g.levels.size() + 1;
-        for (const Workspace::Buf *x : {&g.desc, &g.alias, &g.run_base, &g.run_chunk, &g.run_state, &g.run_final,
+        for (const Buf *x : {&g.desc, &g.alias, &g.run_base, &g.run_chunk, &g.run_state, &g.run_final,
                                         &g.join[0], &g.join[1], &g.ncls[0], &g.ncls[1]})
             out->device_bytes += x->cap;
     }

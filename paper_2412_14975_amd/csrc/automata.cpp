@@ -597,6 +597,17 @@ void build_automata(const std::string &re, uint32_t max_states, Automata &out) {
     }
     out.K = byte_classes(N, out.cls);
     ClassNfa CN = class_nfa(N, out.K, out.cls);
+    if (N.n <= kNfaMaxStates) {
+        const uint32_t W = N.n <= 64 ? 1 : N.n <= 128 ? 2 : 4;
+        out.nfa_words = W;
+        out.nfa_follow.assign((size_t)N.n * W, 0);
+        for (uint32_t q = 0; q < N.n; ++q)
+            for (uint32_t p : N.next[q]) out.nfa_follow[(size_t)q * W + p / 64] |= 1ull << (p % 64);
+        out.nfa_mask.assign((size_t)out.K * W, 0);
+        for (uint32_t p = 1; p < N.n; ++p)
+            for (int b = 0; b < 256; ++b)
+                if (N.sym[p].test(b)) out.nfa_mask[(size_t)out.cls[b] * W + p / 64] |= 1ull << (p % 64);
+    }
 
     // B = RI-DFA(N) and its Nerode classes (Sect. 3.1, 3.4)
     std::vector<uint32_t> all(N.n);
@@ -701,6 +712,7 @@ void build_automata(const std::string &re, uint32_t max_states, Automata &out) {
     }
     for (uint32_t s = 0; s < D.n; ++s) out.dsub_accept[s] = D.final[s];
     out.dsub_delta = std::move(D.delta);
+    out.dsub_content = std::move(D.content);
     out.pos = std::move(N);
 }
 

@@ -81,7 +81,18 @@ struct Automata {
     std::vector<int32_t> dsub_delta;
     std::vector<int32_t> dsub_final_id;   // minimal DFA id of each state
     std::vector<uint8_t> dsub_accept;
+    std::vector<std::vector<uint32_t>> dsub_content;   // the set of N's states of each state (sorted)
+
+    // N as a chunk automaton over sets of states (the NFA device of Sect. 2),
+    // when it has at most kNfaMaxStates states: a move of a set S on class k
+    // is follow(S) & mask(k), follow(S) the union of follow(q) over q in S
+    // (a position automaton enters state p only on p's symbols).
+    uint32_t nfa_words = 0;               // 64-bit words of a set (1, 2 or 4); 0 = too many states
+    std::vector<uint64_t> nfa_follow;     // [n][nfa_words]
+    std::vector<uint64_t> nfa_mask;       // [K][nfa_words]
 };
+
+constexpr uint32_t kNfaMaxStates = 256;
 
 // Throws BuildError (RI_ERR_PARSE / RI_ERR_LIMIT).
 void build_automata(const std::string &re, uint32_t max_states, Automata &out);

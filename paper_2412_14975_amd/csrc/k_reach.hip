@@ -1,0 +1,764 @@
+// HIP kernels of the recognizer for gfx950 (CDNA4, wave64).
+//
+// Reach phase (Sect. 2): for every chunk and every start state of the chunk
+// automaton, one deterministic run over the chunk; its end state (or "no
+// run") is the chunk map lambda_i.  Integer table lookups only; no MFMA work
+// exists on this path.
+//
+//   plain_kernel  every (chunk, start) run to the chunk end or its death, as
+//                 the paper's reach phase is stated.
+//   warm_kernel + long_kernel
+//                 the same chunk maps with state convergence, an optimization
+//                 the paper names as compatible with the RI-DFA (Sect. 5):
+//                 every run is scanned for a short warm-up; the runs of one
+//                 chunk that are then in the same state have the same future
+//                 (the chunk automaton is deterministic), so they are merged
+//                 into one run that alone is scanned to the chunk end.
+//
+// Join phase: an associative composition of chunk maps over a tree of
+// groups of G consecutive members.
+//   Relations (RI-DFA, Sect. 3.2): row s of a chunk is the content of
+//   lambda_i({s}), a set of interface states.  Composing two chunks unions
+//   the rows of the second over the set bits of the first, which is
+//   PLAS_i = lambda_i(if(PLAS_{i-1}) & PIS_i) taken for every PLAS_{i-1}.
+//   Functions (DFA, Sect. 2): lambda_i is a partial map Q -> Q; composition
+//   is a gather.
+// finalize: row 0 (the initial state) of the composition of all chunks,
+// the acceptance test and the minimal-DFA state of the result.
+#include "device.hpp"
+
+#include <mutex>
+#include <unordered_map>
+
+namespace ri {
+namespace {
+
+// ---------------------------------------------------------------------------
+// plain reach
+// ---------------------------------------------------------------------------
+//
+// A job is 64 consecutive chunks x R consecutive starts: lane l scans chunk
+// (64*cg + l) from the R starts at once, so the R runs share each byte and
+// class lookup and give the lane R independent lookup chains.  Jobs are
+// numbered start-group-major and handed out by a global counter to
+// persistent blocks.
+template <typename TE, typename TL, int R, bool LDS>
+__global__ void __launch_bounds__(1024) plain_kernel(PlainArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const TE *tab;
+    const uint16_t *cls;
+    stage_tables<TE, LDS>(a.s, smem, tab, cls);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x % kWave;
+    TL *lam = reinterpret_cast<TL *>(a.lam);
+    for (;;) {
+        const uint32_t job = wave_ticket(a.job_counter);
+        if (job >= a.njobs) break;
+        const uint32_t g = job / a.chunk_groups;
+        const uint32_t chunk = (job - g * a.chunk_groups) * kWave + lane;
+        const bool ok = chunk < a.s.nchunks;
+        uint64_t begin = 0, end = 0;
+        bool first = false;
+        if (ok) chunk_bounds(a.s, chunk, begin, end, first);
+        uint32_t st[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t s = g * R + r;
+            // the first chunk of a text is scanned from the initial state only (I_1 = {q0})
+            st[r] = (ok && s < a.s.L && (!first || s == 0)) ? a.s.starts[s] : a.s.dead;
+        }
+        scan_shared<TE, R>(st, begin, end, tab, cls, a.s.dead);
+        if (ok) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t s = g * R + r;
+                if (s < a.s.L)
+                    lam[(uint64_t)s * a.s.nchunks + chunk] =
+                        st[r] == a.s.dead ? all_ones<TL>() : (TL)(st[r] / a.s.row_bytes);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// converging reach, step 1: warm-up and merging
+// ---------------------------------------------------------------------------
+//
+// One wavefront per chunk; a block of 16 waves takes 16 consecutive chunks
+// at a time (static grid-stride schedule).  The lanes hold the starts, R per
+// lane (start s = base + r * 64 + lane), in blocks of 64 R starts.  The
+// chunk's first `warm` bytes are loaded once, 64 per register, as byte codes;
+// step j broadcasts code j to the wave with readlane, so every lookup of the
+// warm-up is a table access.  After the warm-up the runs of the chunk that
+// are in the same state form one class (one merged run): a leader loop finds
+// the distinct states (one ballot each), lane i keeps the state of class i.
+// A chunk with more than 64 distinct states keeps every live start as its own
+// run (numbered in start order).  The run slots of the block's 16 chunks come
+// from one atomic; the alias row of a chunk ([nchunks][L], class of every
+// start) is written contiguously.
+// Merging by hashing (interfaces of at most 64 R starts, one start block).
+// Each wave owns a table of kMergeSlots slots in LDS; in a round every
+// pending run writes its state into slot hash(state, round), reads it back
+// and is settled when it finds its own state there (one state per slot and
+// round); settled runs elect one representative per slot and the
+// representatives number the classes in (register, lane) order.  A run whose
+// slot was taken by another state tries the next round's hash.  Runs of one
+// class get one class number whatever their register or lane.
+constexpr uint32_t kMergeSlots = 256;
+constexpr uint32_t kMergeSplit = 8;    // bytes scanned by every start between merges while > 64 classes
+
+struct MergeArea {
+    volatile uint32_t *key;    // [kMergeSlots] state offsets; then states by class
+    volatile uint8_t *id;      // [kMergeSlots] representative (register * 64 + lane)
+    volatile uint8_t *rank;    // [kMergeSlots] class number of the slot's state
+};
+
+__device__ __forceinline__ uint32_t merge_hash(uint32_t st, uint32_t round) {
+    return ((st ^ (round * 0x7F4A7C15u)) * 0x9E3779B1u) >> 24;
+}
+
+// Classes of the live runs st[0..R) of the wave: cls[r] in [0, D) or kNone
+// for a dead run.  Returns D (wave-uniform).
+template <int R>
+__device__ uint32_t merge_runs(const uint32_t (&st)[R], uint32_t dead, uint32_t lane, uint64_t lane_lt,
+                               const MergeArea &m, uint32_t (&cls)[R]) {
+    static_assert(kMergeSlots == 256 && R * kWave <= 256, "class numbers and slots are bytes");
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    bool pend[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        pend[r] = st[r] != dead;
+        cls[r] = kNone;
+    }
+    uint32_t D = 0;
+    for (uint32_t round = 0;; ++round) {
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r) any |= pend[r];
+        if (__ballot(any) == 0) break;
+        uint32_t h[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) h[r] = merge_hash(st[r], round);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (pend[r]) m.key[h[r]] = st[r];
+        __builtin_amdgcn_wave_barrier();
+        bool got[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) got[r] = pend[r] && m.key[h[r]] == st[r];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (got[r]) m.id[h[r]] = (uint8_t)(r * kWave + lane);
+        __builtin_amdgcn_wave_barrier();
+        uint32_t base = D;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const bool lead = got[r] && m.id[h[r]] == (uint8_t)(r * kWave + lane);
+            const uint64_t b = __ballot(lead);
+            if (lead) m.rank[h[r]] = (uint8_t)(base + (uint32_t)__builtin_popcountll(b & lane_lt));
+            base += (uint32_t)__builtin_popcountll(b);
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (got[r]) {
+                cls[r] = m.rank[h[r]];
+                pend[r] = false;
+            }
+        D = base;
+        __builtin_amdgcn_wave_barrier();   // the next round writes the slots again
+    }
+    return D;
+}
+
+// Warm-up bytes [j0, j1) (wave-uniform) of the runs of G chunks, R registers
+// each; chunk g stops at its own length wlen[g] (wave-uniform).  Codes of
+// bytes 64 q + lane of chunk g in register code[g][q].  Stepping the G
+// chunks together gives the wave G R independent lookup chains.  Leaves
+// early when every run is dead.
+template <typename TE, int R, int NQ, int G>
+__device__ __forceinline__ void warm_steps(uint32_t (&st)[G][R], const uint32_t (&code)[G][NQ],
+                                           const uint32_t (&wlen)[G], uint32_t j0, uint32_t j1, const TE *tab,
+                                           uint32_t dead) {
+#pragma unroll
+    for (uint32_t q = 0; q < (uint32_t)NQ; ++q) {
+        const uint32_t lo = j0 > q * kWave ? j0 : q * kWave;
+        const uint32_t hi = j1 < q * kWave + kWave ? j1 : q * kWave + kWave;
+        for (uint32_t j = lo; j < hi;) {
+            bool alive = false;
+#pragma unroll
+            for (int g = 0; g < G; ++g) alive |= any_alive<R>(st[g], dead);
+            if (__ballot(alive) == 0) return;
+            const uint32_t e = hi - j < 16 ? hi : j + 16;
+            bool full = e - j == 16;
+#pragma unroll
+            for (int g = 0; g < G; ++g) full &= e <= wlen[g];
+            if (full) {
+#pragma unroll
+                for (uint32_t k = 0; k < 16; ++k) {
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)code[g][q], (int)(j - q * kWave + k));
+#pragma unroll
+                        for (int r = 0; r < R; ++r) st[g][r] = next_state<TE>(tab, st[g][r], c);
+                    }
+                }
+            } else {
+                for (uint32_t k = j; k < e; ++k) {
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        if (k >= wlen[g]) continue;
+                        const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)code[g][q], (int)(k - q * kWave));
+#pragma unroll
+                        for (int r = 0; r < R; ++r) st[g][r] = next_state<TE>(tab, st[g][r], c);
+                    }
+                }
+            }
+            j = e;
+        }
+    }
+}
+
+// Warm-up and merging of G chunks whose starts fit one start block (L <= 64
+// R), stepped together: every start runs kMergeSplit bytes, each chunk's
+// runs are merged, and while a chunk has more than 64 classes the runs go on
+// kMergeSplit bytes more; then each chunk's classes move to one register
+// (class k in lane k) for the rest of the warm-up, and a last merge gives
+// the chunk's runs.  cls[g][r]: class of start r * 64 + lane of chunk g
+// (kNone: no run); D[g]: classes (runs) of chunk g.  The states of chunk g's
+// classes are left to emit_runs (they are in `st`/`one`).
+template <typename TE, int R, int NQ, int G>
+__device__ __forceinline__ void warm_merge_chunks(const TE *tab, const StartList &starts, uint32_t L, uint32_t dead,
+                                                  const bool (&ok)[G], const bool (&first)[G],
+                                                  const uint32_t (&code)[G][NQ], const uint32_t (&wlen)[G],
+                                                  uint32_t lane, uint64_t lane_lt, const MergeArea &m,
+                                                  uint32_t (&cls)[G][R], uint32_t (&one)[G], uint32_t (&D)[G],
+                                                  bool &compacted, uint32_t (&st)[G][R]) {
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    uint32_t W = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        W = wlen[g] > W ? wlen[g] : W;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t s = r * kWave + lane;
+            st[g][r] = (ok[g] && s < L && (!first[g] || s == 0)) ? starts[s] : dead;
+        }
+    }
+    uint32_t j = (R == 1 || W < kMergeSplit) ? W : kMergeSplit;
+    warm_steps<TE, R, NQ, G>(st, code, wlen, 0, j, tab, dead);
+    uint32_t Dmax = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        D[g] = merge_runs<R>(st[g], dead, lane, lane_lt, m, cls[g]);
+        Dmax = D[g] > Dmax ? D[g] : Dmax;
+    }
+    while (j < W && Dmax > kWave) {
+        const uint32_t e = W - j < kMergeSplit ? W : j + kMergeSplit;
+        warm_steps<TE, R, NQ, G>(st, code, wlen, j, e, tab, dead);
+        j = e;
+        Dmax = 0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            D[g] = merge_runs<R>(st[g], dead, lane, lane_lt, m, cls[g]);
+            Dmax = D[g] > Dmax ? D[g] : Dmax;
+        }
+    }
+    compacted = j < W;
+    if (!compacted) return;
+    // at most 64 classes per chunk: class k's state in lane k, one register
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (cls[g][r] != kNone) m.key[cls[g][r]] = st[g][r];
+        __builtin_amdgcn_wave_barrier();
+        one[g] = lane < D[g] ? m.key[lane] : dead;
+        __builtin_amdgcn_wave_barrier();
+    }
+    uint32_t one2[G][1];
+#pragma unroll
+    for (int g = 0; g < G; ++g) one2[g][0] = one[g];
+    warm_steps<TE, 1, NQ, G>(one2, code, wlen, j, W, tab, dead);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        one[g] = one2[g][0];
+        uint32_t c2[1];
+        D[g] = merge_runs<1>(one2[g], dead, lane, lane_lt, m, c2);
+        // every lane takes part in the shuffle (a lane without a run still
+        // holds a class's state for the others to read)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t v = (uint32_t)__shfl((int)c2[0], (int)(cls[g][r] == kNone ? 0u : cls[g][r]));
+            cls[g][r] = cls[g][r] == kNone ? kNone : v;
+        }
+        // lane k of `one` holds class c2[k]'s state; keep it in class order
+        __builtin_amdgcn_wave_barrier();
+        if (c2[0] != kNone) m.key[c2[0]] = one[g];
+        __builtin_amdgcn_wave_barrier();
+        one[g] = lane < D[g] ? m.key[lane] : dead;
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Occupancy: a block is 16 waves (4 per SIMD), so two blocks per CU need 8
+// waves per SIMD; without the attribute the kernel's SGPR use allows 7 and
+// only one block fits (the SGPRs over the limit live in VGPR lanes).
+//
+// warm_kernel: interfaces of more than 64 R starts (several start blocks),
+// one chunk per wave, classes by the leader loop of warm_classes.
+template <typename TE, typename TA, int R, bool LDS, int NQ>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) warm_kernel(WarmArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ uint32_t s_count;   // runs placed in this block's region
+    const TE *tab;
+    const uint16_t *cls;
+    stage_tables<TE, LDS>(a.s, smem, tab, cls);
+    const uint32_t L = a.s.L;
+    uint32_t *ss = reinterpret_cast<uint32_t *>(smem + tables_lds<TE, LDS>(a.s.table_bytes));
+    StartList starts;
+    starts.lds = (const __attribute__((address_space(3))) uint32_t *)ss;
+    starts.glb = (const __attribute__((address_space(1))) uint32_t *)a.s.starts;
+    starts.staged = L <= kStageStarts;
+    if (starts.staged)
+        for (uint32_t i = threadIdx.x; i < L; i += blockDim.x) ss[i] = a.s.starts[i];
+    if (threadIdx.x == 0) s_count = 0;
+    __syncthreads();   // tables and starts staged
+    const uint32_t dead = a.s.dead;
+    const uint32_t lane = threadIdx.x % kWave;
+    const uint32_t wave = wave_uniform(threadIdx.x / kWave);
+    const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    TA *alias = reinterpret_cast<TA *>(a.alias);
+    const uint32_t iters = (a.s.nchunks + kWarmWaves - 1) / kWarmWaves;
+
+    // the warm-up bytes of this wave's chunk in iteration `it` (raw, 64 per
+    // register); loaded one iteration ahead
+    auto fetch = [&](uint32_t it, uint32_t (&raw)[NQ], uint64_t &b, uint32_t &wlen, bool &first) {
+        const uint32_t chunk = it * kWarmWaves + wave;
+        uint64_t e = 0;
+        b = 0;
+        first = false;
+        wlen = 0;
+        if (it < iters && chunk < a.s.nchunks) {
+            chunk_bounds(a.s, chunk, b, e, first);
+            wlen = (uint32_t)(e - b < a.warm ? e - b : a.warm);
+        }
+        b = wave_uniform(b);
+        wlen = wave_uniform(wlen);
+        first = wave_uniform((uint32_t)first) != 0;
+#pragma unroll
+        for (uint32_t q = 0; q < (uint32_t)NQ; ++q) {
+            const uint32_t j = q * kWave + lane;
+            raw[q] = j < wlen ? (uint32_t)*at(b + j) : 0u;
+        }
+    };
+    uint32_t raw[NQ];
+    uint64_t b;
+    uint32_t wlen;
+    bool first;
+    fetch(blockIdx.x, raw, b, wlen, first);
+    const uint64_t region = warm_region(blockIdx.x, gridDim.x, iters, L, kWarmWaves);
+    for (uint32_t it = blockIdx.x; it < iters; it += gridDim.x) {
+        const uint32_t chunk = it * kWarmWaves + wave;
+        const bool ok = chunk < a.s.nchunks;
+        uint32_t code[NQ];
+#pragma unroll
+        for (uint32_t q = 0; q < (uint32_t)NQ; ++q) code[q] = q * kWave + lane < wlen ? cls[raw[q]] : 0u;
+        const uint32_t cur_wlen = wlen;
+        const bool cur_first = first;
+        fetch(it + gridDim.x, raw, b, wlen, first);   // next iteration's bytes, in flight meanwhile
+        TA *arow = alias + (uint64_t)(ok ? chunk : 0) * L;
+        uint32_t al[R], D, cs;
+        bool spill;
+        warm_classes<TE, TA, R, NQ>(tab, starts, L, dead, ok, cur_first, code, cur_wlen, arow, lane, al, D, cs, spill);
+        // slots from the block's region: an LDS counter, no barrier
+        uint32_t base = 0;
+        if (lane == 0 && ok) base = atomicAdd(&s_count, D);
+        const uint32_t firstrun = (uint32_t)(region + (uint32_t)__shfl((int)base, 0));
+        if (ok) {
+            if (lane == 0) {
+                a.run_base[chunk] = firstrun;
+                if (a.run_count) a.run_count[chunk] = D;
+                if (D > kRowCap) atomicOr(&a.counters[2], 1u);
+            }
+            warm_records<TE, TA, R, NQ>(tab, starts, L, dead, a.s.row_bytes, cur_first, code, cur_wlen, arow, lane,
+                                    lane_lt, al, D, cs, spill, firstrun, chunk, a.run_chunk, a.run_state);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) a.block_count[blockIdx.x] = s_count;
+}
+
+// warmg_kernel: interfaces of at most 64 R starts.  A wave takes G chunks
+// at a time (G consecutive chunks of the block's a.cpi = 16 G) and steps
+// their runs together, merging by hashing in its own LDS table.
+template <typename TE, typename TA, int R, bool LDS, int NQ>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) warmg_kernel(WarmArgs a) {
+    constexpr int G = (int)warm_chunks_per_wave(true, R, NQ);
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ uint32_t s_count;   // runs placed in this block's region
+    const TE *tab;
+    const uint16_t *cls;
+    stage_tables<TE, LDS>(a.s, smem, tab, cls);
+    const uint32_t L = a.s.L;
+    uint32_t *ss = reinterpret_cast<uint32_t *>(smem + tables_lds<TE, LDS>(a.s.table_bytes));
+    StartList starts;
+    starts.lds = (const __attribute__((address_space(3))) uint32_t *)ss;
+    starts.glb = (const __attribute__((address_space(1))) uint32_t *)a.s.starts;
+    starts.staged = L <= kStageStarts;
+    if (starts.staged)
+        for (uint32_t i = threadIdx.x; i < L; i += blockDim.x) ss[i] = a.s.starts[i];
+    if (threadIdx.x == 0) s_count = 0;
+    __syncthreads();   // tables and starts staged
+    const uint32_t dead = a.s.dead;
+    const uint32_t lane = threadIdx.x % kWave;
+    const uint32_t wave = wave_uniform(threadIdx.x / kWave);
+    uint8_t *marea = smem + warm_merge_offset(tables_lds<TE, LDS>(a.s.table_bytes), L) + wave * kWarmMergeBytes;
+    const MergeArea merge{reinterpret_cast<volatile uint32_t *>(marea),
+                          reinterpret_cast<volatile uint8_t *>(marea + 4 * kMergeSlots),
+                          reinterpret_cast<volatile uint8_t *>(marea + 5 * kMergeSlots)};
+    const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    TA *alias = reinterpret_cast<TA *>(a.alias);
+    const uint32_t cpi = kWarmWaves * G;
+    const uint32_t iters = (a.s.nchunks + cpi - 1) / cpi;
+
+    // the warm-up bytes of the wave's chunks in iteration `it` (raw, 64 per
+    // register); loaded one iteration ahead
+    auto fetch = [&](uint32_t it, uint32_t (&raw)[G][NQ], uint32_t (&wlen)[G], bool (&first)[G]) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint32_t chunk = it * cpi + wave * G + g;
+            uint64_t b = 0, e = 0;
+            bool f = false;
+            uint32_t w = 0;
+            if (it < iters && chunk < a.s.nchunks) {
+                chunk_bounds(a.s, chunk, b, e, f);
+                w = (uint32_t)(e - b < a.warm ? e - b : a.warm);
+            }
+            b = wave_uniform(b);
+            wlen[g] = wave_uniform(w);
+            first[g] = wave_uniform((uint32_t)f) != 0;
+#pragma unroll
+            for (uint32_t q = 0; q < (uint32_t)NQ; ++q) {
+                const uint32_t j = q * kWave + lane;
+                raw[g][q] = j < wlen[g] ? (uint32_t)*at(b + j) : 0u;
+            }
+        }
+    };
+    uint32_t raw[G][NQ], wlen[G];
+    bool first[G];
+    fetch(blockIdx.x, raw, wlen, first);
+    const uint64_t region = warm_region(blockIdx.x, gridDim.x, iters, L, cpi);
+    for (uint32_t it = blockIdx.x; it < iters; it += gridDim.x) {
+        const uint32_t chunk0 = it * cpi + wave * G;
+        uint32_t code[G][NQ], cur_wlen[G];
+        bool ok[G], cur_first[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            ok[g] = chunk0 + g < a.s.nchunks;
+            cur_wlen[g] = wlen[g];
+            cur_first[g] = first[g];
+#pragma unroll
+            for (uint32_t q = 0; q < (uint32_t)NQ; ++q) code[g][q] = q * kWave + lane < wlen[g] ? cls[raw[g][q]] : 0u;
+        }
+        fetch(it + gridDim.x, raw, wlen, first);   // next iteration's bytes, in flight meanwhile
+        uint32_t cl[G][R], one[G], D[G], st[G][R];
+        bool compacted;
+        warm_merge_chunks<TE, R, NQ, G>(tab, starts, L, dead, ok, cur_first, code, cur_wlen, lane, lane_lt, merge, cl,
+                                        one, D, compacted, st);
+        // runs and alias rows, chunk by chunk: class k's state to lane k
+        // (from the table when the runs were not compacted)
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint32_t chunk = chunk0 + g;
+            uint32_t fst[R];
+            if (compacted) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) fst[r] = r == 0 ? one[g] : dead;
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (cl[g][r] != kNone) merge.key[cl[g][r]] = st[g][r];
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int r = 0; r < R; ++r) fst[r] = r * kWave + lane < D[g] ? merge.key[r * kWave + lane] : dead;
+                __builtin_amdgcn_wave_barrier();
+            }
+            uint32_t base = 0;
+            if (lane == 0 && ok[g]) base = atomicAdd(&s_count, D[g]);
+            const uint32_t firstrun = (uint32_t)(region + (uint32_t)__shfl((int)base, 0));
+            if (ok[g]) {
+                if (lane == 0) {
+                    a.run_base[chunk] = firstrun;
+                    if (a.run_count) a.run_count[chunk] = D[g];
+                    if (D[g] > kRowCap) atomicOr(&a.counters[2], 1u);
+                }
+                TA *arow = alias + (uint64_t)chunk * L;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const uint32_t k = r * kWave + lane;
+                    if (k < D[g]) {
+                        a.run_chunk[firstrun + k] = chunk;
+                        a.run_state[firstrun + k] = fst[r] / a.s.row_bytes;
+                    }
+                    if (k < L) arow[k] = cl[g][r] == kNone ? all_ones<TA>() : (TA)cl[g][r];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) a.block_count[blockIdx.x] = s_count;
+}
+
+// ---------------------------------------------------------------------------
+// converging reach, step 2: merged runs to the chunk end
+// ---------------------------------------------------------------------------
+//
+// A job is 64 x R runs; lane l takes runs (job*64R + r*64 + l).  The R runs
+// of a lane belong to different chunks: each loads its own 16-byte blocks,
+// and the 16 x R lookups of one block step are interleaved so the lane has
+// R independent chains in flight.  Runs of equal length (all but the last
+// chunk's) advance in lockstep; a lane whose runs differ finishes them one
+// by one.
+// Exclusive prefix of the warm-up blocks' run counts in LDS: run i of the
+// dense numbering is in the region of block b with pre[b] <= i < pre[b + 1].
+// Ends with a barrier.
+__device__ __forceinline__ void run_prefix(uint32_t *pre, const uint32_t *block_count, uint32_t G) {
+    for (uint32_t i = threadIdx.x; i < G; i += blockDim.x) pre[i + 1] = block_count[i];
+    __syncthreads();
+    const uint32_t lane = threadIdx.x % kWave;
+    if (threadIdx.x < kWave) {
+        uint32_t carry = 0;
+        for (uint32_t b0 = 0; b0 < G; b0 += kWave) {
+            const uint32_t v = b0 + lane < G ? pre[b0 + lane + 1] : 0u;
+            uint32_t incl = v;
+#pragma unroll
+            for (int k = 1; k < kWave; k <<= 1) {
+                const uint32_t o = __shfl_up(incl, k);
+                if ((int)lane >= k) incl += o;
+            }
+            if (b0 + lane < G) pre[b0 + lane + 1] = carry + incl;
+            carry += (uint32_t)__shfl((int)incl, kWave - 1);
+        }
+        if (lane == 0) pre[0] = 0;
+    }
+    __syncthreads();
+}
+
+// Slot of dense run i (binary search of the prefix).
+__device__ __forceinline__ uint32_t run_slot(const uint32_t *pre, uint32_t G, uint32_t iters, uint32_t L,
+                                             uint32_t cpi, uint32_t i) {
+    uint32_t lo = 0, hi = G;   // pre[lo] <= i < pre[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (pre[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return (uint32_t)(warm_region(lo, G, iters, L, cpi) + (i - pre[lo]));
+}
+
+template <typename TE, int R, bool LDS>
+__global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const TE *tab;
+    const uint16_t *cls;
+    stage_tables<TE, LDS>(a.s, smem, tab, cls);
+    const uint32_t G = a.warm_blocks;
+    uint32_t *pre = reinterpret_cast<uint32_t *>(smem + tables_lds<TE, LDS>(a.s.table_bytes));
+    run_prefix(pre, a.block_count, G);
+    const uint32_t lane = threadIdx.x % kWave;
+    const uint32_t iters = (a.s.nchunks + a.cpi - 1) / a.cpi;
+    auto phys = [&](uint32_t i) -> uint32_t { return run_slot(pre, G, iters, a.s.L, a.cpi, i); };
+    const uint32_t nruns = pre[G];
+    const uint32_t per_job = kWave * R;
+    const uint32_t njobs = (nruns + per_job - 1) / per_job;
+    const uint32_t dead = a.s.dead;
+    // jobs cost about the same (runs of one chunk length): static schedule
+    const uint32_t nwaves_grid = gridDim.x * (blockDim.x / kWave);
+    for (uint32_t job = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; job < njobs;
+         job += nwaves_grid) {
+        uint64_t p[R], vend[R], end[R];
+        uint32_t st[R];
+        bool ok[R];
+        uint32_t ri[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t i = job * per_job + r * kWave + lane;
+            ok[r] = i < nruns;
+            p[r] = vend[r] = end[r] = 0;
+            st[r] = dead;
+            ri[r] = 0;
+            if (ok[r]) {
+                ri[r] = phys(i);
+                uint64_t b, e;
+                bool first;
+                chunk_bounds(a.s, a.run_chunk[ri[r]], b, e, first);
+                p[r] = b + a.warm < e ? b + a.warm : e;
+                vend[r] = p[r] + ((e - p[r]) & ~(uint64_t)15);
+                end[r] = e;
+                st[r] = a.run_state[ri[r]] * a.s.row_bytes;
+            }
+        }
+        // lockstep 64-byte block loop with one block of read-ahead per run.
+        // A run that has no whole block left is parked on the dead row (so
+        // that stepping it changes nothing) until the lane's other runs are
+        // done; its state is restored for the ragged remainder.
+        uint64_t bend[R];
+        uint32_t parked[R];
+        bool pk[R];
+        uint4 cur[R][4];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            bend[r] = p[r] + ((end[r] - p[r]) & ~(uint64_t)63);
+            pk[r] = false;
+            parked[r] = dead;
+            if (ok[r] && p[r] < bend[r]) load64(cur[r], at(p[r]));
+            else cur[r][0] = cur[r][1] = cur[r][2] = cur[r][3] = make_uint4(0, 0, 0, 0);
+        }
+        for (;;) {
+            bool work = false;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (ok[r] && !pk[r] && p[r] >= bend[r]) {
+                    parked[r] = st[r];
+                    st[r] = dead;
+                    pk[r] = true;
+                }
+                work |= ok[r] && !pk[r] && st[r] != dead;
+            }
+            if (__ballot(work) == 0) break;
+            if (work) {
+                uint4 nxt[R][4];
+                bool act[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    act[r] = ok[r] && !pk[r] && st[r] != dead;
+                    const uint64_t q = act[r] && p[r] + 64 < bend[r] ? p[r] + 64 : p[r];
+                    if (act[r]) load64(nxt[r], at(q));
+                    else nxt[r][0] = nxt[r][1] = nxt[r][2] = nxt[r][3] = make_uint4(0, 0, 0, 0);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    uint4 v[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) v[r] = cur[r][q];
+                    step16_each<TE, R>(st, v, tab, cls);
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) cur[r][q] = nxt[r][q];
+                    p[r] += act[r] ? 64 : 0;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (pk[r]) st[r] = parked[r];
+        // remaining blocks and ragged tails, run by run
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (ok[r]) {
+                const uint32_t f = scan_lane<TE>(st[r], p[r], vend[r], end[r], tab, cls, dead);
+                a.run_final[ri[r]] = f == dead ? kNoState : f / a.s.row_bytes;
+            }
+        }
+    }
+}
+
+const void *g_fn = nullptr;   // set by the dispatch below when only the function is wanted
+
+}  // namespace
+
+hipError_t launch_plain(const PlainArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st) {
+    return dispatch_te(k.entry_bytes, [&](auto te) {
+        return dispatch_tl(k.tile_bytes, [&](auto tl) {
+            return dispatch_r(k.runs_per_lane, [&](auto r) {
+                return dispatch_b(k.table_in_lds, [&](auto lds_t) {
+                    auto fn = plain_kernel<decltype(te), decltype(tl), decltype(r)::value, decltype(lds_t)::value>;
+                    if (grid == 0) { g_fn = reinterpret_cast<const void *>(fn); return hipSuccess; }
+                    hipLaunchKernelGGL(fn, dim3(grid), dim3(k.block_threads), lds, st, a);
+                    return hipGetLastError();
+                });
+            });
+        });
+    });
+}
+
+hipError_t launch_warm(const WarmArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st) {
+    return dispatch_te(k.entry_bytes, [&](auto te) {
+        return dispatch_ta(k.alias_bytes, [&](auto ta) {
+            return dispatch_r(k.runs_per_lane, [&](auto r) {
+                return dispatch_b(k.table_in_lds, [&](auto lds_t) {
+                    return dispatch_b(k.code_regs == 1, [&](auto one) {
+                        constexpr int NQ = decltype(one)::value ? 1 : 4;
+                        constexpr int R = decltype(r)::value;
+                        using TE = decltype(te);
+                        using TA = decltype(ta);
+                        constexpr bool L_ = decltype(lds_t)::value;
+                        auto fn = k.hashed ? warmg_kernel<TE, TA, R, L_, NQ> : warm_kernel<TE, TA, R, L_, NQ>;
+                        if (grid == 0) { g_fn = reinterpret_cast<const void *>(fn); return hipSuccess; }
+                        hipLaunchKernelGGL(fn, dim3(grid), dim3(k.block_threads), lds, st, a);
+                        return hipGetLastError();
+                    });
+                });
+            });
+        });
+    });
+}
+
+size_t warm_lds_bytes(const KernelShape &k, uint32_t table_bytes, uint32_t L) {
+    const size_t merge = k.hashed ? (size_t)kWarmWaves * kWarmMergeBytes : 0;
+    return warm_merge_offset((k.table_in_lds ? table_bytes : 0) + 512, L) + merge;
+}
+
+hipError_t launch_long(const LongArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st) {
+    return dispatch_te(k.entry_bytes, [&](auto te) {
+        return dispatch_r(k.runs_per_lane, [&](auto r) {
+            return dispatch_b(k.table_in_lds, [&](auto lds_t) {
+                auto fn = long_kernel<decltype(te), decltype(r)::value, decltype(lds_t)::value>;
+                if (grid == 0) { g_fn = reinterpret_cast<const void *>(fn); return hipSuccess; }
+                hipLaunchKernelGGL(fn, dim3(grid), dim3(k.block_threads), lds, st, a);
+                return hipGetLastError();
+            });
+        });
+    });
+}
+
+// Occupancy does not change for a kernel instance, its block size, LDS size
+// and device: the answers are kept so that a call queries each shape once.
+int blocks_per_cu(int which, const KernelShape &k, size_t lds) {
+    static std::mutex mu;
+    static std::unordered_map<uint64_t, int> known;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return 0;
+    // fields: which 3 bits, entry/tile/alias bytes and runs per lane 3 bits
+    // each (values <= 4), LDS flag, waves per block 5 bits, LDS bytes 18 bits
+    // (<= 160 KiB), device 12 bits, warm-up code registers 3 bits
+    const uint64_t key = (uint64_t)(which & 7) | (uint64_t)(k.entry_bytes & 7) << 3 |
+                         (uint64_t)(k.tile_bytes & 7) << 6 | (uint64_t)(k.alias_bytes & 7) << 9 |
+                         (uint64_t)(k.runs_per_lane & 7) << 12 | (uint64_t)(k.table_in_lds ? 1 : 0) << 15 |
+                         (uint64_t)((k.block_threads / 64) & 31) << 16 | (uint64_t)(lds & 0x3ffff) << 21 |
+                         (uint64_t)(device & 0xfff) << 39 | (uint64_t)(k.code_regs & 7) << 51 |
+                         (uint64_t)(k.hashed ? 1 : 0) << 54;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = known.find(key);
+        if (it != known.end()) return it->second;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    g_fn = nullptr;
+    hipError_t e = hipSuccess;
+    if (which == 0) e = launch_plain(PlainArgs{}, k, 0, lds, nullptr);
+    else if (which == 1) e = launch_warm(WarmArgs{}, k, 0, lds, nullptr);
+    else e = launch_long(LongArgs{}, k, 0, lds, nullptr);
+    if (e != hipSuccess || !g_fn) return 0;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, g_fn, k.block_threads, lds) != hipSuccess) return 0;
+    if (nb > 0) known[key] = nb;
+    return nb;
+}
+
+}  // namespace ri

@@ -38,7 +38,15 @@ struct KernelShape {
     bool table_in_lds;
     int block_threads;         // 1024
     int code_regs = 4;         // warm-up: registers of 64 byte codes (1 when the warm-up is <= 64 bytes)
+    bool hashed = false;       // warm-up: starts fit one start block (L <= 64 runs_per_lane), merging by hashing
 };
+
+// Chunks that one warm-up wave takes at a time: with merging by hashing the
+// wave interleaves the runs of several chunks (independent lookup chains)
+// within the same register budget; otherwise one.
+__host__ __device__ constexpr uint32_t warm_chunks_per_wave(bool hashed, int runs_per_lane, int code_regs) {
+    return !hashed ? 1u : (runs_per_lane == 4 || code_regs == 4) ? 2u : 4u;
+}
 
 // ---- plain reach: every (chunk, start) run to the chunk end or its death ----
 struct PlainArgs {
@@ -53,14 +61,15 @@ hipError_t launch_plain(const PlainArgs &a, const KernelShape &k, int grid, size
 // ---- converging reach, step 1: warm-up of every run, then merging of runs
 // of one chunk that are in the same state (state convergence) ----
 //
-// Run slots: warm-up block b (of G, each taking kWarmChunksPerBlock chunks
-// per iteration of `iters`) owns the region of the run arrays that holds L
-// runs for each of its chunks, starting at warm_region(b); it fills its
-// region from the front and reports the count in block_count[b].
+// Run slots: warm-up block b (of G, each taking cpi chunks per iteration of
+// `iters`) owns the region of the run arrays that holds L runs for each of
+// its chunks, starting at warm_region(b); it fills its region from the front
+// and reports the count in block_count[b].  A block is kWarmChunksPerBlock
+// waves; cpi = kWarmChunksPerBlock * warm_chunks_per_wave(...).
 constexpr uint32_t kWarmChunksPerBlock = 16;
-__host__ __device__ inline uint64_t warm_region(uint32_t b, uint32_t G, uint32_t iters, uint32_t L) {
+__host__ __device__ inline uint64_t warm_region(uint32_t b, uint32_t G, uint32_t iters, uint32_t L, uint32_t cpi) {
     const uint64_t q = iters / G, r = iters % G;
-    return (uint64_t)kWarmChunksPerBlock * L * ((uint64_t)b * q + (b < r ? b : r));
+    return (uint64_t)cpi * L * ((uint64_t)b * q + (b < r ? b : r));
 }
 struct WarmArgs {
     ScanArgs s;
@@ -72,6 +81,7 @@ struct WarmArgs {
     uint32_t *run_state;       // [cap] state id after the warm-up
     uint32_t *counters;        // [2] set to 1 when a chunk has more than kRowCap runs
     uint32_t *block_count;     // [grid] runs in each block's region
+    uint32_t cpi;              // chunks per block iteration
 };
 hipError_t launch_warm(const WarmArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st);
 size_t warm_lds_bytes(const KernelShape &k, uint32_t table_bytes, uint32_t L);
@@ -85,6 +95,7 @@ struct LongArgs {
     uint32_t *run_final;       // state id at the chunk end, kNoState if the run died
     const uint32_t *block_count;   // runs of each warm-up block's region
     uint32_t warm_blocks;      // grid of the warm-up kernel
+    uint32_t cpi;              // chunks per warm-up block iteration
 };
 hipError_t launch_long(const LongArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st);
 
@@ -146,6 +157,7 @@ struct ClsJoinArgs {
     const uint32_t *grp_count;
     const uint32_t *member_chunk;
     uint32_t ngroups;          // with explicit groups
+    const uint32_t *gate;      // non-null: every kernel of the join returns at once while *gate == 0
 };
 size_t cls_join_lds(const ClsJoinArgs &a, int W, int alias_bytes);
 hipError_t launch_join_cls(const ClsJoinArgs &a, int W, int alias_bytes, bool level0, hipStream_t s);
@@ -199,16 +211,20 @@ hipError_t launch_finalize_cls(const FinalArgs &f, const ClsJoinArgs &a, int W, 
 // single chunk) and the final step, in one launch.
 // result[2] = counters[2] (1: the hit-matrix result is not valid).  With
 // out != nullptr an invalid result is redone by propagation in the same
-// launch (prop_words <= kPropMaxWords) and {accept, final} is copied to out.
+// launch (prop_words <= kPropMaxWords) and {accept, final} is copied to out;
+// with gated_after the kernel instead leaves out untouched and counters[2]
+// set, for a class join gated on counters[2] that the caller enqueues next.
 constexpr uint32_t kHitTailMax = 64;
 hipError_t launch_finalize_hit(const FinalArgs &f, const HitArgs &a, int W, int alias_bytes, hipStream_t s,
-                               int32_t *out = nullptr, uint32_t prop_words = 0);
+                               int32_t *out = nullptr, uint32_t prop_words = 0, bool gated_after = false);
 // Join by propagating the set of N' states chunk after chunk (one block; any
 // number of runs per chunk, any interface size up to kPropMaxWords * 32).
 constexpr uint32_t kPropMaxWords = 1024;
 hipError_t launch_propagate(const FinalArgs &f, const HitArgs &a, uint32_t W, int alias_bytes, hipStream_t s);
 // out[0] = accept, out[1] = final_state, in stream order
 hipError_t launch_store_result(int32_t *out, int32_t accept, int32_t final_state, hipStream_t s);
+// p[0 .. n) = 0 in stream order (a kernel, so that a captured graph replays it)
+hipError_t launch_zero_words(uint32_t *p, uint32_t n, hipStream_t s);
 
 // Batch results, one per text, from the last join level (one group per
 // text, in text order): a class-partitioned relation or a function.
@@ -224,6 +240,35 @@ hipError_t launch_batch_final_cls(const BatchFinalArgs &b, const FinalArgs &f, c
 hipError_t launch_batch_final_fun(const BatchFinalArgs &b, const FinalArgs &f, uint32_t L, hipStream_t s);
 // results of texts whose automaton accepts nothing: (0, -1)
 hipError_t launch_batch_fill(const BatchFinalArgs &b, hipStream_t s);
+
+// ---- NFA device: the position NFA as chunk automaton over sets of states ----
+struct NfaArgs {
+    const uint8_t *text;       // one text, 16-byte aligned
+    uint64_t n, cs;            // length, chunk size (multiple of 16)
+    uint32_t nchunks;
+    const uint64_t *follow;    // [L][W] follow sets
+    const uint64_t *mask;      // [K][W] states entered on class k
+    const uint8_t *cls;        // byte -> class
+    uint32_t L, K, W;          // NFA states, classes, 64-bit words of a set (1, 2, 4)
+    uint64_t *maps;            // [nchunks][L][W] set reached from each single state
+    uint32_t *job_counter;     // zero on entry
+    uint32_t njobs;            // L * chunk_groups
+    uint32_t chunk_groups;     // ceil(nchunks / 64)
+};
+hipError_t launch_nfa_reach(const NfaArgs &a, int grid, hipStream_t s);
+
+// groups of G consecutive relations [nin][L][W] composed into [ngroups][L][W]
+struct NfaJoinArgs {
+    const uint64_t *in;
+    uint32_t nin;
+    uint64_t *out;
+    uint32_t L, W, G;
+};
+hipError_t launch_nfa_join(const NfaJoinArgs &a, hipStream_t s);
+// row q0 of total ([L][W], the last relation): f.result = {accept, final state}
+// (f.fmask, f.hash, f.csr_* describe the powerset DFA's states as sets of N's
+// states); out (may be null) receives a copy
+hipError_t launch_nfa_final(const FinalArgs &f, const uint64_t *total, uint32_t W, int32_t *out, hipStream_t s);
 
 // ---- fused batches: many automata in one launch sequence ----
 //

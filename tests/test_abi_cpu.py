@@ -130,7 +130,7 @@ def _compare_with_oracle(pattern):
         assert info["min_dfa_states"] == ref.dfa.n
         assert info["subset_dfa_states"] == oracle.subset_dfa(ref.nfa)[0].n
         assert info["accepts_empty"] == (0 in ref.dfa.final)
-        assert info["starts"] == [ref.nfa_q.n, ref.dfa.n, info["subset_dfa_states"]]
+        assert info["starts"] == [ref.nfa_q.n, ref.dfa.n, info["subset_dfa_states"], ref.nfa.n]
         got = {frozenset(ri.ri_state_content(h, "rid", p)) for p in range(info["ridfa_states"])}
         assert got == set(ref.Bq.content)
     finally:

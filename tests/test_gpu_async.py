@@ -20,7 +20,9 @@ pytestmark = pytest.mark.gpu
 
 ALGOS = ("rid", "dfa", "subset")
 MODES = {"conv64": dict(converge=1, warmup_bytes=64), "conv16": dict(converge=1, warmup_bytes=16),
-         "cls64": dict(converge=1, warmup_bytes=64, join=1), "plain": dict(converge=0)}
+         "cls64": dict(converge=1, warmup_bytes=64, join=1), "plain": dict(converge=0),
+         "conv80": dict(converge=1, warmup_bytes=80), "conv128": dict(converge=1, warmup_bytes=128),
+         "conv256": dict(converge=1, warmup_bytes=256)}
 
 
 @pytest.fixture(scope="module", autouse=True)

@@ -24,7 +24,11 @@ ALGOS = ("rid", "dfa", "subset")
 # reach pipelines: converging (warm-up + merge) with two warm-up lengths and
 # the hit-matrix join, converging with the class join, and plain
 MODES = {"conv64": dict(converge=1, warmup_bytes=64), "conv16": dict(converge=1, warmup_bytes=16),
-         "cls64": dict(converge=1, warmup_bytes=64, join=1), "plain": dict(converge=0)}
+         "cls64": dict(converge=1, warmup_bytes=64, join=1), "plain": dict(converge=0),
+         # warm-ups longer than 64 bytes (four registers of byte codes), also
+         # longer than many chunks of the small texts below
+         "conv80": dict(converge=1, warmup_bytes=80), "conv128": dict(converge=1, warmup_bytes=128),
+         "conv256": dict(converge=1, warmup_bytes=256)}
 
 
 def make(pattern, mode="conv64", runs_per_lane=0):
@@ -417,22 +421,61 @@ def test_motif_union_full_size(seed):
 # log lines: 1 GiB
 # ---------------------------------------------------------------------------
 
-def test_log_lines_full_size():
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_log_lines_full_size(seed):
+    """The 1 GiB log-lines text and its two rejected copies: synchronous
+    calls (RID, all-states DFA; tuned and fixed chunk counts), the queued
+    call (the path the benchmark times) and the plain reach, against the
+    oracle's serial result; chunk maps sampled against the oracle's runs."""
     rx = gen.c3_regex()
     ref = Ref(rx)
-    x, r1, r2 = gen.c3_texts(0)
+    x, r1, r2 = gen.c3_texts(seed)
     assert len(x) > (1 << 30) - 4096
     rec = make(rx, "conv64")
+    plain = make(rx, "plain")
     try:
-        for text in (x, r1, r2):
+        res = torch.full((6, 2), -7, dtype=torch.int32, device="cuda")
+        wants = []
+        for j, text in enumerate((x, r1, r2)):
             want = ref.serial(text)
+            wants.append(want)
             t = dev(text)
             for algo in ("rid", "dfa"):
-                got = rec.recognize(t, algo=algo)
-                assert (got["accept"], got["final_state"]) == want, algo
+                for chunks in ((0, 262144) if j == 0 else (0,)):
+                    got = rec.recognize(t, algo=algo, chunks=chunks)
+                    assert (got["accept"], got["final_state"]) == want, (seed, j, algo, chunks)
+                rec.recognize_async(t, res[2 * j + (algo == "dfa")], algo=algo)
+            if j != 1:
+                got = plain.recognize(t, algo="rid", chunks=65536)
+                assert (got["accept"], got["final_state"]) == want, (seed, j, "plain")
+            torch.cuda.synchronize()
             del t
-        check_maps(rec, ref, x, "rid", 0, sample=4, rng=gen.PCG(1))
-        check_maps(rec, ref, x, "dfa", 0, sample=4, rng=gen.PCG(2))
+        got = res.cpu().numpy()
+        for j, want in enumerate(wants):
+            for a in range(2):
+                assert (bool(got[2 * j + a][0]), int(got[2 * j + a][1])) == want, (seed, j, a, "queued")
+        if seed == 0:
+            check_maps(rec, ref, x, "rid", 0, sample=4, rng=gen.PCG(1))
+            check_maps(rec, ref, x, "dfa", 0, sample=4, rng=gen.PCG(2))
     finally:
         rec.close()
+        plain.close()
     torch.cuda.empty_cache()
+
+
+def test_ri_recognize_entry_point_on_a_side_stream():
+    """ri_recognize itself (RID, automatic chunk count), called through the
+    C ABI on a non-default stream, on the tiny and log-lines expressions."""
+    s = torch.cuda.Stream()
+    for rx, texts in ((gen.c1_regex(), gen.c1_texts(4)), (gen.c3_regex(), gen.c3_texts(3, n=1 << 24)[:3])):
+        ref = Ref(rx)
+        h = ri.binding.ri_build(rx)
+        try:
+            with torch.cuda.stream(s):
+                for x in texts:
+                    t = dev(x)
+                    got = ri.binding.ri_recognize(h, t, stream=s)
+                    assert (got["accept"], got["final_state"]) == ref.serial(x)
+                    assert got["n"] == len(x) and got["chunks"] >= 1
+        finally:
+            ri.binding.ri_free(h)

@@ -105,6 +105,41 @@ def test_fig4_rid_join(fig1):
     assert res["accept"] is exp["accept"]
 
 
+def test_fig1_nfa_step_gives_the_drawn_ridfa_moves(fig1):
+    """The RI-DFA of Fig. 3 is drawn with its contents: the move of a state S
+    on b leads to rho(S, b) (empty = no edge).  nfa_step must give exactly
+    the drawn targets for every drawn state and every symbol."""
+    g, nfa, built = fig1
+    exp = g["ridfa"]
+    want = {}
+    for src, sy, dst in exp["edges"]:
+        for b in syms(sy, g["alphabet"]):
+            want[(fs(src), b)] = fs(dst)
+    for S in exp["states"]:
+        for b in g["alphabet"].encode():
+            assert A.nfa_step(built.nfa, fs(S), b) == want.get((fs(S), b), frozenset()), (S, chr(b))
+    # and on sets that are not RI-DFA states: the union of the singleton moves
+    assert A.nfa_step(built.nfa, fs([1, 2]), ord("b")) == fs([0, 1, 2])
+    assert A.nfa_step(built.nfa, frozenset(), ord("a")) == frozenset()
+
+
+def test_fig4_nfa_chunk_relations(fig1):
+    """NFA as chunk automaton on aab.cab (Fig. 1): lambda_i(q) = rho(q, y_i).
+    The RI-DFA runs of Fig. 4 start at the singletons, so their end-state
+    contents are these sets: chunk 1 from q0 gives {0, 2}, chunk 2 gives
+    {0, 2} from q0 and from q1 and nothing from q2; the composed set after
+    chunk 2 is PLAS_2's content {0, 2}, which meets F = {2}."""
+    g, nfa, built = fig1
+    exp = g["fig4"]
+    res = R.nfa_csdpa(built.nfa, g["text"].encode(), g["bounds"])
+    assert res["lambdas"][0] == {0: fs(exp["lambda1"][0][1])}
+    lam2 = {fs([q]): S for q, S in res["lambdas"][1].items() if S}
+    assert lam2 == {fs(a): fs(b) for a, b in exp["lambda2"]}
+    assert res["lambdas"][1][2] == frozenset()
+    assert res["S"] == fs(exp["plas2"][0])
+    assert res["accept"] is exp["accept"]
+
+
 # ---------------------------------------------------------------------------
 # Fig. 2
 # ---------------------------------------------------------------------------

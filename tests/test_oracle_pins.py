@@ -114,7 +114,7 @@ def test_exhaustive_binary_alphabet(seed):
 def test_exhaustive_ternary_alphabet(seed):
     rng = gen.PCG(5000 + seed)
     pattern = small_pattern(rng, b"abc", int(rng.integers(1, 4)))
-    _check_against_re(pattern, b"abc", 7)
+    _check_against_re(pattern, b"abc", 10)
 
 
 @pytest.mark.parametrize("pattern,alphabet,maxlen", [
@@ -278,3 +278,42 @@ def test_even_bounds():
     assert R.even_bounds(10, 3) == [0, 3, 6, 10]
     assert R.even_bounds(3, 8) == [0, 1, 2, 3]
     assert R.even_bounds(0, 4) == [0, 0]
+
+
+# ---------------------------------------------------------------------------
+# NFA simulation (nfa_step, nfa_reach) and CSDPA with the NFA chunk automaton
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(30))
+def test_nfa_simulation_against_brute_force(seed):
+    """Acceptance by simulating the position NFA with nfa_step from {q0}
+    equals set-semantics membership on every string up to length 8."""
+    rng = gen.PCG(7000 + seed)
+    alphabet = b"abc"[: 2 + seed % 2]
+    pattern = small_pattern(rng, alphabet, int(rng.integers(1, 4)))
+    nfa = A.trim(A.position_nfa(pattern))
+    brute = compile_brute(pattern)
+    for s in strings(alphabet, 8 if len(alphabet) == 2 else 6):
+        S = frozenset([0]) if nfa.n else frozenset()
+        for b in s:
+            S = A.nfa_step(nfa, S, b)
+        assert bool(S & nfa.final) == brute(s), (pattern, s)
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_nfa_csdpa_is_chunk_invariant(seed):
+    """The composed chunk relations give rho(q0, x) for every chunking (the
+    NFA analogue of Lemma 1), so acceptance equals the minimal DFA's."""
+    rng = gen.PCG(8000 + seed)
+    alphabet = b"abcd"[: 2 + seed % 3]
+    pattern = small_pattern(rng, alphabet, int(rng.integers(1, 4)))
+    b = oracle.build(pattern)
+    for n in (1, 7, 60, 257):
+        x = gen.random_text(rng, alphabet, n)
+        whole = R.nfa_reach(b.nfa, [0], x) if b.nfa.n else frozenset()
+        want = R.serial(b.dfa, x)[0]
+        for c in (1, 2, 5, n):
+            cuts = sorted(set([0, n] + [int(v) for v in rng.integers(1, max(2, n), size=c - 1)]))
+            res = R.nfa_csdpa(b.nfa, x, cuts)
+            assert res["S"] == whole, (pattern, n, cuts)
+            assert res["accept"] == want

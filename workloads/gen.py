@@ -588,3 +588,23 @@ def c5_text(rng: np.random.Generator, kws, n: int, plant: bool) -> np.ndarray:
 
 def c5_length(rng: np.random.Generator, median: int = 1 << 16, sigma: float = 1.0, cap: int = 1 << 26) -> int:
     return int(min(cap, max(1, round(float(rng.lognormal(np.log(median), sigma))))))
+
+
+SERVE_SEED = 11
+
+
+def c5_requests(count: int, kws_of, seed: int = SERVE_SEED, keep=None):
+    """The request stream of the serving workload: request i picks automaton
+    k uniform in [0, len(kws_of)), a log-normal length and printable bytes,
+    with a keyword of automaton k planted when i is even.  Yields (i, k, x)
+    for every request whose automaton is in `keep` (all when None); the draws
+    of the skipped requests are still made, so request i is the same byte
+    string whatever `keep` is."""
+    rng = PCG(seed + 1)
+    for i in range(count):
+        k = int(rng.integers(0, len(kws_of)))
+        n = c5_length(rng)
+        if keep is None or k in keep:
+            yield i, k, c5_text(rng, kws_of[k], n, plant=i % 2 == 0)
+        else:
+            c5_text(rng, kws_of[k], n, plant=i % 2 == 0)
