@@ -172,6 +172,30 @@ int ri_recognize_async(const ri_handle *h, const uint8_t *text_dev, size_t n, vo
                        int algo, uint32_t chunks, int32_t *result_dev);
 
 /*
+ * ri_recognize_noalloc -- for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops and harnesses that forbid
+ * hipMalloc): the queued recognition of ri_recognize_async, with the same
+ * arguments and result, that allocates nothing.
+ *
+ * Its scratch memory is one fixed device array of RI_NOALLOC_SCRATCH_BYTES
+ * per GPU, held until the process ends and shared by every call of this
+ * function on that GPU; it keeps the last call's contents.  Calls on one
+ * GPU that overlap in time (different streams, or host threads) race on
+ * it: order them on one stream.  Counters that must start at zero are
+ * cleared by a kernel at the start of each call.
+ *
+ * chunks = 0 chooses the chunk count as ri_recognize_async does and then
+ * halves it until the call fits the array; an explicit chunk count that
+ * does not fit is rejected with RI_ERR_LIMIT (the message gives the bytes
+ * needed).  The handle's tables must already be on the current device
+ * (any earlier recognition call on it uploads them): RI_ERR_ARG otherwise.
+ * Other errors as for ri_recognize_async.
+ */
+#define RI_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int ri_recognize_noalloc(const ri_handle *h, const uint8_t *text_dev, size_t n, void *stream,
+                         int algo, uint32_t chunks, int32_t *result_dev);
+
+/*
  * ri_chunk_maps -- the reach phase only, for inspection: like ri_recognize_ex,
  * and in addition copies the chunk maps lambda_i (Sects. 2 and 3.2) to the
  * host array maps[c * starts + s] (int32, caller-owned, `cap` entries), where

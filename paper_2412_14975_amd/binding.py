@@ -27,7 +27,7 @@ SYMBOLS = ("ri_build", "ri_free", "ri_info", "ri_recognize", "ri_recognize_ex",
            "ri_set_option", "ri_get_option", "ri_autotune", "ri_last_error",
            "ri_batch_create", "ri_batch_free", "ri_batch_run", "ri_batch_capture",
            "ri_batch_launch", "ri_batch_get_info", "ri_batch_get_group", "ri_batch_autotune",
-           "ri_batch_create_ex", "ri_batch_update", "ri_request_footprint")
+           "ri_batch_create_ex", "ri_batch_update", "ri_request_footprint", "ri_recognize_noalloc")
 RI_BATCH_AUTO, RI_BATCH_GROUPED, RI_BATCH_FUSED = 0, 1, 2
 BATCH_MODES = {"auto": RI_BATCH_AUTO, "grouped": RI_BATCH_GROUPED, "fused": RI_BATCH_FUSED}
 RI_OPT_CONVERGE, RI_OPT_WARMUP_BYTES, RI_OPT_RUNS_PER_LANE, RI_OPT_CHUNK_TARGET, RI_OPT_JOIN = 1, 2, 3, 4, 5
@@ -115,6 +115,7 @@ def lib() -> ctypes.CDLL:
     L.ri_recognize.argtypes = [vp, vp, sz, vp, ctypes.POINTER(ri_result)]
     L.ri_recognize_ex.argtypes = [vp, vp, sz, vp, i32, u32, ctypes.POINTER(ri_result)]
     L.ri_recognize_async.argtypes = [vp, vp, sz, vp, i32, u32, vp]
+    L.ri_recognize_noalloc.argtypes = [vp, vp, sz, vp, i32, u32, vp]
     L.ri_chunk_maps.argtypes = [vp, vp, sz, vp, i32, u32, vp, sz, ctypes.POINTER(ri_result)]
     L.ri_state_content.argtypes = [vp, i32, u32, ctypes.POINTER(u32), u32, ctypes.POINTER(u32)]
     L.ri_set_profiling.argtypes = [vp, i32]
@@ -222,6 +223,15 @@ def ri_recognize_async(h: int, text: torch.Tensor, result: torch.Tensor, stream=
     ptr, n = _text_ptr(text)
     _check(lib().ri_recognize_async(h, ptr, n, _stream_ptr(stream), _algo(algo), int(chunks),
                                     _results_ptr(result, 1)))
+
+
+def ri_recognize_noalloc(h: int, text: torch.Tensor, result: torch.Tensor, stream=None, algo="rid",
+                         chunks: int = 0) -> None:
+    """ri_recognize_async with the library's fixed scratch array (no device
+    allocation); the handle's tables must already be on the device."""
+    ptr, n = _text_ptr(text)
+    _check(lib().ri_recognize_noalloc(h, ptr, n, _stream_ptr(stream), _algo(algo), int(chunks),
+                                      _results_ptr(result, 1)))
 
 
 def ri_chunk_maps(h: int, text: torch.Tensor, stream=None, algo="rid", chunks: int = 0):

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libri.so")
 
-SOURCES = ["automata.cpp", "api.cpp", "k_reach.hip", "k_join.hip", "k_batch.hip", "k_nfa.hip"]
+SOURCES = ["automata.cpp", "api.cpp", "k_reach.hip", "k_join.hip", "k_batch.hip", "k_nfa.hip", "noalloc.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",
