@@ -27,7 +27,7 @@ int fail(int code, const std::string &msg) {
 constexpr uint32_t kJoinGroup = 64;          // members per join group
 constexpr uint64_t kMinAutoChunk = 256;      // smallest automatic chunk size (bytes)
 constexpr uint64_t kMaxLamBytes = 1ull << 31;
-constexpr uint64_t kMaxAutoPairs = 1ull << 25;   // (start, chunk) pairs of an automatic chunking
+constexpr uint64_t kMaxAutoPairs = 1ull << 27;   // (start, chunk) pairs of an automatic chunking
 constexpr int kMaxDevices = 64;
 
 uint64_t round_up(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
@@ -1975,7 +1975,7 @@ int ri_autotune(ri_handle *h, const uint8_t *text, size_t n, void *stream, int a
         saved = h->opt;
         h->tuned_valid[algo] = false;
     }
-    static const uint32_t kTargets[] = {32768, 65536, 131072, 262144};
+    static const uint32_t kTargets[] = {32768, 65536, 131072, 262144, 524288};
     static const uint32_t kWarm[] = {16, 32, 64, 128};
     static const uint32_t kRuns[] = {1, 2};
     // the grid: converging reach over targets x warm-up x runs per lane, then

@@ -43,6 +43,13 @@ __host__ __device__ constexpr uint32_t tables_lds(uint32_t table_bytes) {
 
 // One transition: st and c are byte offsets into the table.
 template <typename TE>
+__device__ __forceinline__ uint32_t next_state(const __attribute__((address_space(1))) TE *tab, uint32_t st,
+                                               uint32_t c) {
+    typedef const __attribute__((address_space(1))) uint8_t gb;
+    typedef const __attribute__((address_space(1))) TE gt;
+    return *reinterpret_cast<gt *>(reinterpret_cast<gb *>(tab) + st + c);
+}
+template <typename TE>
 __device__ __forceinline__ uint32_t next_state(const TE *tab, uint32_t st, uint32_t c) {
     return *reinterpret_cast<const TE *>(reinterpret_cast<const uint8_t *>(tab) + st + c);
 }
@@ -60,16 +67,27 @@ __device__ __forceinline__ void step16_shared(uint32_t (&st)[R], const uint4 v, 
     }
 }
 
+// Byte codes (class * entry bytes) of the 256 byte values, one u16 table.
+struct CodeTab {
+    const uint16_t *cls;
+    __device__ __forceinline__ uint32_t operator()(uint32_t b) const { return cls[b]; }
+};
+// The same table in global memory (global loads, not flat ones).
+struct CodeGlobal {
+    const __attribute__((address_space(1))) uint16_t *cls;
+    __device__ __forceinline__ uint32_t operator()(uint32_t b) const { return cls[b]; }
+};
+
 // 16 steps of R runs over R different 16-byte blocks (runs of R chunks).
-template <typename TE, int R>
+template <typename TE, int R, class Code>
 __device__ __forceinline__ void step16_each(uint32_t (&st)[R], const uint4 (&v)[R], const TE *tab,
-                                            const uint16_t *cls) {
+                                            const Code &code) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t w = i < 4 ? v[r].x : i < 8 ? v[r].y : i < 12 ? v[r].z : v[r].w;
-            const uint32_t c = cls[(w >> ((i & 3) * 8)) & 0xffu];
+            const uint32_t c = code((w >> ((i & 3) * 8)) & 0xffu);
             st[r] = next_state<TE>(tab, st[r], c);
         }
     }
@@ -175,6 +193,20 @@ __device__ __forceinline__ uint32_t scan_lane(uint32_t st, uint64_t p, uint64_t 
     return s1[0];
 }
 
+// The same with any byte-code lookup.
+template <typename TE, class Code, typename TP>
+__device__ __forceinline__ uint32_t scan_lane_code(uint32_t st, uint64_t p, uint64_t vend, uint64_t end,
+                                                   TP tab, const Code &code, uint32_t dead) {
+    for (; p < vend && st != dead; p += 16) {
+        const uint4 v = load16(at(p));
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 16; ++i) st = next_state<TE>(tab, st, code((w[i >> 2] >> ((i & 3) * 8)) & 0xffu));
+    }
+    for (p = p < vend ? vend : p; p < end && st != dead; ++p) st = next_state<TE>(tab, st, code(*at(p)));
+    return st;
+}
+
 __device__ __forceinline__ uint32_t wave_ticket(uint32_t *counter) {
     uint32_t t = 0;
     if (threadIdx.x % kWave == 0) t = atomicAdd(counter, 1u);
@@ -202,16 +234,16 @@ constexpr uint32_t kWarmWaves = kWarmChunksPerBlock;
 
 // LDS of the warm-up kernel: tables (tables_bytes), staged starts, then one
 // merge table of kWarmMergeBytes per wave.
-constexpr uint32_t kWarmMergeBytes = 256 * 6;
+constexpr uint32_t kWarmMergeBytes = (257 * 6 + 15) & ~15u;   // 257 slots: u32 key, u8 id, u8 rank
 __host__ __device__ constexpr uint32_t warm_merge_offset(uint32_t tables_bytes, uint32_t L) {
     return (tables_bytes + (L <= kStageStarts ? L * 4u : 0u) + 15u) & ~15u;
 }
 
 // Warm-up of the start block at `base` over codes[0..wlen) (codes of bytes
 // 64 q + lane in register q).
-template <typename TE, int R, int NQ>
+template <typename TE, int R, int NQ, typename TP>
 __device__ __forceinline__ void warm_block(uint32_t (&st)[R], const uint32_t (&code)[NQ], uint32_t wlen,
-                                           const TE *tab, uint32_t dead) {
+                                           TP tab, uint32_t dead) {
 #pragma unroll
     for (uint32_t q = 0; q < (uint32_t)NQ; ++q) {
         const uint32_t j0 = q * kWave;
@@ -241,8 +273,8 @@ __device__ __forceinline__ void warm_block(uint32_t (&st)[R], const uint32_t (&c
 // start base + r * 64 + lane of the last start block; with several start
 // blocks the alias row is written as classes are found.  Once more than 64
 // distinct states are seen the chunk spills: D counts its live starts.
-template <typename TE, typename TA, int R, int NQ>
-__device__ __forceinline__ void warm_classes(const TE *tab, const StartList &starts, uint32_t L, uint32_t dead,
+template <typename TE, typename TA, int R, int NQ, typename TP>
+__device__ __forceinline__ void warm_classes(TP tab, const StartList &starts, uint32_t L, uint32_t dead,
                                              bool ok, bool first, const uint32_t (&code)[NQ], uint32_t wlen,
                                              TA *arow, uint32_t lane, uint32_t (&al)[R], uint32_t &D,
                                              uint32_t &cs, bool &spill) {
@@ -315,8 +347,8 @@ __device__ __forceinline__ void warm_classes(const TE *tab, const StartList &sta
 // Run records of one chunk from slot `firstrun` on, and its alias row (when
 // not written yet).  A spilled chunk's runs are recomputed: every live start
 // is its own run, in start order.
-template <typename TE, typename TA, int R, int NQ>
-__device__ __forceinline__ void warm_records(const TE *tab, const StartList &starts, uint32_t L, uint32_t dead,
+template <typename TE, typename TA, int R, int NQ, typename TP>
+__device__ __forceinline__ void warm_records(TP tab, const StartList &starts, uint32_t L, uint32_t dead,
                                              uint32_t row_bytes, bool first, const uint32_t (&code)[NQ],
                                              uint32_t wlen, TA *arow, uint32_t lane, uint64_t lane_lt,
                                              const uint32_t (&al)[R], uint32_t D, uint32_t cs, bool spill,

@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(1024, 8) mwarm_kernel(MultiArgs a) {
 #pragma unroll
         for (uint32_t q = 0; q < 4; ++q) {
             const uint32_t j = q * kWave + lane;
-            if (j < wlen) code[q] = d.code[*at(b + j)];
+            if (j < wlen) code[q] = ((const __attribute__((address_space(1))) uint16_t *)d.code)[*at(b + j)];
         }
         uint16_t *arow = a.alias + (ok ? a.alias_row[slot] : 0);
         uint32_t al[R], D = 0, cs = 0;
@@ -62,7 +62,8 @@ __global__ void __launch_bounds__(1024, 8) mwarm_kernel(MultiArgs a) {
         if (okl)
             with_entry(d.entry_bytes, [&](auto te) {
                 using TE = decltype(te);
-                warm_classes<TE, uint16_t, R, 4>(reinterpret_cast<const TE *>(d.table), starts, d.L, d.dead, true,
+                warm_classes<TE, uint16_t, R, 4>((const __attribute__((address_space(1))) TE *)(d.table),
+                                                 starts, d.L, d.dead, true,
                                               first, code, wlen, arow, lane, al, D, cs, spill);
             });
         const uint32_t firstrun = warm_slots(s_cnt[buf], lane, wave, ok ? D : 0u, &a.counters[1]);
@@ -75,7 +76,8 @@ __global__ void __launch_bounds__(1024, 8) mwarm_kernel(MultiArgs a) {
             if (okl)
                 with_entry(d.entry_bytes, [&](auto te) {
                     using TE = decltype(te);
-                    warm_records<TE, uint16_t, R, 4>(reinterpret_cast<const TE *>(d.table), starts, d.L, d.dead,
+                    warm_records<TE, uint16_t, R, 4>((const __attribute__((address_space(1))) TE *)(d.table),
+                                                     starts, d.L, d.dead,
                                                   d.row_bytes, first, code, wlen, arow, lane, lane_lt, al, D, cs,
                                                   spill, firstrun, slot, a.run_chunk, a.run_state);
                 });
@@ -97,8 +99,10 @@ __global__ void __launch_bounds__(256) mlong_kernel(MultiArgs a) {
         uint32_t f = 0;
         with_entry(d.entry_bytes, [&](auto te) {
             using TE = decltype(te);
-            f = scan_lane<TE>(a.run_state[i] * d.row_bytes, p, vend, e, reinterpret_cast<const TE *>(d.table), d.code,
-                              d.dead);
+            const CodeGlobal code{(const __attribute__((address_space(1))) uint16_t *)d.code};
+            f = scan_lane_code<TE, CodeGlobal>(a.run_state[i] * d.row_bytes, p, vend, e,
+                                               (const __attribute__((address_space(1))) TE *)(d.table),
+                                               code, d.dead);
         });
         a.run_final[i] = f == d.dead ? kNoState : f / d.row_bytes;
     }

@@ -104,67 +104,86 @@ __global__ void __launch_bounds__(1024) plain_kernel(PlainArgs a) {
 // representatives number the classes in (register, lane) order.  A run whose
 // slot was taken by another state tries the next round's hash.  Runs of one
 // class get one class number whatever their register or lane.
-constexpr uint32_t kMergeSlots = 256;
+constexpr uint32_t kMergeSlots = 256;   // plus one slot that takes the writes of lanes with nothing to write
+constexpr uint32_t kMergeTrash = kMergeSlots;
 constexpr uint32_t kMergeSplit = 8;    // bytes scanned by every start between merges while > 64 classes
 
+// LDS pointers (address space 3, so the accesses are LDS instructions and
+// not flat ones); volatile keeps every access in program order, since other
+// lanes of the wave write what a lane reads.
+typedef volatile __attribute__((address_space(3))) uint32_t lds_u32;
+typedef volatile __attribute__((address_space(3))) uint8_t lds_u8;
 struct MergeArea {
-    volatile uint32_t *key;    // [kMergeSlots] state offsets; then states by class
-    volatile uint8_t *id;      // [kMergeSlots] representative (register * 64 + lane)
-    volatile uint8_t *rank;    // [kMergeSlots] class number of the slot's state
+    lds_u32 *key;    // [kMergeSlots + 1] state offsets; then states by class
+    lds_u8 *id;      // [kMergeSlots + 1] representative (register * 64 + lane)
+    lds_u8 *rank;    // [kMergeSlots + 1] class number of the slot's state
 };
 
-__device__ __forceinline__ uint32_t merge_hash(uint32_t st, uint32_t round) {
-    return ((st ^ (round * 0x7F4A7C15u)) * 0x9E3779B1u) >> 24;
+// 8-bit slot of a state in a round (a 24 x 24-bit multiply: states that
+// agree in their low 24 bits share every round's slot, and one of them
+// settles per round, so merging still ends)
+__device__ __forceinline__ uint32_t merge_hash(uint32_t st, uint32_t salt) {
+    return ((((st ^ salt) & 0xFFFFFFu) * 0x9E3779u) >> 12) & (kMergeSlots - 1);
 }
 
 // Classes of the live runs st[0..R) of the wave: cls[r] in [0, D) or kNone
-// for a dead run.  Returns D (wave-uniform).
+// for a dead run.  Returns D (wave-uniform).  Pending runs are kept as wave
+// masks, so a register with nothing pending is skipped by a scalar branch;
+// writes that a lane must not make go to the trash slot.
 template <int R>
 __device__ uint32_t merge_runs(const uint32_t (&st)[R], uint32_t dead, uint32_t lane, uint64_t lane_lt,
                                const MergeArea &m, uint32_t (&cls)[R]) {
     static_assert(kMergeSlots == 256 && R * kWave <= 256, "class numbers and slots are bytes");
     constexpr uint32_t kNone = 0xFFFFFFFFu;
-    bool pend[R];
+    uint64_t pend[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        pend[r] = st[r] != dead;
         cls[r] = kNone;
+        pend[r] = __ballot(st[r] != dead);
     }
     uint32_t D = 0;
     for (uint32_t round = 0;; ++round) {
-        bool any = false;
+        uint64_t any = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) any |= pend[r];
-        if (__ballot(any) == 0) break;
-        uint32_t h[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) h[r] = merge_hash(st[r], round);
+        if (any == 0) break;
+        const uint32_t salt = round * 0x5BD1E9u;
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            if (pend[r]) m.key[h[r]] = st[r];
+            if (pend[r]) {
+                const bool p = (pend[r] >> lane) & 1;
+                m.key[p ? merge_hash(st[r], salt) : kMergeTrash] = st[r];
+            }
         __builtin_amdgcn_wave_barrier();
-        bool got[R];
+        uint64_t got[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) got[r] = pend[r] && m.key[h[r]] == st[r];
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (got[r]) m.id[h[r]] = (uint8_t)(r * kWave + lane);
+        for (int r = 0; r < R; ++r) {
+            got[r] = 0;
+            if (pend[r]) {
+                const uint32_t h = merge_hash(st[r], salt);
+                const bool g = ((pend[r] >> lane) & 1) && m.key[h] == st[r];
+                got[r] = __ballot(g);
+                m.id[g ? h : kMergeTrash] = (uint8_t)(r * kWave + lane);
+            }
+        }
         __builtin_amdgcn_wave_barrier();
         uint32_t base = D;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const bool lead = got[r] && m.id[h[r]] == (uint8_t)(r * kWave + lane);
-            const uint64_t b = __ballot(lead);
-            if (lead) m.rank[h[r]] = (uint8_t)(base + (uint32_t)__builtin_popcountll(b & lane_lt));
-            base += (uint32_t)__builtin_popcountll(b);
-        }
+        for (int r = 0; r < R; ++r)
+            if (got[r]) {
+                const uint32_t h = merge_hash(st[r], salt);
+                const bool lead = ((got[r] >> lane) & 1) && m.id[h] == (uint8_t)(r * kWave + lane);
+                const uint64_t b = __ballot(lead);
+                m.rank[lead ? h : kMergeTrash] = (uint8_t)(base + (uint32_t)__builtin_popcountll(b & lane_lt));
+                base += (uint32_t)__builtin_popcountll(b);
+            }
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int r = 0; r < R; ++r)
             if (got[r]) {
-                cls[r] = m.rank[h[r]];
-                pend[r] = false;
+                const uint32_t v = m.rank[merge_hash(st[r], salt)];
+                cls[r] = ((got[r] >> lane) & 1) ? v : cls[r];
+                pend[r] &= ~got[r];
             }
         D = base;
         __builtin_amdgcn_wave_barrier();   // the next round writes the slots again
@@ -272,7 +291,7 @@ __device__ __forceinline__ void warm_merge_chunks(const TE *tab, const StartList
     for (int g = 0; g < G; ++g) {
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            if (cls[g][r] != kNone) m.key[cls[g][r]] = st[g][r];
+            m.key[cls[g][r] != kNone ? cls[g][r] : kMergeTrash] = st[g][r];
         __builtin_amdgcn_wave_barrier();
         one[g] = lane < D[g] ? m.key[lane] : dead;
         __builtin_amdgcn_wave_barrier();
@@ -295,7 +314,7 @@ __device__ __forceinline__ void warm_merge_chunks(const TE *tab, const StartList
         }
         // lane k of `one` holds class c2[k]'s state; keep it in class order
         __builtin_amdgcn_wave_barrier();
-        if (c2[0] != kNone) m.key[c2[0]] = one[g];
+        m.key[c2[0] != kNone ? c2[0] : kMergeTrash] = one[g];
         __builtin_amdgcn_wave_barrier();
         one[g] = lane < D[g] ? m.key[lane] : dead;
         __builtin_amdgcn_wave_barrier();
@@ -416,9 +435,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     const uint32_t lane = threadIdx.x % kWave;
     const uint32_t wave = wave_uniform(threadIdx.x / kWave);
     uint8_t *marea = smem + warm_merge_offset(tables_lds<TE, LDS>(a.s.table_bytes), L) + wave * kWarmMergeBytes;
-    const MergeArea merge{reinterpret_cast<volatile uint32_t *>(marea),
-                          reinterpret_cast<volatile uint8_t *>(marea + 4 * kMergeSlots),
-                          reinterpret_cast<volatile uint8_t *>(marea + 5 * kMergeSlots)};
+    const MergeArea merge{(lds_u32 *)(marea), (lds_u8 *)(marea + 4 * (kMergeSlots + 1)),
+                          (lds_u8 *)(marea + 5 * (kMergeSlots + 1))};
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     TA *alias = reinterpret_cast<TA *>(a.alias);
     const uint32_t cpi = kWarmWaves * G;
@@ -480,7 +498,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
             } else {
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    if (cl[g][r] != kNone) merge.key[cl[g][r]] = st[g][r];
+                    merge.key[cl[g][r] != kNone ? cl[g][r] : kMergeTrash] = st[g][r];
                 __builtin_amdgcn_wave_barrier();
 #pragma unroll
                 for (int r = 0; r < R; ++r) fst[r] = r * kWave + lane < D[g] ? merge.key[r * kWave + lane] : dead;
@@ -575,6 +593,7 @@ __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
     const uint32_t per_job = kWave * R;
     const uint32_t njobs = (nruns + per_job - 1) / per_job;
     const uint32_t dead = a.s.dead;
+    const CodeTab code{cls};
     // jobs cost about the same (runs of one chunk length): static schedule
     const uint32_t nwaves_grid = gridDim.x * (blockDim.x / kWave);
     for (uint32_t job = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; job < njobs;
@@ -644,7 +663,7 @@ __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
                     uint4 v[R];
 #pragma unroll
                     for (int r = 0; r < R; ++r) v[r] = cur[r][q];
-                    step16_each<TE, R>(st, v, tab, cls);
+                    step16_each<TE, R, CodeTab>(st, v, tab, code);
                 }
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -661,7 +680,7 @@ __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (ok[r]) {
-                const uint32_t f = scan_lane<TE>(st[r], p[r], vend[r], end[r], tab, cls, dead);
+                const uint32_t f = scan_lane_code<TE, CodeTab>(st[r], p[r], vend[r], end[r], tab, code, dead);
                 a.run_final[ri[r]] = f == dead ? kNoState : f / a.s.row_bytes;
             }
         }

@@ -45,7 +45,7 @@ struct KernelShape {
 // wave interleaves the runs of several chunks (independent lookup chains)
 // within the same register budget; otherwise one.
 __host__ __device__ constexpr uint32_t warm_chunks_per_wave(bool hashed, int runs_per_lane, int code_regs) {
-    return !hashed ? 1u : (runs_per_lane == 4 || code_regs == 4) ? 2u : 4u;
+    return !hashed || code_regs == 4 ? 1u : runs_per_lane == 4 ? 2u : 4u;
 }
 
 // ---- plain reach: every (chunk, start) run to the chunk end or its death ----
