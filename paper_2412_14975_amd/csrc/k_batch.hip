@@ -88,7 +88,10 @@ __global__ void __launch_bounds__(1024, 8) mwarm_kernel(MultiArgs a) {
 // merged runs to the end of their chunks: one run per lane, grid-stride
 __global__ void __launch_bounds__(256) mlong_kernel(MultiArgs a) {
     const uint32_t nruns = *reinterpret_cast<volatile uint32_t *>(&a.counters[1]);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nruns; i += gridDim.x * blockDim.x) {
+    // runs dealt 64 at a time to the blocks in turn, so that every block gets
+    // an equal share however few runs there are
+    const uint32_t first = ((threadIdx.x / kWave) * gridDim.x + blockIdx.x) * kWave + threadIdx.x % kWave;
+    for (uint32_t i = first; i < nruns; i += gridDim.x * blockDim.x) {
         const uint32_t slot = a.run_chunk[i];
         const AutoDesc &d = a.autos[a.slot_auto[slot]];
         uint64_t b, e;

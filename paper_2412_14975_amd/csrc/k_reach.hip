@@ -594,10 +594,11 @@ __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
     const uint32_t njobs = (nruns + per_job - 1) / per_job;
     const uint32_t dead = a.s.dead;
     const CodeTab code{cls};
-    // jobs cost about the same (runs of one chunk length): static schedule
+    // jobs cost about the same (runs of one chunk length): static schedule,
+    // dealt to the blocks in turn (job j to block j mod grid), so that every
+    // block, and so every CU, gets an equal share however few jobs there are
     const uint32_t nwaves_grid = gridDim.x * (blockDim.x / kWave);
-    for (uint32_t job = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; job < njobs;
-         job += nwaves_grid) {
+    for (uint32_t job = (threadIdx.x / kWave) * gridDim.x + blockIdx.x; job < njobs; job += nwaves_grid) {
         uint64_t p[R], vend[R], end[R];
         uint32_t st[R];
         bool ok[R];
