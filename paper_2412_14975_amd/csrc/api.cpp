@@ -373,7 +373,7 @@ ri::KernelShape base_shape(const AlgoHost &H, const DeviceCopy &dc) {
     shape.alias_bytes = H.L <= 254 ? 1 : 2;
     shape.runs_per_lane = 1;
     shape.block_threads = 1024;
-    shape.table_in_lds = H.table.size() + 512 <= dc.max_lds;
+    shape.table_in_lds = H.table.size() + ri::kCodeLdsBytes <= dc.max_lds;
     return shape;
 }
 
@@ -389,7 +389,7 @@ struct ConvCfg {
 int conv_config(const AlgoHost &H, const DeviceCopy &dc, const Options &opt, uint32_t nchunks, ConvCfg *c) {
     if (H.L > 65534) return fail(RI_ERR_LIMIT, "too many starts for the converging reach");
     const ri::KernelShape shape = base_shape(H, dc);
-    const size_t lds_tables = H.table.size() + 512;
+    const size_t lds_tables = H.table.size() + ri::kCodeLdsBytes;
     // warm-up: starts held 64 per lane register, up to 4 registers per lane
     c->warm_shape = shape;
     c->warm_shape.runs_per_lane = H.L <= 64 ? 1 : H.L <= 128 ? 2 : 4;
@@ -413,10 +413,10 @@ int conv_config(const AlgoHost &H, const DeviceCopy &dc, const Options &opt, uin
     c->long_shape = shape;
     c->long_shape.runs_per_lane = (int)(opt.runs_per_lane ? opt.runs_per_lane : 1);
     const size_t pre = round_up(((size_t)c->grid_w + 1) * 4, 16);
-    c->lds_l = (shape.table_in_lds ? lds_tables : 512) + pre;
+    c->lds_l = (shape.table_in_lds ? lds_tables : ri::kCodeLdsBytes) + pre;
     if (c->lds_l > dc.max_lds) {
         c->long_shape.table_in_lds = false;
-        c->lds_l = 512 + pre;
+        c->lds_l = ri::kCodeLdsBytes + pre;
     }
     const uint64_t pairs = (uint64_t)H.L * nchunks;
     const int per_cu_l = std::max(1, ri::blocks_per_cu(2, c->long_shape, c->lds_l));
@@ -858,7 +858,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     const bool hit = cp.hit;
     const size_t pairs = cp.pairs;
     uint32_t R = opt.runs_per_lane ? opt.runs_per_lane : 4;
-    const size_t lds_tables = H.table.size() + 512;
+    const size_t lds_tables = H.table.size() + ri::kCodeLdsBytes;
 
     ri::ScanArgs sa{};
     sa.text = text;
@@ -878,7 +878,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     if (!conv) {
         while (R > 1 && R / 2 >= H.L) R /= 2;
         shape.runs_per_lane = (int)R;
-        const size_t lds = shape.table_in_lds ? lds_tables : 512;
+        const size_t lds = shape.table_in_lds ? lds_tables : ri::kCodeLdsBytes;
         ri::PlainArgs pa{};
         pa.s = sa;
         pa.lam = sc.lam;

@@ -32,13 +32,18 @@ __device__ __forceinline__ void stage_tables(const ScanArgs &s, uint8_t *smem, c
         tab = reinterpret_cast<const TE *>(s.table);
     }
     uint16_t *c = reinterpret_cast<uint16_t *>(smem + off);
-    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) c[i] = s.code[i];
+    uint8_t *c8 = smem + off + 512;
+    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) {
+        const uint16_t v = s.code[i];
+        c[i] = v;
+        c8[i] = (uint8_t)v;
+    }
     cls = c;
 }
 
 template <typename TE, bool LDS>
 __host__ __device__ constexpr uint32_t tables_lds(uint32_t table_bytes) {
-    return (LDS ? table_bytes : 0u) + 512u;
+    return (LDS ? table_bytes : 0u) + kCodeLdsBytes;
 }
 
 // One transition: st and c are byte offsets into the table.
@@ -70,6 +75,11 @@ __device__ __forceinline__ void step16_shared(uint32_t (&st)[R], const uint4 v, 
 // Byte codes (class * entry bytes) of the 256 byte values, one u16 table.
 struct CodeTab {
     const uint16_t *cls;
+    __device__ __forceinline__ uint32_t operator()(uint32_t b) const { return cls[b]; }
+};
+// The codes as bytes (rows of at most 256 bytes), staged after the u16 ones.
+struct CodeTab8 {
+    const uint8_t *cls;
     __device__ __forceinline__ uint32_t operator()(uint32_t b) const { return cls[b]; }
 };
 // The same table in global memory (global loads, not flat ones).

@@ -577,15 +577,10 @@ __device__ __forceinline__ uint32_t run_slot(const uint32_t *pre, uint32_t G, ui
     return (uint32_t)(warm_region(lo, G, iters, L, cpi) + (i - pre[lo]));
 }
 
-template <typename TE, int R, bool LDS>
-__global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    const TE *tab;
-    const uint16_t *cls;
-    stage_tables<TE, LDS>(a.s, smem, tab, cls);
+// The jobs of one wave, with byte codes looked up through `code`.
+template <typename TE, int R, class Code>
+__device__ __forceinline__ void long_jobs(const LongArgs &a, const TE *tab, const Code &code, const uint32_t *pre) {
     const uint32_t G = a.warm_blocks;
-    uint32_t *pre = reinterpret_cast<uint32_t *>(smem + tables_lds<TE, LDS>(a.s.table_bytes));
-    run_prefix(pre, a.block_count, G);
     const uint32_t lane = threadIdx.x % kWave;
     const uint32_t iters = (a.s.nchunks + a.cpi - 1) / a.cpi;
     auto phys = [&](uint32_t i) -> uint32_t { return run_slot(pre, G, iters, a.s.L, a.cpi, i); };
@@ -593,7 +588,6 @@ __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
     const uint32_t per_job = kWave * R;
     const uint32_t njobs = (nruns + per_job - 1) / per_job;
     const uint32_t dead = a.s.dead;
-    const CodeTab code{cls};
     // jobs cost about the same (runs of one chunk length): static schedule,
     // dealt to the blocks in turn (job j to block j mod grid), so that every
     // block, and so every CU, gets an equal share however few jobs there are
@@ -664,7 +658,7 @@ __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
                     uint4 v[R];
 #pragma unroll
                     for (int r = 0; r < R; ++r) v[r] = cur[r][q];
-                    step16_each<TE, R, CodeTab>(st, v, tab, code);
+                    step16_each<TE, R, Code>(st, v, tab, code);
                 }
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -681,11 +675,26 @@ __global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (ok[r]) {
-                const uint32_t f = scan_lane_code<TE, CodeTab>(st[r], p[r], vend[r], end[r], tab, code, dead);
+                const uint32_t f = scan_lane_code<TE, Code>(st[r], p[r], vend[r], end[r], tab, code, dead);
                 a.run_final[ri[r]] = f == dead ? kNoState : f / a.s.row_bytes;
             }
         }
     }
+}
+
+template <typename TE, int R, bool LDS>
+__global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const TE *tab;
+    const uint16_t *cls;
+    stage_tables<TE, LDS>(a.s, smem, tab, cls);
+    uint32_t *pre = reinterpret_cast<uint32_t *>(smem + tables_lds<TE, LDS>(a.s.table_bytes));
+    run_prefix(pre, a.block_count, a.warm_blocks);
+    // every code is below a row's length: bytes when rows are <= 256 bytes
+    if (a.s.row_bytes <= 256)
+        long_jobs<TE, R>(a, tab, CodeTab8{reinterpret_cast<const uint8_t *>(cls) + 512}, pre);
+    else
+        long_jobs<TE, R>(a, tab, CodeTab{cls}, pre);
 }
 
 const void *g_fn = nullptr;   // set by the dispatch below when only the function is wanted
@@ -731,7 +740,7 @@ hipError_t launch_warm(const WarmArgs &a, const KernelShape &k, int grid, size_t
 
 size_t warm_lds_bytes(const KernelShape &k, uint32_t table_bytes, uint32_t L) {
     const size_t merge = k.hashed ? (size_t)kWarmWaves * kWarmMergeBytes : 0;
-    return warm_merge_offset((k.table_in_lds ? table_bytes : 0) + 512, L) + merge;
+    return warm_merge_offset((k.table_in_lds ? table_bytes : 0) + kCodeLdsBytes, L) + merge;
 }
 
 hipError_t launch_long(const LongArgs &a, const KernelShape &k, int grid, size_t lds, hipStream_t st) {

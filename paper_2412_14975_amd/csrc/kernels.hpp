@@ -30,6 +30,12 @@ struct ScanArgs {
     uint32_t dead;             // byte offset of the dead row
 };
 
+// LDS bytes of the byte-code tables staged after the transition table: the
+// 256 codes as u16, then the same codes as u8 (used when every code is below
+// 256, i.e. a row is at most 256 bytes: 256 bytes are 64 dwords, so two
+// lanes that read different codes of ASCII text never share an LDS bank)
+constexpr uint32_t kCodeLdsBytes = 768;
+
 struct KernelShape {
     int entry_bytes;           // table entry: 1, 2, 4
     int tile_bytes;            // state ids in chunk maps / tiles: 2, 4
