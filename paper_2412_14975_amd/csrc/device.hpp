@@ -244,7 +244,6 @@ constexpr uint32_t kWarmWaves = kWarmChunksPerBlock;
 
 // LDS of the warm-up kernel: tables (tables_bytes), staged starts, then one
 // merge table of kWarmMergeBytes per wave.
-constexpr uint32_t kWarmMergeBytes = (257 * 6 + 15) & ~15u;   // 257 slots: u32 key, u8 id, u8 rank
 __host__ __device__ constexpr uint32_t warm_merge_offset(uint32_t tables_bytes, uint32_t L) {
     return (tables_bytes + (L <= kStageStarts ? L * 4u : 0u) + 15u) & ~15u;
 }

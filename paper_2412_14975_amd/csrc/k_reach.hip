@@ -27,6 +27,8 @@
 // the acceptance test and the minimal-DFA state of the result.
 #include "device.hpp"
 
+#include <type_traits>
+
 #include <mutex>
 #include <unordered_map>
 
@@ -321,6 +323,154 @@ __device__ __forceinline__ void warm_merge_chunks(const TE *tab, const StartList
     }
 }
 
+// Merging through a table indexed by state, for automata whose states fit
+// the wave's merge area (one byte per state after a 65-entry key row): no
+// hashing, so every merge is one pass.
+constexpr uint32_t kDirectTrash = 64;   // key[0..63]: states by class; key[64] takes the dead writes
+
+// Index s of a state from its row offset st = s * row_bytes: st converts to
+// float exactly (st < 2^24) and the reciprocal, raised by 2^-21 relative,
+// puts the product in [s, s + 1), so truncation gives s (checked for every
+// s < 2^16 and row length 1..1024).
+struct RowDiv {
+    float inv;
+    __device__ explicit RowDiv(uint32_t row_bytes) : inv((1.0f / (float)row_bytes) * (1.0f + 0x1p-21f)) {}
+    __device__ __forceinline__ uint32_t operator()(uint32_t st) const { return (uint32_t)((float)st * inv); }
+};
+
+// Classes of the live runs st[0..R) of the wave in one pass: every live run
+// writes its id (register * 64 + lane) into its state's byte slot[s] (the
+// dead row's byte takes the dead runs' writes); the run that reads its own
+// id back leads its class; leaders take class numbers in (register, lane)
+// order and write them over the ids; then every run reads its class.
+// cls[r]: class or kNone; idx[r]: state index; lead[r]: leaders (wave mask).
+// Returns the number of classes (wave-uniform).
+template <int R>
+__device__ uint32_t merge_direct(const uint32_t (&st)[R], uint32_t dead, uint32_t lane, uint64_t lane_lt,
+                                 lds_u8 *slot, const RowDiv &rd, uint32_t (&cls)[R], uint32_t (&idx)[R],
+                                 uint64_t (&lead)[R]) {
+    static_assert(R * kWave <= 256, "ids and class numbers are bytes");
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    const uint32_t trash = rd(dead);
+    uint64_t live[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        live[r] = __ballot(st[r] != dead);
+        idx[r] = rd(st[r]);
+        cls[r] = kNone;
+        lead[r] = 0;
+        if (live[r]) slot[idx[r]] = (uint8_t)(r * kWave + lane);
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (live[r]) lead[r] = __ballot(((live[r] >> lane) & 1) && slot[idx[r]] == (uint8_t)(r * kWave + lane));
+    __builtin_amdgcn_wave_barrier();   // every id is read before a class number replaces it
+    uint32_t D = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (lead[r]) {
+            const bool l = (lead[r] >> lane) & 1;
+            slot[l ? idx[r] : trash] = (uint8_t)(D + (uint32_t)__builtin_popcountll(lead[r] & lane_lt));
+            D += (uint32_t)__builtin_popcountll(lead[r]);
+        }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (live[r]) {
+            const uint32_t v = slot[idx[r]];
+            cls[r] = ((live[r] >> lane) & 1) ? v : kNone;
+        }
+    __builtin_amdgcn_wave_barrier();   // the next merge writes the slots again
+    return D;
+}
+
+// warm_merge_chunks with direct merging; instead of returning the runs it
+// hands each chunk's result to emit(g, D, acl, lead, ecl, eidx): acl[r] the
+// class of start r * 64 + lane, and for each register of the last merge the
+// leaders (lead), their class (ecl) and state index (eidx).
+template <typename TE, int R, int NQ, int G, class Emit>
+__device__ __forceinline__ void warm_direct_chunks(const TE *tab, const StartList &starts, uint32_t L, uint32_t dead,
+                                                   const bool (&ok)[G], const bool (&first)[G],
+                                                   const uint32_t (&code)[G][NQ], const uint32_t (&wlen)[G],
+                                                   uint32_t lane, uint64_t lane_lt, lds_u32 *key, lds_u8 *slot,
+                                                   const RowDiv &rd, Emit &&emit) {
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    uint32_t st[G][R], cl[G][R], D[G];
+    uint32_t W = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        W = wlen[g] > W ? wlen[g] : W;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t s = r * kWave + lane;
+            st[g][r] = (ok[g] && s < L && (!first[g] || s == 0)) ? starts[s] : dead;
+        }
+    }
+    uint32_t j = (R == 1 || W < kMergeSplit) ? W : kMergeSplit;
+    warm_steps<TE, R, NQ, G>(st, code, wlen, 0, j, tab, dead);
+    uint32_t Dmax = 0;
+    if (j < W) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            uint32_t ix[R];
+            uint64_t ld[R];
+            D[g] = merge_direct<R>(st[g], dead, lane, lane_lt, slot, rd, cl[g], ix, ld);
+            Dmax = D[g] > Dmax ? D[g] : Dmax;
+        }
+        while (j < W && Dmax > kWave) {
+            const uint32_t e = W - j < kMergeSplit ? W : j + kMergeSplit;
+            warm_steps<TE, R, NQ, G>(st, code, wlen, j, e, tab, dead);
+            j = e;
+            Dmax = 0;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                uint32_t ix[R];
+                uint64_t ld[R];
+                D[g] = merge_direct<R>(st[g], dead, lane, lane_lt, slot, rd, cl[g], ix, ld);
+                Dmax = D[g] > Dmax ? D[g] : Dmax;
+            }
+        }
+    }
+    if (j >= W) {
+        // the warm-up is over with the starts in their own registers: the
+        // last merge gives the runs
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            uint32_t ix[R];
+            uint64_t ld[R];
+            const uint32_t d = merge_direct<R>(st[g], dead, lane, lane_lt, slot, rd, cl[g], ix, ld);
+            emit(g, d, cl[g], ld, cl[g], ix);
+        }
+        return;
+    }
+    // at most 64 classes per chunk: class k's state in lane k, one register
+    uint32_t one[G][1];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) key[cl[g][r] != kNone ? cl[g][r] : kDirectTrash] = st[g][r];
+        __builtin_amdgcn_wave_barrier();
+        one[g][0] = lane < D[g] ? key[lane] : dead;
+        __builtin_amdgcn_wave_barrier();
+    }
+    warm_steps<TE, 1, NQ, G>(one, code, wlen, j, W, tab, dead);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        uint32_t c2[1], ix[1];
+        uint64_t ld[1];
+        const uint32_t d = merge_direct<1>(one[g], dead, lane, lane_lt, slot, rd, c2, ix, ld);
+        // lane k holds the new class of old class k; every lane takes part
+        // in the shuffle
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t v = (uint32_t)__shfl((int)c2[0], (int)(cl[g][r] == kNone ? 0u : cl[g][r]));
+            cl[g][r] = cl[g][r] == kNone ? kNone : v;
+        }
+        emit(g, d, cl[g], ld, c2, ix);
+    }
+}
+
 // Occupancy: a block is 16 waves (4 per SIMD), so two blocks per CU need 8
 // waves per SIMD; without the attribute the kernel's SGPR use allows 7 and
 // only one block fits (the SGPRs over the limit live in VGPR lanes).
@@ -412,9 +562,9 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
 // warmg_kernel: interfaces of at most 64 R starts.  A wave takes G chunks
 // at a time (G consecutive chunks of the block's a.cpi = 16 G) and steps
 // their runs together, merging by hashing in its own LDS table.
-template <typename TE, typename TA, int R, bool LDS, int NQ>
+template <typename TE, typename TA, int R, bool LDS, int NQ, bool DIRECT>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) warmg_kernel(WarmArgs a) {
-    constexpr int G = (int)warm_chunks_per_wave(true, R, NQ);
+    constexpr int G = (int)warm_chunks_per_wave(true, DIRECT, R, NQ);
     constexpr uint32_t kNone = 0xFFFFFFFFu;
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ uint32_t s_count;   // runs placed in this block's region
@@ -438,6 +588,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     const MergeArea merge{(lds_u32 *)(marea), (lds_u8 *)(marea + 4 * (kMergeSlots + 1)),
                           (lds_u8 *)(marea + 5 * (kMergeSlots + 1))};
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    // DIRECT: one byte per state fits the merge area (chosen by the host)
+    const RowDiv rd(a.s.row_bytes);
+    lds_u32 *const dkey = (lds_u32 *)marea;
+    lds_u8 *const dslot = (lds_u8 *)(marea + kDirectKeyBytes);
     TA *alias = reinterpret_cast<TA *>(a.alias);
     const uint32_t cpi = kWarmWaves * G;
     const uint32_t iters = (a.s.nchunks + cpi - 1) / cpi;
@@ -482,6 +636,38 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
             for (uint32_t q = 0; q < (uint32_t)NQ; ++q) code[g][q] = q * kWave + lane < wlen[g] ? cls[raw[g][q]] : 0u;
         }
         fetch(it + gridDim.x, raw, wlen, first);   // next iteration's bytes, in flight meanwhile
+        if constexpr (DIRECT) {
+            // a chunk's runs go to its region slots in class order, written
+            // by the class leaders
+            auto emit = [&](int g, uint32_t Dg, const uint32_t (&acl)[R], const auto &lead, const auto &ecl,
+                            const auto &eidx) {
+                constexpr int RE = (int)std::extent<std::remove_reference_t<decltype(lead)>>::value;
+                const uint32_t chunk = chunk0 + g;
+                uint32_t base = 0;
+                if (lane == 0 && ok[g]) base = atomicAdd(&s_count, Dg);
+                const uint32_t firstrun = (uint32_t)(region + (uint32_t)__shfl((int)base, 0));
+                if (!ok[g]) return;
+                if (lane == 0) {
+                    a.run_base[chunk] = firstrun;
+                    if (a.run_count) a.run_count[chunk] = Dg;
+                    if (Dg > kRowCap) atomicOr(&a.counters[2], 1u);
+                }
+#pragma unroll
+                for (int r = 0; r < RE; ++r)
+                    if ((lead[r] >> lane) & 1) {
+                        a.run_chunk[firstrun + ecl[r]] = chunk;
+                        a.run_state[firstrun + ecl[r]] = eidx[r];
+                    }
+                TA *arow = alias + (uint64_t)chunk * L;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const uint32_t k = r * kWave + lane;
+                    if (k < L) arow[k] = acl[r] == kNone ? all_ones<TA>() : (TA)acl[r];
+                }
+            };
+            warm_direct_chunks<TE, R, NQ, G>(tab, starts, L, dead, ok, cur_first, code, cur_wlen, lane, lane_lt, dkey,
+                                             dslot, rd, emit);
+        } else {
         uint32_t cl[G][R], one[G], D[G], st[G][R];
         bool compacted;
         warm_merge_chunks<TE, R, NQ, G>(tab, starts, L, dead, ok, cur_first, code, cur_wlen, lane, lane_lt, merge, cl,
@@ -524,6 +710,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
                     if (k < L) arow[k] = cl[g][r] == kNone ? all_ones<TA>() : (TA)cl[g][r];
                 }
             }
+        }
         }
     }
     __syncthreads();
@@ -596,7 +783,7 @@ __device__ __forceinline__ void long_jobs(const LongArgs &a, const TE *tab, cons
         uint64_t p[R], vend[R], end[R];
         uint32_t st[R];
         bool ok[R];
-        uint32_t ri[R];
+        uint32_t ri[R], chk[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t i = job * per_job + r * kWave + lane;
@@ -604,11 +791,13 @@ __device__ __forceinline__ void long_jobs(const LongArgs &a, const TE *tab, cons
             p[r] = vend[r] = end[r] = 0;
             st[r] = dead;
             ri[r] = 0;
+            chk[r] = 0xFFFFFFFFu;
             if (ok[r]) {
                 ri[r] = phys(i);
+                chk[r] = a.run_chunk[ri[r]];
                 uint64_t b, e;
                 bool first;
-                chunk_bounds(a.s, a.run_chunk[ri[r]], b, e, first);
+                chunk_bounds(a.s, chk[r], b, e, first);
                 p[r] = b + a.warm < e ? b + a.warm : e;
                 vend[r] = p[r] + ((e - p[r]) & ~(uint64_t)15);
                 end[r] = e;
@@ -631,6 +820,13 @@ __device__ __forceinline__ void long_jobs(const LongArgs &a, const TE *tab, cons
             if (ok[r] && p[r] < bend[r]) load64(cur[r], at(p[r]));
             else cur[r][0] = cur[r][1] = cur[r][2] = cur[r][3] = make_uint4(0, 0, 0, 0);
         }
+        // One run per lane: the runs of a chunk sit in consecutive lanes and
+        // advance in lockstep, so runs that reach the same state merge as they
+        // go (Sect. 5, state convergence): every 4 blocks a lane compares its
+        // run with the lane below; when both are live runs of one chunk in one
+        // state the upper run stops and takes the lower one's end state.
+        uint32_t tgt = lane;   // lane whose end state this lane's run takes
+        uint32_t blk = 0;
         for (;;) {
             bool work = false;
 #pragma unroll
@@ -640,8 +836,21 @@ __device__ __forceinline__ void long_jobs(const LongArgs &a, const TE *tab, cons
                     st[r] = dead;
                     pk[r] = true;
                 }
-                work |= ok[r] && !pk[r] && st[r] != dead;
             }
+            if constexpr (R == 1) {
+                if ((++blk & 3u) == 0) {
+                    const bool live = ok[0] && !pk[0] && st[0] != dead;
+                    const uint32_t key = live ? chk[0] : 0xFFFFFFFFu;
+                    const uint32_t key_dn = (uint32_t)__shfl_up((int)key, 1);
+                    const uint32_t st_dn = (uint32_t)__shfl_up((int)st[0], 1);
+                    if (live && lane > 0 && key_dn == key && st_dn == st[0]) {
+                        tgt = lane - 1;
+                        st[0] = dead;
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) work |= ok[r] && !pk[r] && st[r] != dead;
             if (__ballot(work) == 0) break;
             if (work) {
                 uint4 nxt[R][4];
@@ -672,18 +881,30 @@ __device__ __forceinline__ void long_jobs(const LongArgs &a, const TE *tab, cons
         for (int r = 0; r < R; ++r)
             if (pk[r]) st[r] = parked[r];
         // remaining blocks and ragged tails, run by run
+        if constexpr (R == 1) {
+            uint32_t f = ok[0] ? scan_lane_code<TE, Code>(st[0], p[0], vend[0], end[0], tab, code, dead) : dead;
+            // merged runs take the end state at the root of their chain of
+            // merges (targets are lower lanes; pointer jumping, 64 = 2^6)
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (ok[r]) {
-                const uint32_t f = scan_lane_code<TE, Code>(st[r], p[r], vend[r], end[r], tab, code, dead);
-                a.run_final[ri[r]] = f == dead ? kNoState : f / a.s.row_bytes;
+            for (int k = 0; k < 6; ++k) {
+                f = (uint32_t)__shfl((int)f, (int)tgt);
+                tgt = (uint32_t)__shfl((int)tgt, (int)tgt);
+            }
+            if (ok[0]) a.run_final[ri[0]] = f == dead ? kNoState : f / a.s.row_bytes;
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (ok[r]) {
+                    const uint32_t f = scan_lane_code<TE, Code>(st[r], p[r], vend[r], end[r], tab, code, dead);
+                    a.run_final[ri[r]] = f == dead ? kNoState : f / a.s.row_bytes;
+                }
             }
         }
     }
 }
 
 template <typename TE, int R, bool LDS>
-__global__ void __launch_bounds__(1024) long_kernel(LongArgs a) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(R == 1 ? 8 : 4))) long_kernel(LongArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     const TE *tab;
     const uint16_t *cls;
@@ -727,7 +948,9 @@ hipError_t launch_warm(const WarmArgs &a, const KernelShape &k, int grid, size_t
                         using TE = decltype(te);
                         using TA = decltype(ta);
                         constexpr bool L_ = decltype(lds_t)::value;
-                        auto fn = k.hashed ? warmg_kernel<TE, TA, R, L_, NQ> : warm_kernel<TE, TA, R, L_, NQ>;
+                        auto fn = !k.hashed ? warm_kernel<TE, TA, R, L_, NQ>
+                                  : k.direct ? warmg_kernel<TE, TA, R, L_, NQ, true>
+                                             : warmg_kernel<TE, TA, R, L_, NQ, false>;
                         if (grid == 0) { g_fn = reinterpret_cast<const void *>(fn); return hipSuccess; }
                         hipLaunchKernelGGL(fn, dim3(grid), dim3(k.block_threads), lds, st, a);
                         return hipGetLastError();
@@ -771,7 +994,7 @@ int blocks_per_cu(int which, const KernelShape &k, size_t lds) {
                          (uint64_t)(k.runs_per_lane & 7) << 12 | (uint64_t)(k.table_in_lds ? 1 : 0) << 15 |
                          (uint64_t)((k.block_threads / 64) & 31) << 16 | (uint64_t)(lds & 0x3ffff) << 21 |
                          (uint64_t)(device & 0xfff) << 39 | (uint64_t)(k.code_regs & 7) << 51 |
-                         (uint64_t)(k.hashed ? 1 : 0) << 54;
+                         (uint64_t)(k.hashed ? 1 : 0) << 54 | (uint64_t)(k.direct ? 1 : 0) << 55;
     {
         std::lock_guard<std::mutex> lk(mu);
         auto it = known.find(key);

@@ -36,6 +36,15 @@ struct ScanArgs {
 // lanes that read different codes of ASCII text never share an LDS bank)
 constexpr uint32_t kCodeLdsBytes = 768;
 
+// Merge area of a warm-up wave (hashed merging): 257 slots of a u32 key, a
+// u8 id and a u8 rank.  Direct merging uses it as a 65-entry u32 key row
+// (272 bytes) and then one byte per state, the dead row's included.
+constexpr uint32_t kWarmMergeBytes = (257 * 6 + 15) & ~15u;
+constexpr uint32_t kDirectKeyBytes = 272;
+__host__ __device__ constexpr bool warm_direct_fits(uint32_t nstates) {
+    return kDirectKeyBytes + nstates + 1 <= kWarmMergeBytes;
+}
+
 struct KernelShape {
     int entry_bytes;           // table entry: 1, 2, 4
     int tile_bytes;            // state ids in chunk maps / tiles: 2, 4
@@ -45,12 +54,15 @@ struct KernelShape {
     int block_threads;         // 1024
     int code_regs = 4;         // warm-up: registers of 64 byte codes (1 when the warm-up is <= 64 bytes)
     bool hashed = false;       // warm-up: starts fit one start block (L <= 64 runs_per_lane), merging by hashing
+    bool direct = false;       // hashed warm-up merging through a table indexed by state instead (warm_direct_fits)
 };
 
 // Chunks that one warm-up wave takes at a time: with merging by hashing the
 // wave interleaves the runs of several chunks (independent lookup chains)
 // within the same register budget; otherwise one.
-__host__ __device__ constexpr uint32_t warm_chunks_per_wave(bool hashed, int runs_per_lane, int code_regs) {
+__host__ __device__ constexpr uint32_t warm_chunks_per_wave(bool hashed, bool direct, int runs_per_lane,
+                                                           int code_regs) {
+    (void)direct;   // direct merging takes the same number (measured: fewer is slower)
     return !hashed || code_regs == 4 ? 1u : runs_per_lane == 4 ? 2u : 4u;
 }
 
