@@ -99,11 +99,17 @@ CALIB_BYTES = 256 << 20
 
 
 def kernel_source_hash():
+    """Hash of the reach kernels' code: comments and layout are left out,
+    so that only a change of the code itself drops the traffic record."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for p in KERNEL_SRCS:
-        with open(p, "rb") as f:
-            h.update(f.read())
+        with open(p, encoding="utf-8") as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()
 
 

@@ -7,24 +7,16 @@
 //
 //   plain_kernel  every (chunk, start) run to the chunk end or its death, as
 //                 the paper's reach phase is stated.
-//   warm_kernel + long_kernel
+//   warmg_kernel / warm_kernel + long_kernel
 //                 the same chunk maps with state convergence, an optimization
 //                 the paper names as compatible with the RI-DFA (Sect. 5):
 //                 every run is scanned for a short warm-up; the runs of one
 //                 chunk that are then in the same state have the same future
 //                 (the chunk automaton is deterministic), so they are merged
-//                 into one run that alone is scanned to the chunk end.
+//                 into one run that alone is scanned to the chunk end, and
+//                 runs of a chunk that meet later are merged again there.
 //
-// Join phase: an associative composition of chunk maps over a tree of
-// groups of G consecutive members.
-//   Relations (RI-DFA, Sect. 3.2): row s of a chunk is the content of
-//   lambda_i({s}), a set of interface states.  Composing two chunks unions
-//   the rows of the second over the set bits of the first, which is
-//   PLAS_i = lambda_i(if(PLAS_{i-1}) & PIS_i) taken for every PLAS_{i-1}.
-//   Functions (DFA, Sect. 2): lambda_i is a partial map Q -> Q; composition
-//   is a gather.
-// finalize: row 0 (the initial state) of the composition of all chunks,
-// the acceptance test and the minimal-DFA state of the result.
+// The join kernels are in k_join.hip.
 #include "device.hpp"
 
 #include <type_traits>
@@ -98,8 +90,10 @@ __global__ void __launch_bounds__(1024) plain_kernel(PlainArgs a) {
 // run (numbered in start order).  The run slots of the block's 16 chunks come
 // from one atomic; the alias row of a chunk ([nchunks][L], class of every
 // start) is written contiguously.
-// Merging by hashing (interfaces of at most 64 R starts, one start block).
-// Each wave owns a table of kMergeSlots slots in LDS; in a round every
+// Merging by hashing (interfaces of at most 64 R starts, one start block;
+// automata with few states merge through a table indexed by state instead,
+// see merge_direct).  Each wave owns a table of kMergeSlots slots in LDS; in
+// a round every
 // pending run writes its state into slot hash(state, round), reads it back
 // and is settled when it finds its own state there (one state per slot and
 // round); settled runs elect one representative per slot and the
