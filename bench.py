@@ -22,7 +22,9 @@ chunk on every usable core, for RID and the DFA on a 64 MiB prefix.
 
 --workload batch: 4096 texts (1 KiB - 4 MiB, log-uniform, about 2 GB) over
 16 random expressions, recognized by one captured graph launch of a batch
-(ri_batch_*), RID and all-states DFA, against one ri_recognize_ex call per
+(ri_batch_*, one launch sequence per automaton), RID and all-states DFA,
+against the same batch with the long runs of every automaton in one
+work-queue launch (RI_BATCH_QUEUE) and against one ri_recognize_ex call per
 text.
 
 --workload sweep: the regexp family (a|b)*a(a|b)^k for k = 3..12 (minimal
@@ -301,10 +303,12 @@ def main_batch(args):
     recs = [ri.Recognizer(rx) for rx in regexes]
     torch.cuda.synchronize()
 
-    res = {}
-    for algo in ("rid", "dfa"):
+    res, res_pg = {}, {}
+    # the default grouped plan (one launch sequence per automaton), then the
+    # long runs of every automaton in one work-queue launch
+    for mode, algo in (("grouped", "rid"), ("grouped", "dfa"), ("queue", "rid"), ("queue", "dfa")):
         t0 = time.perf_counter()
-        b = ri.Batch([(recs[k], v, algo) for (k, _, _), v in zip(items, views)])
+        b = ri.Batch([(recs[k], v, algo) for (k, _, _), v in zip(items, views)], mode=mode)
         tun = b.autotune()
         b.capture()
         setup_s = time.perf_counter() - t0
@@ -328,7 +332,8 @@ def main_batch(args):
         info = b.info()
         groups = [b.group(g) for g in range(info["groups"])]
         b.close()
-        res[algo] = dict(gbps=total * args.steps / wall / 1e9, ms_per_step=wall / args.steps * 1e3,
+        (res if mode == "grouped" else res_pg)[algo] = dict(
+                         gbps=total * args.steps / wall / 1e9, ms_per_step=wall / args.steps * 1e3,
                          p50_ms=float(np.percentile(ms, 50)), p99_ms=float(np.percentile(ms, 99)),
                          gbps_p50=total / (np.percentile(ms, 50) * 1e-3) / 1e9,
                          gbps_p99=total / (np.percentile(ms, 99) * 1e-3) / 1e9,
@@ -337,7 +342,8 @@ def main_batch(args):
                          tuning=dict(trials=tun["trials"], best_ms=tun["best_ms"],
                                      chunk_bytes=sorted({g["chunk_bytes"] for g in groups}),
                                      warmup_bytes=sorted({g["warmup_bytes"] for g in groups})))
-        print(f"# batch {algo}: {res[algo]['gbps']:.1f} GB/s exact={exact}", file=sys.stderr, flush=True)
+        m = (res if mode == "grouped" else res_pg)[algo]
+        print(f"# batch {mode} {algo}: {m['gbps']:.1f} GB/s exact={exact}", file=sys.stderr, flush=True)
 
     # one ri_recognize_ex call per text (each call enqueues its kernels and
     # waits for its result), same texts, same automata
@@ -389,8 +395,12 @@ def main_batch(args):
                    "expression_seed": spec["seed"], "launch": "one captured hipGraph per step"},
         "p50_ms": round(r["p50_ms"], 4),
         "p99_ms": round(r["p99_ms"], 4),
-        "bitexact": all(v["bitexact"] for v in res.values()) and all(v["bitexact"] for v in per_text.values()),
+        "bitexact": all(v["bitexact"] for v in res.values()) and all(v["bitexact"] for v in per_text.values())
+        and all(v["bitexact"] for v in res_pg.values()),
         "batch": {a: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in m.items()} for a, m in res.items()},
+        "batch_work_queue": {a: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in m.items()}
+                             for a, m in res_pg.items()},
+        "speedup_work_queue_vs_grouped": round(res_pg["rid"]["gbps"] / res["rid"]["gbps"], 4),
         "per_text_calls": {a: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in m.items()}
                            for a, m in per_text.items()},
         "speedup_rid_vs_dfa": round(res["rid"]["gbps"] / res["dfa"]["gbps"], 4),

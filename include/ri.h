@@ -351,6 +351,14 @@ int ri_batch_create(const ri_request *reqs, uint32_t count, uint32_t chunk_bytes
  *   mode          RI_BATCH_GROUPED: one launch sequence per (handle, algo)
  *                 group, tables staged in LDS, per-group tuning (interfaces
  *                 up to 2048 states);
+ *                 RI_BATCH_QUEUE: as GROUPED for the warm-up and the joins,
+ *                 but the long runs of every group go to one persistent
+ *                 work-queue launch: a job is 64 consecutive runs of one
+ *                 group; a workgroup takes the groups in turn, stages the
+ *                 group's table in LDS (when it fits, else it reads it from
+ *                 L2) and its waves pull that group's jobs until none is
+ *                 left (the paper's reach phase, Sect. 2, over many texts
+ *                 at once);
  *                 RI_BATCH_FUSED: one launch sequence for every text of every
  *                 automaton: each chunk slot and text names its automaton,
  *                 tables are read from global memory (L2), every automaton
@@ -368,6 +376,7 @@ int ri_batch_create(const ri_request *reqs, uint32_t count, uint32_t chunk_bytes
 #define RI_BATCH_AUTO     0
 #define RI_BATCH_GROUPED  1
 #define RI_BATCH_FUSED    2
+#define RI_BATCH_QUEUE    3
 typedef struct {
     uint32_t chunk_bytes;
     uint32_t mode;

@@ -28,8 +28,9 @@ SYMBOLS = ("ri_build", "ri_free", "ri_info", "ri_recognize", "ri_recognize_ex",
            "ri_batch_create", "ri_batch_free", "ri_batch_run", "ri_batch_capture",
            "ri_batch_launch", "ri_batch_get_info", "ri_batch_get_group", "ri_batch_autotune",
            "ri_batch_create_ex", "ri_batch_update", "ri_request_footprint", "ri_recognize_noalloc")
-RI_BATCH_AUTO, RI_BATCH_GROUPED, RI_BATCH_FUSED = 0, 1, 2
-BATCH_MODES = {"auto": RI_BATCH_AUTO, "grouped": RI_BATCH_GROUPED, "fused": RI_BATCH_FUSED}
+RI_BATCH_AUTO, RI_BATCH_GROUPED, RI_BATCH_FUSED, RI_BATCH_QUEUE = 0, 1, 2, 3
+BATCH_MODES = {"auto": RI_BATCH_AUTO, "grouped": RI_BATCH_GROUPED, "fused": RI_BATCH_FUSED,
+               "queue": RI_BATCH_QUEUE}
 RI_OPT_CONVERGE, RI_OPT_WARMUP_BYTES, RI_OPT_RUNS_PER_LANE, RI_OPT_CHUNK_TARGET, RI_OPT_JOIN = 1, 2, 3, 4, 5
 OPTIONS = {"converge": RI_OPT_CONVERGE, "warmup_bytes": RI_OPT_WARMUP_BYTES,
            "runs_per_lane": RI_OPT_RUNS_PER_LANE, "chunk_target": RI_OPT_CHUNK_TARGET,

@@ -1158,6 +1158,7 @@ struct BatchGroup {
 namespace {
 
 constexpr uint64_t kFusedTextPairs = 1ull << 22;   // (start, chunk) pairs of one text in a fused batch
+constexpr size_t kMaxQueueGroups = 4096;             // automata of one queued batch
 
 // Plan of a fused batch: all texts, all automata, one launch sequence.
 struct FusedPlan {
@@ -1193,6 +1194,14 @@ struct ri_batch {
     int32_t *graph_results = nullptr;
     hipStream_t side[kBatchSide] = {};
     hipEvent_t fork = nullptr, joins[kBatchSide] = {};
+    // grouped batches: the long runs of every group in one work-queue launch
+    bool queue = false;
+    Buf qdesc;                      // ri::QueueGroup per non-empty group
+    uint32_t *qcounters = nullptr;  // items taken per group
+    uint32_t qgroups = 0;
+    int qgrid = 0;
+    size_t qlds = 0;
+    hipEvent_t fork2 = nullptr, joins2[kBatchSide] = {};
     std::vector<void *> retired;    // buffers replaced by a re-plan, freed with the batch
 };
 
@@ -1326,17 +1335,8 @@ const T *at_off(const BatchGroup &g, size_t off) {
     return reinterpret_cast<const T *>(static_cast<const uint8_t *>(g.desc.p) + off);
 }
 
-// Enqueue one group's kernels; results[2 * request] = (accept, final state).
-int run_group(ri_batch *b, const BatchGroup &g, hipStream_t stream, int32_t *results) {
-    ri::BatchFinalArgs bf{};
-    bf.ntexts = (uint32_t)g.req.size();
-    bf.text_slot = at_off<uint32_t>(g, g.off_slot);
-    bf.text_out = at_off<uint32_t>(g, g.off_out);
-    bf.results = results;
-    if (g.empty) {
-        HIP_TRY(ri::launch_batch_fill(bf, stream));
-        return RI_OK;
-    }
+// Reach arguments of one group (chunk descriptors, tables, starts).
+ri::ScanArgs group_scan_args(const ri_batch *b, const BatchGroup &g) {
     const AlgoHost &H = g.h->algo[g.algo];
     const AlgoDevice &D = g.h->dev[b->device].algo[g.algo];
     ri::ScanArgs sa{};
@@ -1353,11 +1353,63 @@ int run_group(ri_batch *b, const BatchGroup &g, hipStream_t stream, int32_t *res
     sa.L = H.L;
     sa.row_bytes = H.K * H.entry_bytes;
     sa.dead = H.dead;
+    return sa;
+}
+
+// Long-run arguments of one group (as launch_conv sets them).
+ri::LongArgs group_long_args(const ri_batch *b, const BatchGroup &g) {
+    ri::LongArgs la{};
+    la.s = group_scan_args(b, g);
+    la.warm = g.opt.warm;
+    la.run_chunk = static_cast<const uint32_t *>(g.run_chunk.p);
+    la.run_state = static_cast<const uint32_t *>(g.run_state.p);
+    la.run_final = static_cast<uint32_t *>(g.run_final.p);
+    la.block_count = static_cast<const uint32_t *>(g.block_count.p);
+    la.warm_blocks = (uint32_t)g.cc.grid_w;
+    la.cpi = g.cc.cpi;
+    return la;
+}
+
+// Phases of a group's launch sequence: everything, or (queued batches) the
+// warm-up alone and the joins alone, with the long runs of every group in
+// between in one work-queue launch.
+enum GroupPhase { kAllPhases, kWarmPhase, kJoinPhase };
+
+// Enqueue one group's kernels; results[2 * request] = (accept, final state).
+int run_group(ri_batch *b, const BatchGroup &g, hipStream_t stream, int32_t *results, GroupPhase phase = kAllPhases) {
+    ri::BatchFinalArgs bf{};
+    bf.ntexts = (uint32_t)g.req.size();
+    bf.text_slot = at_off<uint32_t>(g, g.off_slot);
+    bf.text_out = at_off<uint32_t>(g, g.off_out);
+    bf.results = results;
+    if (g.empty) {
+        if (phase != kWarmPhase) HIP_TRY(ri::launch_batch_fill(bf, stream));
+        return RI_OK;
+    }
+    const AlgoHost &H = g.h->algo[g.algo];
+    const AlgoDevice &D = g.h->dev[b->device].algo[g.algo];
+    const ri::ScanArgs sa = group_scan_args(b, g);
     ReachBufs rb{g.alias.p, static_cast<uint32_t *>(g.run_base.p), static_cast<uint32_t *>(g.run_chunk.p),
                  static_cast<uint32_t *>(g.run_state.p), static_cast<uint32_t *>(g.run_final.p), g.counters, nullptr,
                  static_cast<uint32_t *>(g.block_count.p)};
-    int rc = launch_conv(g.cc, sa, g.opt, rb, stream, nullptr);
-    if (rc) return rc;
+    if (phase == kAllPhases) {
+        const int rc = launch_conv(g.cc, sa, g.opt, rb, stream, nullptr);
+        if (rc) return rc;
+    } else if (phase == kWarmPhase) {
+        ri::WarmArgs wa{};
+        wa.s = sa;
+        wa.warm = g.opt.warm;
+        wa.alias = rb.alias;
+        wa.run_base = rb.run_base;
+        wa.run_count = rb.run_count;
+        wa.run_chunk = rb.run_chunk;
+        wa.run_state = rb.run_state;
+        wa.counters = rb.counters;
+        wa.block_count = rb.block_count;
+        wa.cpi = g.cc.cpi;
+        HIP_TRY(ri::launch_warm(wa, g.cc.warm_shape, g.cc.grid_w, g.cc.lds_w, stream));
+        return RI_OK;
+    }
 
     const int alias_bytes = g.cc.long_shape.alias_bytes;
     ri::FinalArgs fa{};
@@ -1429,6 +1481,72 @@ int run_group(ri_batch *b, const BatchGroup &g, hipStream_t stream, int32_t *res
         fa.total = g.join[cur].p;
         HIP_TRY(ri::launch_batch_final_fun(bf, fa, H.L, stream));
     }
+    return RI_OK;
+}
+
+// Descriptors of the queued long runs (after every group is planned).  The
+// launch's LDS holds the largest group table that fits a workgroup's LDS
+// (with the byte codes and the group's dense run prefix); groups with larger
+// tables read them from L2.
+int plan_queue(ri_batch *b) {
+    std::vector<ri::QueueGroup> qg;
+    size_t lds = ri::kCodeLdsBytes;
+    int budget = 0;
+    HIP_TRY(hipDeviceGetAttribute(&budget, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device));
+
+    for (const auto &g : b->groups) {
+        if (g.empty || g.slots == 0) continue;
+        const AlgoHost &H = g.h->algo[g.algo];
+        ri::QueueGroup d{};
+        d.la = group_long_args(b, g);
+        d.entry_bytes = H.entry_bytes;
+        const size_t need = H.table.size() + ri::kCodeLdsBytes;
+        const size_t pre = round_up(((size_t)g.cc.grid_w + 1) * 4, 16);   // dense run prefix
+        d.lds = need + pre <= (size_t)budget ? 1u : 0u;
+        lds = std::max(lds, (d.lds ? need : ri::kCodeLdsBytes) + pre);
+        qg.push_back(d);
+    }
+    b->qgroups = (uint32_t)qg.size();
+    b->qlds = lds;
+    if (qg.empty()) return RI_OK;
+    int rc = grow(b->qdesc, qg.size() * sizeof(ri::QueueGroup), &b->retired);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpy(b->qdesc.p, qg.data(), qg.size() * sizeof(ri::QueueGroup), hipMemcpyHostToDevice));
+    if (!b->qcounters) HIP_TRY(hipMalloc(reinterpret_cast<void **>(&b->qcounters), kMaxQueueGroups * 4));
+    if (qg.size() > kMaxQueueGroups) return fail(RI_ERR_LIMIT, "too many automata in one queued batch");
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
+    const int per_cu = std::max(1, ri::queue_long_blocks_per_cu(lds));
+    b->qgrid = cus * per_cu;
+    return RI_OK;
+}
+
+// The long runs of every group: counters cleared by a kernel (capturable),
+// then the work-queue launch.
+int run_queue(ri_batch *b, hipStream_t stream) {
+    if (b->qgroups == 0) return RI_OK;
+    HIP_TRY(ri::launch_zero_words(b->qcounters, b->qgroups, stream));
+    ri::QueueArgs qa{};
+    qa.groups = static_cast<const ri::QueueGroup *>(b->qdesc.p);
+    qa.ngroups = b->qgroups;
+    qa.counters = b->qcounters;
+    HIP_TRY(ri::launch_queue_long(qa, b->qgrid, b->qlds, stream));
+    return RI_OK;
+}
+
+// Every group of a grouped batch on one stream.
+int run_groups(ri_batch *b, hipStream_t stream, int32_t *results) {
+    int rc = RI_OK;
+    if (!b->queue) {
+        for (const auto &g : b->groups)
+            if ((rc = run_group(b, g, stream, results)) != RI_OK) return rc;
+        return RI_OK;
+    }
+    for (const auto &g : b->groups)
+        if ((rc = run_group(b, g, stream, results, kWarmPhase)) != RI_OK) return rc;
+    if ((rc = run_queue(b, stream)) != RI_OK) return rc;
+    for (const auto &g : b->groups)
+        if ((rc = run_group(b, g, stream, results, kJoinPhase)) != RI_OK) return rc;
     return RI_OK;
 }
 
@@ -1745,7 +1863,9 @@ int batch_setup(ri_batch *b, const ri_request *reqs, uint32_t count, const ri_ba
     }
     for (auto &s : b->side) HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&b->fork2, hipEventDisableTiming));
     for (auto &e : b->joins) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto &e : b->joins2) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     bool wide = false;   // an interface beyond the grouped path's dense join
     for (auto &g : b->groups) {
         std::lock_guard<std::mutex> lk(g.h->mu);
@@ -1766,17 +1886,19 @@ int batch_setup(ri_batch *b, const ri_request *reqs, uint32_t count, const ri_ba
         b->fz.warm = o.warmup_bytes ? o.warmup_bytes : 64;
         return plan_fused(b);
     }
+    b->queue = o.mode == RI_BATCH_QUEUE;
     for (auto &g : b->groups) {
         uint64_t bytes = 0;
         for (uint32_t r : g.req) bytes += b->reqs[r].n;
         g.cs = o.chunk_bytes ? o.chunk_bytes
-                             : std::min(kBatchMaxChunk,
-                                        std::max(kBatchMinChunk, round_up((bytes + kBatchAutoChunkTarget - 1) /
-                                                                              kBatchAutoChunkTarget, 16)));
+                             : spread_chunk(std::min(kBatchMaxChunk,
+                                                     std::max(kBatchMinChunk,
+                                                              round_up((bytes + kBatchAutoChunkTarget - 1) /
+                                                                           kBatchAutoChunkTarget, 16))));
         const int rc = plan_group(b, g);
         if (rc) return rc;
     }
-    return RI_OK;
+    return b->queue ? plan_queue(b) : RI_OK;
 }
 
 }  // namespace
@@ -2076,7 +2198,7 @@ int ri_batch_create_ex(const ri_request *reqs, uint32_t count, const ri_batch_op
     if (opts) o = *opts;
     if (o.chunk_bytes % 16) return fail(RI_ERR_ARG, "chunk_bytes must be a multiple of 16");
     if (o.chunk_bytes > (1u << 30)) return fail(RI_ERR_ARG, "chunk_bytes too large");
-    if (o.mode > RI_BATCH_FUSED) return fail(RI_ERR_ARG, "unknown batch mode");
+    if (o.mode > RI_BATCH_QUEUE) return fail(RI_ERR_ARG, "unknown batch mode");
     if (o.warmup_bytes && (o.warmup_bytes < 16 || o.warmup_bytes > 256 || o.warmup_bytes % 16))
         return fail(RI_ERR_ARG, "bad warm-up length");
     if (o.reserved) return fail(RI_ERR_ARG, "reserved must be 0");
@@ -2157,11 +2279,16 @@ void ri_batch_free(ri_batch *b) {
         if (g.counters) (void)hipFree(g.counters);
     }
     release_fused(b->fz);
+    release(b->qdesc);
+    if (b->qcounters) (void)hipFree(b->qcounters);
     for (void *p : b->retired) (void)hipFree(p);
     for (auto s : b->side)
         if (s) (void)hipStreamDestroy(s);
-    if (b->fork) (void)hipEventDestroy(b->fork);
+    for (hipEvent_t e : {b->fork, b->fork2})
+        if (e) (void)hipEventDestroy(e);
     for (auto e : b->joins)
+        if (e) (void)hipEventDestroy(e);
+    for (auto e : b->joins2)
         if (e) (void)hipEventDestroy(e);
     (void)hipSetDevice(prev);
     delete b;
@@ -2173,11 +2300,7 @@ int ri_batch_run(ri_batch *b, void *stream_v, int32_t *results_dev) {
     if (rc) return rc;
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
     if (b->fused) return run_fused(b, stream, results_dev);
-    for (const auto &g : b->groups) {
-        rc = run_group(b, g, stream, results_dev);
-        if (rc) return rc;
-    }
-    return RI_OK;
+    return run_groups(b, stream, results_dev);
 }
 
 int ri_batch_capture(ri_batch *b, int32_t *results_dev) {
@@ -2196,11 +2319,25 @@ int ri_batch_capture(ri_batch *b, int32_t *results_dev) {
     e = hipEventRecord(b->fork, cap);
     for (int k = 0; k < kBatchSide && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->side[k], b->fork, 0);
     if (b->fused && e == hipSuccess) rc = run_fused(b, b->side[0], results_dev);
+    const GroupPhase first = b->queue ? kWarmPhase : kAllPhases;
     for (size_t i = 0; !b->fused && i < b->groups.size() && e == hipSuccess && rc == RI_OK; ++i)
-        rc = run_group(b, b->groups[i], b->side[i % kBatchSide], results_dev);
+        rc = run_group(b, b->groups[i], b->side[i % kBatchSide], results_dev, first);
     for (int k = 0; k < kBatchSide && e == hipSuccess; ++k) {
         e = hipEventRecord(b->joins[k], b->side[k]);
         if (e == hipSuccess) e = hipStreamWaitEvent(cap, b->joins[k], 0);
+    }
+    if (!b->fused && b->queue && e == hipSuccess && rc == RI_OK) {
+        // every group's warm-up is done: the long runs of all groups in one
+        // launch, then the joins spread over the branches again
+        rc = run_queue(b, cap);
+        if (rc == RI_OK) e = hipEventRecord(b->fork2, cap);
+        for (int k = 0; k < kBatchSide && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->side[k], b->fork2, 0);
+        for (size_t i = 0; i < b->groups.size() && e == hipSuccess && rc == RI_OK; ++i)
+            rc = run_group(b, b->groups[i], b->side[i % kBatchSide], results_dev, kJoinPhase);
+        for (int k = 0; k < kBatchSide && e == hipSuccess; ++k) {
+            e = hipEventRecord(b->joins2[k], b->side[k]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(cap, b->joins2[k], 0);
+        }
     }
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(cap, &graph);
@@ -2246,10 +2383,14 @@ int ri_batch_get_info(const ri_batch *b, ri_batch_info *out) {
     for (const auto &g : b->groups) {
         if (b->fused) break;
         out->slots += g.slots;
-        out->kernels += g.empty ? 1 : 2 + (uint32_t)g.levels.size() + 1;
+        out->kernels += g.empty ? 1 : (b->queue ? 1 : 2) + (uint32_t)g.levels.size() + 1;
         for (const Buf *x : {&g.desc, &g.alias, &g.run_base, &g.run_chunk, &g.run_state, &g.run_final,
                                         &g.join[0], &g.join[1], &g.ncls[0], &g.ncls[1]})
             out->device_bytes += x->cap;
+    }
+    if (!b->fused && b->queue && b->qgroups) {
+        out->kernels += 2;   // counter clear and the work-queue launch
+        out->device_bytes += b->qdesc.cap + kMaxQueueGroups * 4;
     }
     out->captured = b->exec != nullptr;
     out->fused = b->fused ? 1u : 0u;
@@ -2312,7 +2453,7 @@ int ri_batch_autotune(ri_batch *b, void *stream_v, ri_batch_tuning *out) {
         if (b->fixed_chunk && cs != kChunk[0]) break;
         for (uint32_t w : kWarm) {
             for (auto &g : b->groups) {
-                g.cs = b->fixed_chunk ? b->fixed_chunk : cs;
+                g.cs = b->fixed_chunk ? b->fixed_chunk : spread_chunk(cs);
                 g.opt.warm = w;
                 rc = g.empty ? RI_OK : plan_group(b, g);
                 if (rc) { cleanup(); return rc; }
@@ -2360,6 +2501,7 @@ int ri_batch_autotune(ri_batch *b, void *stream_v, ri_batch_tuning *out) {
         rc = g.empty ? RI_OK : plan_group(b, g);
         if (rc) { cleanup(); return rc; }
     }
+    if (b->queue && (rc = plan_queue(b)) != RI_OK) { cleanup(); return rc; }
     cleanup();
     if (out) {
         out->trials = trials;

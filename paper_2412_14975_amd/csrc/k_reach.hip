@@ -758,36 +758,23 @@ __device__ __forceinline__ uint32_t run_slot(const uint32_t *pre, uint32_t G, ui
     return (uint32_t)(warm_region(lo, G, iters, L, cpi) + (i - pre[lo]));
 }
 
-// The jobs of one wave, with byte codes looked up through `code`.
+// One job of a wave: the runs in slots ri[r] (where ok[r]) from the end of
+// their chunk's warm-up to the chunk end; byte codes through `code`.
 template <typename TE, int R, class Code>
-__device__ __forceinline__ void long_jobs(const LongArgs &a, const TE *tab, const Code &code, const uint32_t *pre) {
-    const uint32_t G = a.warm_blocks;
+__device__ __forceinline__ void long_job(const LongArgs &a, const TE *tab, const Code &code, const bool (&ok)[R],
+                                         const uint32_t (&ri)[R]) {
     const uint32_t lane = threadIdx.x % kWave;
-    const uint32_t iters = (a.s.nchunks + a.cpi - 1) / a.cpi;
-    auto phys = [&](uint32_t i) -> uint32_t { return run_slot(pre, G, iters, a.s.L, a.cpi, i); };
-    const uint32_t nruns = pre[G];
-    const uint32_t per_job = kWave * R;
-    const uint32_t njobs = (nruns + per_job - 1) / per_job;
     const uint32_t dead = a.s.dead;
-    // jobs cost about the same (runs of one chunk length): static schedule,
-    // dealt to the blocks in turn (job j to block j mod grid), so that every
-    // block, and so every CU, gets an equal share however few jobs there are
-    const uint32_t nwaves_grid = gridDim.x * (blockDim.x / kWave);
-    for (uint32_t job = (threadIdx.x / kWave) * gridDim.x + blockIdx.x; job < njobs; job += nwaves_grid) {
+    {
         uint64_t p[R], vend[R], end[R];
         uint32_t st[R];
-        bool ok[R];
-        uint32_t ri[R], chk[R];
+        uint32_t chk[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const uint32_t i = job * per_job + r * kWave + lane;
-            ok[r] = i < nruns;
             p[r] = vend[r] = end[r] = 0;
             st[r] = dead;
-            ri[r] = 0;
             chk[r] = 0xFFFFFFFFu;
             if (ok[r]) {
-                ri[r] = phys(i);
                 chk[r] = a.run_chunk[ri[r]];
                 uint64_t b, e;
                 bool first;
@@ -897,6 +884,32 @@ __device__ __forceinline__ void long_jobs(const LongArgs &a, const TE *tab, cons
     }
 }
 
+// The jobs of one wave in the dense run numbering (prefix `pre`).
+template <typename TE, int R, class Code>
+__device__ __forceinline__ void long_jobs(const LongArgs &a, const TE *tab, const Code &code, const uint32_t *pre) {
+    const uint32_t G = a.warm_blocks;
+    const uint32_t lane = threadIdx.x % kWave;
+    const uint32_t iters = (a.s.nchunks + a.cpi - 1) / a.cpi;
+    const uint32_t nruns = pre[G];
+    const uint32_t per_job = kWave * R;
+    const uint32_t njobs = (nruns + per_job - 1) / per_job;
+    // jobs cost about the same (runs of one chunk length): static schedule,
+    // dealt to the blocks in turn (job j to block j mod grid), so that every
+    // block, and so every CU, gets an equal share however few jobs there are
+    const uint32_t nwaves_grid = gridDim.x * (blockDim.x / kWave);
+    for (uint32_t job = (threadIdx.x / kWave) * gridDim.x + blockIdx.x; job < njobs; job += nwaves_grid) {
+        bool ok[R];
+        uint32_t ri[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t i = job * per_job + r * kWave + lane;
+            ok[r] = i < nruns;
+            ri[r] = ok[r] ? run_slot(pre, G, iters, a.s.L, a.cpi, i) : 0u;
+        }
+        long_job<TE, R, Code>(a, tab, code, ok, ri);
+    }
+}
+
 template <typename TE, int R, bool LDS>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(R == 1 ? 8 : 4))) long_kernel(LongArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -910,6 +923,85 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(R == 
         long_jobs<TE, R>(a, tab, CodeTab8{reinterpret_cast<const uint8_t *>(cls) + 512}, pre);
     else
         long_jobs<TE, R>(a, tab, CodeTab{cls}, pre);
+}
+
+// Codes (and the table when `lds`) of one group of a queued batch in LDS,
+// laid out as by stage_tables.
+__device__ __forceinline__ void stage_group(const ScanArgs &s, bool lds, uint8_t *smem) {
+    uint32_t off = 0;
+    if (lds) {
+        uint4 *dst = reinterpret_cast<uint4 *>(smem);
+        const uint4 *src = reinterpret_cast<const uint4 *>(s.table);
+        for (uint32_t i = threadIdx.x; i < s.table_bytes / 16; i += blockDim.x) dst[i] = src[i];
+        off = s.table_bytes;
+    }
+    uint16_t *c = reinterpret_cast<uint16_t *>(smem + off);
+    uint8_t *c8 = smem + off + 512;
+    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) {
+        const uint16_t v = s.code[i];
+        c[i] = v;
+        c8[i] = (uint8_t)v;
+    }
+}
+
+// One 64-run job of a queued group, with the group's entry width, table
+// placement and code width chosen per item (wave-uniform branches).
+template <typename TE, bool LDS>
+__device__ __forceinline__ void queue_job(const LongArgs &a, uint8_t *smem, const bool (&ok)[1],
+                                          const uint32_t (&ri)[1]) {
+    const TE *tab = LDS ? reinterpret_cast<const TE *>(smem) : reinterpret_cast<const TE *>(a.s.table);
+    const uint16_t *cls = reinterpret_cast<const uint16_t *>(smem + (LDS ? a.s.table_bytes : 0u));
+    if (a.s.row_bytes <= 256)
+        long_job<TE, 1>(a, tab, CodeTab8{reinterpret_cast<const uint8_t *>(cls) + 512}, ok, ri);
+    else
+        long_job<TE, 1>(a, tab, CodeTab{cls}, ok, ri);
+}
+
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) queue_long_kernel(QueueArgs q) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ uint32_t s_left;
+    const uint32_t lane = threadIdx.x % kWave;
+    const uint32_t g0 = (uint32_t)(((uint64_t)blockIdx.x * q.ngroups) / gridDim.x);
+    for (uint32_t k = 0; k < q.ngroups; ++k) {
+        const uint32_t g = g0 + k < q.ngroups ? g0 + k : g0 + k - q.ngroups;
+        const QueueGroup &d = q.groups[g];
+        const LongArgs &a = d.la;
+        const uint32_t G = a.warm_blocks;
+        // dense numbering of the group's runs (prefix of its warm-up blocks'
+        // counts, after the tables); a job is 64 consecutive runs
+        uint32_t *pre = reinterpret_cast<uint32_t *>(smem + (d.lds ? a.s.table_bytes : 0u) + kCodeLdsBytes);
+        run_prefix(pre, a.block_count, G);
+        const uint32_t nruns = pre[G];
+        const uint32_t njobs = (nruns + kWave - 1) / kWave;
+        // one thread looks whether the group has jobs left, for the block
+        if (threadIdx.x == 0) s_left = *reinterpret_cast<volatile uint32_t *>(&q.counters[g]) < njobs ? 1u : 0u;
+        __syncthreads();
+        const bool left = s_left != 0;
+        __syncthreads();
+        if (!left) continue;
+        stage_group(a.s, d.lds != 0, smem);
+        __syncthreads();
+        const uint32_t iters = (a.s.nchunks + a.cpi - 1) / a.cpi;
+        for (;;) {
+            uint32_t job = 0;
+            if (lane == 0) job = atomicAdd(&q.counters[g], 1u);
+            job = wave_uniform((uint32_t)__shfl((int)job, 0));
+            if (job >= njobs) break;
+            const uint32_t i = job * kWave + lane;
+            const bool ok[1] = {i < nruns};
+            const uint32_t ri[1] = {ok[0] ? run_slot(pre, G, iters, a.s.L, a.cpi, i) : 0u};
+            if (d.lds) {
+                if (d.entry_bytes == 1) queue_job<uint8_t, true>(a, smem, ok, ri);
+                else if (d.entry_bytes == 2) queue_job<uint16_t, true>(a, smem, ok, ri);
+                else queue_job<uint32_t, true>(a, smem, ok, ri);
+            } else {
+                if (d.entry_bytes == 1) queue_job<uint8_t, false>(a, smem, ok, ri);
+                else if (d.entry_bytes == 2) queue_job<uint16_t, false>(a, smem, ok, ri);
+                else queue_job<uint32_t, false>(a, smem, ok, ri);
+            }
+        }
+        __syncthreads();   // every wave is done with the group's tables and prefix
+    }
 }
 
 const void *g_fn = nullptr;   // set by the dispatch below when only the function is wanted
@@ -953,6 +1045,19 @@ hipError_t launch_warm(const WarmArgs &a, const KernelShape &k, int grid, size_t
             });
         });
     });
+}
+
+hipError_t launch_queue_long(const QueueArgs &a, int grid, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL(queue_long_kernel, dim3(grid), dim3(1024), lds, st, a);
+    return hipGetLastError();
+}
+
+int queue_long_blocks_per_cu(size_t lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(queue_long_kernel), 1024,
+                                                     lds) != hipSuccess)
+        return 0;
+    return nb;
 }
 
 size_t warm_lds_bytes(const KernelShape &k, uint32_t table_bytes, uint32_t L) {

@@ -120,6 +120,27 @@ hipError_t launch_long(const LongArgs &a, const KernelShape &k, int grid, size_t
 // blocks of a kernel that fit on one CU: which = 0 plain, 1 warm, 2 long
 int blocks_per_cu(int which, const KernelShape &k, size_t lds);
 
+// ---- long runs of a grouped batch: one persistent work-queue launch ----
+// An item is a job of 64 consecutive runs of one group (automaton) in the
+// group's dense run numbering.  A workgroup takes the groups in turn,
+// starting at group blockIdx * ngroups / grid; for each group that still has
+// jobs it computes the group's run prefix and stages its byte codes (and its
+// table when `lds`) in LDS, and its waves pull jobs from the group's counter
+// until none is left.  Runs are stepped as by launch_long (one run per
+// lane).
+struct QueueGroup {
+    LongArgs la;
+    uint32_t entry_bytes;      // 1, 2, 4
+    uint32_t lds;              // 1: the table is staged in LDS
+};
+struct QueueArgs {
+    const QueueGroup *groups;
+    uint32_t ngroups;
+    uint32_t *counters;        // [ngroups] jobs taken; zero before the launch
+};
+hipError_t launch_queue_long(const QueueArgs &a, int grid, size_t lds, hipStream_t st);
+int queue_long_blocks_per_cu(size_t lds);
+
 // ---- join ----
 struct JoinArgs {
     // level 0 input: either plain chunk maps or the converged form

@@ -71,7 +71,7 @@ def mixed_requests(seed):
     return out
 
 
-MODES = ("grouped", "fused")
+MODES = ("grouped", "fused", "queue")
 
 
 def check_batch(reqs, chunk_bytes, refs, recs, launch="run", mode="auto"):
@@ -79,14 +79,24 @@ def check_batch(reqs, chunk_bytes, refs, recs, launch="run", mode="auto"):
     b = ri.Batch([(recs[p], t, a) for (p, _, a), t in zip(reqs, texts)], chunk_bytes=chunk_bytes, mode=mode)
     try:
         if launch == "run":
-            got = b.run().cpu().numpy()
+            runs = [b.run().cpu().numpy()]
         else:
+            # replays of one captured graph, with eager work of the same batch
+            # in between: every replay must give the same results
             b.capture()
-            got = b.launch().cpu().numpy()
+            runs = []
+            for rep in range(3):
+                runs.append(b.launch().cpu().numpy())
+                if rep == 0:
+                    b.run()
+                torch.cuda.synchronize()
         torch.cuda.synchronize()
+        for got in runs:
+            for i, (p, x, a) in enumerate(reqs):
+                want = refs[p].serial(x)
+                assert (bool(got[i, 0]), int(got[i, 1])) == want, (p, len(x), a, chunk_bytes)
         for i, (p, x, a) in enumerate(reqs):
             want = refs[p].serial(x)
-            assert (bool(got[i, 0]), int(got[i, 1])) == want, (p, len(x), a, chunk_bytes)
             if len(x) and i % 3 == 0:
                 alone = recs[p].recognize(texts[i], algo=a)
                 assert (alone["accept"], alone["final_state"]) == want
