@@ -379,6 +379,82 @@ __device__ uint32_t merge_direct(const uint32_t (&st)[R], uint32_t dead, uint32_
     return D;
 }
 
+// Single-register warm-up steps [j0, j1) of G chunks with their byte codes
+// broadcast from LDS instead of readlane: the codes are written once to the
+// wave's key area (free between merges), u8 when every code is below 256,
+// and read back 8 at a time by every lane (one address: no bank conflict),
+// so a step costs one add and one lookup.  Every chunk must have all
+// j1 - j0 bytes.  Leaves early when every run is dead.
+template <typename TE, int NQ, int G, typename CT>
+__device__ __forceinline__ void warm_steps_lds(uint32_t (&st)[G][1], const uint32_t (&code)[G][NQ], uint32_t j0,
+                                               uint32_t j1, const TE *tab, uint32_t dead, lds_u32 *key, uint32_t lane) {
+    typedef volatile __attribute__((address_space(3))) CT lds_ct;
+    typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+    typedef const __attribute__((address_space(3))) v2u lds_u2;
+    typedef const __attribute__((address_space(3))) v4u lds_u4;
+    const uint32_t n = j1 - j0;
+    const uint32_t stride = (n * (uint32_t)sizeof(CT) + 15u) & ~15u;
+    lds_ct *area = (lds_ct *)key;
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (uint32_t q = 0; q < (uint32_t)NQ; ++q) {
+            const uint32_t p = q * kWave + lane;
+            if (p >= j0 && p < j1) area[(g * stride) / sizeof(CT) + (p - j0)] = (CT)code[g][q];
+        }
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t k = 0; k < n; k += 8) {
+        bool alive = false;
+#pragma unroll
+        for (int g = 0; g < G; ++g) alive |= st[g][0] != dead;
+        if (__ballot(alive) == 0) break;
+        uint32_t w[G][sizeof(CT) == 1 ? 2 : 4];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint32_t off = g * stride + k * (uint32_t)sizeof(CT);
+            if constexpr (sizeof(CT) == 1) {
+                const v2u v = *(lds_u2 *)((const __attribute__((address_space(3))) uint8_t *)key + off);
+                w[g][0] = v.x;
+                w[g][1] = v.y;
+            } else {
+                const v4u v = *(lds_u4 *)((const __attribute__((address_space(3))) uint8_t *)key + off);
+                w[g][0] = v.x;
+                w[g][1] = v.y;
+                w[g][2] = v.z;
+                w[g][3] = v.w;
+            }
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < 8; ++i)
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const uint32_t c = sizeof(CT) == 1 ? (w[g][i >> 2] >> ((i & 3) * 8)) & 0xffu
+                                                   : (w[g][i >> 1] >> ((i & 1) * 16)) & 0xffffu;
+                st[g][0] = next_state<TE>(tab, st[g][0], c);
+            }
+    }
+    __builtin_amdgcn_wave_barrier();   // the key area is written again by the next chunks
+}
+
+// Single-register steps [j0, j1) through LDS codes when they fit the key area
+// and every chunk has all the bytes, else by readlane.
+template <typename TE, int NQ, int G>
+__device__ __forceinline__ void warm_steps1(uint32_t (&st)[G][1], const uint32_t (&code)[G][NQ],
+                                            const uint32_t (&wlen)[G], uint32_t j0, uint32_t j1, const TE *tab,
+                                            uint32_t dead, lds_u32 *key, uint32_t lane, bool code8) {
+    bool full = j1 > j0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) full &= wlen[g] >= j1;
+    const uint32_t n = j1 - j0;
+    if (full && (n & 7u) == 0 && code8 && G * ((n + 15u) & ~15u) <= kDirectKeyBytes - 16)
+        warm_steps_lds<TE, NQ, G, uint8_t>(st, code, j0, j1, tab, dead, key, lane);
+    else if (full && (n & 7u) == 0 && G * ((2 * n + 15u) & ~15u) <= kDirectKeyBytes - 16)
+        warm_steps_lds<TE, NQ, G, uint16_t>(st, code, j0, j1, tab, dead, key, lane);
+    else
+        warm_steps<TE, 1, NQ, G>(st, code, wlen, j0, j1, tab, dead);
+}
+
 // warm_merge_chunks with direct merging; instead of returning the runs it
 // hands each chunk's result to emit(g, D, acl, lead, ecl, eidx): acl[r] the
 // class of start r * 64 + lane, and for each register of the last merge the
@@ -388,7 +464,7 @@ __device__ __forceinline__ void warm_direct_chunks(const TE *tab, const StartLis
                                                    const bool (&ok)[G], const bool (&first)[G],
                                                    const uint32_t (&code)[G][NQ], const uint32_t (&wlen)[G],
                                                    uint32_t lane, uint64_t lane_lt, lds_u32 *key, lds_u8 *slot,
-                                                   const RowDiv &rd, Emit &&emit) {
+                                                   const RowDiv &rd, bool code8, Emit &&emit) {
     constexpr uint32_t kNone = 0xFFFFFFFFu;
     uint32_t st[G][R], cl[G][R], D[G];
     uint32_t W = 0;
@@ -402,7 +478,10 @@ __device__ __forceinline__ void warm_direct_chunks(const TE *tab, const StartLis
         }
     }
     uint32_t j = (R == 1 || W < kMergeSplit) ? W : kMergeSplit;
-    warm_steps<TE, R, NQ, G>(st, code, wlen, 0, j, tab, dead);
+    if constexpr (R == 1)
+        warm_steps1<TE, NQ, G>(st, code, wlen, 0, j, tab, dead, key, lane, code8);
+    else
+        warm_steps<TE, R, NQ, G>(st, code, wlen, 0, j, tab, dead);
     uint32_t Dmax = 0;
     if (j < W) {
 #pragma unroll
@@ -448,7 +527,7 @@ __device__ __forceinline__ void warm_direct_chunks(const TE *tab, const StartLis
         one[g][0] = lane < D[g] ? key[lane] : dead;
         __builtin_amdgcn_wave_barrier();
     }
-    warm_steps<TE, 1, NQ, G>(one, code, wlen, j, W, tab, dead);
+    warm_steps1<TE, NQ, G>(one, code, wlen, j, W, tab, dead, key, lane, code8);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         uint32_t c2[1], ix[1];
@@ -660,7 +739,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
                 }
             };
             warm_direct_chunks<TE, R, NQ, G>(tab, starts, L, dead, ok, cur_first, code, cur_wlen, lane, lane_lt, dkey,
-                                             dslot, rd, emit);
+                                             dslot, rd, a.s.row_bytes <= 256, emit);
         } else {
         uint32_t cl[G][R], one[G], D[G], st[G][R];
         bool compacted;
