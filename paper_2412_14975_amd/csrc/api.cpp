@@ -1026,8 +1026,43 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         if (gated_cls) {
             ca.gate = sc.counters + 2;
             fa.result = result_dev;
-            rc = cls_join();
-            if (rc) return rc;
+            // the levels of the class join, enqueued as one gated launch when
+            // they are few enough (else one gated launch per level)
+            ri::ClsJoinAll all{};
+            uint32_t nl = 0;
+            ca.G = gc;
+            ca.nmembers = plan.nchunks;
+            ca.span = 1;
+            ca.ncls_in = nullptr;
+            ca.cont_in = nullptr;
+            ca.ncls_out = sc.ncls[0];
+            ca.cont_out = static_cast<uint32_t *>(sc.join[0]);
+            all.lv[nl++] = ca;
+            int cur = 0;
+            uint32_t nm = (plan.nchunks + gc - 1) / gc;
+            uint64_t span = gc;
+            while (nm > 1 && nl < ri::kMaxClsLevels) {
+                ca.nmembers = nm;
+                ca.span = span;
+                ca.ncls_in = sc.ncls[cur];
+                ca.cont_in = static_cast<const uint32_t *>(sc.join[cur]);
+                ca.ncls_out = sc.ncls[cur ^ 1];
+                ca.cont_out = static_cast<uint32_t *>(sc.join[cur ^ 1]);
+                all.lv[nl++] = ca;
+                cur ^= 1;
+                span *= gc;
+                nm = (nm + gc - 1) / gc;
+            }
+            if (nm == 1) {
+                all.nlevels = nl;
+                all.final_rel = static_cast<const uint32_t *>(sc.join[cur]);
+                all.f = fa;
+                all.done = sc.counters + 8;
+                HIP_TRY(ri::launch_cls_join_all(all, (int)H.W, shape.alias_bytes, stream));
+            } else {
+                rc = cls_join();
+                if (rc) return rc;
+            }
         }
     } else if (gc) {
         if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(sc.dbg), stream));

@@ -176,16 +176,16 @@ __global__ void __launch_bounds__(256) join0_tile_kernel(JoinArgs a, View view) 
 // classes; larger classes are read from global memory.
 constexpr uint32_t kClsStage = 8;
 
+// One group `grp` of a class-join level, by the calling block (LDS at smem,
+// cls_join_lds bytes).  Starts and ends by reading and writing LDS: a block
+// that takes several groups synchronizes between them.
 template <int W, typename TA, bool LEVEL0>
-__global__ void __launch_bounds__(256) join_cls_kernel(ClsJoinArgs a) {
-    if (a.gate && *reinterpret_cast<const volatile uint32_t *>(a.gate) == 0) return;
-    extern __shared__ __align__(16) uint8_t smem[];
+__device__ void cls_group(const ClsJoinArgs &a, uint32_t grp, uint8_t *smem) {
     uint32_t *scont = reinterpret_cast<uint32_t *>(smem);                    // [G][kClsStage][W]
     uint32_t *sncls = scont + (size_t)a.G * kClsStage * W;                    // [G]
     TA *salias = reinterpret_cast<TA *>(sncls + a.G);                         // [L][GS]
     const uint32_t G = a.G, L = a.L;
     const uint32_t GS = tile_stride<TA>(G);
-    const uint32_t grp = blockIdx.x;
     const uint32_t m0 = a.grp_first ? a.grp_first[grp] : grp * G;
     const uint32_t gn = a.grp_first ? a.grp_count[grp] : m0 + G < a.nmembers ? G : a.nmembers - m0;
     const TA *alias = reinterpret_cast<const TA *>(a.alias);
@@ -265,6 +265,52 @@ __global__ void __launch_bounds__(256) join_cls_kernel(ClsJoinArgs a) {
         if (lane < (uint32_t)W) a.cont_out[((uint64_t)grp * L + cls) * W + lane] = xw;
     }
     if (threadIdx.x == 0) a.ncls_out[grp] = ncls0;
+}
+
+template <int W, typename TA, bool LEVEL0>
+__global__ void __launch_bounds__(256) join_cls_kernel(ClsJoinArgs a) {
+    if (a.gate && *reinterpret_cast<const volatile uint32_t *>(a.gate) == 0) return;
+    extern __shared__ __align__(16) uint8_t smem[];
+    cls_group<W, TA, LEVEL0>(a, blockIdx.x, smem);
+}
+
+// The whole class join in one launch, for queued calls where it is gated on
+// the hit join's flag: while the flag is clear every block returns at once
+// (one launch instead of one per level and the final step).  Otherwise
+// every block joins one group of level 0; the last block to finish (a
+// counter after a device-scope fence, so that it sees every group's output)
+// joins the upper levels group by group and takes the final step.
+template <int W, typename TA>
+__global__ void __launch_bounds__(256) cls_join_all_kernel(ClsJoinAll c) {
+    if (*reinterpret_cast<const volatile uint32_t *>(c.lv[0].gate) == 0) return;
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ uint32_t s_last;
+    cls_group<W, TA, true>(c.lv[0], blockIdx.x, smem);
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(c.done, 1u) == gridDim.x - 1 ? 1u : 0u;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    for (uint32_t l = 1; l < c.nlevels; ++l) {
+        const ClsJoinArgs &a = c.lv[l];
+        const uint32_t ngroups = (a.nmembers + a.G - 1) / a.G;
+        for (uint32_t grp = 0; grp < ngroups; ++grp) {
+            cls_group<W, TA, false>(a, grp, smem);
+            __syncthreads();
+        }
+        __threadfence();   // this level's output is read by the next one
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const ClsJoinArgs &a = c.lv[c.nlevels - 1];
+        const TA c0 = reinterpret_cast<const TA *>(a.alias)[0];
+        uint32_t x[W];
+        load_row<W>(x, c0 != all_ones<TA>() ? c.final_rel + (uint64_t)c0 * W : nullptr);
+        decide<W>(x, c.f, c.f.result);
+        reset_counters(c.f.counters);
+        *c.done = 0;
+    }
 }
 
 // Level 0, fused with the hit rows: wave per group of 64 matrices; lane l
@@ -702,6 +748,19 @@ hipError_t launch_join_cls(const ClsJoinArgs &a, int W, int alias_bytes, bool le
 #undef CALLC
             return hipGetLastError();
         });
+    });
+}
+
+hipError_t launch_cls_join_all(const ClsJoinAll &c, int W, int alias_bytes, hipStream_t s) {
+    const ClsJoinArgs &a = c.lv[0];
+    const uint32_t ngroups = (a.nmembers + a.G - 1) / a.G;
+    size_t lds = 0;
+    for (uint32_t l = 0; l < c.nlevels; ++l) lds = std::max(lds, cls_join_lds(c.lv[l], W, alias_bytes));
+    return dispatch_ta(alias_bytes, [&](auto ta) {
+#define CALLA(w) hipLaunchKernelGGL((cls_join_all_kernel<w, decltype(ta)>), dim3(ngroups), dim3(256), lds, s, c);
+        RI_DISPATCH_W(W, CALLA)
+#undef CALLA
+        return hipGetLastError();
     });
 }
 

@@ -80,8 +80,9 @@ def test_queued_calls_match_the_oracle(mode):
 @pytest.mark.parametrize("k", [8, 9, 16])
 def test_hit_join_fallback_on_the_device(k):
     """Counting a's modulo k keeps k runs per chunk: above 8 the hit-matrix
-    result is invalid and the queued call redoes the join by propagation on
-    the device, with no host decision."""
+    result is invalid and the queued call redoes the join on the device (the
+    class join, one launch gated on the hit join's flag), with no host
+    decision."""
     rx = b"((b*a){%d})*b*" % k
     ref = serial_ref(rx)
     rec = ri.Recognizer(rx)
