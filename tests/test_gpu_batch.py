@@ -312,3 +312,38 @@ def test_fused_batch_of_large_automata():
     finally:
         for r in recs.values():
             r.close()
+
+
+def test_queue_with_tables_in_l2():
+    """Work-queue batches mixing an automaton whose tables do not fit LDS
+    (40 keywords under a star: B' of 1584 states over 38 classes, 241 KB,
+    read from L2 by the queue) with small ones staged in LDS: every text
+    gets the oracle's result, RID and DFA, run and graph."""
+    rng = np.random.default_rng(5)
+    letters = b"abcdefghijklmnopqrstuvwxyz0123456789"
+    kws = [bytes(rng.choice(list(letters), size=int(rng.integers(4, 9)))) for _ in range(40)]
+    big = b"(" + b"|".join(kws) + b")*"
+    pats = [big, gen.c1_regex(), b"ab*"]
+    refs = {p: MinRef(p) for p in pats}
+    recs = {p: ri.Recognizer(p) for p in pats}
+    assert recs[big].info()["table_bytes"][0] > 160 * 1024
+    prng = gen.PCG(77)
+    reqs = []
+    for i, n_words in enumerate((0, 1, 7, 300, 4000, 20000)):
+        x = np.frombuffer(b"".join(kws[int(j)] for j in rng.integers(0, len(kws), size=n_words)), np.uint8).copy()
+        if i % 2 and len(x):
+            x[int(rng.integers(0, len(x)))] = ord("#")   # rejected
+        reqs.append((big, x, ("rid", "dfa")[i % 2]))
+        reqs.append((big, x, ("dfa", "rid")[i % 2]))
+    for p in pats[1:]:
+        for n in (100, 70001):
+            x = gen.random_text(prng, b"ab", n)
+            reqs.append((p, x, "rid"))
+            reqs.append((p, x, "dfa"))
+    try:
+        for launch in ("run", "graph"):
+            info = check_batch(reqs, 0, refs, recs, launch=launch, mode="queue")
+            assert info["texts"] == len(reqs)
+    finally:
+        for r in recs.values():
+            r.close()
