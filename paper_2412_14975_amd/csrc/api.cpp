@@ -2148,8 +2148,8 @@ int ri_autotune(ri_handle *h, const uint8_t *text, size_t n, void *stream, int a
         saved = h->opt;
         h->tuned_valid[algo] = false;
     }
-    static const uint32_t kTargets[] = {32768, 65536, 131072, 262144, 524288};
-    static const uint32_t kWarm[] = {16, 32, 64, 128};
+    static const uint32_t kTargets[] = {32768, 65536, 98304, 131072, 196608, 262144, 524288};
+    static const uint32_t kWarm[] = {16, 32, 48, 64, 96, 128};
     static const uint32_t kRuns[] = {1, 2};
     // the grid: converging reach over targets x warm-up x runs per lane, then
     // the plain reach over targets x runs per lane
