@@ -846,6 +846,27 @@ def main():
         trec.close()
         del tt
         print(f"# tiny done", file=sys.stderr, flush=True)
+        # the class-join fallback at scale: counting a's modulo 9 keeps 9 runs
+        # per chunk (more than a hit-matrix row holds), so every call redoes
+        # the join as a class join (queued: gated on the hit join's flag)
+        frx = b"((b*a){9})*b*"
+        fx = gen.random_text(gen.PCG(31), b"ab", 256 << 20)
+        fref = oracle.build(frx)
+        fwant = oracle.serial(fref.dfa, fx)
+        frec = ri.Recognizer(frx)
+        ft = torch.from_numpy(fx).to("cuda")
+        fb = {}
+        for chunks in (131072,):
+            m = time_algo(torch, frec, ft, "rid", chunks, 10, 2, fwant, {"warmup_bytes": 16, "converge": 1})
+            fb[f"c{chunks}"] = dict(gbps=round(len(fx) * 10 / m["queued"] / 1e9, 2),
+                                    ms_per_step=round(m["queued"] / 10 * 1e3, 4),
+                                    join_ms=round(float(m["join_ms"].mean()), 4),
+                                    sync_p50_ms=round(float(np.percentile(m["per_call"], 50)) * 1e3, 4),
+                                    chunks=m["result"]["chunks"], bitexact=bool(m["exact"]))
+        extras["class_join_fallback_mod9_256MiB"] = fb
+        frec.close()
+        del ft
+        print(f"# fallback done", file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel: the long-run kernel of the converging
     # reach.  Algorithmic bytes per launch = the text bytes it must read, i.e.
@@ -908,6 +929,7 @@ def main():
             plain is None or (plain["rid"]["bitexact"] and plain["dfa"]["bitexact"])) and (
             extras is None or (extras["all_states_subset_dfa"]["bitexact"] and all(
                 v["bitexact"] for a in ("rid", "dfa") for v in extras["tiny_regexp_k3_1MiB"][a].values())
+                and all(v["bitexact"] for v in extras["class_join_fallback_mod9_256MiB"].values())
                 and extras.get("nfa_device", {}).get("bitexact", True))),
         "rid": rounded(s_rid) if prim == "rid" else None,
         "all_states_dfa": rounded(s_dfa) if s_dfa else (rounded(s_rid) if prim == "dfa" else None),

@@ -1026,8 +1026,10 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         if (gated_cls) {
             ca.gate = sc.counters + 2;
             fa.result = result_dev;
-            // the levels of the class join, enqueued as one gated launch when
-            // they are few enough (else one gated launch per level)
+            // the class join, gated: level 0 in one launch, then level 1 in
+            // one launch whose last block takes the higher levels (few groups)
+            // and the final step (a single launch when level 0 is the only
+            // level); one launch per level when there are too many levels
             ri::ClsJoinAll all{};
             uint32_t nl = 0;
             ca.G = gc;
@@ -1054,11 +1056,18 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
                 nm = (nm + gc - 1) / gc;
             }
             if (nm == 1) {
-                all.nlevels = nl;
                 all.final_rel = static_cast<const uint32_t *>(sc.join[cur]);
                 all.f = fa;
                 all.done = sc.counters + 8;
-                HIP_TRY(ri::launch_cls_join_all(all, (int)H.W, shape.alias_bytes, stream));
+                if (nl == 1) {
+                    all.nlevels = 1;
+                    HIP_TRY(ri::launch_cls_join_all(all, (int)H.W, shape.alias_bytes, true, stream));
+                } else {
+                    HIP_TRY(ri::launch_join_cls(all.lv[0], (int)H.W, shape.alias_bytes, true, stream));
+                    for (uint32_t l = 1; l < nl; ++l) all.lv[l - 1] = all.lv[l];
+                    all.nlevels = nl - 1;
+                    HIP_TRY(ri::launch_cls_join_all(all, (int)H.W, shape.alias_bytes, false, stream));
+                }
             } else {
                 rc = cls_join();
                 if (rc) return rc;

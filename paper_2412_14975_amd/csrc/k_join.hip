@@ -274,18 +274,19 @@ __global__ void __launch_bounds__(256) join_cls_kernel(ClsJoinArgs a) {
     cls_group<W, TA, LEVEL0>(a, blockIdx.x, smem);
 }
 
-// The whole class join in one launch, for queued calls where it is gated on
-// the hit join's flag: while the flag is clear every block returns at once
-// (one launch instead of one per level and the final step).  Otherwise
-// every block joins one group of level 0; the last block to finish (a
-// counter after a device-scope fence, so that it sees every group's output)
-// joins the upper levels group by group and takes the final step.
-template <int W, typename TA>
+// The class join's levels lv[0 ..] and final step in one launch, for queued
+// calls where it is gated on the hit join's flag: while the flag is clear
+// every block returns at once.  Otherwise every block joins one group of
+// lv[0] (level 0 when FIRST0); the last block to finish (a counter after a
+// device-scope fence, so that it sees every group's output) joins the
+// remaining levels group by group (a few groups: lv[0] is level 0 or 1) and
+// takes the final step.
+template <int W, typename TA, bool FIRST0>
 __global__ void __launch_bounds__(256) cls_join_all_kernel(ClsJoinAll c) {
     if (*reinterpret_cast<const volatile uint32_t *>(c.lv[0].gate) == 0) return;
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ uint32_t s_last;
-    cls_group<W, TA, true>(c.lv[0], blockIdx.x, smem);
+    cls_group<W, TA, FIRST0>(c.lv[0], blockIdx.x, smem);
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) s_last = atomicAdd(c.done, 1u) == gridDim.x - 1 ? 1u : 0u;
@@ -751,16 +752,18 @@ hipError_t launch_join_cls(const ClsJoinArgs &a, int W, int alias_bytes, bool le
     });
 }
 
-hipError_t launch_cls_join_all(const ClsJoinAll &c, int W, int alias_bytes, hipStream_t s) {
+hipError_t launch_cls_join_all(const ClsJoinAll &c, int W, int alias_bytes, bool first0, hipStream_t s) {
     const ClsJoinArgs &a = c.lv[0];
     const uint32_t ngroups = (a.nmembers + a.G - 1) / a.G;
     size_t lds = 0;
     for (uint32_t l = 0; l < c.nlevels; ++l) lds = std::max(lds, cls_join_lds(c.lv[l], W, alias_bytes));
     return dispatch_ta(alias_bytes, [&](auto ta) {
-#define CALLA(w) hipLaunchKernelGGL((cls_join_all_kernel<w, decltype(ta)>), dim3(ngroups), dim3(256), lds, s, c);
-        RI_DISPATCH_W(W, CALLA)
+        return dispatch_b(first0, [&](auto f0) {
+#define CALLA(w) hipLaunchKernelGGL((cls_join_all_kernel<w, decltype(ta), decltype(f0)::value>), dim3(ngroups), dim3(256), lds, s, c);
+            RI_DISPATCH_W(W, CALLA)
 #undef CALLA
-        return hipGetLastError();
+            return hipGetLastError();
+        });
     });
 }
 

@@ -246,10 +246,11 @@ struct FinalArgs {
 hipError_t launch_finalize_rel(const FinalArgs &a, int W, hipStream_t s);
 hipError_t launch_finalize_fun(const FinalArgs &a, hipStream_t s);
 hipError_t launch_finalize_cls(const FinalArgs &f, const ClsJoinArgs &a, int W, int alias_bytes, hipStream_t s);
-// The class join of a queued call in one launch, gated on *lv[0].gate: the
-// levels lv[0 .. nlevels) (level 0 one group per block, the upper levels by
-// the block that finishes level 0 last), then the final step on final_rel,
-// the relation rows the last level wrote.
+// Levels of the class join of a queued call and its final step in one
+// launch, gated on *lv[0].gate: lv[0] (level 0 when first0, else level 1) one
+// group per block, the remaining levels by the block that finishes lv[0]
+// last, then the final step on final_rel, the relation rows the last level
+// wrote.
 constexpr uint32_t kMaxClsLevels = 8;
 struct ClsJoinAll {
     ClsJoinArgs lv[kMaxClsLevels];
@@ -258,7 +259,7 @@ struct ClsJoinAll {
     FinalArgs f;
     uint32_t *done;            // zero before the launch, left zero
 };
-hipError_t launch_cls_join_all(const ClsJoinAll &c, int W, int alias_bytes, hipStream_t s);
+hipError_t launch_cls_join_all(const ClsJoinAll &c, int W, int alias_bytes, bool first0, hipStream_t s);
 // The last level (a.nmembers <= kHitTailMax products in a.prod_in, 0 for a
 // single chunk) and the final step, in one launch.
 // result[2] = counters[2] (1: the hit-matrix result is not valid).  With
