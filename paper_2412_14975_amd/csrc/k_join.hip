@@ -328,11 +328,27 @@ __global__ void __launch_bounds__(256) hit_prod0_kernel(HitArgs a) {
     const uint32_t k = g * kWave + lane;
     const TA *alias = reinterpret_cast<const TA *>(a.alias);
     // STAGE: the wave's next-chunk rows (chunks 64 g + 1 .. 64 g + gn, one
-    // contiguous span) are copied to LDS first, lanes over elements
-    TA *srow = reinterpret_cast<TA *>(hsm) + (size_t)(threadIdx.x / kWave) * kWave * a.L;
+    // contiguous span of bytes [b0, b1)) are copied to LDS first: the LDS
+    // image keeps the span's alignment (it starts at b0 rounded down to 16),
+    // so the 16-byte-aligned interior moves as 16-byte words and only the
+    // head and tail bytes one by one; nothing outside the span is read
+    uint8_t *simg = hsm + (size_t)(threadIdx.x / kWave) * kHitStageBytes(a.L, sizeof(TA));
+    TA *srow = nullptr;
     if constexpr (STAGE) {
-        const TA *src = alias + (uint64_t)(g * kWave + 1) * a.L;
-        for (uint32_t i = lane; i < gn * a.L; i += kWave) srow[i] = src[i];
+        const uint8_t *gb = reinterpret_cast<const uint8_t *>(alias);
+        const uint64_t b0 = (uint64_t)(g * kWave + 1) * a.L * sizeof(TA);
+        const uint64_t b1 = b0 + (uint64_t)gn * a.L * sizeof(TA);
+        const uint64_t base = b0 & ~(uint64_t)15;
+        const uint64_t a0 = (b0 + 15) & ~(uint64_t)15, a1 = b1 & ~(uint64_t)15;
+        if (a0 < a1) {
+            for (uint64_t o = a0 + 16 * lane; o < a1; o += 16 * kWave)
+                *reinterpret_cast<uint4 *>(simg + (o - base)) = *reinterpret_cast<const uint4 *>(gb + o);
+            for (uint64_t o = b0 + lane; o < a0; o += kWave) simg[o - base] = gb[o];
+            for (uint64_t o = a1 + lane; o < b1; o += kWave) simg[o - base] = gb[o];
+        } else {
+            for (uint64_t o = b0 + lane; o < b1; o += kWave) simg[o - base] = gb[o];
+        }
+        srow = reinterpret_cast<TA *>(simg + (b0 - base));
         __builtin_amdgcn_wave_barrier();   // the rows are read by other lanes of this wave
     }
     uint64_t M = 0;
@@ -796,7 +812,7 @@ hipError_t launch_hit_prod(const HitArgs &a, int W, int alias_bytes, bool level0
         return hipGetLastError();
     }
     // next-chunk rows staged in LDS when 4 waves x 64 rows fit in 64 KiB
-    const size_t stage = (size_t)4 * kWave * a.L * alias_bytes;
+    const size_t stage = (size_t)4 * kHitStageBytes(a.L, alias_bytes);
     const bool st = stage <= 65536;
     return dispatch_ta(alias_bytes, [&](auto ta) {
         return dispatch_b(st, [&](auto stg) {

@@ -228,6 +228,11 @@ struct HitArgs {
 };
 // W: words of the dense content bitsets, 0 = member lists
 hipError_t launch_hit_prod(const HitArgs &a, int W, int alias_bytes, bool level0, hipStream_t s);
+// LDS bytes of one wave's staged alias rows in hit_prod0 (64 rows, plus 16
+// for the alignment of the image)
+__host__ __device__ constexpr size_t kHitStageBytes(uint32_t L, size_t alias_bytes) {
+    return (((size_t)64 * L * alias_bytes + 16) + 15) & ~(size_t)15;
+}
 
 struct FinalArgs {
     const void *total;         // one relation [L][W] or one function [L]
