@@ -809,6 +809,16 @@ def main():
                                                states=info["subset_dfa_states"],
                                                speedup_rid_vs_subset=round(s_rid["gbps"] / (n * max(3, args.steps // 3) / m["queued"] / 1e9), 4))
         print(f"# subset done", file=sys.stderr, flush=True)
+        # RID with every start stepping from the first byte of its chunk (no
+        # walk of the starts' transformation automaton), at the tuned setting
+        if info["prefix_depth"][0]:
+            k = max(3, args.steps // 3)
+            rec.set_option("prefix", 0)
+            m = time_algo(torch, rec, t, "rid", args.chunks, k, 2, want, fixed.get("rid"))
+            rec.set_option("prefix", 1)
+            extras["rid_without_prefix_walk"] = dict(rounded(summary(m, k)), prefix_depth=info["prefix_depth"][0],
+                                                     prefix_states=info["prefix_states"][0])
+            print(f"# no-prefix done", file=sys.stderr, flush=True)
         # the NFA device of Sect. 2: the position NFA as chunk automaton,
         # every NFA state speculated, runs as sets of states
         if info["starts"][3] <= 256:
@@ -930,7 +940,8 @@ def main():
             extras is None or (extras["all_states_subset_dfa"]["bitexact"] and all(
                 v["bitexact"] for a in ("rid", "dfa") for v in extras["tiny_regexp_k3_1MiB"][a].values())
                 and all(v["bitexact"] for v in extras["class_join_fallback_mod9_256MiB"].values())
-                and extras.get("nfa_device", {}).get("bitexact", True))),
+                and extras.get("nfa_device", {}).get("bitexact", True)
+                and extras.get("rid_without_prefix_walk", {}).get("bitexact", True))),
         "rid": rounded(s_rid) if prim == "rid" else None,
         "all_states_dfa": rounded(s_dfa) if s_dfa else (rounded(s_rid) if prim == "dfa" else None),
         "speedup_rid_vs_dfa": round(s_rid["gbps"] / s_dfa["gbps"], 4) if s_dfa else None,

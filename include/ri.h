@@ -90,6 +90,10 @@ typedef struct {
     uint32_t starts[RI_NUM_ALGOS];      /* speculative starts per chunk, per algo      */
     uint32_t entry_bytes[RI_NUM_ALGOS]; /* bytes per transition-table entry, per algo  */
     uint64_t table_bytes[RI_NUM_ALGOS]; /* device transition-table bytes, per algo     */
+    uint32_t prefix_depth[RI_NUM_ALGOS];  /* warm-up bytes covered by the transformation
+                                             automaton of the starts (0: none; see
+                                             RI_OPT_PREFIX)                               */
+    uint32_t prefix_states[RI_NUM_ALGOS]; /* its states                                 */
 } ri_info_t;
 
 /*
@@ -98,7 +102,9 @@ typedef struct {
  * position NFA N, RI-DFA B = RI-DFA(N) (Sect. 3.1), Nerode classes of B and
  * the interface reduction (Sect. 3.4), the quotient NFA N' whose states are
  * the surviving interface states, B' = RI-DFA(N'), the minimal DFA and the
- * powerset DFA.  No device call is made; tables are uploaded to the current
+ * powerset DFA, and for automata of at most 256 starts the transformation
+ * automaton of the starts over the first bytes (RI_OPT_PREFIX).  No device
+ * call is made; tables are uploaded to the current
  * device by the first recognition call on it.
  * opts may be NULL.  On success *out owns everything until ri_free.
  * Errors: RI_ERR_ARG (NULL re/out, flags != 0), RI_ERR_PARSE, RI_ERR_LIMIT,
@@ -249,6 +255,16 @@ int ri_last_timings(const ri_handle *h, float ms[5]);
  *                         to 1.  1: class-partitioned relations composed
  *                         member by member within groups.  Results are
  *                         identical; only the speed differs.
+ *   RI_OPT_PREFIX         1 (default): when the starts fit the grouped
+ *                         warm-up (at most 256 starts, direct merging), the
+ *                         first warm-up bytes of a chunk are read by the
+ *                         transformation automaton of the starts, built by
+ *                         ri_build (a state = the states every start reaches
+ *                         on the bytes read so far; every word of up to
+ *                         ri_info_t.prefix_depth bytes, at most 32768
+ *                         states); the walk covers that depth rounded down to
+ *                         a multiple of 8, at most the warm-up.  0: every
+ *                         start steps byte by byte.  Results are identical.
  * Errors: RI_ERR_ARG for an unknown option or a value out of range.
  */
 #define RI_OPT_CONVERGE       1
@@ -256,6 +272,7 @@ int ri_last_timings(const ri_handle *h, float ms[5]);
 #define RI_OPT_RUNS_PER_LANE  3
 #define RI_OPT_CHUNK_TARGET   4
 #define RI_OPT_JOIN           5
+#define RI_OPT_PREFIX         6
 int ri_set_option(ri_handle *h, int option, int64_t value);
 int ri_get_option(const ri_handle *h, int option, int64_t *value);
 

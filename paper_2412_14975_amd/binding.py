@@ -32,9 +32,10 @@ RI_BATCH_AUTO, RI_BATCH_GROUPED, RI_BATCH_FUSED, RI_BATCH_QUEUE = 0, 1, 2, 3
 BATCH_MODES = {"auto": RI_BATCH_AUTO, "grouped": RI_BATCH_GROUPED, "fused": RI_BATCH_FUSED,
                "queue": RI_BATCH_QUEUE}
 RI_OPT_CONVERGE, RI_OPT_WARMUP_BYTES, RI_OPT_RUNS_PER_LANE, RI_OPT_CHUNK_TARGET, RI_OPT_JOIN = 1, 2, 3, 4, 5
+RI_OPT_PREFIX = 6
 OPTIONS = {"converge": RI_OPT_CONVERGE, "warmup_bytes": RI_OPT_WARMUP_BYTES,
            "runs_per_lane": RI_OPT_RUNS_PER_LANE, "chunk_target": RI_OPT_CHUNK_TARGET,
-           "join": RI_OPT_JOIN}
+           "join": RI_OPT_JOIN, "prefix": RI_OPT_PREFIX}
 
 
 class RIError(RuntimeError):
@@ -66,7 +67,9 @@ class ri_info_t(ctypes.Structure):
                 ("classes", ctypes.c_uint32), ("accepts_empty", ctypes.c_uint32),
                 ("starts", ctypes.c_uint32 * RI_NUM_ALGOS),
                 ("entry_bytes", ctypes.c_uint32 * RI_NUM_ALGOS),
-                ("table_bytes", ctypes.c_uint64 * RI_NUM_ALGOS)]
+                ("table_bytes", ctypes.c_uint64 * RI_NUM_ALGOS),
+                ("prefix_depth", ctypes.c_uint32 * RI_NUM_ALGOS),
+                ("prefix_states", ctypes.c_uint32 * RI_NUM_ALGOS)]
 
 
 class ri_request(ctypes.Structure):
@@ -192,7 +195,7 @@ def ri_info(h: int) -> dict:
     info = ri_info_t()
     _check(lib().ri_info(h, ctypes.byref(info)))
     out = {name: getattr(info, name) for name, _ in ri_info_t._fields_}
-    for k in ("starts", "entry_bytes", "table_bytes"):
+    for k in ("starts", "entry_bytes", "table_bytes", "prefix_depth", "prefix_states"):
         out[k] = list(out[k])
     return out
 

@@ -42,6 +42,17 @@ uint32_t hash_members(const std::vector<uint32_t> &m) {
 
 constexpr uint32_t kMaxDenseWords = 64;   // dense content bitsets up to 2048 interface states
 
+// The transformation automaton of the starts over their first bytes (built
+// for the grouped warm-up with direct merging; see ri::PrefixArgs).
+struct PrefixHost {
+    uint32_t depth = 0;                        // every word of up to `depth` bytes is expanded; 0 = none
+    uint32_t n = 0;                            // states
+    std::vector<uint16_t> next;                // [n][K], 0xFFFF where not expanded
+    std::vector<uint8_t> count;                // [n] distinct live states, kPrefixWide above 64
+    std::vector<uint16_t> tgt;                 // [n][64] their ids
+    std::vector<uint8_t> map;                  // [n][L] start -> index into tgt, 0xFF = dead
+};
+
 struct AlgoHost {
     bool relational = false;
     uint32_t nstates = 0, K = 0, L = 0, W = 0;
@@ -62,6 +73,7 @@ struct AlgoHost {
     bool nfa = false;
     uint32_t nfa_words = 0;                    // 0: N is too large for the device NFA
     std::vector<uint64_t> follow, mask;        // [L][nfa_words], [K][nfa_words]
+    PrefixHost prefix;
 };
 
 struct AlgoDevice {
@@ -72,6 +84,8 @@ struct AlgoDevice {
     int32_t *final_of_state = nullptr;
     uint8_t *accept_of_state = nullptr;
     uint64_t *follow = nullptr, *mask = nullptr;
+    uint16_t *pfx_next = nullptr, *pfx_tgt = nullptr;
+    uint8_t *pfx_count = nullptr, *pfx_map = nullptr;
 };
 
 struct DeviceCopy {
@@ -106,6 +120,7 @@ struct Options {
     uint32_t warm = 64;
     uint32_t runs_per_lane = 0;
     uint32_t chunk_target = 131072;
+    int prefix = 1;            // transformation-automaton walk of the first warm-up bytes
 };
 
 }  // namespace
@@ -150,6 +165,130 @@ void pack_table(AlgoHost &h, uint32_t n, uint32_t K, const std::vector<int32_t> 
         }
     for (int b = 0; b < 256; ++b) h.code[b] = (uint16_t)(cls[b] * eb);
     h.lam_bytes = n < 0xFFFF ? 2 : 4;
+}
+
+// Breadth-first expansion of the transformation automaton: its root is the
+// vector of the start states, and class c maps a vector v to (delta(v[s], c))_s.
+// Level d holds the vectors of the words of exactly d bytes.  Levels are
+// added while the states stay within the cap (and the work n K L within a
+// budget); a level that would cross it is dropped whole, so every word of up
+// to `depth` bytes ends in a state whose transitions below that depth exist.
+constexpr uint32_t kPrefixCap = 32768;
+constexpr uint64_t kPrefixWork = 1ull << 27;
+constexpr uint32_t kPrefixMaxDepth = 64;
+
+void build_prefix(AlgoHost &H) {
+    PrefixHost &P = H.prefix;
+    P = PrefixHost{};
+    if (H.nfa || H.L == 0 || H.L > 256 || !ri::warm_direct_fits(H.nstates) || H.nstates >= 0xFFFF) return;
+    const uint32_t K = H.K, L = H.L, eb = H.entry_bytes, rb = K * eb;
+    const uint32_t dead = H.dead / rb;
+    const uint64_t cap64 = std::min<uint64_t>(kPrefixCap, kPrefixWork / ((uint64_t)K * L));
+    if (cap64 < 2) return;
+    const uint32_t cap = (uint32_t)cap64;
+    // transitions by state id (the dead row included)
+    std::vector<uint16_t> tr((size_t)(H.nstates + 1) * K);
+    for (uint32_t q = 0; q <= H.nstates; ++q)
+        for (uint32_t c = 0; c < K; ++c) {
+            const size_t off = (size_t)q * rb + (size_t)c * eb;
+            uint32_t e = 0;
+            for (uint32_t i = 0; i < eb; ++i) e |= (uint32_t)H.table[off + i] << (8 * i);
+            tr[(size_t)q * K + c] = (uint16_t)(e / rb);
+        }
+    std::vector<uint16_t> vec;                 // [n][L]
+    uint32_t hcap = 1;
+    while (hcap < 2 * cap) hcap *= 2;
+    std::vector<uint32_t> slot(hcap, 0xFFFFFFFFu);
+    auto hash = [&](const uint16_t *v) {
+        uint64_t x = 1469598103934665603ull;
+        for (uint32_t s = 0; s < L; ++s) x = (x ^ v[s]) * 1099511628211ull;
+        return (uint32_t)(x ^ (x >> 29));
+    };
+    uint32_t n = 0;
+    // id of v, added when new; 0xFFFFFFFF when the cap is reached
+    auto find_or_add = [&](const uint16_t *v) -> uint32_t {
+        uint32_t i = hash(v) & (hcap - 1);
+        while (slot[i] != 0xFFFFFFFFu) {
+            if (std::memcmp(&vec[(size_t)slot[i] * L], v, (size_t)L * 2) == 0) return slot[i];
+            i = (i + 1) & (hcap - 1);
+        }
+        if (n >= cap) return 0xFFFFFFFFu;
+        slot[i] = n;
+        vec.insert(vec.end(), v, v + L);
+        return n++;
+    };
+    std::vector<uint16_t> v(L);
+    for (uint32_t s = 0; s < L; ++s) v[s] = (uint16_t)(H.starts[s] / rb);
+    find_or_add(v.data());
+    std::vector<uint16_t> next;                // grows with n
+    std::vector<uint8_t> expanded;
+    std::vector<uint32_t> level{0}, nlevel, stamp;
+    uint32_t depth = 0;
+    for (uint32_t d = 0; d < kPrefixMaxDepth; ++d) {
+        const uint32_t n0 = n;
+        const size_t vec0 = vec.size();
+        std::vector<uint32_t> fresh;           // states expanded in this level
+        bool over = false;
+        nlevel.clear();
+        stamp.resize(cap, 0);
+        for (uint32_t f : level) {
+            if (f < expanded.size() && expanded[f]) continue;
+            if (next.size() < (size_t)(f + 1) * K) next.resize((size_t)(f + 1) * K, 0xFFFF);
+            if (expanded.size() < (size_t)f + 1) expanded.resize((size_t)f + 1, 0);
+            for (uint32_t c = 0; c < K && !over; ++c) {
+                for (uint32_t s = 0; s < L; ++s) v[s] = tr[(size_t)vec[(size_t)f * L + s] * K + c];
+                const uint32_t g = find_or_add(v.data());
+                if (g == 0xFFFFFFFFu) over = true;
+                else next[(size_t)f * K + c] = (uint16_t)g;
+            }
+            expanded[f] = 1;
+            fresh.push_back(f);
+            if (over) break;
+        }
+        if (over) {
+            // undo the level: its new states and transitions are never reached
+            for (uint32_t f : fresh) {
+                expanded[f] = 0;
+                for (uint32_t c = 0; c < K; ++c) next[(size_t)f * K + c] = 0xFFFF;
+            }
+            n = n0;
+            vec.resize(vec0);
+            break;
+        }
+        for (uint32_t f : level)
+            for (uint32_t c = 0; c < K; ++c) {
+                const uint32_t g = next[(size_t)f * K + c];
+                if (stamp[g] != d + 1) { stamp[g] = d + 1; nlevel.push_back(g); }
+            }
+        level.swap(nlevel);
+        depth = d + 1;
+    }
+    if (depth == 0) return;
+    P.depth = depth;
+    P.n = n;
+    next.resize((size_t)n * K, 0xFFFF);
+    P.next = std::move(next);
+    P.count.assign(n, 0);
+    P.tgt.assign((size_t)n * 64, 0);
+    P.map.assign((size_t)n * L, 0xFF);
+    std::vector<int32_t> where(H.nstates + 1, -1);
+    for (uint32_t f = 0; f < n; ++f) {
+        const uint16_t *x = &vec[(size_t)f * L];
+        uint32_t cnt = 0;
+        bool wide = false;
+        for (uint32_t s = 0; s < L && !wide; ++s) {
+            const uint32_t q = x[s];
+            if (q == dead) continue;
+            if (where[q] < 0) {
+                if (cnt == 64) { wide = true; break; }
+                where[q] = (int32_t)cnt;
+                P.tgt[(size_t)f * 64 + cnt++] = (uint16_t)q;
+            }
+            P.map[(size_t)f * L + s] = (uint8_t)where[q];
+        }
+        for (uint32_t i = 0; i < cnt; ++i) where[P.tgt[(size_t)f * 64 + i]] = -1;
+        P.count[f] = wide ? ri::kPrefixWide : (uint8_t)cnt;
+    }
 }
 
 void pack_all(ri_handle *h) {
@@ -247,6 +386,7 @@ void pack_all(ri_handle *h) {
             v.hash[(size_t)slot * 2 + 1] = (uint32_t)A.dsub_final_id[t];
         }
     }
+    for (int a : {RI_ALGO_RID, RI_ALGO_DFA, RI_ALGO_SUBSET}) build_prefix(h->algo[a]);
 }
 
 // Zero device memory and wait for it: the memset runs on the null stream,
@@ -287,6 +427,13 @@ int ensure_device(ri_handle *h, int device) {
         HIP_TRY(upload(&D.table, H.table.data(), H.table.size()));
         HIP_TRY(upload(&D.code, H.code, sizeof(H.code)));
         HIP_TRY(upload(&D.starts, H.starts.data(), H.starts.size() * 4));
+        if (H.prefix.depth) {
+            const PrefixHost &P = H.prefix;
+            HIP_TRY(upload(&D.pfx_next, P.next.data(), P.next.size() * 2));
+            HIP_TRY(upload(&D.pfx_count, P.count.data(), P.count.size()));
+            HIP_TRY(upload(&D.pfx_tgt, P.tgt.data(), P.tgt.size() * 2));
+            HIP_TRY(upload(&D.pfx_map, P.map.data(), P.map.size()));
+        }
         if (H.nfa) {
             HIP_TRY(upload(&D.follow, H.follow.data(), H.follow.size() * 8));
             HIP_TRY(upload(&D.mask, H.mask.data(), H.mask.size() * 8));
@@ -445,14 +592,30 @@ struct ReachBufs {
     uint32_t *run_base, *run_chunk, *run_state, *run_final, *counters;
     uint32_t *run_count;
     uint32_t *block_count;   // [warm-up grid]
+    ri::PrefixArgs pfx{};     // k = 0: no transformation-automaton walk
 };
 
-// Warm-up and merging, then the merged runs to the chunk ends; `mid`
-// (optional) is recorded between the two kernels.
-int launch_conv(const ConvCfg &c, const ri::ScanArgs &sa, const Options &opt, const ReachBufs &rb,
-                hipStream_t stream, hipEvent_t mid) {
+// The walk of the first warm-up bytes: every word of up to `depth` bytes is
+// expanded; k is rounded down to a multiple of 8 (the rest of the warm-up then
+// steps 8 bytes per broadcast of codes) and is at most the warm-up.
+ri::PrefixArgs prefix_args(const AlgoHost &H, const AlgoDevice &D, const Options &opt) {
+    ri::PrefixArgs p{};
+    const uint32_t depth = H.prefix.depth;
+    if (!opt.prefix || !opt.converge || depth == 0 || !D.pfx_next) return p;
+    p.k = std::min<uint32_t>(depth >= 8 ? depth & ~7u : depth, opt.warm);
+    p.next = D.pfx_next;
+    p.count = D.pfx_count;
+    p.tgt = D.pfx_tgt;
+    p.map = D.pfx_map;
+    p.K = H.K;
+    p.shift = H.entry_bytes == 1 ? 0 : H.entry_bytes == 2 ? 1 : 2;
+    return p;
+}
+
+ri::WarmArgs warm_args(const ConvCfg &c, const ri::ScanArgs &sa, const Options &opt, const ReachBufs &rb) {
     ri::WarmArgs wa{};
     wa.s = sa;
+    wa.pfx = rb.pfx;
     wa.warm = opt.warm;
     wa.alias = rb.alias;
     wa.run_base = rb.run_base;
@@ -462,7 +625,14 @@ int launch_conv(const ConvCfg &c, const ri::ScanArgs &sa, const Options &opt, co
     wa.counters = rb.counters;
     wa.block_count = rb.block_count;
     wa.cpi = c.cpi;
-    HIP_TRY(ri::launch_warm(wa, c.warm_shape, c.grid_w, c.lds_w, stream));
+    return wa;
+}
+
+// Warm-up and merging, then the merged runs to the chunk ends; `mid`
+// (optional) is recorded between the two kernels.
+int launch_conv(const ConvCfg &c, const ri::ScanArgs &sa, const Options &opt, const ReachBufs &rb,
+                hipStream_t stream, hipEvent_t mid) {
+    HIP_TRY(ri::launch_warm(warm_args(c, sa, opt, rb), c.warm_shape, c.grid_w, c.lds_w, stream));
     if (mid) HIP_TRY(hipEventRecord(mid, stream));
     ri::LongArgs la{};
     la.s = sa;
@@ -907,7 +1077,7 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         if (prof) HIP_TRY(hipEventRecord(ws->ev[4], stream));
     } else {
         ReachBufs rb{sc.alias, sc.run_base, sc.run_chunk, sc.run_state, sc.run_final, sc.counters, sc.run_count,
-                     sc.block_count};
+                     sc.block_count, prefix_args(H, D, opt)};
         rc = launch_conv(cc, sa, opt, rb, stream, prof ? ws->ev[5] : nullptr);
         if (rc) return rc;
         if (prof) HIP_TRY(hipEventRecord(ws->ev[4], stream));
@@ -1435,23 +1605,12 @@ int run_group(ri_batch *b, const BatchGroup &g, hipStream_t stream, int32_t *res
     const ri::ScanArgs sa = group_scan_args(b, g);
     ReachBufs rb{g.alias.p, static_cast<uint32_t *>(g.run_base.p), static_cast<uint32_t *>(g.run_chunk.p),
                  static_cast<uint32_t *>(g.run_state.p), static_cast<uint32_t *>(g.run_final.p), g.counters, nullptr,
-                 static_cast<uint32_t *>(g.block_count.p)};
+                 static_cast<uint32_t *>(g.block_count.p), prefix_args(H, D, g.opt)};
     if (phase == kAllPhases) {
         const int rc = launch_conv(g.cc, sa, g.opt, rb, stream, nullptr);
         if (rc) return rc;
     } else if (phase == kWarmPhase) {
-        ri::WarmArgs wa{};
-        wa.s = sa;
-        wa.warm = g.opt.warm;
-        wa.alias = rb.alias;
-        wa.run_base = rb.run_base;
-        wa.run_count = rb.run_count;
-        wa.run_chunk = rb.run_chunk;
-        wa.run_state = rb.run_state;
-        wa.counters = rb.counters;
-        wa.block_count = rb.block_count;
-        wa.cpi = g.cc.cpi;
-        HIP_TRY(ri::launch_warm(wa, g.cc.warm_shape, g.cc.grid_w, g.cc.lds_w, stream));
+        HIP_TRY(ri::launch_warm(warm_args(g.cc, sa, g.opt, rb), g.cc.warm_shape, g.cc.grid_w, g.cc.lds_w, stream));
         return RI_OK;
     }
 
@@ -2001,6 +2160,10 @@ void ri_free(ri_handle *h) {
             (void)hipFree(D.hash);
             (void)hipFree(D.final_of_state);
             (void)hipFree(D.accept_of_state);
+            (void)hipFree(D.pfx_next);
+            (void)hipFree(D.pfx_count);
+            (void)hipFree(D.pfx_tgt);
+            (void)hipFree(D.pfx_map);
             (void)hipFree(D.follow);
             (void)hipFree(D.mask);
         }
@@ -2042,6 +2205,8 @@ int ri_info(const ri_handle *h, ri_info_t *out) {
         out->entry_bytes[a] = h->algo[a].nfa ? 8 * h->algo[a].nfa_words : h->algo[a].entry_bytes;
         out->table_bytes[a] = h->algo[a].nfa ? 8 * (h->algo[a].follow.size() + h->algo[a].mask.size())
                                              : h->algo[a].table.size();
+        out->prefix_depth[a] = h->algo[a].prefix.depth;
+        out->prefix_states[a] = h->algo[a].prefix.n;
     }
     return RI_OK;
 }
@@ -2131,6 +2296,10 @@ int ri_set_option(ri_handle *h, int option, int64_t value) {
         if (value < 1 || value > (1ll << 30)) return fail(RI_ERR_ARG, "bad chunk target");
         h->opt.chunk_target = (uint32_t)value;
         return RI_OK;
+    case RI_OPT_PREFIX:
+        if (value != 0 && value != 1) return fail(RI_ERR_ARG, "RI_OPT_PREFIX must be 0 or 1");
+        h->opt.prefix = (int)value;
+        return RI_OK;
     }
     return fail(RI_ERR_ARG, "unknown option");
 }
@@ -2144,6 +2313,7 @@ int ri_get_option(const ri_handle *h, int option, int64_t *value) {
     case RI_OPT_RUNS_PER_LANE: *value = h->opt.runs_per_lane; return RI_OK;
     case RI_OPT_CHUNK_TARGET: *value = h->opt.chunk_target; return RI_OK;
     case RI_OPT_JOIN: *value = h->opt.join; return RI_OK;
+    case RI_OPT_PREFIX: *value = h->opt.prefix; return RI_OK;
     }
     return fail(RI_ERR_ARG, "unknown option");
 }

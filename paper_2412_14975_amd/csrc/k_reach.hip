@@ -455,6 +455,33 @@ __device__ __forceinline__ void warm_steps1(uint32_t (&st)[G][1], const uint32_t
         warm_steps<TE, 1, NQ, G>(st, code, wlen, j0, j1, tab, dead);
 }
 
+// The single-register end of the warm-up of G chunks: class k's state in
+// lane k of one[g], start r * 64 + lane in class cl[g][r]; bytes [j, W) are
+// scanned, the runs merged once more and handed to emit with every start's
+// final class.
+template <typename TE, int R, int NQ, int G, class Emit>
+__device__ __forceinline__ void warm_tail1(uint32_t (&one)[G][1], uint32_t (&cl)[G][R], uint32_t j, uint32_t W,
+                                           const uint32_t (&code)[G][NQ], const uint32_t (&wlen)[G], const TE *tab,
+                                           uint32_t dead, uint32_t lane, uint64_t lane_lt, lds_u32 *key, lds_u8 *slot,
+                                           const RowDiv &rd, bool code8, Emit &emit) {
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    warm_steps1<TE, NQ, G>(one, code, wlen, j, W, tab, dead, key, lane, code8);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        uint32_t c2[1], ix[1];
+        uint64_t ld[1];
+        const uint32_t d = merge_direct<1>(one[g], dead, lane, lane_lt, slot, rd, c2, ix, ld);
+        // lane k holds the new class of old class k; every lane takes part
+        // in the shuffle
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t v = (uint32_t)__shfl((int)c2[0], (int)(cl[g][r] == kNone ? 0u : cl[g][r]));
+            cl[g][r] = cl[g][r] == kNone ? kNone : v;
+        }
+        emit(g, d, cl[g], ld, c2, ix);
+    }
+}
+
 // warm_merge_chunks with direct merging; instead of returning the runs it
 // hands each chunk's result to emit(g, D, acl, lead, ecl, eidx): acl[r] the
 // class of start r * 64 + lane, and for each register of the last merge the
@@ -527,21 +554,40 @@ __device__ __forceinline__ void warm_direct_chunks(const TE *tab, const StartLis
         one[g][0] = lane < D[g] ? key[lane] : dead;
         __builtin_amdgcn_wave_barrier();
     }
-    warm_steps1<TE, NQ, G>(one, code, wlen, j, W, tab, dead, key, lane, code8);
+    warm_tail1<TE, R, NQ, G>(one, cl, j, W, code, wlen, tab, dead, lane, lane_lt, key, slot, rd, code8, emit);
+}
+
+// The walk of the transformation automaton stands for the first k bytes of
+// every start of G chunks: prefix state f[g] gives the chunk's live runs
+// (at most 64, class k in lane k) and every start's class; the rest of the
+// warm-up is the single-register tail.
+template <typename TE, int R, int NQ, int G, class Emit>
+__device__ __forceinline__ void warm_prefix_chunks(const TE *tab, const PrefixArgs &p, const uint32_t (&f)[G],
+                                                   uint32_t L, uint32_t dead, uint32_t row_bytes, const bool (&ok)[G],
+                                                   const uint32_t (&code)[G][NQ], const uint32_t (&wlen)[G],
+                                                   uint32_t lane, uint64_t lane_lt, lds_u32 *key, lds_u8 *slot,
+                                                   const RowDiv &rd, bool code8, Emit &&emit) {
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    uint32_t one[G][1], cl[G][R];
+    uint32_t W = 0;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        uint32_t c2[1], ix[1];
-        uint64_t ld[1];
-        const uint32_t d = merge_direct<1>(one[g], dead, lane, lane_lt, slot, rd, c2, ix, ld);
-        // lane k holds the new class of old class k; every lane takes part
-        // in the shuffle
+        W = wlen[g] > W ? wlen[g] : W;
+        one[g][0] = dead;
+#pragma unroll
+        for (int r = 0; r < R; ++r) cl[g][r] = kNone;
+        if (!ok[g]) continue;
+        const uint32_t n = (uint32_t)__builtin_amdgcn_readfirstlane((int)p.count[f[g]]);
+        if (lane < n) one[g][0] = (uint32_t)p.tgt[(uint64_t)f[g] * kWave + lane] * row_bytes;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const uint32_t v = (uint32_t)__shfl((int)c2[0], (int)(cl[g][r] == kNone ? 0u : cl[g][r]));
-            cl[g][r] = cl[g][r] == kNone ? kNone : v;
+            const uint32_t s = r * kWave + lane;
+            const uint32_t m = s < L ? (uint32_t)p.map[(uint64_t)f[g] * L + s] : 0xFFu;
+            cl[g][r] = m == 0xFFu ? kNone : m;
         }
-        emit(g, d, cl[g], ld, c2, ix);
     }
+    warm_tail1<TE, R, NQ, G>(one, cl, p.k < W ? p.k : W, W, code, wlen, tab, dead, lane, lane_lt, key, slot, rd,
+                             code8, emit);
 }
 
 // Occupancy: a block is 16 waves (4 per SIMD), so two blocks per CU need 8
@@ -696,7 +742,33 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     bool first[G];
     fetch(blockIdx.x, raw, wlen, first);
     const uint64_t region = warm_region(blockIdx.x, gridDim.x, iters, L, cpi);
-    for (uint32_t it = blockIdx.x; it < iters; it += gridDim.x) {
+    // transformation-automaton walks of the wave's chunks, 64 / G iterations
+    // at a time: lane t G + g walks chunk g of iteration pbase + t (kNone:
+    // no walk, e.g. a chunk that begins its text)
+    const uint32_t pk = DIRECT ? a.pfx.k : 0u;
+    constexpr uint32_t kPerWalk = kWave / G;
+    uint32_t pf = kNone, pbase = 0;
+    auto prewalk = [&](uint32_t t0) {
+        pbase = t0;
+        pf = kNone;
+        const uint32_t t = t0 + lane / G, g = lane % G;
+        const uint32_t it = blockIdx.x + t * gridDim.x;
+        if (lane >= kPerWalk * G || it >= iters) return;
+        const uint32_t chunk = it * cpi + wave * G + g;
+        if (chunk >= a.s.nchunks) return;
+        uint64_t b, e;
+        bool fst;
+        chunk_bounds(a.s, chunk, b, e, fst);
+        if (fst) return;
+        const uint32_t w = (uint32_t)(e - b < a.warm ? e - b : a.warm);
+        const uint32_t m = w < pk ? w : pk;
+        uint32_t f = 0;
+#pragma unroll 8
+        for (uint32_t j = 0; j < m; ++j) f = a.pfx.next[f * a.pfx.K + ((uint32_t)cls[*at(b + j)] >> a.pfx.shift)];
+        pf = f;
+    };
+    if (pk) prewalk(0);
+    for (uint32_t it = blockIdx.x, t = 0; it < iters; it += gridDim.x, ++t) {
         const uint32_t chunk0 = it * cpi + wave * G;
         uint32_t code[G][NQ], cur_wlen[G];
         bool ok[G], cur_first[G];
@@ -738,8 +810,24 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
                     if (k < L) arow[k] = acl[r] == kNone ? all_ones<TA>() : (TA)acl[r];
                 }
             };
-            warm_direct_chunks<TE, R, NQ, G>(tab, starts, L, dead, ok, cur_first, code, cur_wlen, lane, lane_lt, dkey,
-                                             dslot, rd, a.s.row_bytes <= 256, emit);
+            bool fast = pk != 0;
+            uint32_t f[G];
+            if (fast) {
+                if (t - pbase >= kPerWalk) prewalk(t);
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    f[g] = (uint32_t)__builtin_amdgcn_readlane((int)pf, (int)((t - pbase) * G + g));
+                    if (ok[g])
+                        fast = fast && f[g] != kNone &&
+                               (uint32_t)__builtin_amdgcn_readfirstlane((int)a.pfx.count[f[g]]) <= kWave;
+                }
+            }
+            if (fast)
+                warm_prefix_chunks<TE, R, NQ, G>(tab, a.pfx, f, L, dead, a.s.row_bytes, ok, code, cur_wlen, lane,
+                                                 lane_lt, dkey, dslot, rd, a.s.row_bytes <= 256, emit);
+            else
+                warm_direct_chunks<TE, R, NQ, G>(tab, starts, L, dead, ok, cur_first, code, cur_wlen, lane, lane_lt,
+                                                 dkey, dslot, rd, a.s.row_bytes <= 256, emit);
         } else {
         uint32_t cl[G][R], one[G], D[G], st[G][R];
         bool compacted;

@@ -89,8 +89,24 @@ __host__ __device__ inline uint64_t warm_region(uint32_t b, uint32_t G, uint32_t
     const uint64_t q = iters / G, r = iters % G;
     return (uint64_t)cpi * L * ((uint64_t)b * q + (b < r ? b : r));
 }
+// The first bytes of the warm-up read by the transformation automaton of the
+// starts (the simultaneous automaton of Sin'ya, Matsuzaki and Sassa, ICPP
+// 2013): its state after a word u is the vector of the states that every
+// start reaches on u, so one lookup per byte advances every start of a chunk
+// at once.  The host expands every word of up to k bytes.
+struct PrefixArgs {
+    const uint16_t *next;      // [n][K] successor by byte class (only states of depth < k)
+    const uint8_t *count;      // [n] distinct live states, kPrefixWide when more than 64
+    const uint16_t *tgt;       // [n][64] those states (ids), in order of the first start reaching them
+    const uint8_t *map;        // [n][L] start -> index into tgt, 0xFF = dead
+    uint32_t k;                // bytes walked; 0 = no walk
+    uint32_t K;                // classes
+    uint32_t shift;            // class = byte code >> shift
+};
+constexpr uint8_t kPrefixWide = 0xFF;
 struct WarmArgs {
     ScanArgs s;
+    PrefixArgs pfx;            // used by the grouped warm-up with direct merging
     uint32_t warm;             // bytes scanned by every run before merging (<= 256)
     void *alias;               // [nchunks][L] class (merged run) of every start, all-ones = no run
     uint32_t *run_base;        // [nchunks] first run of the chunk

@@ -22,7 +22,9 @@ ALGOS = ("rid", "dfa", "subset")
 MODES = {"conv64": dict(converge=1, warmup_bytes=64), "conv16": dict(converge=1, warmup_bytes=16),
          "cls64": dict(converge=1, warmup_bytes=64, join=1), "plain": dict(converge=0),
          "conv80": dict(converge=1, warmup_bytes=80), "conv128": dict(converge=1, warmup_bytes=128),
-         "conv256": dict(converge=1, warmup_bytes=256)}
+         "conv256": dict(converge=1, warmup_bytes=256),
+         # every start stepping from the first byte (no transformation-automaton walk)
+         "noprefix64": dict(converge=1, warmup_bytes=64, prefix=0)}
 
 
 @pytest.fixture(scope="module", autouse=True)

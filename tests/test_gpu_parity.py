@@ -28,7 +28,9 @@ MODES = {"conv64": dict(converge=1, warmup_bytes=64), "conv16": dict(converge=1,
          # warm-ups longer than 64 bytes (four registers of byte codes), also
          # longer than many chunks of the small texts below
          "conv80": dict(converge=1, warmup_bytes=80), "conv128": dict(converge=1, warmup_bytes=128),
-         "conv256": dict(converge=1, warmup_bytes=256)}
+         "conv256": dict(converge=1, warmup_bytes=256),
+         # every start stepping from the first byte (no transformation-automaton walk)
+         "noprefix64": dict(converge=1, warmup_bytes=64, prefix=0)}
 
 
 def make(pattern, mode="conv64", runs_per_lane=0):
@@ -418,6 +420,36 @@ def test_motif_union_full_size(seed):
 
 
 # ---------------------------------------------------------------------------
+# the walk of the transformation automaton over the first warm-up bytes
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("size", [16, 32, 48, 8320])
+def test_prefix_walk_chunk_lengths(size):
+    """The log-lines grammar walks 24 bytes of every chunk in the
+    transformation automaton of its 227 starts.  Chunks shorter than the walk
+    end it early (and may keep more than 64 runs, which takes every start
+    instead); results and sampled chunk maps with the walk on and off against
+    the oracle."""
+    rx = gen.c3_regex()
+    ref = Ref(rx)
+    x, r1, _ = gen.c3_texts(5, n=1 << 20)
+    for pf in (1, 0):
+        rec = make(rx, "conv64")
+        rec.set_option("prefix", pf)
+        try:
+            assert rec.info()["prefix_depth"][0] >= 24
+            chunks = -(-len(x) // size)
+            for text in (x, r1):
+                want = ref.serial(text)
+                got = rec.recognize(dev(text), algo="rid", chunks=chunks)
+                assert (got["accept"], got["final_state"]) == want, (size, pf)
+                assert got["chunk_size"] == size or size == 8320
+            check_maps(rec, ref, x, "rid", chunks, sample=8, rng=gen.PCG(size + pf))
+        finally:
+            rec.close()
+
+
+# ---------------------------------------------------------------------------
 # log lines: 1 GiB
 # ---------------------------------------------------------------------------
 
@@ -448,6 +480,11 @@ def test_log_lines_full_size(seed):
             if j != 1:
                 got = plain.recognize(t, algo="rid", chunks=65536)
                 assert (got["accept"], got["final_state"]) == want, (seed, j, "plain")
+            if seed == 0:
+                rec.set_option("prefix", 0)
+                got = rec.recognize(t, algo="rid")
+                rec.set_option("prefix", 1)
+                assert (got["accept"], got["final_state"]) == want, (seed, j, "no prefix walk")
             torch.cuda.synchronize()
             del t
         got = res.cpu().numpy()
