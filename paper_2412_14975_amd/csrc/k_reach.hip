@@ -437,9 +437,55 @@ __device__ __forceinline__ void warm_steps_lds(uint32_t (&st)[G][1], const uint3
     __builtin_amdgcn_wave_barrier();   // the key area is written again by the next chunks
 }
 
-// Single-register steps [j0, j1) through LDS codes when they fit the key area
-// and every chunk has all the bytes, else by readlane.
+// Single-register steps [j0, j1) of G chunks whose table sits in LDS
+// (j1 - j0 a multiple of 8, every chunk full).  The byte codes of 16 bytes
+// at a time, with the table's LDS offset added, are written as words to the
+// wave's key area and read back 4 at a time by every lane at one address
+// (a broadcast); the address is kept in a vector register so that the words
+// stay vector operands, and a step is one add and one lookup.
 template <typename TE, int NQ, int G>
+__device__ __forceinline__ void warm_steps_lds32(uint32_t (&st)[G][1], const uint32_t (&code)[G][NQ], uint32_t j0,
+                                                 uint32_t j1, const TE *tab, uint32_t dead, lds_u32 *key,
+                                                 uint32_t lane) {
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+    typedef const __attribute__((address_space(3))) v4u lds_u4;
+    typedef const __attribute__((address_space(3))) TE lds_te;
+    static_assert(G * 16 * 4 <= kDirectKeyBytes - 16, "code window");
+    const uint32_t tb = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint8_t *)tab;
+    for (uint32_t w0 = j0; w0 < j1; w0 += 16) {
+        bool alive = false;
+#pragma unroll
+        for (int g = 0; g < G; ++g) alive |= st[g][0] != dead;
+        if (__ballot(alive) == 0) break;
+        const uint32_t nw = j1 - w0 < 16 ? j1 - w0 : 16;   // 8 or 16
+        __builtin_amdgcn_wave_barrier();   // the previous window is read
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (uint32_t q = 0; q < (uint32_t)NQ; ++q) {
+                const uint32_t p = q * kWave + lane;
+                if (p >= w0 && p < w0 + nw) key[g * 16 + (p - w0)] = code[g][q] + tb;
+            }
+        __builtin_amdgcn_wave_barrier();
+        uint32_t a = (uint32_t)(uintptr_t)key;
+        asm volatile("" : "+v"(a));   // a per-lane register: the words are read into vector registers
+        for (uint32_t k = 0; k < nw; k += 4) {
+            v4u c[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) c[g] = *(lds_u4 *)(uintptr_t)(a + 4 * (g * 16 + k));
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int g = 0; g < G; ++g) st[g][0] = *(lds_te *)(uintptr_t)(st[g][0] + c[g][e]);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();   // the key area is written again by the next chunks
+}
+
+// Single-register steps [j0, j1) through LDS codes when they fit the key area
+// and every chunk has all the bytes (as words when the table is in LDS, TL),
+// else by readlane.
+template <typename TE, int NQ, int G, bool TL = false>
 __device__ __forceinline__ void warm_steps1(uint32_t (&st)[G][1], const uint32_t (&code)[G][NQ],
                                             const uint32_t (&wlen)[G], uint32_t j0, uint32_t j1, const TE *tab,
                                             uint32_t dead, lds_u32 *key, uint32_t lane, bool code8) {
@@ -447,6 +493,12 @@ __device__ __forceinline__ void warm_steps1(uint32_t (&st)[G][1], const uint32_t
 #pragma unroll
     for (int g = 0; g < G; ++g) full &= wlen[g] >= j1;
     const uint32_t n = j1 - j0;
+    if constexpr (TL && G <= 4) {
+        if (full && (n & 7u) == 0) {
+            warm_steps_lds32<TE, NQ, G>(st, code, j0, j1, tab, dead, key, lane);
+            return;
+        }
+    }
     if (full && (n & 7u) == 0 && code8 && G * ((n + 15u) & ~15u) <= kDirectKeyBytes - 16)
         warm_steps_lds<TE, NQ, G, uint8_t>(st, code, j0, j1, tab, dead, key, lane);
     else if (full && (n & 7u) == 0 && G * ((2 * n + 15u) & ~15u) <= kDirectKeyBytes - 16)
@@ -459,13 +511,13 @@ __device__ __forceinline__ void warm_steps1(uint32_t (&st)[G][1], const uint32_t
 // lane k of one[g], start r * 64 + lane in class cl[g][r]; bytes [j, W) are
 // scanned, the runs merged once more and handed to emit with every start's
 // final class.
-template <typename TE, int R, int NQ, int G, class Emit>
+template <typename TE, int R, int NQ, int G, bool TL, class Emit>
 __device__ __forceinline__ void warm_tail1(uint32_t (&one)[G][1], uint32_t (&cl)[G][R], uint32_t j, uint32_t W,
                                            const uint32_t (&code)[G][NQ], const uint32_t (&wlen)[G], const TE *tab,
                                            uint32_t dead, uint32_t lane, uint64_t lane_lt, lds_u32 *key, lds_u8 *slot,
                                            const RowDiv &rd, bool code8, Emit &emit) {
     constexpr uint32_t kNone = 0xFFFFFFFFu;
-    warm_steps1<TE, NQ, G>(one, code, wlen, j, W, tab, dead, key, lane, code8);
+    warm_steps1<TE, NQ, G, TL>(one, code, wlen, j, W, tab, dead, key, lane, code8);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         uint32_t c2[1], ix[1];
@@ -486,7 +538,7 @@ __device__ __forceinline__ void warm_tail1(uint32_t (&one)[G][1], uint32_t (&cl)
 // hands each chunk's result to emit(g, D, acl, lead, ecl, eidx): acl[r] the
 // class of start r * 64 + lane, and for each register of the last merge the
 // leaders (lead), their class (ecl) and state index (eidx).
-template <typename TE, int R, int NQ, int G, class Emit>
+template <typename TE, int R, int NQ, int G, bool TL, class Emit>
 __device__ __forceinline__ void warm_direct_chunks(const TE *tab, const StartList &starts, uint32_t L, uint32_t dead,
                                                    const bool (&ok)[G], const bool (&first)[G],
                                                    const uint32_t (&code)[G][NQ], const uint32_t (&wlen)[G],
@@ -506,7 +558,7 @@ __device__ __forceinline__ void warm_direct_chunks(const TE *tab, const StartLis
     }
     uint32_t j = (R == 1 || W < kMergeSplit) ? W : kMergeSplit;
     if constexpr (R == 1)
-        warm_steps1<TE, NQ, G>(st, code, wlen, 0, j, tab, dead, key, lane, code8);
+        warm_steps1<TE, NQ, G, TL>(st, code, wlen, 0, j, tab, dead, key, lane, code8);
     else
         warm_steps<TE, R, NQ, G>(st, code, wlen, 0, j, tab, dead);
     uint32_t Dmax = 0;
@@ -554,16 +606,16 @@ __device__ __forceinline__ void warm_direct_chunks(const TE *tab, const StartLis
         one[g][0] = lane < D[g] ? key[lane] : dead;
         __builtin_amdgcn_wave_barrier();
     }
-    warm_tail1<TE, R, NQ, G>(one, cl, j, W, code, wlen, tab, dead, lane, lane_lt, key, slot, rd, code8, emit);
+    warm_tail1<TE, R, NQ, G, TL>(one, cl, j, W, code, wlen, tab, dead, lane, lane_lt, key, slot, rd, code8, emit);
 }
 
 // The walk of the transformation automaton stands for the first k bytes of
-// every start of G chunks: prefix state f[g] gives the chunk's live runs
-// (at most 64, class k in lane k) and every start's class; the rest of the
+// every start of G chunks: prefix state f[g] gives the chunk's nrun[g] <= 64
+// live runs (class k in lane k) and every start's class; the rest of the
 // warm-up is the single-register tail.
-template <typename TE, int R, int NQ, int G, class Emit>
+template <typename TE, int R, int NQ, int G, bool TL, class Emit>
 __device__ __forceinline__ void warm_prefix_chunks(const TE *tab, const PrefixArgs &p, const uint32_t (&f)[G],
-                                                   uint32_t L, uint32_t dead, uint32_t row_bytes, const bool (&ok)[G],
+                                                   const uint32_t (&nrun)[G], uint32_t L, uint32_t dead, uint32_t row_bytes, const bool (&ok)[G],
                                                    const uint32_t (&code)[G][NQ], const uint32_t (&wlen)[G],
                                                    uint32_t lane, uint64_t lane_lt, lds_u32 *key, lds_u8 *slot,
                                                    const RowDiv &rd, bool code8, Emit &&emit) {
@@ -577,7 +629,7 @@ __device__ __forceinline__ void warm_prefix_chunks(const TE *tab, const PrefixAr
 #pragma unroll
         for (int r = 0; r < R; ++r) cl[g][r] = kNone;
         if (!ok[g]) continue;
-        const uint32_t n = (uint32_t)__builtin_amdgcn_readfirstlane((int)p.count[f[g]]);
+        const uint32_t n = nrun[g];
         if (lane < n) one[g][0] = (uint32_t)p.tgt[(uint64_t)f[g] * kWave + lane] * row_bytes;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -586,8 +638,8 @@ __device__ __forceinline__ void warm_prefix_chunks(const TE *tab, const PrefixAr
             cl[g][r] = m == 0xFFu ? kNone : m;
         }
     }
-    warm_tail1<TE, R, NQ, G>(one, cl, p.k < W ? p.k : W, W, code, wlen, tab, dead, lane, lane_lt, key, slot, rd,
-                             code8, emit);
+    warm_tail1<TE, R, NQ, G, TL>(one, cl, p.k < W ? p.k : W, W, code, wlen, tab, dead, lane, lane_lt, key, slot,
+                                 rd, code8, emit);
 }
 
 // Occupancy: a block is 16 waves (4 per SIMD), so two blocks per CU need 8
@@ -747,10 +799,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     // no walk, e.g. a chunk that begins its text)
     const uint32_t pk = DIRECT ? a.pfx.k : 0u;
     constexpr uint32_t kPerWalk = kWave / G;
-    uint32_t pf = kNone, pbase = 0;
+    uint32_t pf = kNone, pn = 0, pbase = 0;   // state reached and its live runs
     auto prewalk = [&](uint32_t t0) {
         pbase = t0;
         pf = kNone;
+        pn = 0;
         const uint32_t t = t0 + lane / G, g = lane % G;
         const uint32_t it = blockIdx.x + t * gridDim.x;
         if (lane >= kPerWalk * G || it >= iters) return;
@@ -766,6 +819,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
 #pragma unroll 8
         for (uint32_t j = 0; j < m; ++j) f = a.pfx.next[f * a.pfx.K + ((uint32_t)cls[*at(b + j)] >> a.pfx.shift)];
         pf = f;
+        pn = a.pfx.count[f];
     };
     if (pk) prewalk(0);
     for (uint32_t it = blockIdx.x, t = 0; it < iters; it += gridDim.x, ++t) {
@@ -811,22 +865,22 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
                 }
             };
             bool fast = pk != 0;
-            uint32_t f[G];
+            uint32_t f[G], n[G];
             if (fast) {
                 if (t - pbase >= kPerWalk) prewalk(t);
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    f[g] = (uint32_t)__builtin_amdgcn_readlane((int)pf, (int)((t - pbase) * G + g));
-                    if (ok[g])
-                        fast = fast && f[g] != kNone &&
-                               (uint32_t)__builtin_amdgcn_readfirstlane((int)a.pfx.count[f[g]]) <= kWave;
+                    const int src = (int)((t - pbase) * G + g);
+                    f[g] = (uint32_t)__builtin_amdgcn_readlane((int)pf, src);
+                    n[g] = (uint32_t)__builtin_amdgcn_readlane((int)pn, src);
+                    if (ok[g]) fast = fast && f[g] != kNone && n[g] <= kWave;
                 }
             }
             if (fast)
-                warm_prefix_chunks<TE, R, NQ, G>(tab, a.pfx, f, L, dead, a.s.row_bytes, ok, code, cur_wlen, lane,
+                warm_prefix_chunks<TE, R, NQ, G, LDS>(tab, a.pfx, f, n, L, dead, a.s.row_bytes, ok, code, cur_wlen, lane,
                                                  lane_lt, dkey, dslot, rd, a.s.row_bytes <= 256, emit);
             else
-                warm_direct_chunks<TE, R, NQ, G>(tab, starts, L, dead, ok, cur_first, code, cur_wlen, lane, lane_lt,
+                warm_direct_chunks<TE, R, NQ, G, LDS>(tab, starts, L, dead, ok, cur_first, code, cur_wlen, lane, lane_lt,
                                                  dkey, dslot, rd, a.s.row_bytes <= 256, emit);
         } else {
         uint32_t cl[G][R], one[G], D[G], st[G][R];
