@@ -256,7 +256,7 @@ int ri_last_timings(const ri_handle *h, float ms[5]);
  *                         member by member within groups.  Results are
  *                         identical; only the speed differs.
  *   RI_OPT_PREFIX         1 (default): when the starts fit the grouped
- *                         warm-up (at most 256 starts, direct merging), the
+ *                         warm-up (at most 256 starts), the
  *                         first warm-up bytes of a chunk are read by the
  *                         transformation automaton of the starts, built by
  *                         ri_build (a state = the states every start reaches

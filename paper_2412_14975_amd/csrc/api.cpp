@@ -43,7 +43,7 @@ uint32_t hash_members(const std::vector<uint32_t> &m) {
 constexpr uint32_t kMaxDenseWords = 64;   // dense content bitsets up to 2048 interface states
 
 // The transformation automaton of the starts over their first bytes (built
-// for the grouped warm-up with direct merging; see ri::PrefixArgs).
+// for the grouped warm-up, at most 256 starts; see ri::PrefixArgs).
 struct PrefixHost {
     uint32_t depth = 0;                        // every word of up to `depth` bytes is expanded; 0 = none
     uint32_t n = 0;                            // states
@@ -180,7 +180,7 @@ constexpr uint32_t kPrefixMaxDepth = 64;
 void build_prefix(AlgoHost &H) {
     PrefixHost &P = H.prefix;
     P = PrefixHost{};
-    if (H.nfa || H.L == 0 || H.L > 256 || !ri::warm_direct_fits(H.nstates) || H.nstates >= 0xFFFF) return;
+    if (H.nfa || H.L == 0 || H.L > 256 || H.nstates >= 0xFFFF) return;
     const uint32_t K = H.K, L = H.L, eb = H.entry_bytes, rb = K * eb;
     const uint32_t dead = H.dead / rb;
     const uint64_t cap64 = std::min<uint64_t>(kPrefixCap, kPrefixWork / ((uint64_t)K * L));

@@ -610,27 +610,21 @@ __device__ __forceinline__ void warm_direct_chunks(const TE *tab, const StartLis
 }
 
 // The walk of the transformation automaton stands for the first k bytes of
-// every start of G chunks: prefix state f[g] gives the chunk's nrun[g] <= 64
-// live runs (class k in lane k) and every start's class; the rest of the
-// warm-up is the single-register tail.
-template <typename TE, int R, int NQ, int G, bool TL, class Emit>
-__device__ __forceinline__ void warm_prefix_chunks(const TE *tab, const PrefixArgs &p, const uint32_t (&f)[G],
-                                                   const uint32_t (&nrun)[G], uint32_t L, uint32_t dead, uint32_t row_bytes, const bool (&ok)[G],
-                                                   const uint32_t (&code)[G][NQ], const uint32_t (&wlen)[G],
-                                                   uint32_t lane, uint64_t lane_lt, lds_u32 *key, lds_u8 *slot,
-                                                   const RowDiv &rd, bool code8, Emit &&emit) {
+// every start of G chunks: prefix state f[g] with nrun[g] <= 64 live runs
+// gives the chunk's runs (class k's state in lane k of one[g]) and every
+// start's class (cl[g][r] for start r * 64 + lane).
+template <int R, int G>
+__device__ __forceinline__ void prefix_rows(const PrefixArgs &p, const uint32_t (&f)[G], const uint32_t (&nrun)[G],
+                                            const bool (&ok)[G], uint32_t L, uint32_t dead, uint32_t row_bytes,
+                                            uint32_t lane, uint32_t (&one)[G][1], uint32_t (&cl)[G][R]) {
     constexpr uint32_t kNone = 0xFFFFFFFFu;
-    uint32_t one[G][1], cl[G][R];
-    uint32_t W = 0;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        W = wlen[g] > W ? wlen[g] : W;
         one[g][0] = dead;
 #pragma unroll
         for (int r = 0; r < R; ++r) cl[g][r] = kNone;
         if (!ok[g]) continue;
-        const uint32_t n = nrun[g];
-        if (lane < n) one[g][0] = (uint32_t)p.tgt[(uint64_t)f[g] * kWave + lane] * row_bytes;
+        if (lane < nrun[g]) one[g][0] = (uint32_t)p.tgt[(uint64_t)f[g] * kWave + lane] * row_bytes;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t s = r * kWave + lane;
@@ -638,8 +632,61 @@ __device__ __forceinline__ void warm_prefix_chunks(const TE *tab, const PrefixAr
             cl[g][r] = m == 0xFFu ? kNone : m;
         }
     }
+}
+
+// Direct merging after the walk: the rest of the warm-up is the
+// single-register tail.
+template <typename TE, int R, int NQ, int G, bool TL, class Emit>
+__device__ __forceinline__ void warm_prefix_chunks(const TE *tab, const PrefixArgs &p, const uint32_t (&f)[G],
+                                                   const uint32_t (&nrun)[G], uint32_t L, uint32_t dead,
+                                                   uint32_t row_bytes, const bool (&ok)[G],
+                                                   const uint32_t (&code)[G][NQ], const uint32_t (&wlen)[G],
+                                                   uint32_t lane, uint64_t lane_lt, lds_u32 *key, lds_u8 *slot,
+                                                   const RowDiv &rd, bool code8, Emit &&emit) {
+    uint32_t one[G][1], cl[G][R];
+    prefix_rows<R, G>(p, f, nrun, ok, L, dead, row_bytes, lane, one, cl);
+    uint32_t W = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) W = wlen[g] > W ? wlen[g] : W;
     warm_tail1<TE, R, NQ, G, TL>(one, cl, p.k < W ? p.k : W, W, code, wlen, tab, dead, lane, lane_lt, key, slot,
                                  rd, code8, emit);
+}
+
+// Hashed merging after the walk (as the single-register end of
+// warm_merge_chunks): cls[g][r] the class of start r * 64 + lane, one[g]
+// class k's state in lane k, D[g] the chunk's runs.
+template <typename TE, int R, int NQ, int G, bool TL>
+__device__ __forceinline__ void warm_prefix_hashed(const TE *tab, const PrefixArgs &p, const uint32_t (&f)[G],
+                                                   const uint32_t (&nrun)[G], uint32_t L, uint32_t dead,
+                                                   uint32_t row_bytes, const bool (&ok)[G],
+                                                   const uint32_t (&code)[G][NQ], const uint32_t (&wlen)[G],
+                                                   uint32_t lane, uint64_t lane_lt, const MergeArea &m,
+                                                   uint32_t (&cls)[G][R], uint32_t (&one)[G], uint32_t (&D)[G]) {
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    uint32_t one2[G][1];
+    prefix_rows<R, G>(p, f, nrun, ok, L, dead, row_bytes, lane, one2, cls);
+    uint32_t W = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) W = wlen[g] > W ? wlen[g] : W;
+    warm_steps1<TE, NQ, G, TL>(one2, code, wlen, p.k < W ? p.k : W, W, tab, dead, m.key, lane, false);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        one[g] = one2[g][0];
+        uint32_t c2[1];
+        D[g] = merge_runs<1>(one2[g], dead, lane, lane_lt, m, c2);
+        // every lane takes part in the shuffle
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t v = (uint32_t)__shfl((int)c2[0], (int)(cls[g][r] == kNone ? 0u : cls[g][r]));
+            cls[g][r] = cls[g][r] == kNone ? kNone : v;
+        }
+        // lane k of `one` holds class c2[k]'s state; keep it in class order
+        __builtin_amdgcn_wave_barrier();
+        m.key[c2[0] != kNone ? c2[0] : kMergeTrash] = one[g];
+        __builtin_amdgcn_wave_barrier();
+        one[g] = lane < D[g] ? m.key[lane] : dead;
+        __builtin_amdgcn_wave_barrier();
+    }
 }
 
 // Occupancy: a block is 16 waves (4 per SIMD), so two blocks per CU need 8
@@ -797,7 +844,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     // transformation-automaton walks of the wave's chunks, 64 / G iterations
     // at a time: lane t G + g walks chunk g of iteration pbase + t (kNone:
     // no walk, e.g. a chunk that begins its text)
-    const uint32_t pk = DIRECT ? a.pfx.k : 0u;
+    const uint32_t pk = a.pfx.k;
     constexpr uint32_t kPerWalk = kWave / G;
     uint32_t pf = kNone, pn = 0, pbase = 0;   // state reached and its live runs
     auto prewalk = [&](uint32_t t0) {
@@ -835,6 +882,18 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
             for (uint32_t q = 0; q < (uint32_t)NQ; ++q) code[g][q] = q * kWave + lane < wlen[g] ? cls[raw[g][q]] : 0u;
         }
         fetch(it + gridDim.x, raw, wlen, first);   // next iteration's bytes, in flight meanwhile
+        bool fast = pk != 0;
+        uint32_t f[G], n[G];
+        if (fast) {
+            if (t - pbase >= kPerWalk) prewalk(t);
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int src = (int)((t - pbase) * G + g);
+                f[g] = (uint32_t)__builtin_amdgcn_readlane((int)pf, src);
+                n[g] = (uint32_t)__builtin_amdgcn_readlane((int)pn, src);
+                if (ok[g]) fast = fast && f[g] != kNone && n[g] <= kWave;
+            }
+        }
         if constexpr (DIRECT) {
             // a chunk's runs go to its region slots in class order, written
             // by the class leaders
@@ -864,18 +923,6 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
                     if (k < L) arow[k] = acl[r] == kNone ? all_ones<TA>() : (TA)acl[r];
                 }
             };
-            bool fast = pk != 0;
-            uint32_t f[G], n[G];
-            if (fast) {
-                if (t - pbase >= kPerWalk) prewalk(t);
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    const int src = (int)((t - pbase) * G + g);
-                    f[g] = (uint32_t)__builtin_amdgcn_readlane((int)pf, src);
-                    n[g] = (uint32_t)__builtin_amdgcn_readlane((int)pn, src);
-                    if (ok[g]) fast = fast && f[g] != kNone && n[g] <= kWave;
-                }
-            }
             if (fast)
                 warm_prefix_chunks<TE, R, NQ, G, LDS>(tab, a.pfx, f, n, L, dead, a.s.row_bytes, ok, code, cur_wlen, lane,
                                                  lane_lt, dkey, dslot, rd, a.s.row_bytes <= 256, emit);
@@ -884,9 +931,13 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
                                                  dkey, dslot, rd, a.s.row_bytes <= 256, emit);
         } else {
         uint32_t cl[G][R], one[G], D[G], st[G][R];
-        bool compacted;
-        warm_merge_chunks<TE, R, NQ, G>(tab, starts, L, dead, ok, cur_first, code, cur_wlen, lane, lane_lt, merge, cl,
-                                        one, D, compacted, st);
+        bool compacted = true;
+        if (fast)
+            warm_prefix_hashed<TE, R, NQ, G, LDS>(tab, a.pfx, f, n, L, dead, a.s.row_bytes, ok, code, cur_wlen, lane,
+                                                  lane_lt, merge, cl, one, D);
+        else
+            warm_merge_chunks<TE, R, NQ, G>(tab, starts, L, dead, ok, cur_first, code, cur_wlen, lane, lane_lt, merge,
+                                            cl, one, D, compacted, st);
         // runs and alias rows, chunk by chunk: class k's state to lane k
         // (from the table when the runs were not compacted)
 #pragma unroll

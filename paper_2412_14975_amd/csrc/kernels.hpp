@@ -106,7 +106,7 @@ struct PrefixArgs {
 constexpr uint8_t kPrefixWide = 0xFF;
 struct WarmArgs {
     ScanArgs s;
-    PrefixArgs pfx;            // used by the grouped warm-up with direct merging
+    PrefixArgs pfx;            // used by the grouped warm-up (at most 256 starts)
     uint32_t warm;             // bytes scanned by every run before merging (<= 256)
     void *alias;               // [nchunks][L] class (merged run) of every start, all-ones = no run
     uint32_t *run_base;        // [nchunks] first run of the chunk
