@@ -255,13 +255,13 @@ int ri_last_timings(const ri_handle *h, float ms[5]);
  *                         to 1.  1: class-partitioned relations composed
  *                         member by member within groups.  Results are
  *                         identical; only the speed differs.
- *   RI_OPT_PREFIX         1 (default): when the starts fit the grouped
- *                         warm-up (at most 256 starts), the
+ *   RI_OPT_PREFIX         1 (default): for 65 to 256 starts (the grouped
+ *                         warm-up, more than one register of starts), the
  *                         first warm-up bytes of a chunk are read by the
  *                         transformation automaton of the starts, built by
  *                         ri_build (a state = the states every start reaches
  *                         on the bytes read so far; every word of up to
- *                         ri_info_t.prefix_depth bytes, at most 32768
+ *                         ri_info_t.prefix_depth bytes, at most 65535
  *                         states); the walk covers that depth rounded down to
  *                         a multiple of 8, at most the warm-up.  0: every
  *                         start steps byte by byte.  Results are identical.

@@ -173,7 +173,7 @@ void pack_table(AlgoHost &h, uint32_t n, uint32_t K, const std::vector<int32_t> 
 // added while the states stay within the cap (and the work n K L within a
 // budget); a level that would cross it is dropped whole, so every word of up
 // to `depth` bytes ends in a state whose transitions below that depth exist.
-constexpr uint32_t kPrefixCap = 32768;
+constexpr uint32_t kPrefixCap = 65535;   // ids are u16, 0xFFFF marks a transition not expanded
 constexpr uint64_t kPrefixWork = 1ull << 27;
 constexpr uint32_t kPrefixMaxDepth = 64;
 
@@ -597,11 +597,13 @@ struct ReachBufs {
 
 // The walk of the first warm-up bytes: every word of up to `depth` bytes is
 // expanded; k is rounded down to a multiple of 8 (the rest of the warm-up then
-// steps 8 bytes per broadcast of codes) and is at most the warm-up.
+// steps 8 bytes per broadcast of codes) and is at most the warm-up.  Starts
+// that fit one register (64) step byte by byte: there a walk of dependent
+// loads from L2 saves no lookups, it only adds their latency.
 ri::PrefixArgs prefix_args(const AlgoHost &H, const AlgoDevice &D, const Options &opt) {
     ri::PrefixArgs p{};
     const uint32_t depth = H.prefix.depth;
-    if (!opt.prefix || !opt.converge || depth == 0 || !D.pfx_next) return p;
+    if (!opt.prefix || !opt.converge || depth == 0 || !D.pfx_next || H.L <= 64) return p;
     p.k = std::min<uint32_t>(depth >= 8 ? depth & ~7u : depth, opt.warm);
     p.next = D.pfx_next;
     p.count = D.pfx_count;

@@ -844,7 +844,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     // transformation-automaton walks of the wave's chunks, 64 / G iterations
     // at a time: lane t G + g walks chunk g of iteration pbase + t (kNone:
     // no walk, e.g. a chunk that begins its text)
-    const uint32_t pk = a.pfx.k;
+    const uint32_t pk = R > 1 ? a.pfx.k : 0u;   // the host walks only starts of several registers
     constexpr uint32_t kPerWalk = kWave / G;
     uint32_t pf = kNone, pn = 0, pbase = 0;   // state reached and its live runs
     auto prewalk = [&](uint32_t t0) {

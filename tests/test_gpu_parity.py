@@ -423,21 +423,31 @@ def test_motif_union_full_size(seed):
 # the walk of the transformation automaton over the first warm-up bytes
 # ---------------------------------------------------------------------------
 
+def _prefix_texts(grammar):
+    if grammar == "log":
+        x, r1, _ = gen.c3_texts(5, n=1 << 20)
+        return gen.c3_regex(), x, r1, 24
+    rx, motifs = gen.c2_regex_and_motifs(0)
+    x, r1 = gen.c2_texts(5, n=1 << 20, motifs=motifs, mean_gap=512)
+    return rx, x, r1, 8
+
+
+@pytest.mark.parametrize("grammar", ["log", "motif"])
 @pytest.mark.parametrize("size", [16, 32, 48, 8320])
-def test_prefix_walk_chunk_lengths(size):
+def test_prefix_walk_chunk_lengths(grammar, size):
     """The log-lines grammar walks 24 bytes of every chunk in the
-    transformation automaton of its 227 starts.  Chunks shorter than the walk
-    end it early (and may keep more than 64 runs, which takes every start
-    instead); results and sampled chunk maps with the walk on and off against
-    the oracle."""
-    rx = gen.c3_regex()
+    transformation automaton of its 227 starts (then direct merging), the
+    motif union 8 bytes of its 88 starts (then hashed merging).  Chunks
+    shorter than the walk end it early (and may keep more than 64 runs, which
+    takes every start instead); results and sampled chunk maps with the walk
+    on and off against the oracle."""
+    rx, x, r1, depth = _prefix_texts(grammar)
     ref = Ref(rx)
-    x, r1, _ = gen.c3_texts(5, n=1 << 20)
     for pf in (1, 0):
         rec = make(rx, "conv64")
         rec.set_option("prefix", pf)
         try:
-            assert rec.info()["prefix_depth"][0] >= 24
+            assert rec.info()["prefix_depth"][0] >= depth
             chunks = -(-len(x) // size)
             for text in (x, r1):
                 want = ref.serial(text)

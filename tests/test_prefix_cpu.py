@@ -18,7 +18,7 @@ from workloads import gen
 
 ri = pytest.importorskip("paper_2412_14975_amd")
 
-CAP = 32768            # the builder's state cap
+CAP = 65535            # the builder's state cap
 WORK = 1 << 27         # and its budget for states x classes x starts
 MAX_DEPTH = 64
 
