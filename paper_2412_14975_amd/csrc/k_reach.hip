@@ -15,6 +15,10 @@
 //                 (the chunk automaton is deterministic), so they are merged
 //                 into one run that alone is scanned to the chunk end, and
 //                 runs of a chunk that meet later are merged again there.
+//                 For 65 to 256 starts the first warm-up bytes of a chunk
+//                 are one walk in the transformation automaton of the
+//                 starts (built on the host, every word up to a depth),
+//                 whose state lists the runs every start has become.
 //
 // The join kernels are in k_join.hip.
 #include "device.hpp"
