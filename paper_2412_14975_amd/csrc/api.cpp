@@ -170,9 +170,10 @@ void pack_table(AlgoHost &h, uint32_t n, uint32_t K, const std::vector<int32_t> 
 // Breadth-first expansion of the transformation automaton: its root is the
 // vector of the start states, and class c maps a vector v to (delta(v[s], c))_s.
 // Level d holds the vectors of the words of exactly d bytes.  Levels are
-// added while the states stay within the cap (and the work n K L within a
-// budget); a level that would cross it is dropped whole, so every word of up
-// to `depth` bytes ends in a state whose transitions below that depth exist.
+// added while the states stay within the cap (and the work n K L, and the
+// level visits, within a budget); a level that would cross the cap is dropped
+// whole, so every word of up to `depth` bytes ends in a state whose
+// transitions below that depth exist.
 constexpr uint32_t kPrefixCap = 65535;   // ids are u16, 0xFFFF marks a transition not expanded
 constexpr uint64_t kPrefixWork = 1ull << 27;
 constexpr uint32_t kPrefixMaxDepth = 64;
@@ -224,6 +225,7 @@ void build_prefix(AlgoHost &H) {
     std::vector<uint8_t> expanded;
     std::vector<uint32_t> level{0}, nlevel, stamp;
     uint32_t depth = 0;
+    uint64_t lwork = 0;                        // level x class visits, bounded like the expansion
     for (uint32_t d = 0; d < kPrefixMaxDepth; ++d) {
         const uint32_t n0 = n;
         const size_t vec0 = vec.size();
@@ -262,6 +264,8 @@ void build_prefix(AlgoHost &H) {
             }
         level.swap(nlevel);
         depth = d + 1;
+        lwork += (uint64_t)level.size() * K;
+        if (lwork > kPrefixWork) break;
     }
     if (depth == 0) return;
     P.depth = depth;
