@@ -486,6 +486,39 @@ __device__ __forceinline__ void warm_steps_lds32(uint32_t (&st)[G][1], const uin
     __builtin_amdgcn_wave_barrier();   // the key area is written again by the next chunks
 }
 
+// Steps [j0, j1) of two chunks packed in one register (lanes 0..31 run
+// chunk 0, lanes 32..63 chunk 1) whose table sits in LDS; as
+// warm_steps_lds32, each half reads its own chunk's code words.
+template <typename TE, int NQ>
+__device__ __forceinline__ void warm_steps_pair32(uint32_t &st, const uint32_t (&code)[2][NQ], uint32_t j0,
+                                                  uint32_t j1, const TE *tab, uint32_t dead, lds_u32 *key,
+                                                  uint32_t lane) {
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+    typedef const __attribute__((address_space(3))) v4u lds_u4;
+    typedef const __attribute__((address_space(3))) TE lds_te;
+    const uint32_t tb = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint8_t *)tab;
+    for (uint32_t w0 = j0; w0 < j1; w0 += 16) {
+        if (__ballot(st != dead) == 0) break;
+        const uint32_t nw = j1 - w0 < 16 ? j1 - w0 : 16;   // 8 or 16
+        __builtin_amdgcn_wave_barrier();   // the previous window is read
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (uint32_t q = 0; q < (uint32_t)NQ; ++q) {
+                const uint32_t p = q * kWave + lane;
+                if (p >= w0 && p < w0 + nw) key[g * 16 + (p - w0)] = code[g][q] + tb;
+            }
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t a = (uint32_t)(uintptr_t)key + (lane >> 5) * 64u;   // this half's chunk
+        for (uint32_t k = 0; k < nw; k += 4) {
+            const v4u c = *(lds_u4 *)(uintptr_t)(a + 4 * k);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) st = *(lds_te *)(uintptr_t)(st + c[e]);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();   // the key area is written again by the next chunks
+}
+
 // Single-register steps [j0, j1) through LDS codes when they fit the key area
 // and every chunk has all the bytes (as words when the table is in LDS, TL),
 // else by readlane.
@@ -652,8 +685,37 @@ __device__ __forceinline__ void warm_prefix_chunks(const TE *tab, const PrefixAr
     uint32_t W = 0;
 #pragma unroll
     for (int g = 0; g < G; ++g) W = wlen[g] > W ? wlen[g] : W;
-    warm_tail1<TE, R, NQ, G, TL>(one, cl, p.k < W ? p.k : W, W, code, wlen, tab, dead, lane, lane_lt, key, slot,
-                                 rd, code8, emit);
+    const uint32_t j = p.k < W ? p.k : W;
+    if constexpr (TL && G == 2) {
+        // two chunks of at most 32 runs each share one register: half the
+        // lookups; each half is then merged on its own
+        bool pack = W > j && ((W - j) & 7u) == 0;
+#pragma unroll
+        for (int g = 0; g < 2; ++g) pack = pack && (!ok[g] || (nrun[g] <= 32 && wlen[g] >= W));
+        if (pack) {
+            constexpr uint32_t kNone = 0xFFFFFFFFu;
+            const uint32_t s0 = (uint32_t)__shfl((int)one[0][0], (int)(lane & 31u));
+            const uint32_t s1 = (uint32_t)__shfl((int)one[1][0], (int)(lane & 31u));
+            uint32_t st = lane < 32 ? s0 : s1;
+            warm_steps_pair32<TE, NQ>(st, code, j, W, tab, dead, key, lane);
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                uint32_t h[1] = {(lane >> 5) == (uint32_t)g ? st : dead};
+                uint32_t c2[1], ix[1];
+                uint64_t ld[1];
+                const uint32_t d = merge_direct<1>(h, dead, lane, lane_lt, slot, rd, c2, ix, ld);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const uint32_t v =
+                        (uint32_t)__shfl((int)c2[0], (int)(cl[g][r] == kNone ? 0u : 32u * g + cl[g][r]));
+                    cl[g][r] = cl[g][r] == kNone ? kNone : v;
+                }
+                emit(g, d, cl[g], ld, c2, ix);
+            }
+            return;
+        }
+    }
+    warm_tail1<TE, R, NQ, G, TL>(one, cl, j, W, code, wlen, tab, dead, lane, lane_lt, key, slot, rd, code8, emit);
 }
 
 // Hashed merging after the walk (as the single-register end of
