@@ -459,6 +459,47 @@ def test_prefix_walk_chunk_lengths(grammar, size):
             rec.close()
 
 
+def _counter_text(seed, n_runs):
+    """Runs of 1..100 a's, each closed by b (in the language (a{1,100}b)*),
+    and a copy with one run of 101 a's (rejected)."""
+    rng = gen.PCG(seed)
+    lens = rng.integers(1, 101, size=n_runs)
+    parts = [b"a" * int(k) + b"b" for k in lens]
+    x = np.frombuffer(b"".join(parts), dtype=np.uint8)
+    j = n_runs // 2
+    bad = np.frombuffer(b"".join(parts[:j] + [b"a" * 101 + b"b"] + parts[j + 1:]), dtype=np.uint8)
+    return x, bad
+
+
+@pytest.mark.parametrize("mode", ["conv64", "conv80", "conv128", "conv256"])
+@pytest.mark.parametrize("size", [160, 1024, 4096])
+def test_prefix_walk_many_live_runs(mode, size):
+    """(a{1,100}b)*: 101 starts, a walk of 64 bytes.  A chunk that begins
+    inside a long run of a's keeps one live run per count that has not yet
+    overflowed (more than 32 after the walk), a chunk that meets a b early
+    keeps one or two: with warm-ups beyond the walk, chunks of both kinds sit
+    side by side in the waves of the warm-up tail.  Results and sampled chunk
+    maps against the oracle."""
+    rx = b"(a{1,100}b)*"
+    ref = Ref(rx)
+    x, bad = _counter_text(11 + size, 6000)
+    rec = make(rx, mode)
+    try:
+        info = rec.info()
+        assert info["interface_states"] == 101 and info["prefix_depth"][0] >= 64
+        chunks = -(-len(x) // size)
+        for text in (x, bad):
+            want = ref.serial(text)
+            assert want[0] == (text is x)
+            got = rec.recognize(dev(text), algo="rid", chunks=chunks)
+            assert (got["accept"], got["final_state"]) == want, (mode, size)
+            got = rec.recognize(dev(text), algo="dfa", chunks=chunks)
+            assert (got["accept"], got["final_state"]) == want, (mode, size, "dfa")
+        check_maps(rec, ref, x, "rid", chunks, sample=12, rng=gen.PCG(size))
+    finally:
+        rec.close()
+
+
 # ---------------------------------------------------------------------------
 # log lines: 1 GiB
 # ---------------------------------------------------------------------------
