@@ -551,6 +551,62 @@ def test_log_lines_full_size(seed):
     torch.cuda.empty_cache()
 
 
+def test_text_beyond_4_gib():
+    """17 copies of a 256 MiB log-lines text: 4.25 GiB, so chunk offsets run
+    past 32 bits.  The whole text, the text with its last 9 bytes cut, and
+    the text whose last copy is a rejected one; RID and the all-states DFA,
+    synchronous and queued, automatic chunk counts.  The expected result is
+    the serial run of the minimal DFA over the concatenation, carried copy by
+    copy (the end state of one copy is the start of the next)."""
+    rx = gen.c3_regex()
+    ref = Ref(rx)
+    base, bad, _ = gen.c3_texts(6, n=1 << 28)
+    assert len(bad) == len(base)
+    copies, nb = 17, len(base)
+    n = copies * nb
+    assert n > (1 << 32)
+
+    def carry(s, x, end):
+        return oracle.run(ref.tdfa, s, x, 0, end)[0] if s >= 0 else -1
+
+    after = {}
+    s = 0
+    for _ in range(copies - 1):
+        if s not in after:
+            after[s] = carry(s, base, nb)
+        s = after[s]
+    ends = {"whole": carry(s, base, nb), "cut": carry(s, base, nb - 9), "bad": carry(s, bad, nb)}
+    wants = {k: (e >= 0 and e in ref.b.dfa.final, e) for k, e in ends.items()}
+    assert wants["whole"][0] and not wants["bad"][0]
+
+    t = torch.empty(n, dtype=torch.uint8, device="cuda")
+    bd = dev(base)
+    for i in range(copies):
+        t[i * nb:(i + 1) * nb].copy_(bd)
+    del bd
+    rec = make(rx, "conv64")
+    res = torch.full((6, 2), -7, dtype=torch.int32, device="cuda")
+    try:
+        for j, case in enumerate(("whole", "cut", "bad")):
+            if case == "bad":
+                t[(copies - 1) * nb:].copy_(dev(bad))
+            text = t[: n - 9] if case == "cut" else t
+            for a, algo in enumerate(("rid", "dfa")):
+                got = rec.recognize(text, algo=algo)
+                assert (got["accept"], got["final_state"]) == wants[case], (case, algo)
+                assert got["n"] == len(text)
+                rec.recognize_async(text, res[2 * j + a], algo=algo)
+            torch.cuda.synchronize()
+        got = res.cpu().numpy()
+        for j, case in enumerate(("whole", "cut", "bad")):
+            for a in range(2):
+                assert (bool(got[2 * j + a][0]), int(got[2 * j + a][1])) == wants[case], (case, a, "queued")
+    finally:
+        rec.close()
+        del t
+        torch.cuda.empty_cache()
+
+
 def test_ri_recognize_entry_point_on_a_side_stream():
     """ri_recognize itself (RID, automatic chunk count), called through the
     C ABI on a non-default stream, on the tiny and log-lines expressions."""
