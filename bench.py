@@ -303,10 +303,12 @@ def main_batch(args):
     recs = [ri.Recognizer(rx) for rx in regexes]
     torch.cuda.synchronize()
 
-    res, res_pg = {}, {}
-    # the default grouped plan (one launch sequence per automaton), then the
-    # long runs of every automaton in one work-queue launch
-    for mode, algo in (("grouped", "rid"), ("grouped", "dfa"), ("queue", "rid"), ("queue", "dfa")):
+    res, res_pg, res_auto = {}, {}, {}
+    # the grouped plan (one launch sequence per automaton), the long runs of
+    # every automaton in one work-queue launch, and the automatic mode, whose
+    # autotune picks one of the two
+    for mode, algo in (("grouped", "rid"), ("grouped", "dfa"), ("queue", "rid"), ("queue", "dfa"),
+                       ("auto", "rid"), ("auto", "dfa")):
         t0 = time.perf_counter()
         b = ri.Batch([(recs[k], v, algo) for (k, _, _), v in zip(items, views)], mode=mode)
         tun = b.autotune()
@@ -332,7 +334,8 @@ def main_batch(args):
         info = b.info()
         groups = [b.group(g) for g in range(info["groups"])]
         b.close()
-        (res if mode == "grouped" else res_pg)[algo] = dict(
+        dest = {"grouped": res, "queue": res_pg, "auto": res_auto}[mode]
+        dest[algo] = dict(
                          gbps=total * args.steps / wall / 1e9, ms_per_step=wall / args.steps * 1e3,
                          p50_ms=float(np.percentile(ms, 50)), p99_ms=float(np.percentile(ms, 99)),
                          gbps_p50=total / (np.percentile(ms, 50) * 1e-3) / 1e9,
@@ -342,7 +345,9 @@ def main_batch(args):
                          tuning=dict(trials=tun["trials"], best_ms=tun["best_ms"],
                                      chunk_bytes=sorted({g["chunk_bytes"] for g in groups}),
                                      warmup_bytes=sorted({g["warmup_bytes"] for g in groups})))
-        m = (res if mode == "grouped" else res_pg)[algo]
+        if mode == "auto":
+            dest[algo]["plan"] = "fused" if info["fused"] else "queue" if info["queue"] else "grouped"
+        m = dest[algo]
         print(f"# batch {mode} {algo}: {m['gbps']:.1f} GB/s exact={exact}", file=sys.stderr, flush=True)
 
     # one ri_recognize_ex call per text (each call enqueues its kernels and
@@ -396,11 +401,13 @@ def main_batch(args):
         "p50_ms": round(r["p50_ms"], 4),
         "p99_ms": round(r["p99_ms"], 4),
         "bitexact": all(v["bitexact"] for v in res.values()) and all(v["bitexact"] for v in per_text.values())
-        and all(v["bitexact"] for v in res_pg.values()),
+        and all(v["bitexact"] for v in res_pg.values()) and all(v["bitexact"] for v in res_auto.values()),
         "batch": {a: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in m.items()} for a, m in res.items()},
         "batch_work_queue": {a: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in m.items()}
                              for a, m in res_pg.items()},
         "speedup_work_queue_vs_grouped": round(res_pg["rid"]["gbps"] / res["rid"]["gbps"], 4),
+        "batch_auto": {a: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in m.items()}
+                       for a, m in res_auto.items()},
         "per_text_calls": {a: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in m.items()}
                            for a, m in per_text.items()},
         "speedup_rid_vs_dfa": round(res["rid"]["gbps"] / res["dfa"]["gbps"], 4),

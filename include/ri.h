@@ -327,6 +327,9 @@ typedef struct {
     uint32_t kernels;          /* kernel launches per run                             */
     uint32_t captured;         /* 1 after a successful ri_batch_capture               */
     uint32_t fused;            /* 1: fused plan (RI_BATCH_FUSED), 0: grouped          */
+    uint32_t queue;            /* grouped: 1 when the long runs of every group go to  */
+                               /* one work-queue launch (RI_BATCH_QUEUE, or chosen by */
+                               /* ri_batch_autotune for an RI_BATCH_AUTO batch)       */
 } ri_batch_info;
 
 typedef struct {
@@ -451,8 +454,12 @@ int ri_batch_get_group(const ri_batch *b, uint32_t index, ri_batch_group *out);
  * ri_batch_autotune -- time the batch under a fixed grid of chunk sizes
  * (unless chunk_bytes was given at creation) and warm-up lengths and re-plan
  * with the fastest: per group for a grouped batch, for the whole batch for a
- * fused one.  Every trial's results must equal the first trial's (RI_ERR_DEVICE
- * otherwise).  Synchronizes `stream`; allocates.  out may be NULL.
+ * fused one.  A grouped batch created with RI_BATCH_AUTO then also times its
+ * two placements of the long runs -- one launch sequence per group, or every
+ * group's long runs in one work-queue launch (as RI_BATCH_QUEUE) -- and keeps
+ * the faster (ri_batch_info.queue).  Every trial's results must equal the
+ * first trial's (RI_ERR_DEVICE otherwise).  Synchronizes `stream`; allocates.
+ * out may be NULL; out->best_ms is then the whole run's time for such a batch.
  */
 int ri_batch_autotune(ri_batch *b, void *stream, ri_batch_tuning *out);
 

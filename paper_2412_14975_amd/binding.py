@@ -80,7 +80,8 @@ class ri_request(ctypes.Structure):
 class ri_batch_info(ctypes.Structure):
     _fields_ = [("texts", ctypes.c_uint32), ("groups", ctypes.c_uint32), ("slots", ctypes.c_uint64),
                 ("bytes", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
-                ("kernels", ctypes.c_uint32), ("captured", ctypes.c_uint32), ("fused", ctypes.c_uint32)]
+                ("kernels", ctypes.c_uint32), ("captured", ctypes.c_uint32), ("fused", ctypes.c_uint32),
+                ("queue", ctypes.c_uint32)]
 
 
 class ri_batch_opts(ctypes.Structure):

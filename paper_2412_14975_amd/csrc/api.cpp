@@ -1416,6 +1416,7 @@ struct ri_batch {
     hipEvent_t fork = nullptr, joins[kBatchSide] = {};
     // grouped batches: the long runs of every group in one work-queue launch
     bool queue = false;
+    bool auto_mode = false;         // created with RI_BATCH_AUTO: the autotuner may switch `queue`
     Buf qdesc;                      // ri::QueueGroup per non-empty group
     uint32_t *qcounters = nullptr;  // items taken per group
     uint32_t qgroups = 0;
@@ -2096,6 +2097,7 @@ int batch_setup(ri_batch *b, const ri_request *reqs, uint32_t count, const ri_ba
         return plan_fused(b);
     }
     b->queue = o.mode == RI_BATCH_QUEUE;
+    b->auto_mode = o.mode == RI_BATCH_AUTO;
     for (auto &g : b->groups) {
         uint64_t bytes = 0;
         for (uint32_t r : g.req) bytes += b->reqs[r].n;
@@ -2592,6 +2594,7 @@ int ri_batch_get_info(const ri_batch *b, ri_batch_info *out) {
     out->texts = (uint32_t)b->reqs.size();
     out->groups = (uint32_t)b->groups.size();
     out->bytes = b->bytes;
+    out->queue = !b->fused && b->queue ? 1u : 0u;
     if (b->fused) {
         const FusedPlan &z = b->fz;
         out->slots = z.nslots;
@@ -2721,7 +2724,36 @@ int ri_batch_autotune(ri_batch *b, void *stream_v, ri_batch_tuning *out) {
         rc = g.empty ? RI_OK : plan_group(b, g);
         if (rc) { cleanup(); return rc; }
     }
-    if (b->queue && (rc = plan_queue(b)) != RI_OK) { cleanup(); return rc; }
+    // an automatic-mode batch also chooses where its long runs go: one
+    // launch sequence per group (groups overlapping on the side streams) or
+    // every group's long runs in one work-queue launch.  Both are timed as
+    // ri_batch_run runs them and must give the per-group trials' results.
+    if (b->auto_mode && nr && ng) {
+        float tm[2] = {0.f, 0.f};
+        for (int q = 0; q < 2 && !rc; ++q) {
+            b->queue = q == 1;
+            if (b->queue) rc = plan_queue(b);
+            for (int it = 0; it < 3 && !rc; ++it) {   // first pass is a warm-up
+                if (hipEventRecord(ev[0], stream) != hipSuccess) rc = fail(RI_ERR_DEVICE, "hipEventRecord");
+                if (!rc) rc = run_groups(b, stream, dres);
+                if (!rc && hipEventRecord(ev[1], stream) != hipSuccess) rc = fail(RI_ERR_DEVICE, "hipEventRecord");
+                if (!rc && hipStreamSynchronize(stream) != hipSuccess) rc = fail(RI_ERR_DEVICE, "hipStreamSynchronize");
+                float t = 0;
+                if (!rc && hipEventElapsedTime(&t, ev[0], ev[1]) != hipSuccess) rc = fail(RI_ERR_DEVICE, "hipEventElapsedTime");
+                if (!rc && it > 0) tm[q] += t / 2;
+            }
+            if (!rc && hipMemcpy(got.data(), dres, nr * 8, hipMemcpyDeviceToHost) != hipSuccess)
+                rc = fail(RI_ERR_DEVICE, "hipMemcpy");
+            if (!rc && got != ref) rc = fail(RI_ERR_DEVICE, "internal: results differ between batch plans");
+            ++trials;
+        }
+        if (rc) { cleanup(); return rc; }
+        b->queue = tm[1] < tm[0];   // the work-queue plan is still in place when chosen
+        total = b->queue ? tm[1] : tm[0];
+    } else if (b->queue && (rc = plan_queue(b)) != RI_OK) {
+        cleanup();
+        return rc;
+    }
     cleanup();
     if (out) {
         out->trials = trials;

@@ -213,6 +213,40 @@ def test_batch_autotune_keeps_results(mode):
         rec.close()
 
 
+def test_batch_autotune_chooses_the_long_run_plan():
+    """A batch in automatic mode with enough text per group takes the grouped
+    plan; its autotune times one launch sequence per group against one
+    work-queue launch for every group's long runs and keeps the faster.  The
+    results stay the oracle's either way, also after a graph capture."""
+    rx, motifs = gen.c2_regex_and_motifs(1)
+    ref = MinRef(rx)
+    xs = []
+    for k in range(4):
+        x, rej = gen.c2_texts(300 + k, n=(24 << 20) + 16 * k + 3, motifs=motifs)
+        xs.append(x if k % 2 == 0 else rej)
+    rec = ri.Recognizer(rx)
+    texts = [dev(x) for x in xs]
+    b = ri.Batch([(rec, t, ("rid", "dfa")[i % 2]) for i, t in enumerate(texts)], mode="auto")
+    try:
+        info = b.info()
+        assert info["fused"] == 0 and info["queue"] == 0
+        tun = b.autotune()
+        assert tun["trials"] >= 8 and tun["best_ms"] > 0
+        assert b.info()["queue"] in (0, 1)
+        wants = [ref.serial(x) for x in xs]
+        for run in (b.run, None):
+            if run is None:
+                b.capture()
+                got = b.launch().cpu().numpy()
+            else:
+                got = run().cpu().numpy()
+            for i, want in enumerate(wants):
+                assert (bool(got[i, 0]), int(got[i, 1])) == want, (i, run is None)
+    finally:
+        b.close()
+        rec.close()
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_batched_workload_sample(mode):
     """Four expressions of the batched workload, 48 texts of 1 KiB - 512 KiB,
