@@ -1156,6 +1156,53 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         return RI_OK;
     };
     ri::HitArgs ha{};
+    // queued calls: a result that a chunk with too many runs made invalid is
+    // redone by the class join, whose kernels are enqueued behind the hit join
+    // and return at once unless the flag is set (interfaces of at most 2048
+    // states), or else by propagation inside the final kernel.  Its levels:
+    // level 0, then level 1 in one launch whose last block takes the higher
+    // levels (few groups) and the final step (a single launch when level 0 is
+    // the only level); one launch per level when there are too many levels.
+    const bool gated_cls = hit && result_dev && gc != 0;
+    ri::ClsJoinAll all{};
+    uint32_t gated_levels = 0;
+    bool gated_tree = false;    // every level fits the launches above
+    if (gated_cls) {
+        ca.gate = sc.counters + 2;
+        ca.G = gc;
+        ca.nmembers = plan.nchunks;
+        ca.span = 1;
+        ca.ncls_in = nullptr;
+        ca.cont_in = nullptr;
+        ca.ncls_out = sc.ncls[0];
+        ca.cont_out = static_cast<uint32_t *>(sc.join[0]);
+        all.lv[gated_levels++] = ca;
+        int cur = 0;
+        uint32_t nm = (plan.nchunks + gc - 1) / gc;
+        uint64_t span = gc;
+        while (nm > 1 && gated_levels < ri::kMaxClsLevels) {
+            ri::ClsJoinArgs l = ca;
+            l.nmembers = nm;
+            l.span = span;
+            l.ncls_in = sc.ncls[cur];
+            l.cont_in = static_cast<const uint32_t *>(sc.join[cur]);
+            l.ncls_out = sc.ncls[cur ^ 1];
+            l.cont_out = static_cast<uint32_t *>(sc.join[cur ^ 1]);
+            all.lv[gated_levels++] = l;
+            cur ^= 1;
+            span *= gc;
+            nm = (nm + gc - 1) / gc;
+        }
+        gated_tree = nm == 1;
+        if (gated_tree) {
+            all.final_rel = static_cast<const uint32_t *>(sc.join[cur]);
+            all.done = sc.counters + 8;
+        }
+    }
+    // the gated level 0 rides in the hit join's first launch (extra blocks)
+    // when it is followed by the launch of the higher levels
+    const bool fuse_cls0 = gated_cls && gated_tree && gated_levels > 1 && plan.nchunks > 1 && H.W > 0 &&
+                           H.W <= kMaxDenseWords;
     if (hit) {
         // products of hit matrices: level 0 over the K - 1 matrices, then
         // groups of 64 products until at most 64 are left; the last level and
@@ -1176,7 +1223,10 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
             ha.nmembers = plan.nchunks - 1;
             ha.prod_out = sc.hprod[0];
             ha.rows_out = sc.hrows[0];
-            HIP_TRY(ri::launch_hit_prod(ha, H.W <= kMaxDenseWords ? (int)H.W : 0, shape.alias_bytes, true, stream));
+            if (fuse_cls0)
+                HIP_TRY(ri::launch_hit_prod_cls(ha, all.lv[0], (int)H.W, shape.alias_bytes, stream));
+            else
+                HIP_TRY(ri::launch_hit_prod(ha, H.W <= kMaxDenseWords ? (int)H.W : 0, shape.alias_bytes, true, stream));
             uint32_t nm = (ha.nmembers + 63) / 64;
             while (nm > ri::kHitTailMax) {
                 ha.nmembers = nm;
@@ -1192,56 +1242,20 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
             ha.nmembers = nm;
         }
         if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(sc.dbg), stream));
-        // queued calls: a result that a chunk with too many runs made invalid
-        // is redone by the class join, whose kernels are enqueued behind the
-        // hit join and return at once unless the flag is set (interfaces of at
-        // most 2048 states), or else by propagation inside the final kernel
-        const bool gated_cls = result_dev && gc != 0;
         HIP_TRY(ri::launch_finalize_hit(fa, ha, H.W <= kMaxDenseWords ? (int)H.W : 0, shape.alias_bytes, stream,
                                         result_dev, result_dev && !gated_cls ? H.W : 0, gated_cls));
         if (gated_cls) {
-            ca.gate = sc.counters + 2;
             fa.result = result_dev;
-            // the class join, gated: level 0 in one launch, then level 1 in
-            // one launch whose last block takes the higher levels (few groups)
-            // and the final step (a single launch when level 0 is the only
-            // level); one launch per level when there are too many levels
-            ri::ClsJoinAll all{};
-            uint32_t nl = 0;
-            ca.G = gc;
-            ca.nmembers = plan.nchunks;
-            ca.span = 1;
-            ca.ncls_in = nullptr;
-            ca.cont_in = nullptr;
-            ca.ncls_out = sc.ncls[0];
-            ca.cont_out = static_cast<uint32_t *>(sc.join[0]);
-            all.lv[nl++] = ca;
-            int cur = 0;
-            uint32_t nm = (plan.nchunks + gc - 1) / gc;
-            uint64_t span = gc;
-            while (nm > 1 && nl < ri::kMaxClsLevels) {
-                ca.nmembers = nm;
-                ca.span = span;
-                ca.ncls_in = sc.ncls[cur];
-                ca.cont_in = static_cast<const uint32_t *>(sc.join[cur]);
-                ca.ncls_out = sc.ncls[cur ^ 1];
-                ca.cont_out = static_cast<uint32_t *>(sc.join[cur ^ 1]);
-                all.lv[nl++] = ca;
-                cur ^= 1;
-                span *= gc;
-                nm = (nm + gc - 1) / gc;
-            }
-            if (nm == 1) {
-                all.final_rel = static_cast<const uint32_t *>(sc.join[cur]);
+            if (gated_tree) {
                 all.f = fa;
-                all.done = sc.counters + 8;
-                if (nl == 1) {
+                if (gated_levels == 1) {
                     all.nlevels = 1;
                     HIP_TRY(ri::launch_cls_join_all(all, (int)H.W, shape.alias_bytes, true, stream));
                 } else {
-                    HIP_TRY(ri::launch_join_cls(all.lv[0], (int)H.W, shape.alias_bytes, true, stream));
-                    for (uint32_t l = 1; l < nl; ++l) all.lv[l - 1] = all.lv[l];
-                    all.nlevels = nl - 1;
+                    if (!fuse_cls0)
+                        HIP_TRY(ri::launch_join_cls(all.lv[0], (int)H.W, shape.alias_bytes, true, stream));
+                    for (uint32_t l = 1; l < gated_levels; ++l) all.lv[l - 1] = all.lv[l];
+                    all.nlevels = gated_levels - 1;
                     HIP_TRY(ri::launch_cls_join_all(all, (int)H.W, shape.alias_bytes, false, stream));
                 }
             } else {

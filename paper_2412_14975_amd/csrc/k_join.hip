@@ -318,10 +318,9 @@ __global__ void __launch_bounds__(256) cls_join_all_kernel(ClsJoinAll c) {
 // builds M_k (k = 64 g + l) from the end states of chunk k's runs and the
 // alias column of chunk k + 1.
 template <int W, typename TA, bool STAGE>
-__global__ void __launch_bounds__(256) hit_prod0_kernel(HitArgs a) {
-    extern __shared__ __align__(16) uint8_t hsm[];
+__device__ __forceinline__ void hit_prod0_block(const HitArgs &a, uint32_t block, uint8_t *hsm) {
     const uint32_t lane = threadIdx.x % kWave;
-    const uint32_t g = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const uint32_t g = block * (blockDim.x / kWave) + threadIdx.x / kWave;
     const uint32_t ngroups = (a.nmembers + kWave - 1) / kWave;
     if (g >= ngroups) return;
     const uint32_t gn = g * kWave + kWave <= a.nmembers ? kWave : a.nmembers - g * kWave;
@@ -386,6 +385,27 @@ __global__ void __launch_bounds__(256) hit_prod0_kernel(HitArgs a) {
         a.prod_out[g] = M;
         a.rows_out[g] = R;
     }
+}
+
+template <int W, typename TA, bool STAGE>
+__global__ void __launch_bounds__(256) hit_prod0_kernel(HitArgs a) {
+    extern __shared__ __align__(16) uint8_t hsm[];
+    hit_prod0_block<W, TA, STAGE>(a, blockIdx.x, hsm);
+}
+
+// Queued calls: level 0 of the hit join in blocks [0, hit_blocks) and level
+// 0 of the gated class join in the blocks after them, which return at once
+// unless the warm-up flagged a chunk with more runs than a hit row holds (the
+// flag is final once the warm-up has run).  The two write separate buffers.
+template <int W, typename TA, bool STAGE>
+__global__ void __launch_bounds__(256) hit_prod0_cls_kernel(HitArgs a, ClsJoinArgs c, uint32_t hit_blocks) {
+    extern __shared__ __align__(16) uint8_t hcsm[];
+    if (blockIdx.x < hit_blocks) {
+        hit_prod0_block<W, TA, STAGE>(a, blockIdx.x, hcsm);
+        return;
+    }
+    if (*reinterpret_cast<const volatile uint32_t *>(c.gate) == 0) return;
+    cls_group<W, TA, true>(c, blockIdx.x - hit_blocks, hcsm);
 }
 
 // Level >= 1: wave per group of 64 products of the level below.
@@ -802,6 +822,25 @@ hipError_t launch_finalize_rel(const FinalArgs &a, int W, hipStream_t s) {
 hipError_t launch_finalize_fun(const FinalArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(finalize_fun_kernel, dim3(1), dim3(64), 0, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_hit_prod_cls(const HitArgs &a, const ClsJoinArgs &c, int W, int alias_bytes, hipStream_t s) {
+    if (W <= 0 || !c.gate) return hipErrorInvalidValue;
+    const uint32_t ngroups = (a.nmembers + kWave - 1) / kWave;
+    const uint32_t blocks = (ngroups + 3) / 4;
+    const uint32_t cls_groups = (c.nmembers + c.G - 1) / c.G;
+    const size_t stage = (size_t)4 * kHitStageBytes(a.L, alias_bytes);
+    const bool st = stage <= 65536;
+    const size_t lds = std::max(st ? stage : (size_t)0, cls_join_lds(c, W, alias_bytes));
+    return dispatch_ta(alias_bytes, [&](auto ta) {
+        return dispatch_b(st, [&](auto stg) {
+            constexpr bool S = decltype(stg)::value;
+#define CALLHC(w) hipLaunchKernelGGL((hit_prod0_cls_kernel<w, decltype(ta), S>), dim3(blocks + cls_groups), dim3(256), lds, s, a, c, blocks);
+            RI_DISPATCH_W(W, CALLHC)
+#undef CALLHC
+            return hipGetLastError();
+        });
+    });
 }
 
 hipError_t launch_hit_prod(const HitArgs &a, int W, int alias_bytes, bool level0, hipStream_t s) {

@@ -244,6 +244,9 @@ struct HitArgs {
 };
 // W: words of the dense content bitsets, 0 = member lists
 hipError_t launch_hit_prod(const HitArgs &a, int W, int alias_bytes, bool level0, hipStream_t s);
+// level 0 of the hit join and, in the same launch, level 0 of the class join
+// gated on c.gate (W > 0; c.grp_first unused)
+hipError_t launch_hit_prod_cls(const HitArgs &a, const ClsJoinArgs &c, int W, int alias_bytes, hipStream_t s);
 // LDS bytes of one wave's staged alias rows in hit_prod0 (64 rows, plus 16
 // for the alignment of the image)
 __host__ __device__ constexpr size_t kHitStageBytes(uint32_t L, size_t alias_bytes) {
