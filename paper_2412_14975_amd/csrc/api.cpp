@@ -1200,7 +1200,8 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
         }
     }
     // the gated level 0 rides in the hit join's first launch (extra blocks)
-    // when it is followed by the launch of the higher levels
+    // and the upper levels in its last one, when the hit join has a level 0
+    // and the class join more than one level
     const bool fuse_cls0 = gated_cls && gated_tree && gated_levels > 1 && plan.nchunks > 1 && H.W > 0 &&
                            H.W <= kMaxDenseWords;
     if (hit) {
@@ -1242,25 +1243,35 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
             ha.nmembers = nm;
         }
         if (maps) HIP_TRY(ri::launch_materialize(ja, static_cast<int32_t *>(sc.dbg), stream));
-        HIP_TRY(ri::launch_finalize_hit(fa, ha, H.W <= kMaxDenseWords ? (int)H.W : 0, shape.alias_bytes, stream,
-                                        result_dev, result_dev && !gated_cls ? H.W : 0, gated_cls));
-        if (gated_cls) {
-            fa.result = result_dev;
-            if (gated_tree) {
-                all.f = fa;
-                if (gated_levels == 1) {
-                    all.nlevels = 1;
-                    HIP_TRY(ri::launch_cls_join_all(all, (int)H.W, shape.alias_bytes, true, stream));
-                } else {
-                    if (!fuse_cls0)
+        if (fuse_cls0) {
+            // the class join's level 0 ran in the first launch: the last hit
+            // level, the final step and the gated upper levels in one launch
+            ri::FinalArgs fr = fa;
+            fr.result = result_dev;
+            all.f = fr;
+            for (uint32_t l = 1; l < gated_levels; ++l) all.lv[l - 1] = all.lv[l];
+            all.nlevels = gated_levels - 1;
+            HIP_TRY(ri::launch_hit_tail_cls(fa, ha, result_dev, all, (int)H.W, shape.alias_bytes, stream));
+        } else {
+            HIP_TRY(ri::launch_finalize_hit(fa, ha, H.W <= kMaxDenseWords ? (int)H.W : 0, shape.alias_bytes, stream,
+                                            result_dev, result_dev && !gated_cls ? H.W : 0, gated_cls));
+            if (gated_cls) {
+                fa.result = result_dev;
+                if (gated_tree) {
+                    all.f = fa;
+                    if (gated_levels == 1) {
+                        all.nlevels = 1;
+                        HIP_TRY(ri::launch_cls_join_all(all, (int)H.W, shape.alias_bytes, true, stream));
+                    } else {
                         HIP_TRY(ri::launch_join_cls(all.lv[0], (int)H.W, shape.alias_bytes, true, stream));
-                    for (uint32_t l = 1; l < gated_levels; ++l) all.lv[l - 1] = all.lv[l];
-                    all.nlevels = gated_levels - 1;
-                    HIP_TRY(ri::launch_cls_join_all(all, (int)H.W, shape.alias_bytes, false, stream));
+                        for (uint32_t l = 1; l < gated_levels; ++l) all.lv[l - 1] = all.lv[l];
+                        all.nlevels = gated_levels - 1;
+                        HIP_TRY(ri::launch_cls_join_all(all, (int)H.W, shape.alias_bytes, false, stream));
+                    }
+                } else {
+                    rc = cls_join();
+                    if (rc) return rc;
                 }
-            } else {
-                rc = cls_join();
-                if (rc) return rc;
             }
         }
     } else if (gc) {

@@ -598,6 +598,69 @@ __global__ void __launch_bounds__(64) hit_tail_kernel(FinalArgs f, HitArgs a, ui
     }
 }
 
+// Queued calls whose gated class join has run its level 0 already (inside
+// the hit join's first launch): the last level of the hit-matrix product and
+// the final step in wave 0 of block 0, and the class join's upper levels in
+// the blocks after it, gated on the warm-up's flag.  Flag clear: block 0
+// writes the result and clears the counters, the other blocks return at once.
+// Flag set: block 0 writes nothing; every block, block 0 included, counts
+// itself done, and the last one (so after block 0 has read the flag) joins
+// the remaining levels group by group, takes the final step and clears the
+// counters and the done count.
+template <int W, typename TA>
+__global__ void __launch_bounds__(256) hit_tail_cls_kernel(FinalArgs f, HitArgs a, int32_t *out, ClsJoinAll c) {
+    extern __shared__ __align__(16) uint8_t tcsm[];
+    __shared__ uint32_t s_flag, s_last;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < kWave) {
+            const uint32_t lane = threadIdx.x;
+            const uint32_t nm = a.nmembers;
+            uint64_t M = lane < nm ? a.prod_in[lane] : 0ull;
+            if (nm > 1) wave_tree_product(M, lane, nm);
+            if (lane == 0) {
+                const uint32_t flag = finalize_hit_one<W, TA>(f, a, nm > 0, M, true);
+                if (!flag) {
+                    out[0] = f.result[0];
+                    out[1] = f.result[1];
+                }
+                s_flag = flag;
+            }
+        }
+        __syncthreads();
+        if (s_flag == 0) return;
+    } else {
+        if (threadIdx.x == 0) s_flag = *reinterpret_cast<const volatile uint32_t *>(c.lv[0].gate);
+        __syncthreads();
+        if (s_flag == 0) return;
+        cls_group<W, TA, false>(c.lv[0], blockIdx.x - 1, tcsm);
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(c.done, 1u) == gridDim.x - 1 ? 1u : 0u;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    for (uint32_t l = 1; l < c.nlevels; ++l) {
+        const ClsJoinArgs &la = c.lv[l];
+        const uint32_t ngroups = (la.nmembers + la.G - 1) / la.G;
+        for (uint32_t grp = 0; grp < ngroups; ++grp) {
+            cls_group<W, TA, false>(la, grp, tcsm);
+            __syncthreads();
+        }
+        __threadfence();   // this level's output is read by the next one
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const ClsJoinArgs &la = c.lv[c.nlevels - 1];
+        const TA c0 = reinterpret_cast<const TA *>(la.alias)[0];
+        uint32_t x[W];
+        load_row<W>(x, c0 != all_ones<TA>() ? c.final_rel + (uint64_t)c0 * W : nullptr);
+        decide<W>(x, c.f, c.f.result);
+        reset_counters(c.f.counters);
+        *c.done = 0;
+    }
+}
+
 // One block: the set X of N' states (a bitset in LDS) is carried from chunk
 // to chunk: the classes of chunk k hit by X are {alias[k][t] : t in X}, and
 // the new X is the union of the contents of their end states.  Exact for any
@@ -882,6 +945,21 @@ hipError_t launch_finalize_hit(const FinalArgs &f, const HitArgs &a, int W, int 
 #define CALLFH(w) hipLaunchKernelGGL((hit_tail_kernel<w, decltype(ta)>), dim3(1), dim3(kWave), lds, s, f, a, prop_words, out, ga);
         RI_DISPATCH_W(W, CALLFH)
 #undef CALLFH
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_hit_tail_cls(const FinalArgs &f, const HitArgs &a, int32_t *out, const ClsJoinAll &c, int W,
+                               int alias_bytes, hipStream_t s) {
+    if (W <= 0 || !out || a.nmembers > kHitTailMax || c.nlevels == 0 || !c.lv[0].gate) return hipErrorInvalidValue;
+    const ClsJoinArgs &l0 = c.lv[0];
+    const uint32_t ngroups = (l0.nmembers + l0.G - 1) / l0.G;
+    size_t lds = 0;
+    for (uint32_t l = 0; l < c.nlevels; ++l) lds = std::max(lds, cls_join_lds(c.lv[l], W, alias_bytes));
+    return dispatch_ta(alias_bytes, [&](auto ta) {
+#define CALLTC(w) hipLaunchKernelGGL((hit_tail_cls_kernel<w, decltype(ta)>), dim3(1 + ngroups), dim3(256), lds, s, f, a, out, c);
+        RI_DISPATCH_W(W, CALLTC)
+#undef CALLTC
         return hipGetLastError();
     });
 }

@@ -284,6 +284,11 @@ struct ClsJoinAll {
     uint32_t *done;            // zero before the launch, left zero
 };
 hipError_t launch_cls_join_all(const ClsJoinAll &c, int W, int alias_bytes, bool first0, hipStream_t s);
+// queued calls: the hit join's last level and final step (result to `out`
+// unless the flag c.lv[0].gate is set) and, in the same launch, the gated
+// class join from its level 1 (c.lv[0]) up (W > 0)
+hipError_t launch_hit_tail_cls(const FinalArgs &f, const HitArgs &a, int32_t *out, const ClsJoinAll &c, int W,
+                               int alias_bytes, hipStream_t s);
 // The last level (a.nmembers <= kHitTailMax products in a.prod_in, 0 for a
 // single chunk) and the final step, in one launch.
 // result[2] = counters[2] (1: the hit-matrix result is not valid).  With
