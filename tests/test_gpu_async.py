@@ -109,6 +109,45 @@ def test_hit_join_fallback_on_the_device(k):
         rec.close()
 
 
+def test_hit_join_fallback_with_a_three_level_class_join():
+    """As above with k = 9 on 4 MiB: 8192 and about 16 384 chunks give the
+    gated class join three levels -- level 0 inside the hit join's first
+    launch, the others with the hit join's last level -- and it must still
+    replace the invalid hit result; a call with k = 2 (valid hit result)
+    queued in between must keep its own."""
+    rx9, rx2 = b"((b*a){9})*b*", b"((b*a){2})*b*"
+    ref9, ref2 = serial_ref(rx9), serial_ref(rx2)
+    r9, r2 = ri.Recognizer(rx9), ri.Recognizer(rx2)
+    try:
+        rng = gen.PCG(931)
+        xs = []
+        for accept in (False, True):
+            x = gen.random_text(rng, b"ab", (1 << 22) + 5)
+            if accept:
+                need = (-int((x == ord("a")).sum())) % 9
+                x[np.flatnonzero(x == ord("b"))[:need]] = ord("a")
+            xs.append(x)
+        ts = [dev(x) for x in xs]
+        stream = torch.cuda.Stream()
+        res = torch.full((8, 2), -7, dtype=torch.int32, device="cuda")
+        want = []
+        i = 0
+        for t, x in zip(ts, xs):
+            for chunks in (8192, 0):
+                r9.recognize_async(t, res[i], algo="rid", chunks=chunks, stream=stream)
+                want.append(ref9(x))
+                r2.recognize_async(t, res[i + 1], algo="rid", chunks=chunks, stream=stream)
+                want.append(ref2(x))
+                i += 2
+        stream.synchronize()
+        got = [(bool(a), int(f)) for a, f in res.cpu().numpy()]
+        assert got == want
+        assert want[4][0] and not want[0][0]
+    finally:
+        r9.close()
+        r2.close()
+
+
 def test_empty_text_and_empty_language_side_stream():
     s = torch.cuda.Stream()
     e = ri.Recognizer(b"a[^\\x00-\\xff]")
