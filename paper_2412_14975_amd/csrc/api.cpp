@@ -58,6 +58,7 @@ struct AlgoHost {
     uint32_t nstates = 0, K = 0, L = 0, W = 0;
     uint32_t entry_bytes = 0, lam_bytes = 2;
     uint32_t dead = 0;                         // byte offset of the dead row
+    uint32_t sink[2] = {0xFFFFFFFFu, 0xFFFFFFFFu};   // offsets of up to two sink rows, ~0 = none
     uint16_t code[256] = {};                   // byte -> class * entry_bytes
     std::vector<uint8_t> table;                // padded to 16 bytes
     std::vector<uint32_t> starts;              // entry offsets of the start states
@@ -165,6 +166,15 @@ void pack_table(AlgoHost &h, uint32_t n, uint32_t K, const std::vector<int32_t> 
         }
     for (int b = 0; b < 256; ++b) h.code[b] = (uint16_t)(cls[b] * eb);
     h.lam_bytes = n < 0xFFFF ? 2 : 4;
+    // sinks: every class leads back to the state (e.g. the state after a
+    // match of .*(...).*); the first two found are passed to the kernels
+    h.sink[0] = h.sink[1] = 0xFFFFFFFFu;
+    uint32_t ns = 0;
+    for (uint32_t s = 0; s < n && ns < 2; ++s) {
+        bool sink = K > 0;
+        for (uint32_t k = 0; k < K && sink; ++k) sink = delta[(size_t)s * K + k] == (int32_t)s;
+        if (sink) h.sink[ns++] = s * K * eb;
+    }
 }
 
 // Breadth-first expansion of the transformation automaton: its root is the
@@ -1064,6 +1074,8 @@ int recognize(const ri_handle *hc, const uint8_t *text, size_t n, void *stream_v
     sa.L = H.L;
     sa.row_bytes = H.K * H.entry_bytes;
     sa.dead = H.dead;
+    sa.sink0 = H.sink[0];
+    sa.sink1 = H.sink[1];
     const uint32_t chunk_groups = (plan.nchunks + 63) / 64;
 
     if (prof) HIP_TRY(hipEventRecord(ws->ev[0], stream));
@@ -1599,6 +1611,8 @@ ri::ScanArgs group_scan_args(const ri_batch *b, const BatchGroup &g) {
     sa.L = H.L;
     sa.row_bytes = H.K * H.entry_bytes;
     sa.dead = H.dead;
+    sa.sink0 = H.sink[0];
+    sa.sink1 = H.sink[1];
     return sa;
 }
 
@@ -1835,6 +1849,8 @@ ri::AutoDesc auto_desc(const BatchGroup &g, int device) {
     d.L = H.L;
     d.row_bytes = H.K * H.entry_bytes;
     d.dead = H.dead;
+    d.sink0 = H.sink[0];
+    d.sink1 = H.sink[1];
     d.entry_bytes = H.entry_bytes;
     d.functional = H.relational ? 0u : 1u;
     d.W = H.relational ? H.W : (H.L + 31) / 32;

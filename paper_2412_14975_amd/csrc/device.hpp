@@ -203,17 +203,21 @@ __device__ __forceinline__ uint32_t scan_lane(uint32_t st, uint64_t p, uint64_t 
     return s1[0];
 }
 
-// The same with any byte-code lookup.
-template <typename TE, class Code, typename TP>
+// The same with any byte-code lookup.  SINK: a run in one of the sink rows
+// sink0/1 stays there, so it stops as at the dead row (checked every 16
+// bytes); without SINK the rows are ignored.
+template <typename TE, class Code, bool SINK = false, typename TP>
 __device__ __forceinline__ uint32_t scan_lane_code(uint32_t st, uint64_t p, uint64_t vend, uint64_t end,
-                                                   TP tab, const Code &code, uint32_t dead) {
-    for (; p < vend && st != dead; p += 16) {
+                                                   TP tab, const Code &code, uint32_t dead,
+                                                   uint32_t sink0 = 0xFFFFFFFFu, uint32_t sink1 = 0xFFFFFFFFu) {
+    auto going = [&]() { return st != dead && (!SINK || (st != sink0 && st != sink1)); };
+    for (; p < vend && going(); p += 16) {
         const uint4 v = load16(at(p));
         const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int i = 0; i < 16; ++i) st = next_state<TE>(tab, st, code((w[i >> 2] >> ((i & 3) * 8)) & 0xffu));
     }
-    for (p = p < vend ? vend : p; p < end && st != dead; ++p) st = next_state<TE>(tab, st, code(*at(p)));
+    for (p = p < vend ? vend : p; p < end && going(); ++p) st = next_state<TE>(tab, st, code(*at(p)));
     return st;
 }
 

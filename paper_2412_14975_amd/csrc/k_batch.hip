@@ -103,9 +103,9 @@ __global__ void __launch_bounds__(256) mlong_kernel(MultiArgs a) {
         with_entry(d.entry_bytes, [&](auto te) {
             using TE = decltype(te);
             const CodeGlobal code{(const __attribute__((address_space(1))) uint16_t *)d.code};
-            f = scan_lane_code<TE, CodeGlobal>(a.run_state[i] * d.row_bytes, p, vend, e,
+            f = scan_lane_code<TE, CodeGlobal, true>(a.run_state[i] * d.row_bytes, p, vend, e,
                                                (const __attribute__((address_space(1))) TE *)(d.table),
-                                               code, d.dead);
+                                               code, d.dead, d.sink0, d.sink1);
         });
         a.run_final[i] = f == d.dead ? kNoState : f / d.row_bytes;
     }

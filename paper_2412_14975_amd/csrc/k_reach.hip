@@ -1098,11 +1098,14 @@ __device__ __forceinline__ uint32_t run_slot(const uint32_t *pre, uint32_t G, ui
 
 // One job of a wave: the runs in slots ri[r] (where ok[r]) from the end of
 // their chunk's warm-up to the chunk end; byte codes through `code`.
-template <typename TE, int R, class Code>
+// SINK: the automaton has sink rows (a.s.sink0/1); without them the checks
+// are compiled out.
+template <typename TE, int R, class Code, bool SINK = true>
 __device__ __forceinline__ void long_job(const LongArgs &a, const TE *tab, const Code &code, const bool (&ok)[R],
                                          const uint32_t (&ri)[R]) {
     const uint32_t lane = threadIdx.x % kWave;
     const uint32_t dead = a.s.dead;
+    const uint32_t sink0 = SINK ? a.s.sink0 : 0xFFFFFFFFu, sink1 = SINK ? a.s.sink1 : 0xFFFFFFFFu;
     {
         uint64_t p[R], vend[R], end[R];
         uint32_t st[R];
@@ -1150,7 +1153,9 @@ __device__ __forceinline__ void long_job(const LongArgs &a, const TE *tab, const
             bool work = false;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                if (ok[r] && !pk[r] && p[r] >= bend[r]) {
+                // parked: no whole block left, or in a sink row (whose run
+                // ends there; the remainder scan then stops at once)
+                if (ok[r] && !pk[r] && (p[r] >= bend[r] || (SINK && (st[r] == sink0 || st[r] == sink1)))) {
                     parked[r] = st[r];
                     st[r] = dead;
                     pk[r] = true;
@@ -1201,7 +1206,9 @@ __device__ __forceinline__ void long_job(const LongArgs &a, const TE *tab, const
             if (pk[r]) st[r] = parked[r];
         // remaining blocks and ragged tails, run by run
         if constexpr (R == 1) {
-            uint32_t f = ok[0] ? scan_lane_code<TE, Code>(st[0], p[0], vend[0], end[0], tab, code, dead) : dead;
+            uint32_t f = ok[0] ? scan_lane_code<TE, Code, SINK>(st[0], p[0], vend[0], end[0], tab, code, dead, sink0,
+                                                                sink1)
+                               : dead;
             // merged runs take the end state at the root of their chain of
             // merges (targets are lower lanes; pointer jumping, 64 = 2^6)
 #pragma unroll
@@ -1214,7 +1221,8 @@ __device__ __forceinline__ void long_job(const LongArgs &a, const TE *tab, const
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 if (ok[r]) {
-                    const uint32_t f = scan_lane_code<TE, Code>(st[r], p[r], vend[r], end[r], tab, code, dead);
+                    const uint32_t f = scan_lane_code<TE, Code, SINK>(st[r], p[r], vend[r], end[r], tab, code,
+                                                                      dead, sink0, sink1);
                     a.run_final[ri[r]] = f == dead ? kNoState : f / a.s.row_bytes;
                 }
             }
@@ -1223,7 +1231,7 @@ __device__ __forceinline__ void long_job(const LongArgs &a, const TE *tab, const
 }
 
 // The jobs of one wave in the dense run numbering (prefix `pre`).
-template <typename TE, int R, class Code>
+template <typename TE, int R, bool SINK, class Code>
 __device__ __forceinline__ void long_jobs(const LongArgs &a, const TE *tab, const Code &code, const uint32_t *pre) {
     const uint32_t G = a.warm_blocks;
     const uint32_t lane = threadIdx.x % kWave;
@@ -1244,11 +1252,11 @@ __device__ __forceinline__ void long_jobs(const LongArgs &a, const TE *tab, cons
             ok[r] = i < nruns;
             ri[r] = ok[r] ? run_slot(pre, G, iters, a.s.L, a.cpi, i) : 0u;
         }
-        long_job<TE, R, Code>(a, tab, code, ok, ri);
+        long_job<TE, R, Code, SINK>(a, tab, code, ok, ri);
     }
 }
 
-template <typename TE, int R, bool LDS>
+template <typename TE, int R, bool LDS, bool SINK>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(R == 1 ? 8 : 4))) long_kernel(LongArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     const TE *tab;
@@ -1258,9 +1266,9 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(R == 
     run_prefix(pre, a.block_count, a.warm_blocks);
     // every code is below a row's length: bytes when rows are <= 256 bytes
     if (a.s.row_bytes <= 256)
-        long_jobs<TE, R>(a, tab, CodeTab8{reinterpret_cast<const uint8_t *>(cls) + 512}, pre);
+        long_jobs<TE, R, SINK>(a, tab, CodeTab8{reinterpret_cast<const uint8_t *>(cls) + 512}, pre);
     else
-        long_jobs<TE, R>(a, tab, CodeTab{cls}, pre);
+        long_jobs<TE, R, SINK>(a, tab, CodeTab{cls}, pre);
 }
 
 // Codes (and the table when `lds`) of one group of a queued batch in LDS,
@@ -1407,10 +1415,13 @@ hipError_t launch_long(const LongArgs &a, const KernelShape &k, int grid, size_t
     return dispatch_te(k.entry_bytes, [&](auto te) {
         return dispatch_r(k.runs_per_lane, [&](auto r) {
             return dispatch_b(k.table_in_lds, [&](auto lds_t) {
-                auto fn = long_kernel<decltype(te), decltype(r)::value, decltype(lds_t)::value>;
-                if (grid == 0) { g_fn = reinterpret_cast<const void *>(fn); return hipSuccess; }
-                hipLaunchKernelGGL(fn, dim3(grid), dim3(k.block_threads), lds, st, a);
-                return hipGetLastError();
+                return dispatch_b(a.s.sink0 != 0xFFFFFFFFu, [&](auto sk) {
+                    auto fn = long_kernel<decltype(te), decltype(r)::value, decltype(lds_t)::value,
+                                          decltype(sk)::value>;
+                    if (grid == 0) { g_fn = reinterpret_cast<const void *>(fn); return hipSuccess; }
+                    hipLaunchKernelGGL(fn, dim3(grid), dim3(k.block_threads), lds, st, a);
+                    return hipGetLastError();
+                });
             });
         });
     });

@@ -28,6 +28,9 @@ struct ScanArgs {
     uint32_t L;
     uint32_t row_bytes;        // K * entry_bytes
     uint32_t dead;             // byte offset of the dead row
+    // up to two sink rows (every class leads back to the state): a run that
+    // enters one ends there, so the converging reach stops it; ~0 = none
+    uint32_t sink0 = 0xFFFFFFFFu, sink1 = 0xFFFFFFFFu;
 };
 
 // LDS bytes of the byte-code tables staged after the transition table: the
@@ -369,6 +372,7 @@ struct AutoDesc {
     uint32_t hash_cap;
     const int32_t *final_of_state;
     const uint8_t *accept_of_state;
+    uint32_t sink0 = 0xFFFFFFFFu, sink1 = 0xFFFFFFFFu;   // sink rows as in ScanArgs
 };
 
 struct MultiArgs {

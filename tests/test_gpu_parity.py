@@ -459,6 +459,36 @@ def test_prefix_walk_chunk_lengths(grammar, size):
             rec.close()
 
 
+@pytest.mark.parametrize("mode,runs", [("conv64", 0), ("conv16", 0), ("conv64", 2), ("conv64", 4), ("plain", 0)])
+def test_runs_that_enter_a_sink(mode, runs):
+    """Expressions with a sink (a state that every byte maps back to itself,
+    like the state after a match of .*(...).*): converging runs stop there,
+    since their end state is known; results and chunk maps must be the
+    oracle's, for texts that reach the sink early, late, in many chunks or
+    never, RID and the all-states DFA."""
+    rng = gen.PCG(4242)
+    for rx, alphabet, never in ((b".*(ab|bca)a.*", b"abc", b"bc"), (b"[ab]*c.*", b"abc", b"ab"),
+                                (b"(a|b)*b.*", b"ab", b"a")):
+        ref = Ref(rx)
+        rec = make(rx, mode, runs_per_lane=runs)
+        try:
+            texts = [gen.random_text(rng, alphabet, 200001), gen.random_text(rng, never, 70001)]
+            late = gen.random_text(rng, never, 150001)
+            late[-3:] = np.frombuffer(alphabet[-1:] * 3, np.uint8) if rx != b".*(ab|bca)a.*" else \
+                np.frombuffer(b"aba", np.uint8)
+            texts.append(late)
+            for x in texts:
+                want = ref.serial(x)
+                for algo in ("rid", "dfa"):
+                    for chunks in (1, 7, 1000, 0):
+                        got = rec.recognize(dev(x), algo=algo, chunks=chunks)
+                        assert (got["accept"], got["final_state"]) == want, (rx, mode, runs, algo, chunks)
+            check_maps(rec, ref, texts[0], "rid", 1000, sample=10, rng=gen.PCG(7))
+            check_maps(rec, ref, texts[0], "dfa", 1000, sample=10, rng=gen.PCG(8))
+        finally:
+            rec.close()
+
+
 def _counter_text(seed, n_runs):
     """Runs of 1..100 a's, each closed by b (in the language (a{1,100}b)*),
     and a copy with one run of 101 a's (rejected)."""
