@@ -281,7 +281,9 @@ int ri_get_option(const ri_handle *h, int option, int64_t *value);
  * grid of them on the given device text (same arguments as ri_recognize_ex;
  * every trial is a full recognition whose result is checked against the
  * first one): the converging reach over chunk targets x warm-up bytes x runs
- * per lane, and the plain reach over chunk targets x runs per lane.  The
+ * per lane, and the plain reach over chunk targets x runs per lane; a
+ * setting the automaton does not support (RI_ERR_LIMIT, e.g. the plain reach
+ * of an interface wider than its join takes) is skipped.  The
  * best setting is stored in the handle for that algorithm and used by later
  * calls with chunks = 0, until ri_set_option is called.  `out` (may be
  * NULL) receives the chosen values and the best time.  Must not run

@@ -2419,6 +2419,10 @@ int ri_autotune(ri_handle *h, const uint8_t *text, size_t n, void *stream, int a
         }
         double t[3];
         rc = timed(&t[0]);   // warm-up call; a setting far slower than the best is not timed further
+        if (rc == RI_ERR_LIMIT) {   // a setting this automaton does not support (e.g. the plain
+            rc = RI_OK;             // reach of an interface too wide for its join): skipped
+            continue;
+        }
         if (rc) break;
         if (t[0] > 4 * best_ms) continue;
         for (double &ti : t) {

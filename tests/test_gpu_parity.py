@@ -374,6 +374,26 @@ def test_autotune_keeps_results_exact():
         rec.close()
 
 
+def test_autotune_skips_settings_the_automaton_does_not_support():
+    """An interface wider than the plain reach's join (more than 2048 starts)
+    makes those trials RI_ERR_LIMIT: the autotuner skips them, keeps a
+    converging setting and the tuned call stays exact."""
+    rx, kws = gen.c5_automaton(11, 3, nkw=300)
+    dmin = oracle.min_dfa_of(oracle.trim(oracle.position_nfa(rx)))
+    rec = ri.Recognizer(rx)
+    try:
+        assert rec.info()["interface_states"] > 2048
+        rng = gen.PCG(17)
+        x = gen.c5_text(rng, kws, 3 << 20, plant=True)
+        t = dev(x)
+        tun = rec.autotune(t, algo="rid")
+        assert tun["converge"] == 1 and tun["trials"] > 0
+        got = rec.recognize(t, algo="rid")
+        assert (got["accept"], got["final_state"]) == oracle.serial(dmin, x)
+    finally:
+        rec.close()
+
+
 def test_side_stream_and_handle_reuse(tiny):
     rec, ref = tiny
     acc, rej = gen.c1_texts(9, n=1 << 18)
